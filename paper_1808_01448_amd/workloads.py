@@ -1,0 +1,150 @@
+"""Seeded synthetic workloads of the LB-IB adhesion hot path.
+
+This module only *describes inputs*: lattice sizes, particle placement and the paper's
+parameter values as numbers, plus seeded random arrays.  It holds none of the method's
+arithmetic, so the GPU library and the CPU oracle can both be fed from it without sharing
+any computation.
+
+Parameter groups follow Table 1 of Coclite et al. (arXiv 1808.01448): the bond spring
+constant, the Hamaker constant and the thermal energy are given as the paper's
+dimensionless groups (sigma H / (rho nu^2), H_k / (rho nu^2 H), k_B T / (rho nu^2 H)), the
+critical bond length as y_cr / H and the equilibrium length as a fraction of y_cr
+("Wall-particle interaction").  Each side converts them to lattice units itself.
+"""
+from __future__ import annotations
+
+import copy
+import math
+
+import numpy as np
+
+# Table 1, dimensionless column: sigma / (rho_ref nu_ref^2 / H) for the two bond strengths.
+SIGMA_HAT = {1: 27.8, 2: 55.5}
+# Table 1: H_k / (rho_ref nu_ref^2 H).
+HAMAKER_HAT = 1.74e-8
+# "Wall-particle interaction": y_cr = 6.8e-3 H, y_cr,eq = 0.5 y_cr.
+Y_CR_HAT = 6.8e-3
+Y_EQ_RATIO = 0.5
+# Results section: k_f / k_r0 = 8.5e3.  The paper does not give k_f itself; k_f = 1 per
+# time step is the reading taken.
+K_F = 1.0
+K_R0 = 1.0 / 8.5e3
+# k_B T is not reported either.  Reading: the thermal energy that makes the rupture rate
+# of a fully stretched soft bond (sigma label 1, extension y_eq) equal to k_f:
+#   (sigma - sigma*) y_eq^2 / (2 kBT) = ln(k_f / k_r0)  with sigma* = sigma / 2.
+KBT_HAT = SIGMA_HAT[1] * (Y_EQ_RATIO * Y_CR_HAT) ** 2 / (4.0 * math.log(K_F / K_R0))
+
+PRECISION = {"fp64": 0, "fp32": 1}
+
+
+def _ligand(rho_l: tuple[int, int], strength: int) -> dict:
+    return dict(
+        rho_l_num=rho_l[0], rho_l_den=rho_l[1], sigma_hat=SIGMA_HAT[strength], sigma_star_ratio=0.5,
+        y_cr_hat=Y_CR_HAT, y_eq_ratio=Y_EQ_RATIO, k_f=K_F, k_r0=K_R0, kbt_hat=KBT_HAT,
+        hamaker_hat=HAMAKER_HAT,
+    )
+
+
+def channel_small_fp64() -> dict:
+    """256 x 64 channel, tau 0.8, Re 0.1, FP64; circle of diameter 16 with 64 markers whose
+    centroid sits 12 lattice units above the bottom wall; ligand density 1/2, bond strength
+    1, seed 0, 2000 steps."""
+    return dict(
+        name="channel_256x64_circle_fp64",
+        lattice=dict(nx=256, ny=64, tau=0.8, re=0.1, drive=0, precision=PRECISION["fp64"], seed=0),
+        particle=dict(shape=0, a_major=8.0, b_minor=8.0, xc=64.0, yc=12.0, theta0=0.0, rho_p=1.0,
+                      n_markers=64),
+        ligand=_ligand((1, 2), 1),
+        receptor=dict(wall=0, density=1.0),
+        steps=2000,
+    )
+
+
+def channel_small_binding(precision: str = "fp64") -> dict:
+    """The 256 x 64 case with the circle lowered so its gap to the receptor wall is
+    y_eq = 0.5 y_cr: bonds can form from the first step."""
+    w = channel_small_fp64()
+    w["name"] = "channel_256x64_circle_binding_" + precision
+    w["lattice"]["precision"] = PRECISION[precision]
+    y_cr = Y_CR_HAT * w["lattice"]["ny"]
+    w["particle"]["yc"] = -0.5 + Y_EQ_RATIO * y_cr + w["particle"]["a_major"]
+    return w
+
+
+def channel_large_fp32() -> dict:
+    """4096 x 1024 channel, tau 0.8, Re 1, FP32 (stored as f - w_q); ellipse of aspect ratio 3
+    (major axis 48, minor 16) with 256 markers, major axis normal to the wall, initial gap
+    3e-3 H; ligand density 7/10, bond strength 2, seed 0, 100k steps."""
+    ny = 1024
+    a, b = 24.0, 8.0
+    return dict(
+        name="channel_4096x1024_ellipse_ar3_fp32",
+        lattice=dict(nx=4096, ny=ny, tau=0.8, re=1.0, drive=0, precision=PRECISION["fp32"], seed=0),
+        particle=dict(shape=1, a_major=a, b_minor=b, xc=1024.0, yc=-0.5 + 3e-3 * ny + a, theta0=0.0,
+                      rho_p=1.0, n_markers=256),
+        ligand=_ligand((7, 10), 2),
+        receptor=dict(wall=0, density=1.0),
+        steps=100_000,
+    )
+
+
+def scaled(w: dict, nx: int, ny: int, *, name: str | None = None) -> dict:
+    """The same particle problem on a different channel: the particle keeps its size relative
+    to H and its gap relative to H (used for sizes between the two configurations above)."""
+    w = copy.deepcopy(w)
+    s = ny / w["lattice"]["ny"]
+    gap = w["particle"]["yc"] + 0.5 - w["particle"]["a_major"]
+    w["lattice"]["nx"], w["lattice"]["ny"] = nx, ny
+    p = w["particle"]
+    p["a_major"] *= s
+    p["b_minor"] *= s
+    p["xc"] = nx / 4.0
+    p["yc"] = -0.5 + gap * s + p["a_major"]
+    if name:
+        w["name"] = name
+    return w
+
+
+def without_particle(w: dict) -> dict:
+    w = copy.deepcopy(w)
+    w.pop("particle", None)
+    w.pop("ligand", None)
+    w["name"] = w["name"] + "_no_particle"
+    return w
+
+
+def with_precision(w: dict, precision: str) -> dict:
+    w = copy.deepcopy(w)
+    w["lattice"]["precision"] = PRECISION[precision]
+    return w
+
+
+# ----------------------------------------------------------------------------------------
+# Seeded random arrays (for unit-level parity tests)
+# ----------------------------------------------------------------------------------------
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.default_rng(seed)
+
+
+def random_points(seed: int, n: int, nx: int, ny: int, *, y_lo: float = -0.45, y_hi: float | None = None):
+    """n evaluation points spread over the channel, including the periodic seam and the
+    rows next to both walls."""
+    g = rng(seed)
+    y_hi = ny - 0.55 if y_hi is None else y_hi
+    x = g.uniform(-2.0, nx + 2.0, n)
+    y = g.uniform(y_lo, y_hi, n)
+    # force a share of the points onto the seam and next to the walls
+    k = n // 8
+    x[:k] = g.uniform(-1.5, 1.5, k)
+    y[k:2 * k] = g.uniform(y_lo, 1.5, k)
+    y[2 * k:3 * k] = g.uniform(ny - 2.5, y_hi, k)
+    return np.stack([x, y], axis=1)
+
+
+def random_perturbation(seed: int, shape, scale: float) -> np.ndarray:
+    return rng(seed).uniform(-scale, scale, shape)
+
+
+def random_u32(seed: int, shape) -> np.ndarray:
+    return rng(seed).integers(0, 2**32, size=shape, dtype=np.uint64).astype(np.uint32)
