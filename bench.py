@@ -1,0 +1,171 @@
+#!/usr/bin/env python3
+"""Benchmark of the LB-IB adhesion hot path on one MI355X.
+
+A step is one full time step n -> n+1 of the coupled method (particle phase + lattice
+sweep) on the 4096 x 1024 FP32 channel with one aspect-ratio-3 ellipse (256 markers,
+ligand density 0.7, bond strength 2, Re 1), inputs resident in HBM.  Prints one JSON line:
+whole-step throughput in MLUPS, the lattice sweep's roofline (algorithmic bytes per
+launch over its HIP-event-timed average duration, against the 8 TB/s HBM peak), the
+measured copy bandwidth, and the FP64 CPU oracle timed on a bounded sample of the same
+workload on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "aggregate MLUPS & % HBM roofline; batched/served vs plain; p50/p99 solve latency"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweep_4096x1024_fp32.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1808_01448_amd", "csrc", "lbib_kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(cells: int):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary, or None when
+    the counters were taken on a different kernel source."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash() or t.get("cells") != cells:
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(workload: dict, steps: int):
+    import oracle
+
+    o = oracle.Sim.from_workload(workload)
+    o.step(1)  # first touch of the arrays outside the timed region
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    cells = workload["lattice"]["nx"] * workload["lattice"]["ny"]
+    return {
+        "value": round(cells * steps / dt / 1e6, 3),
+        "unit": "MLUPS",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{steps} full steps (after 1 untimed) of the same {workload['lattice']['nx']}x"
+                  f"{workload['lattice']['ny']} workload, FP64, {dt:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--cpu-steps", type=int, default=60, help="oracle steps of the CPU baseline (0: skip)")
+    ap.add_argument("--no-timing-events", action="store_true", help="time only the whole steps")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the single-simulation path has no multi-GPU form in this build "
+              "(see the sharding notes in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1808_01448_amd import lbib
+    from paper_1808_01448_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    w = W.channel_large_fp32()
+    nx, ny = w["lattice"]["nx"], w["lattice"]["ny"]
+    cells = nx * ny
+
+    stream = torch.cuda.Stream()
+    log(f"bench: building {w['name']}")
+    sim = lbib.Sim(w, stream=stream)
+    bpu = sim.bytes_per_update
+    log(f"bench: warmup {args.warmup} steps")
+    sim.step(args.warmup)
+    sim.sync()
+
+    copy_gbs = lbib.bandwidth_probe(1 << 31, 10, stream=stream)
+    log(f"bench: copy bandwidth {copy_gbs:.0f} GB/s")
+
+    if not args.no_timing_events:
+        sim.kernel_timing(True)
+    torch.cuda.synchronize()
+    log(f"bench: timing {args.steps} steps")
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = dt * 1e3 / args.steps
+    mlups = cells * args.steps / dt / 1e6
+
+    roofline = None
+    if not args.no_timing_events:
+        ms0, n0 = sim.kernel_time(0)
+        ms1, n1 = sim.kernel_time(1)
+        sweep_ms = ms0 / max(n0, 1)
+        part_ms = ms1 / max(n1, 1)
+        achieved = bpu * cells / (sweep_ms * 1e-3) / 1e9
+        traffic = measured_traffic(cells)
+        roofline = {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "sweep_kernel<float, true>", "algorithmic_bytes_per_launch": bpu * cells,
+            "avg_launch_us": round(sweep_ms * 1e3, 2), "launches_timed": n0,
+            "frac_of_measured_copy": round(achieved / copy_gbs, 4) if copy_gbs > 0 else None,
+            "particle_phase_avg_us": round(part_ms * 1e3, 2),
+        }
+    p = sim.particle()
+    sim.close()
+
+    cpu = None
+    if args.cpu_steps > 0:
+        log(f"bench: CPU oracle baseline, {args.cpu_steps} steps")
+        cpu = cpu_baseline(w, args.cpu_steps)
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": w["name"], "nx": nx, "ny": ny, "storage": "fp32 (f - w_q)",
+            "particles": 1, "shape": "ellipse AR3 48x16", "markers": w["particle"]["n_markers"],
+            "rho_l": "7/10", "bond_strength": 2, "re": w["lattice"]["re"], "tau": w["lattice"]["tau"],
+            "particle_phase_dtype": "f64",
+        },
+        "roofline": roofline,
+        "copy_bandwidth_gbs": round(copy_gbs, 1),
+        "cpu_baseline": cpu,
+        "final_particle": {k: p[k] for k in ("step", "xc", "yc", "theta", "n_bonds")},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

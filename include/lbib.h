@@ -1,0 +1,263 @@
+/*
+ * lbib.h -- C-ABI of the MI355X (gfx950) LB-IB particle-adhesion library.
+ *
+ * The library advances the combined lattice Boltzmann - immersed boundary model of
+ * Coclite et al., "Predicting Different Adhesive Regimens of Circulating Particles at Blood
+ * Capillary Walls" (arXiv 1808.01448, section "Computational method"): a D2Q9 BGK fluid with
+ * Guo forcing (eq 1-6), a rigid particle coupled through moving-least-squares (MLS)
+ * immersed-boundary interpolation and spreading, surface loads from normal probes (eq 7-8),
+ * stochastic ligand-receptor bonds (eq 9-11), a wall force (eq 12) and an explicit
+ * second-order rigid-body update (eq 13-16).  Every step of the time loop runs in HIP
+ * kernels on the GPU; the host only validates, allocates and enqueues.
+ *
+ * Conventions shared by every call
+ *  - Lattice units: dx = dt = 1, rho_ref = 1, cs^2 = 1/3, nu = (tau - 1/2)/3.
+ *  - Node (i, j) sits at (x, y) = (i, j), 0 <= i < nx, 0 <= j < ny.  x is periodic.  Resting
+ *    half-way bounce-back walls lie at y = -1/2 (the receptor wall) and y = ny - 1/2, so the
+ *    channel height is H = ny.  The flow is driven by the body force g = (8 nu u_max / H^2, 0)
+ *    with u_max = Re nu / H (the centre-line velocity of the Poiseuille profile).
+ *  - Populations are D2Q9 in the order e_0 = (0,0), e_1 = (1,0), e_2 = (0,1), e_3 = (-1,0),
+ *    e_4 = (0,-1), e_5 = (1,1), e_6 = (-1,1), e_7 = (-1,-1), e_8 = (1,-1) (eq 3).  Host arrays
+ *    of populations are plain f (not shifted), FP64, laid out [q][j][i] with i fastest.
+ *  - Particle angle theta: 0 means the major axis (semi-axis a) is normal to the wall;
+ *    positive is counter-clockwise.  Angular velocity omega is counter-clockwise positive.
+ *  - Every function returns an lbib_status; nothing throws or aborts across this boundary.
+ *    Arguments are validated before anything is allocated or changed: a call that fails
+ *    validation leaves the handle as it was.  lbib_last_error() then describes the failure.
+ *  - Numerical failure (non-finite force, velocity or torque, a particle touching the wall,
+ *    a singular MLS system, a spread tile overflow) is detected on the GPU and reported as
+ *    LBIB_E_NUMERIC by the next lbib_sync / lbib_read_* call; lbib_step then returns
+ *    LBIB_E_STATE until lbib_load restores a good state.
+ *  - Ownership: descriptors are copied on entry.  The handle owns all device memory.  Host
+ *    read buffers belong to the caller and come with an explicit capacity; too small a
+ *    capacity returns LBIB_E_INVALID and names the required size in lbib_last_error().
+ *  - Threading: one handle is used from one host thread at a time; distinct handles are
+ *    independent.  Work is enqueued on the handle's HIP stream.
+ *  - Determinism: identical descriptors and seed give bit-identical results on the same
+ *    build and GPU (the spread is accumulated in 64-bit fixed point, every other reduction
+ *    has a fixed order, and bond draws come from a counter-based generator).
+ */
+#ifndef LBIB_H
+#define LBIB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBIB_ABI_VERSION 1
+
+typedef struct lbib_sim* lbib_handle;
+
+typedef enum {
+    LBIB_OK = 0,
+    LBIB_E_INVALID = -1,     /* bad argument: nothing was changed */
+    LBIB_E_STATE = -2,       /* call out of order, or the simulation is in the failed state */
+    LBIB_E_NOMEM = -3,       /* device or host allocation failed */
+    LBIB_E_DEVICE = -4,      /* a HIP runtime call failed */
+    LBIB_E_NUMERIC = -5,     /* the GPU watchdog raised a numerical failure */
+    LBIB_E_UNSUPPORTED = -6  /* valid request this build does not implement */
+} lbib_status;
+
+/* Precision of the population storage.  FP64 stores f - w_q in double and collides in
+ * double; FP32 stores f - w_q in float and collides in float.  The particle phase (MLS
+ * solves, interpolation, loads, bonds, reductions, rigid body) is FP64 in both. */
+enum { LBIB_FP64 = 0, LBIB_FP32 = 1 };
+
+/* Lattice (section "Modeling the adhesion dynamics ..."; Table 1).  drive must be 0
+ * (body-force Poiseuille with resting bounce-back walls).  Requirements: nx >= 4, ny >= 4,
+ * tau > 1/2, Re >= 0. */
+typedef struct {
+    int32_t nx, ny;
+    double tau;
+    double re;
+    int32_t drive;
+    int32_t precision;
+    uint64_t seed; /* key of the bond draws */
+} lbib_lattice_desc;
+
+/* Rigid particle (section "Pressure and viscous stresses"; particle shapes of the results
+ * section).  shape 0: circle of radius a_major (b_minor ignored); shape 1: ellipse with
+ * semi-axis a_major along the body y axis and b_minor along the body x axis.  The surface
+ * is cut into n_markers straight elements of equal arc length starting at the body point
+ * (0, -a) and running counter-clockwise; each element's centroid is a Lagrangian marker.
+ * rho_p is the particle density (mass = rho_p pi a b).  Requirements: 8 <= n_markers <= 1024,
+ * marker spacing (perimeter / n_markers) >= 0.25, the particle inside the channel with a
+ * positive gap to both walls, 2 a_major + 6 <= nx. */
+typedef struct {
+    int32_t shape;
+    double a_major, b_minor;
+    double xc, yc, theta0;
+    double rho_p;
+    int32_t n_markers;
+} lbib_particle_desc;
+
+/* Ligands and bonds (section "Wall-particle interaction", eq 9-12, Table 1).  The ligand
+ * density rho_l = rho_l_num / rho_l_den (0 <= rho_l <= 1) selects floor(n rho_l) elements
+ * spread evenly along the perimeter.  Table 1 dimensionless groups, converted with
+ * nu = (tau - 1/2)/3 and H = ny:
+ *   sigma = sigma_hat nu^2 / H            spring constant (eq 9)
+ *   sigma* = sigma_star_ratio sigma       (eq 11; 0.5 gives slip bonds)
+ *   y_cr = y_cr_hat H                     critical separation for bond formation
+ *   y_eq = y_eq_ratio y_cr                equilibrium bond length (eq 9)
+ *   k_BT = kbt_hat nu^2 H                 thermal energy (eq 11)
+ *   H_k = hamaker_hat nu^2 H              Hamaker constant (eq 12)
+ * k_f and k_r0 are rates per time step (eq 10-11). */
+typedef struct {
+    int32_t rho_l_num, rho_l_den;
+    double sigma_hat, sigma_star_ratio;
+    double y_cr_hat, y_eq_ratio;
+    double k_f, k_r0;
+    double kbt_hat, hamaker_hat;
+} lbib_ligand_desc;
+
+/* Receptors: the paper covers the wall completely (density 1).  wall must be 0 (bottom) and
+ * density must be 1.0; anything else returns LBIB_E_UNSUPPORTED. */
+typedef struct {
+    int32_t wall;
+    double density;
+} lbib_receptor_desc;
+
+/* One particle record: the state after a step and the loads used in it.  n_bonds counts
+ * the bonds after the step's update, n_probing the ligands that were within y_cr. */
+typedef struct {
+    int64_t step; /* index n of the step n -> n+1 this record describes */
+    double xc, yc, theta, ux, uy, omega;   /* time level n+1 */
+    double fx, fy, torque;                 /* total load used for the update */
+    double fx_hydro, fy_hydro, m_hydro;    /* eq 7-8 */
+    double fx_bond, fy_bond, m_bond;       /* eq 9 summed over bonded elements */
+    double fy_wall;                        /* eq 12 */
+    double gap;                            /* analytic gap to y = -1/2 at level n */
+    int32_t n_bonds, n_probing;
+} lbib_particle_state;
+
+int lbib_abi_version(void);
+
+/* Create a simulation.  hip_stream: the hipStream_t to enqueue on, or NULL for a stream the
+ * handle creates and owns.  On success *out receives the handle. */
+lbib_status lbib_create(const lbib_lattice_desc* desc, void* hip_stream, lbib_handle* out);
+
+/* Add the particle (at most one per simulation in this build).  *particle_id receives 0. */
+lbib_status lbib_particle_add(lbib_handle h, const lbib_particle_desc* desc, int32_t* particle_id);
+
+/* Decorate particle particle_id with ligands; required before lbib_init when a particle
+ * exists. */
+lbib_status lbib_ligands_set(lbib_handle h, int32_t particle_id, const lbib_ligand_desc* desc);
+
+/* Receptors on the wall; optional (the default is the paper's full coverage). */
+lbib_status lbib_receptors_set(lbib_handle h, const lbib_receptor_desc* desc);
+
+/* Allocate device memory and set the initial state: f = f_eq(1, u(y)) with the Poiseuille
+ * profile u(y) = 4 u_max (y + 1/2)(H - 1/2 - y) / H^2; particle at rest; no bonds. */
+lbib_status lbib_init(lbib_handle h);
+
+/* Enqueue n_steps time steps (asynchronous: returns before the GPU finishes). */
+lbib_status lbib_step(lbib_handle h, int64_t n_steps);
+
+/* Wait for enqueued work; returns LBIB_E_NUMERIC when the watchdog fired. */
+lbib_status lbib_sync(lbib_handle h);
+
+/* Steps completed by the enqueued work (host count). */
+lbib_status lbib_step_count(lbib_handle h, int64_t* steps);
+
+/* Latest particle record (after the last completed step; before any step: the initial
+ * state with zero loads and step = -1). */
+lbib_status lbib_read_particle(lbib_handle h, int32_t pid, lbib_particle_state* out);
+
+/* Bond and ligand flags per element (capacity >= n_markers). */
+lbib_status lbib_read_bonds(lbib_handle h, int32_t pid, uint8_t* bonded, uint8_t* ligand, int32_t capacity);
+
+/* Marker positions and outward normals at the current time level, xy and nxy as
+ * [n_markers][2] (capacity counts markers). */
+lbib_status lbib_read_markers(lbib_handle h, int32_t pid, double* xy, double* nxy, int32_t capacity);
+
+/* Read a field at the current time level into out (capacity in doubles):
+ *   which 0: rho = sum_q f_q                                  [ny][nx]
+ *   which 1: u_x = (sum_q f_q e_qx + g_x / 2) / rho           [ny][nx]
+ *   which 2: u_y likewise                                     [ny][nx]
+ *   which 3: the populations f_q, plain FP64                  [9][ny][nx]
+ * (the velocity excludes the immersed-boundary force of the coming step). */
+lbib_status lbib_read_field(lbib_handle h, int32_t which, double* out, int64_t capacity);
+
+/* Overwrite the populations with plain FP64 values laid out [9][ny][nx] (count = 9 nx ny).
+ * Allowed after lbib_init. */
+lbib_status lbib_write_populations(lbib_handle h, const double* f, int64_t count);
+
+/* Overwrite the particle's rigid-body state: xc, yc, theta, ux, uy, omega at level n and the
+ * same six at level n-1 (12 doubles).  Allowed after lbib_init. */
+lbib_status lbib_write_particle(lbib_handle h, int32_t pid, const double* state12);
+
+/* Overwrite the bond flags (count = n_markers; flags on elements without a ligand must be 0). */
+lbib_status lbib_write_bonds(lbib_handle h, int32_t pid, const uint8_t* bonded, int32_t count);
+
+/* Record one lbib_particle_state per step into a device buffer of `capacity` records,
+ * starting with the next enqueued step (capacity 0 switches recording off). */
+lbib_status lbib_trace_enable(lbib_handle h, int32_t pid, int64_t capacity);
+
+/* Copy the recorded states (up to capacity) to out; *count receives the number copied. */
+lbib_status lbib_read_trace(lbib_handle h, int32_t pid, lbib_particle_state* out, int64_t capacity,
+                            int64_t* count);
+
+/* Checkpoint: with blob == NULL, *size receives the number of bytes needed; otherwise the
+ * complete state (populations, particle, bonds, step counter) is written to blob (which
+ * holds *size bytes).  lbib_load restores it into a handle created and initialised with the
+ * same descriptors, and clears the failed state. */
+lbib_status lbib_save(lbib_handle h, void* blob, int64_t* size);
+lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size);
+
+/* Kernel timing: when enabled, HIP events bracket every launch of the lattice sweep
+ * (kernel 0) and of the particle phase (kernel 1).  lbib_kernel_time synchronises and
+ * returns the summed milliseconds and launch counts since the last enable. */
+lbib_status lbib_kernel_timing(lbib_handle h, int32_t enable);
+lbib_status lbib_kernel_time(lbib_handle h, int32_t kernel, double* total_ms, int64_t* launches);
+
+/* Bytes of HBM the algorithm moves per lattice update (9 populations read + 9 written):
+ * 144 for FP64 storage, 72 for FP32. */
+lbib_status lbib_bytes_per_update(lbib_handle h, int64_t* bytes);
+
+/* Description of the last failure on this handle; valid until the next call on it. */
+const char* lbib_last_error(lbib_handle h);
+
+/* Release everything the handle owns.  NULL-safe. */
+void lbib_destroy(lbib_handle h);
+
+/* ---------------------------------------------------------------------------------------
+ * Kernel-level entry points.  They run the same device functions as the time step on
+ * caller-owned DEVICE buffers, enqueued on hip_stream (NULL = the default stream), so each
+ * piece can be checked alone.  n <= 2^31 - 1.
+ * ------------------------------------------------------------------------------------- */
+
+/* Philox4x32-10 (Salmon et al., SC'11): out[4i..4i+3] = philox(ctr[4i..4i+3], key[2i..2i+1]). */
+lbib_status lbib_kernel_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n,
+                               void* hip_stream);
+
+/* MLS shape functions at points pts[2i], pts[2i+1] on an nx x ny lattice (the reading of
+ * the paper's MLS reconstruction: nodes within 1.5 per axis, x periodic, wall rows cut;
+ * linear basis; cubic B-spline weights of radius 1.5).  For each point and each of the 3 x 3
+ * candidate nodes k = 3 dj + di: node[2(9i+k)] = wrapped node i (or -1 when not in the
+ * support), node[2(9i+k)+1] = node j; phi, psix, psiy [9 n]. */
+lbib_status lbib_kernel_mls(const double* pts, int64_t n, int32_t nx, int32_t ny, int32_t* node, double* phi,
+                            double* psix, double* psiy, void* hip_stream);
+
+/* Bond update of n_sets independent particles with nl elements each (eq 10-11): for set s,
+ * d[s nl + l] is the element's distance from the receptor wall, ligand / b_in its flags and
+ * step[s] its step counter; b_out receives the flags after the update, n_bonds[s] and
+ * n_probing[s] the counts.  params = {y_cr, y_eq, sigma, sigma_star, k_f, k_r0, kBT}
+ * (host array of 7 doubles).  The draws use key (seed lo, seed hi) and counter
+ * (step lo, step hi, l, pid). */
+lbib_status lbib_kernel_bonds(const uint8_t* ligand, const double* d, const uint8_t* b_in, uint8_t* b_out,
+                              const int64_t* step, int32_t* n_bonds, int32_t* n_probing, int32_t nl,
+                              int32_t n_sets, const double* params, uint64_t seed, uint32_t pid,
+                              void* hip_stream);
+
+/* Device-to-device copy of `bytes` bytes (a multiple of 16), timed over `iters` repeats on
+ * the given stream; *gbps receives the best (read + write) bandwidth in GB/s.  Used as the
+ * measured HBM reference for the lattice sweep's roofline. */
+lbib_status lbib_bandwidth_probe(int64_t bytes, int32_t iters, void* hip_stream, double* gbps);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBIB_H */

@@ -83,6 +83,7 @@ def lib():
             "orc_geometry": (C.c_int32, [C.c_int32, C.c_double, C.c_double, C.c_int32, _D, _D, _D, _D]),
             "orc_ligand_flags": (None, [C.c_int32, C.c_int32, C.c_int32, _U8]),
             "orc_philox4x32_10": (None, [_U32, _U32, _U32]),
+            "orc_philox_batch": (None, [C.c_int64, _U32, _U32, _U32]),
             "orc_threshold": (C.c_uint64, [C.c_double]),
             "orc_bonds": (C.c_int32, [C.c_int32, _U8, _D, _U8, _U8, C.c_double, C.c_double, C.c_double,
                                       C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint64,
@@ -110,6 +111,7 @@ def lib():
             "orc_sim_get_geometry": (None, [C.c_void_p, _D, _D, _D]),
             "orc_sim_get_markers": (None, [C.c_void_p, _D, _D]),
             "orc_num_threads": (C.c_int32, []),
+            "orc_set_threads": (None, [C.c_int32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -202,6 +204,14 @@ def philox(ctr, key):
     return out
 
 
+def philox_batch(ctr, key):
+    """ctr uint32 [n, 4], key uint32 [n, 2] -> uint32 [n, 4]."""
+    ctr = np.ascontiguousarray(ctr, np.uint32); key = np.ascontiguousarray(key, np.uint32)
+    out = np.zeros_like(ctr)
+    lib().orc_philox_batch(len(ctr), _p(ctr, _U32), _p(key, _U32), _p(out, _U32))
+    return out
+
+
 def threshold(P):
     return int(lib().orc_threshold(float(P)))
 
@@ -262,6 +272,10 @@ def tractions(nu, rho, ux, uy, P, n, S):
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int):
+    lib().orc_set_threads(int(n))
 
 
 # ----------------------------------------------------------------------------------------

@@ -355,6 +355,12 @@ void orc_philox4x32_10(const uint32_t* ctr_in, const uint32_t* key_in, uint32_t*
     out[3] = c3;
 }
 
+/* n independent draws: out[4k..4k+3] = philox(ctr[4k..4k+3], key[2k..2k+1]). */
+void orc_philox_batch(int64_t n, const uint32_t* ctr, const uint32_t* key, uint32_t* out)
+{
+    for (int64_t k = 0; k < n; ++k) orc_philox4x32_10(ctr + 4 * k, key + 2 * k, out + 4 * k);
+}
+
 /* Integer threshold of a probability: an event of probability P fires iff the uniform
  * 32-bit draw r satisfies r < T(P) = floor(P * 2^32); T(0) = 0 never fires, T(1) = 2^32
  * always fires.  NaN is taken as 0. */
@@ -823,5 +829,14 @@ int32_t orc_num_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+void orc_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }

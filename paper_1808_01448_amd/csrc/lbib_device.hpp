@@ -1,0 +1,186 @@
+// lbib_device.hpp -- device functions of the LB-IB adhesion step (gfx950).
+//
+// Lattice constants of D2Q9 (eq 3 and the weights below it), the Philox4x32-10 counter-based
+// generator used for the bond draws (Salmon et al., SC'11), the moving-least-squares shape
+// functions used for interpolation, spreading and probe derivatives, and the per-element
+// stochastic bond decision (eq 10-11).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbib {
+namespace dev {
+
+// ---------------------------------------------------------------------------------------
+// D2Q9
+// ---------------------------------------------------------------------------------------
+constexpr int kEx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int kEy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+constexpr double kW[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
+                          1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+// Density and momentum of shifted populations g_q = f_q - w_q: rho = 1 + sum g (the weights
+// sum to one), j = sum g e (the weights carry no momentum).
+template <typename R, typename S>
+__device__ __forceinline__ void shifted_moments(const S* g, R& drho, R& jx, R& jy)
+{
+    R g0 = (R)g[0], g1 = (R)g[1], g2 = (R)g[2], g3 = (R)g[3], g4 = (R)g[4];
+    R g5 = (R)g[5], g6 = (R)g[6], g7 = (R)g[7], g8 = (R)g[8];
+    drho = ((g0 + g1) + (g2 + g3)) + ((g4 + g5) + (g6 + g7)) + g8;
+    jx = (g1 - g3) + (g5 - g7) + (g8 - g6);
+    jy = (g2 - g4) + (g5 - g7) + (g6 - g8);
+}
+
+// ---------------------------------------------------------------------------------------
+// Philox4x32-10: ten rounds of the Philox S-box on a 128-bit counter; the 64-bit key is
+// advanced by the Weyl increments (0x9E3779B9, 0xBB67AE85) between rounds.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3, uint32_t k0,
+                                              uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t a = c0, b = c2;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, a), lo0 = 0xD2511F53u * a;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, b), lo1 = 0xCD9E8D57u * b;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// An event of probability P fires when a uniform 32-bit draw r satisfies r < T(P) with
+// T(P) = floor(P 2^32); T(0) = 0 never fires, T(1) = 2^32 always does; NaN counts as 0.
+__device__ __forceinline__ uint64_t prob_threshold(double P)
+{
+    if (!(P > 0.0)) return 0ull;
+    if (P >= 1.0) return 4294967296ull;
+    return (uint64_t)floor(P * 4294967296.0);
+}
+
+// ---------------------------------------------------------------------------------------
+// Moving least squares on the lattice (reading of the MLS reconstruction the paper cites):
+// support = nodes with |i - X| < 1.5 (x periodic) and |j - Y| < 1.5 inside the fluid rows
+// 0..ny-1; basis [1, dx, dy] with d = node - point; weight w(|dx|/1.5) w(|dy|/1.5) with w the
+// cubic B-spline.  The support is a tensor grid of nxs x nys nodes starting at (i0, j0)
+// (i0 unwrapped); entry k = 3 b + a refers to node (i0 + a, j0 + b).
+// ---------------------------------------------------------------------------------------
+struct Mls {
+    int i0, j0, nxs, nys;
+    double phi[9], psx[9], psy[9];
+};
+
+__device__ __forceinline__ double bspline(double s)
+{
+    if (s <= 0.5) return 2.0 / 3.0 + s * s * (4.0 * s - 4.0);
+    if (s < 1.0) {
+        const double r = 1.0 - s;
+        return (4.0 / 3.0) * r * r * r;
+    }
+    return 0.0;
+}
+
+// Returns false when the moment matrix is singular (empty or degenerate support).
+__device__ inline bool mls_shape(double X, double Y, int ny, Mls& m, bool want_grad)
+{
+    if (!(fabs(X) < 1e9 && fabs(Y) < 1e9)) {  // non-finite or absurd point: empty support
+        m.i0 = m.j0 = 0;
+        m.nxs = m.nys = 0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) m.phi[k] = m.psx[k] = m.psy[k] = 0.0;
+        return false;
+    }
+    const int ilo = (int)floor(X - 1.5) + 1, ihi = (int)ceil(X + 1.5) - 1;
+    int jlo = (int)floor(Y - 1.5) + 1, jhi = (int)ceil(Y + 1.5) - 1;
+    jlo = jlo < 0 ? 0 : jlo;
+    jhi = jhi > ny - 1 ? ny - 1 : jhi;
+    m.i0 = ilo;
+    m.j0 = jlo;
+    m.nxs = ihi - ilo + 1;
+    m.nys = jhi - jlo + 1;
+    double wx[3], dx[3], wy[3], dy[3];
+    // one-dimensional moments; the weight is a tensor product, so the 3x3 moment matrix is
+    // built from products of these sums
+    double x0 = 0, x1 = 0, x2 = 0, y0 = 0, y1 = 0, y2 = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        dx[a] = (double)(ilo + a) - X;
+        wx[a] = a < m.nxs ? bspline(fabs(dx[a]) * (1.0 / 1.5)) : 0.0;
+        x0 += wx[a];
+        x1 += wx[a] * dx[a];
+        x2 += wx[a] * dx[a] * dx[a];
+        dy[a] = (double)(jlo + a) - Y;
+        wy[a] = (a < m.nys && m.nys > 0) ? bspline(fabs(dy[a]) * (1.0 / 1.5)) : 0.0;
+        y0 += wy[a];
+        y1 += wy[a] * dy[a];
+        y2 += wy[a] * dy[a] * dy[a];
+    }
+    const double a00 = x0 * y0, a01 = x1 * y0, a02 = x0 * y1;
+    const double a11 = x2 * y0, a12 = x1 * y1, a22 = x0 * y2;
+    // symmetric inverse by cofactors
+    const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22, c02 = a01 * a12 - a02 * a11;
+    const double c11 = a00 * a22 - a02 * a02, c12 = a01 * a02 - a00 * a12, c22 = a00 * a11 - a01 * a01;
+    const double det = a00 * c00 + a01 * c01 + a02 * c02;
+    if (!(det > 0.0) || m.nys <= 0) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) m.phi[k] = m.psx[k] = m.psy[k] = 0.0;
+        return false;
+    }
+    const double id = 1.0 / det;
+    const double i00 = c00 * id, i01 = c01 * id, i02 = c02 * id, i11 = c11 * id, i12 = c12 * id, i22 = c22 * id;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double W = wx[a] * wy[b];
+            m.phi[3 * b + a] = W * (i00 + i01 * dx[a] + i02 * dy[b]);
+            if (want_grad) {
+                m.psx[3 * b + a] = W * (i01 + i11 * dx[a] + i12 * dy[b]);
+                m.psy[3 * b + a] = W * (i02 + i12 * dx[a] + i22 * dy[b]);
+            }
+        }
+    }
+    return true;
+}
+
+__device__ __forceinline__ int wrap(int i, int n)
+{
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+// ---------------------------------------------------------------------------------------
+// Bonds (eq 10-11)
+// ---------------------------------------------------------------------------------------
+struct BondParams {
+    double y_cr, y_eq, sigma, sigma_star, k_f, k_r0, kBT;
+};
+
+// Bond flag after the update of element l.  Tf = T(P_f) of the particle (eq 10).  A bond
+// present at the start of the step ruptures when draw r1 < T(P_r) (eq 11, bond length d);
+// otherwise a ligand within y_cr of the wall forms a bond when draw r0 < Tf.  A bond broken
+// in this step does not re-form in it.  Key (seed lo, seed hi), counter (step lo, step hi,
+// l, pid).
+__device__ __forceinline__ uint8_t bond_update(bool ligand, bool bonded, double d, uint64_t Tf, const BondParams& p,
+                                               uint64_t seed, int64_t step, uint32_t l, uint32_t pid)
+{
+    if (!ligand) return 0;
+    uint32_t c0 = (uint32_t)(uint64_t)step, c1 = (uint32_t)((uint64_t)step >> 32), c2 = l, c3 = pid;
+    philox4x32_10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+    if (bonded) {
+        const double ext = d - p.y_eq;
+        const double Pr = -expm1(-p.k_r0 * exp((p.sigma - p.sigma_star) * ext * ext / (2.0 * p.kBT)));
+        return (uint64_t)c1 < prob_threshold(Pr) ? 0 : 1;
+    }
+    if (d < p.y_cr) return (uint64_t)c0 < Tf ? 1 : 0;
+    return 0;
+}
+
+}  // namespace dev
+}  // namespace lbib

@@ -1,0 +1,348 @@
+"""ctypes binding of the gfx950 LB-IB adhesion library (include/lbib.h).
+
+Argument marshalling only: every step of the time loop runs in the library's HIP kernels.
+PyTorch provides device memory for the kernel-level entry points and the HIP stream the
+simulation is enqueued on.  If the shared library has not been built, importing the
+binding's functions raises immediately: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "liblbib.so")
+
+OK, E_INVALID, E_STATE, E_NOMEM, E_DEVICE, E_NUMERIC, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_STATE", -3: "E_NOMEM", -4: "E_DEVICE", -5: "E_NUMERIC",
+                -6: "E_UNSUPPORTED"}
+FP64, FP32 = 0, 1
+
+
+class LbibError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class LatticeDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("tau", C.c_double), ("re", C.c_double),
+                ("drive", C.c_int32), ("precision", C.c_int32), ("seed", C.c_uint64)]
+
+
+class ParticleDesc(C.Structure):
+    _fields_ = [("shape", C.c_int32), ("a_major", C.c_double), ("b_minor", C.c_double), ("xc", C.c_double),
+                ("yc", C.c_double), ("theta0", C.c_double), ("rho_p", C.c_double), ("n_markers", C.c_int32)]
+
+
+class LigandDesc(C.Structure):
+    _fields_ = [("rho_l_num", C.c_int32), ("rho_l_den", C.c_int32), ("sigma_hat", C.c_double),
+                ("sigma_star_ratio", C.c_double), ("y_cr_hat", C.c_double), ("y_eq_ratio", C.c_double),
+                ("k_f", C.c_double), ("k_r0", C.c_double), ("kbt_hat", C.c_double), ("hamaker_hat", C.c_double)]
+
+
+class ReceptorDesc(C.Structure):
+    _fields_ = [("wall", C.c_int32), ("density", C.c_double)]
+
+
+class ParticleState(C.Structure):
+    _fields_ = [("step", C.c_int64), ("xc", C.c_double), ("yc", C.c_double), ("theta", C.c_double),
+                ("ux", C.c_double), ("uy", C.c_double), ("omega", C.c_double), ("fx", C.c_double),
+                ("fy", C.c_double), ("torque", C.c_double), ("fx_hydro", C.c_double), ("fy_hydro", C.c_double),
+                ("m_hydro", C.c_double), ("fx_bond", C.c_double), ("fy_bond", C.c_double), ("m_bond", C.c_double),
+                ("fy_wall", C.c_double), ("gap", C.c_double), ("n_bonds", C.c_int32), ("n_probing", C.c_int32)]
+
+
+STATE_FIELDS = [n for n, _ in ParticleState._fields_]
+
+_P = C.c_void_p
+_D = C.POINTER(C.c_double)
+_U8 = C.POINTER(C.c_uint8)
+_I64 = C.POINTER(C.c_int64)
+
+_SIGS = {
+    "lbib_abi_version": (C.c_int, []),
+    "lbib_create": (C.c_int, [C.POINTER(LatticeDesc), _P, C.POINTER(_P)]),
+    "lbib_particle_add": (C.c_int, [_P, C.POINTER(ParticleDesc), C.POINTER(C.c_int32)]),
+    "lbib_ligands_set": (C.c_int, [_P, C.c_int32, C.POINTER(LigandDesc)]),
+    "lbib_receptors_set": (C.c_int, [_P, C.POINTER(ReceptorDesc)]),
+    "lbib_init": (C.c_int, [_P]),
+    "lbib_step": (C.c_int, [_P, C.c_int64]),
+    "lbib_sync": (C.c_int, [_P]),
+    "lbib_step_count": (C.c_int, [_P, _I64]),
+    "lbib_read_particle": (C.c_int, [_P, C.c_int32, C.POINTER(ParticleState)]),
+    "lbib_read_bonds": (C.c_int, [_P, C.c_int32, _U8, _U8, C.c_int32]),
+    "lbib_read_markers": (C.c_int, [_P, C.c_int32, _D, _D, C.c_int32]),
+    "lbib_read_field": (C.c_int, [_P, C.c_int32, _D, C.c_int64]),
+    "lbib_write_populations": (C.c_int, [_P, _D, C.c_int64]),
+    "lbib_write_particle": (C.c_int, [_P, C.c_int32, _D]),
+    "lbib_write_bonds": (C.c_int, [_P, C.c_int32, _U8, C.c_int32]),
+    "lbib_trace_enable": (C.c_int, [_P, C.c_int32, C.c_int64]),
+    "lbib_read_trace": (C.c_int, [_P, C.c_int32, C.POINTER(ParticleState), C.c_int64, _I64]),
+    "lbib_save": (C.c_int, [_P, _P, _I64]),
+    "lbib_load": (C.c_int, [_P, _P, C.c_int64]),
+    "lbib_kernel_timing": (C.c_int, [_P, C.c_int32]),
+    "lbib_kernel_time": (C.c_int, [_P, C.c_int32, _D, _I64]),
+    "lbib_bytes_per_update": (C.c_int, [_P, _I64]),
+    "lbib_last_error": (C.c_char_p, [_P]),
+    "lbib_destroy": (None, [_P]),
+    "lbib_kernel_philox": (C.c_int, [_P, _P, _P, C.c_int64, _P]),
+    "lbib_kernel_mls": (C.c_int, [_P, C.c_int64, C.c_int32, C.c_int32, _P, _P, _P, _P, _P]),
+    "lbib_kernel_bonds": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, C.c_int32, C.c_int32, _D, C.c_uint64,
+                                    C.c_uint32, _P]),
+    "lbib_bandwidth_probe": (C.c_int, [C.c_int64, C.c_int32, _P, _D]),
+}
+EXPORTED = tuple(_SIGS)
+
+_lib = None
+
+
+def lib():
+    """Load the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int, handle=None):
+    if status != OK:
+        msg = lib().lbib_last_error(handle)
+        raise LbibError(status, msg.decode() if msg else "")
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    return C.c_void_p(int(stream.cuda_stream if hasattr(stream, "cuda_stream") else stream))
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor."""
+    return C.c_void_p(t.data_ptr())
+
+
+# ----------------------------------------------------------------------------------------
+# Simulation handle
+# ----------------------------------------------------------------------------------------
+
+class Sim:
+    """One simulation: lattice, at most one particle, ligands, receptors."""
+
+    def __init__(self, workload: dict, stream=None, *, init: bool = True):
+        L = lib()
+        lat = workload["lattice"]
+        self.workload = workload
+        self.nx, self.ny = int(lat["nx"]), int(lat["ny"])
+        self.precision = int(lat.get("precision", FP64))
+        d = LatticeDesc(self.nx, self.ny, float(lat["tau"]), float(lat["re"]), int(lat.get("drive", 0)),
+                        self.precision, int(lat.get("seed", 0)))
+        self._h = C.c_void_p()
+        self.stream = stream
+        _check(L.lbib_create(C.byref(d), _stream_ptr(stream), C.byref(self._h)))
+        self.nl = 0
+        try:
+            part = workload.get("particle")
+            if part is not None:
+                pd = ParticleDesc(int(part["shape"]), float(part["a_major"]), float(part["b_minor"]),
+                                  float(part["xc"]), float(part["yc"]), float(part["theta0"]),
+                                  float(part["rho_p"]), int(part["n_markers"]))
+                pid = C.c_int32()
+                self._call(L.lbib_particle_add, C.byref(pd), C.byref(pid))
+                self.nl = int(part["n_markers"])
+                g = workload["ligand"]
+                ld = LigandDesc(int(g["rho_l_num"]), int(g["rho_l_den"]), float(g["sigma_hat"]),
+                                float(g["sigma_star_ratio"]), float(g["y_cr_hat"]), float(g["y_eq_ratio"]),
+                                float(g["k_f"]), float(g["k_r0"]), float(g["kbt_hat"]), float(g["hamaker_hat"]))
+                self._call(L.lbib_ligands_set, 0, C.byref(ld))
+                r = workload.get("receptor", {"wall": 0, "density": 1.0})
+                rd = ReceptorDesc(int(r["wall"]), float(r["density"]))
+                self._call(L.lbib_receptors_set, C.byref(rd))
+            if init:
+                self._call(L.lbib_init)
+        except Exception:
+            self.close()
+            raise
+
+    def _call(self, fn, *args):
+        _check(fn(self._h, *args), self._h)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().lbib_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- time loop ---------------------------------------------------------------------
+    def init(self):
+        self._call(lib().lbib_init)
+
+    def step(self, n: int = 1):
+        self._call(lib().lbib_step, int(n))
+
+    def sync(self):
+        self._call(lib().lbib_sync)
+
+    @property
+    def steps(self) -> int:
+        v = C.c_int64()
+        self._call(lib().lbib_step_count, C.byref(v))
+        return v.value
+
+    @property
+    def bytes_per_update(self) -> int:
+        v = C.c_int64()
+        self._call(lib().lbib_bytes_per_update, C.byref(v))
+        return v.value
+
+    # -- reads ---------------------------------------------------------------------------
+    def particle(self, pid: int = 0) -> dict:
+        s = ParticleState()
+        self._call(lib().lbib_read_particle, pid, C.byref(s))
+        return {n: getattr(s, n) for n in STATE_FIELDS}
+
+    def bonds(self, pid: int = 0):
+        b = np.zeros(self.nl, np.uint8)
+        lg = np.zeros(self.nl, np.uint8)
+        self._call(lib().lbib_read_bonds, pid, b.ctypes.data_as(_U8), lg.ctypes.data_as(_U8), self.nl)
+        return b, lg
+
+    def markers(self, pid: int = 0):
+        X = np.zeros((self.nl, 2))
+        n = np.zeros((self.nl, 2))
+        self._call(lib().lbib_read_markers, pid, X.ctypes.data_as(_D), n.ctypes.data_as(_D), self.nl)
+        return X, n
+
+    def field(self, which: int) -> np.ndarray:
+        shape = (9, self.ny, self.nx) if which == 3 else (self.ny, self.nx)
+        out = np.zeros(shape)
+        self._call(lib().lbib_read_field, int(which), out.ctypes.data_as(_D), out.size)
+        return out
+
+    @property
+    def f(self) -> np.ndarray:
+        return self.field(3)
+
+    def fields(self):
+        return self.field(0), self.field(1), self.field(2)
+
+    # -- writes --------------------------------------------------------------------------
+    def write_populations(self, f: np.ndarray):
+        f = np.ascontiguousarray(f, np.float64)
+        assert f.shape == (9, self.ny, self.nx)
+        self._call(lib().lbib_write_populations, f.ctypes.data_as(_D), f.size)
+
+    def write_particle(self, state12, pid: int = 0):
+        v = np.ascontiguousarray(state12, np.float64)
+        assert v.shape == (12,)
+        self._call(lib().lbib_write_particle, pid, v.ctypes.data_as(_D))
+
+    def write_bonds(self, bonded, pid: int = 0):
+        b = np.ascontiguousarray(bonded, np.uint8)
+        self._call(lib().lbib_write_bonds, pid, b.ctypes.data_as(_U8), len(b))
+
+    # -- trace ---------------------------------------------------------------------------
+    def trace_enable(self, capacity: int, pid: int = 0):
+        self._call(lib().lbib_trace_enable, pid, int(capacity))
+
+    def trace(self, capacity: int, pid: int = 0) -> np.ndarray:
+        """Recorded states as a float64 array [count, 20] in the field order of STATE_FIELDS."""
+        buf = (ParticleState * max(1, capacity))()
+        cnt = C.c_int64()
+        self._call(lib().lbib_read_trace, pid, buf, int(capacity), C.byref(cnt))
+        return np.array([[float(getattr(buf[k], n)) for n in STATE_FIELDS] for k in range(cnt.value)]).reshape(
+            cnt.value, len(STATE_FIELDS))
+
+    # -- checkpoints ---------------------------------------------------------------------
+    def save(self) -> bytes:
+        size = C.c_int64()
+        self._call(lib().lbib_save, None, C.byref(size))
+        buf = C.create_string_buffer(size.value)
+        self._call(lib().lbib_save, buf, C.byref(size))
+        return buf.raw[: size.value]
+
+    def load(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        self._call(lib().lbib_load, buf, len(blob))
+
+    # -- timing --------------------------------------------------------------------------
+    def kernel_timing(self, enable: bool):
+        self._call(lib().lbib_kernel_timing, 1 if enable else 0)
+
+    def kernel_time(self, kernel: int):
+        """(total milliseconds, launches) of kernel 0 (lattice sweep) or 1 (particle phase)."""
+        ms = C.c_double()
+        n = C.c_int64()
+        self._call(lib().lbib_kernel_time, int(kernel), C.byref(ms), C.byref(n))
+        return ms.value, n.value
+
+
+# ----------------------------------------------------------------------------------------
+# Kernel-level entry points (torch tensors on the GPU)
+# ----------------------------------------------------------------------------------------
+
+def philox(ctr, key, stream=None):
+    """ctr: uint32-compatible int32 tensor [n, 4]; key [n, 2] -> [n, 4] (as int32 bit patterns)."""
+    import torch
+
+    n = ctr.shape[0]
+    out = torch.empty((n, 4), dtype=torch.int32, device=ctr.device)
+    _check(lib().lbib_kernel_philox(_ptr(ctr), _ptr(key), _ptr(out), n, _stream_ptr(stream)))
+    return out
+
+
+def mls(pts, nx: int, ny: int, stream=None):
+    """pts: float64 [n, 2] -> (node int32 [n, 9, 2], phi, psix, psiy float64 [n, 9])."""
+    import torch
+
+    n = pts.shape[0]
+    dev = pts.device
+    node = torch.empty((n, 9, 2), dtype=torch.int32, device=dev)
+    phi = torch.empty((n, 9), dtype=torch.float64, device=dev)
+    psx = torch.empty_like(phi)
+    psy = torch.empty_like(phi)
+    _check(lib().lbib_kernel_mls(_ptr(pts), n, nx, ny, _ptr(node), _ptr(phi), _ptr(psx), _ptr(psy),
+                                 _stream_ptr(stream)))
+    return node, phi, psx, psy
+
+
+def bonds(ligand, d, b_in, step, params, seed: int, pid: int = 0, stream=None):
+    """Batched bond update: ligand/b_in uint8 [sets, nl], d float64 [sets, nl], step int64 [sets];
+    params = (y_cr, y_eq, sigma, sigma_star, k_f, k_r0, kBT).  Returns (b_out, n_bonds, n_probing)."""
+    import torch
+
+    sets, nl = d.shape
+    dev = d.device
+    b_out = torch.empty((sets, nl), dtype=torch.uint8, device=dev)
+    nb = torch.empty(sets, dtype=torch.int32, device=dev)
+    npr = torch.empty(sets, dtype=torch.int32, device=dev)
+    p = (C.c_double * 7)(*[float(x) for x in params])
+    _check(lib().lbib_kernel_bonds(_ptr(ligand), _ptr(d), _ptr(b_in), _ptr(b_out), _ptr(step), _ptr(nb), _ptr(npr),
+                                   nl, sets, p, int(seed), int(pid), _stream_ptr(stream)))
+    return b_out, nb, npr
+
+
+def bandwidth_probe(nbytes: int, iters: int = 10, stream=None) -> float:
+    v = C.c_double()
+    _check(lib().lbib_bandwidth_probe(int(nbytes), int(iters), _stream_ptr(stream), C.byref(v)))
+    return v.value
