@@ -32,7 +32,8 @@
  *    read buffers belong to the caller and come with an explicit capacity; too small a
  *    capacity returns LBIB_E_INVALID and names the required size in lbib_last_error().
  *  - Threading: one handle is used from one host thread at a time; distinct handles are
- *    independent.  Work is enqueued on the handle's HIP stream.
+ *    independent.  Work is enqueued on the handle's HIP stream (and on a second stream the
+ *    handle owns, joined back into the first at the end of every lbib_step).
  *  - Determinism: identical descriptors and seed give bit-identical results on the same
  *    build and GPU (the spread is accumulated in 64-bit fixed point, every other reduction
  *    has a fixed order, and bond draws come from a counter-based generator).
@@ -60,9 +61,11 @@ typedef enum {
     LBIB_E_UNSUPPORTED = -6  /* valid request this build does not implement */
 } lbib_status;
 
-/* Precision of the population storage.  FP64 stores f - w_q in double and collides in
- * double; FP32 stores f - w_q in float and collides in float.  The particle phase (MLS
- * solves, interpolation, loads, bonds, reductions, rigid body) is FP64 in both. */
+/* Precision of the population storage: f - w_q in double (FP64) or in float (FP32).  The
+ * collision is evaluated in FP64 for both (in FP32 arithmetic its rounding breaks the
+ * momentum balance at a level that accumulates over thousands of steps at the small
+ * velocities of capillary flow).  The particle phase (MLS solves, interpolation, loads,
+ * bonds, reductions, rigid body) is FP64 in both. */
 enum { LBIB_FP64 = 0, LBIB_FP32 = 1 };
 
 /* Lattice (section "Modeling the adhesion dynamics ..."; Table 1).  drive must be 0
@@ -206,8 +209,19 @@ lbib_status lbib_read_trace(lbib_handle h, int32_t pid, lbib_particle_state* out
 lbib_status lbib_save(lbib_handle h, void* blob, int64_t* size);
 lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size);
 
-/* Kernel timing: when enabled, HIP events bracket every launch of the lattice sweep
- * (kernel 0) and of the particle phase (kernel 1).  lbib_kernel_time synchronises and
+/* Schedule of a step.  Overlapped (mode 1): the particle phase of step n runs on a second
+ * stream the handle owns, concurrently with the sweep of every node outside the particle's
+ * box (the nodes the step's MLS supports reach, predicted exactly by step n-1); the box is
+ * swept after the particle phase.  Serial (mode 0), and always on the first step after
+ * lbib_init / lbib_load / lbib_write_particle: the particle phase and a sweep of all nodes
+ * run one after the other on the handle's stream.  Mode 2 (the default) overlaps when one
+ * sweep moves at least 64 MiB; below that the two cross-stream waits of a step cost more
+ * than they hide.  Both schedules give bit-identical results. */
+lbib_status lbib_set_overlap(lbib_handle h, int32_t mode);
+
+/* Kernel timing: when enabled, HIP events bracket every launch of the lattice sweep of all
+ * nodes or of the nodes outside the particle's box (kernel 0), of the particle phase
+ * (kernel 1) and of the sweep of the box (kernel 2).  lbib_kernel_time synchronises and
  * returns the summed milliseconds and launch counts since the last enable. */
 lbib_status lbib_kernel_timing(lbib_handle h, int32_t enable);
 lbib_status lbib_kernel_time(lbib_handle h, int32_t kernel, double* total_ms, int64_t* launches);

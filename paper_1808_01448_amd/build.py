@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "liblbib.so")
-SOURCES = ["lbib_kernels.hip", "lbib_runtime.cpp", "lbib_geometry.cpp"]
+SOURCES = ["lbib_sweep.hip", "lbib_particle.hip", "lbib_runtime.cpp", "lbib_geometry.cpp"]
 ARCH = "gfx950"
 
 FLAGS = [

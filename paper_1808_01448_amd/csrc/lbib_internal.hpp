@@ -27,14 +27,15 @@ struct DevParticle {
     lbib_particle_state last;             // record of the last completed step
 };
 
-// Footprint of the spread force written by the particle phase and read by the sweep:
-// nodes i0w + di (mod nx), j0 + dj for 0 <= di < w, 0 <= dj < h; the force components are
-// 64-bit fixed point with value = q * 2^-scale.
+// The particle's box: every node that an MLS support of a marker or probe of one step
+// reaches, nodes i0w + di (mod nx), j0 + dj for 0 <= di < w, 0 <= dj < h (i0u is the same
+// origin before wrapping).  The spread force on the box is 64-bit fixed point, value =
+// q * 2^-scale, laid out [dj][di][2].
 struct TileDesc {
     int32_t i0w, j0, w, h;
     int32_t scale;
     int32_t active;
-    int32_t pad0, pad1;
+    int32_t i0u, pad;
 };
 
 // Lattice constants of one sweep (the collision is evaluated in FP64 for both storage
@@ -65,23 +66,38 @@ struct ParticleArgs {
     double sigma, sigma_star, y_cr, y_eq, k_f, k_r0, kBT, hamaker;
     uint64_t seed;
     uint32_t pid;
-    int64_t* tile;  // [cap_h][cap_w][2] fixed-point spread force
-    int32_t cap_w, cap_h;
-    TileDesc* desc;
+    int64_t* tile;      // [box_cap][2] fixed-point spread force on the box (read by the sweep)
+    double* box_global;  // [6][box_cap] node fields when the box does not fit in LDS
+    int32_t box_cap;     // node capacity of the box
+    TileDesc* desc;      // this step's box
+    TileDesc* zone;      // zone[2]: boxes of future steps, slot = step parity
+    int32_t parity_in;   // slot holding this step's box as predicted by the previous step
+    int32_t parity_out;  // slot receiving the next step's box
+    int32_t check_zone;  // compare this step's box with zone[parity_in]
     DevParticle* st;
     lbib_particle_state* trace;
     int64_t trace_cap, trace_start;
     int32_t* flags;
 };
 
-// Launchers (lbib_kernels.hip).  All enqueue on `stream` and return the launch status.
+// Launchers (lbib_sweep.hip, lbib_particle.hip).  All enqueue on `stream` and return the launch status.
 template <typename T>
 hipError_t launch_init(T* f, int32_t nx, int32_t ny, int32_t pitch, int64_t plane, double umax, hipStream_t stream);
+// Sweep modes: every node (forces from desc/tile when desc != NULL); only nodes outside
+// the box in `desc` (which carry no spread force); only the nodes of the box in `desc`
+// (box_cap bounds the launch).
+enum SweepMode { SWEEP_ALL = 0, SWEEP_OUTSIDE = 1, SWEEP_BOX = 2 };
+// t0 / t1 (optional) receive the kernel's own start and end times.
 template <typename T>
-hipError_t launch_sweep(const T* fin, T* fout, const SweepArgs& a, const TileDesc* desc, const int64_t* tile,
-                        hipStream_t stream);
+hipError_t launch_sweep(const T* fin, T* fout, const SweepArgs& a, int mode, const TileDesc* desc,
+                        const int64_t* tile, int32_t box_cap, hipStream_t stream, hipEvent_t t0 = nullptr,
+                        hipEvent_t t1 = nullptr);
+// Bytes of dynamic LDS the particle phase needs for a box of box_cap nodes, or 0 when the
+// box is kept in global memory instead.
+size_t particle_lds_bytes(int32_t box_cap);
 template <typename T>
-hipError_t launch_particle(const ParticleArgs<T>& a, hipStream_t stream);
+hipError_t launch_particle(const ParticleArgs<T>& a, hipStream_t stream, hipEvent_t t0 = nullptr,
+                           hipEvent_t t1 = nullptr);
 
 hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n, hipStream_t stream);
 hipError_t launch_mls(const double* pts, int64_t n, int32_t nx, int32_t ny, int32_t* node, double* phi, double* psix,

@@ -1,0 +1,726 @@
+// lbib_particle.hip -- gfx950 particle-phase kernels of the LB-IB particle-adhesion step.
+//
+// The particle phase of step n runs as one workgroup per particle: it stages the node
+// fields of the particle's box (every node an MLS support of a marker or probe reaches),
+// interpolates the fluid velocity at the Lagrangian markers, forms the direct-forcing
+// marker forces and spreads them into a 64-bit fixed-point force field on the box (read by
+// the lattice sweep), evaluates the probe loads (eq 7-8), updates the stochastic bonds
+// (eq 9-11), adds the wall force (eq 12), reduces force and torque in FP64 and advances the
+// rigid body (eq 13-16).  It also predicts the box of step n+1, so the sweep of the nodes
+// outside it may run concurrently with the next particle phase.
+//
+// The file also holds the kernel-level entry points (Philox, MLS, bond update) and the
+// copy kernel of the bandwidth probe.
+#include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "lbib_device.hpp"
+#include "lbib_internal.hpp"
+
+namespace lbib {
+
+using namespace dev;
+
+// ---------------------------------------------------------------------------------------
+// Workgroup reductions: butterfly within each 64-wide wavefront, then the per-wave partials
+// in wave order.  The order is fixed, so results are bit-reproducible.
+// ---------------------------------------------------------------------------------------
+constexpr int PB = 256;       // threads of the particle workgroup
+constexpr int NW = PB / 64;   // wavefronts per workgroup
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_isum(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_ior(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v |= __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_imin(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Sum of N doubles over the workgroup; every thread receives the totals.
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N], double (*sh)[NW])
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) sh[k][w] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        double s = sh[k][0];
+#pragma unroll
+        for (int u = 1; u < NW; ++u) s += sh[k][u];
+        v[k] = s;
+    }
+    __syncthreads();
+}
+
+// Integer combination over the workgroup: op 0 sum, 1 or, 2 min.
+template <int N>
+__device__ __forceinline__ void block_int(int (&v)[N], const int (&op)[N], int (*sh)[NW])
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = op[k] == 0 ? wave_isum(v[k]) : op[k] == 1 ? wave_ior(v[k]) : wave_imin(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) sh[k][w] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        int s = sh[k][0];
+#pragma unroll
+        for (int u = 1; u < NW; ++u) s = op[k] == 0 ? s + sh[k][u] : op[k] == 1 ? (s | sh[k][u]) : min(s, sh[k][u]);
+        v[k] = s;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------------------
+// Particle phase
+// ---------------------------------------------------------------------------------------
+
+__device__ __forceinline__ double fluid_row(double y, int ny)
+{
+    // transfer points between a wall and the first node row are transferred as if they sat
+    // on that row (the linear fit would otherwise extrapolate and destabilise the coupling)
+    return y < 0.0 ? 0.0 : (y > ny - 1.0 ? ny - 1.0 : y);
+}
+
+// Node range an MLS support at (X, Y) can reach (the candidate box of mls_shape; rows cut at
+// the walls).  False for non-finite or absurd points.
+__device__ __forceinline__ bool support_range(double X, double Y, int ny, int& ilo, int& ihi, int& jlo, int& jhi)
+{
+    if (!(fabs(X) < 1e9 && fabs(Y) < 1e9)) return false;
+    ilo = (int)floor(X - 1.5) + 1;
+    ihi = (int)ceil(X + 1.5) - 1;
+    jlo = max((int)floor(Y - 1.5) + 1, 0);
+    jhi = min((int)ceil(Y + 1.5) - 1, ny - 1);
+    return jhi >= jlo;
+}
+
+// Marker l of a particle at (xc, yc, theta): position, outward normal and probe point.
+struct MarkerGeo {
+    double X, Y, nx, ny, px, py;
+};
+
+__device__ __forceinline__ MarkerGeo marker_geo(const double* xi, const double* nuv, int l, double xc, double yc,
+                                                double cth, double sth, int ny)
+{
+    MarkerGeo g;
+    const double bx = xi[2 * l], by = xi[2 * l + 1];
+    const double mx = nuv[2 * l], my = nuv[2 * l + 1];
+    g.X = xc + cth * bx - sth * by;
+    g.Y = yc + sth * bx + cth * by;
+    g.nx = cth * mx - sth * my;
+    g.ny = sth * mx + cth * my;
+    g.px = g.X + 1.2 * g.nx;  // probe 1.2 dx along the outward normal (below eq 8)
+    g.py = fluid_row(g.Y + 1.2 * g.ny, ny);
+    return g;
+}
+
+// Bounding box (unwrapped x) of every support a particle at (xc, yc, theta) reaches:
+// minima of (i_lo, -i_hi, j_lo, -j_hi) accumulated into r[4].
+template <typename T, int MPT>
+__device__ __forceinline__ void accumulate_bounds(const ParticleArgs<T>& a, double xc, double yc, double cth,
+                                                  double sth, int (&r)[4])
+{
+#pragma unroll
+    for (int k = 0; k < MPT; ++k) {
+        const int l = threadIdx.x + k * PB;
+        if (l < a.nl) {
+            const MarkerGeo g = marker_geo(a.xi, a.nuv, l, xc, yc, cth, sth, a.ny);
+            int ilo, ihi, jlo, jhi;
+            if (support_range(g.X, fluid_row(g.Y, a.ny), a.ny, ilo, ihi, jlo, jhi)) {
+                r[0] = min(r[0], ilo);
+                r[1] = min(r[1], -ihi);
+                r[2] = min(r[2], jlo);
+                r[3] = min(r[3], -jhi);
+            }
+            if (support_range(g.px, g.py, a.ny, ilo, ihi, jlo, jhi)) {
+                r[0] = min(r[0], ilo);
+                r[1] = min(r[1], -ihi);
+                r[2] = min(r[2], jlo);
+                r[3] = min(r[3], -jhi);
+            }
+        }
+    }
+}
+
+// Node fields of the box, structure of arrays over box_cap nodes: rho, u* (the velocity
+// with half the uniform drive, without the spread force), 1/rho, and the two fixed-point
+// spread-force accumulators.
+struct BoxView {
+    double *rho, *ux, *uy, *inv;
+    unsigned long long *fx, *fy;
+};
+
+constexpr int kBoxDoubles = 6;  // 4 doubles + 2 64-bit integers per node
+
+size_t particle_lds_bytes(int32_t box_cap)
+{
+    const size_t bytes = (size_t)box_cap * kBoxDoubles * 8;
+    return bytes <= 158 * 1024 ? bytes : 0;  // gfx950: 160 KB of LDS per workgroup
+}
+
+template <bool LDS>
+__device__ __forceinline__ void force_add(unsigned long long* p, int64_t v)
+{
+    if (LDS)
+        atomicAdd(p, (unsigned long long)v);
+    else
+        __hip_atomic_fetch_add(p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// MPT markers per thread (nl <= MPT * PB).  LDS: the box lives in dynamic LDS, else in the
+// global scratch a.box_global (plain loads and stores ordered by the workgroup barriers,
+// device-scope atomics for the force).
+template <typename T, int MPT, bool LDS>
+__global__ __launch_bounds__(PB) void particle_kernel(ParticleArgs<T> a)
+{
+    extern __shared__ double lds_box[];
+    __shared__ double shd[8][NW];
+    __shared__ int shi[8][NW];
+    const int tid = threadIdx.x;
+    const int nl = a.nl;
+    const int cap = a.box_cap;
+    double* base = LDS ? lds_box : a.box_global;
+    BoxView B;
+    B.rho = base;
+    B.ux = base + cap;
+    B.uy = base + 2 * cap;
+    B.inv = base + 3 * cap;
+    B.fx = (unsigned long long*)(base + 4 * cap);
+    B.fy = (unsigned long long*)(base + 5 * cap);
+
+    DevParticle* st = a.st;
+    const double xc = st->xc, yc = st->yc, th = st->th, ux = st->ux, uy = st->uy, om = st->om;
+    const int64_t step = st->step;
+    const double cth = cos(th), sth = sin(th);
+    int flags = 0;
+
+    // ---- the box: every node a marker or probe support reaches this step --------------
+    int r[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
+    accumulate_bounds<T, MPT>(a, xc, yc, cth, sth, r);
+    {
+        const int op[4] = {2, 2, 2, 2};
+        block_int<4>(r, op, shi);
+    }
+    const int x0 = r[0], y0 = r[2];
+    const int w = (r[0] != 0x7fffffff) ? -r[1] - r[0] + 1 : 0;
+    const int h = (r[2] != 0x7fffffff) ? -r[3] - r[2] + 1 : 0;
+    const bool box_ok = w > 0 && h > 0 && w <= a.nx && (int64_t)w * h <= cap;
+    if (!box_ok && tid == 0) flags |= FLAG_TILE;
+
+    // ---- node fields of the box, several nodes per thread in flight --------------------
+    const int nbox = box_ok ? w * h : 0;
+    constexpr int U = 4;
+    for (int k0 = tid; k0 < nbox; k0 += U * PB) {
+        T v[U][9];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = min(k0 + u * PB, nbox - 1);  // clamped: duplicates are recomputed, not stored
+            const int j = y0 + k / w;
+            const size_t c = (size_t)j * a.pitch + wrap(x0 + k % w, a.nx);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) v[u][q] = a.f[q * a.plane + c];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u * PB;
+            if (k < nbox) {
+                double dr, jx, jy;
+                shifted_moments<double, T>(v[u], dr, jx, jy);
+                const double rho = 1.0 + dr;
+                const double inv = 1.0 / rho;
+                B.rho[k] = rho;
+                B.inv[k] = inv;
+                B.ux[k] = (jx + 0.5 * a.gx) * inv;
+                B.uy[k] = (jy + 0.5 * a.gy) * inv;
+                B.fx[k] = 0ull;
+                B.fy[k] = 0ull;
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- markers: MLS interpolation and direct forcing ----------------------------------
+    double X[MPT], Y[MPT], NX[MPT], NY[MPT], PX[MPT], PY[MPT], S[MPT], SFx[MPT], SFy[MPT], PH[MPT][9];
+    int I0[MPT], J0[MPT], NXS[MPT], NYS[MPT];
+    bool OK[MPT], LIG[MPT], BND[MPT];
+    double maxsf = 0.0;
+#pragma unroll
+    for (int k = 0; k < MPT; ++k) {
+        const int l = tid + k * PB;
+        OK[k] = false;
+        NXS[k] = NYS[k] = 0;
+        SFx[k] = SFy[k] = 0.0;
+        if (l < nl) {
+            const MarkerGeo g = marker_geo(a.xi, a.nuv, l, xc, yc, cth, sth, a.ny);
+            X[k] = g.X;
+            Y[k] = g.Y;
+            NX[k] = g.nx;
+            NY[k] = g.ny;
+            PX[k] = g.px;
+            PY[k] = g.py;
+            S[k] = a.S[l];
+            LIG[k] = a.ligand[l] != 0;
+            BND[k] = a.bond[l] != 0;
+            Mls m;
+            const bool ok = box_ok && mls_shape(g.X, fluid_row(g.Y, a.ny), a.ny, m, false);
+            if (ok) {
+                double rl = 0.0, usx = 0.0, usy = 0.0;
+#pragma unroll
+                for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc) {
+                        const double p = m.phi[3 * bb + cc];
+                        PH[k][3 * bb + cc] = p;
+                        if (bb < m.nys && cc < m.nxs) {
+                            const int n = (m.j0 + bb - y0) * w + (m.i0 + cc - x0);
+                            rl += p * B.rho[n];
+                            usx += p * B.ux[n];
+                            usy += p * B.uy[n];
+                        }
+                    }
+                const double rx = g.X - xc, ry = g.Y - yc;
+                OK[k] = true;
+                SFx[k] = S[k] * (2.0 * rl * (ux - om * ry - usx));
+                SFy[k] = S[k] * (2.0 * rl * (uy + om * rx - usy));
+                I0[k] = m.i0;
+                J0[k] = m.j0;
+                NXS[k] = m.nxs;
+                NYS[k] = m.nys;
+                const double mag = fmax(fabs(SFx[k]), fabs(SFy[k]));
+                maxsf = (mag <= 1e300) ? fmax(maxsf, mag) : INFINITY;
+            } else if (box_ok) {
+                flags |= FLAG_MLS;
+            }
+        }
+    }
+    maxsf = wave_max(maxsf);
+    if ((tid & 63) == 0) shd[0][tid >> 6] = maxsf;
+    __syncthreads();
+    maxsf = shd[0][0];
+#pragma unroll
+    for (int u = 1; u < NW; ++u) maxsf = fmax(maxsf, shd[0][u]);
+    __syncthreads();
+
+    // ---- spread: 64-bit fixed point, so the sum does not depend on the order --------
+    // |phi| < 2 and at most 64 markers reach a node, so |sum| < 2^7 maxsf; with
+    // maxsf < 2^e the scale 2^(55-e) keeps every node below 2^62.
+    const bool finite_sf = maxsf <= 1e300;
+    const bool spread_ok = box_ok && finite_sf;
+    if (box_ok && !finite_sf && tid == 0) flags |= FLAG_NONFINITE;
+    int e2 = 0;
+    frexp(finite_sf ? maxsf : 1.0, &e2);
+    const int scale = 55 - e2;
+    if (spread_ok) {
+#pragma unroll
+        for (int k = 0; k < MPT; ++k) {
+            if (!OK[k]) continue;
+#pragma unroll
+            for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) {
+                    if (bb >= NYS[k] || cc >= NXS[k]) continue;
+                    const double p = PH[k][3 * bb + cc];
+                    const int n = (J0[k] + bb - y0) * w + (I0[k] + cc - x0);
+                    force_add<LDS>(B.fx + n, (int64_t)llrint(ldexp(p * SFx[k], scale)));
+                    force_add<LDS>(B.fy + n, (int64_t)llrint(ldexp(p * SFy[k], scale)));
+                }
+        }
+    }
+    __syncthreads();
+    if (spread_ok) {
+        for (int k = tid; k < nbox; k += PB) {
+            unsigned long long qx, qy;
+            if (LDS) {
+                qx = B.fx[k];
+                qy = B.fy[k];
+            } else {
+                qx = __hip_atomic_load(B.fx + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                qy = __hip_atomic_load(B.fy + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            a.tile[2 * k] = (int64_t)qx;
+            a.tile[2 * k + 1] = (int64_t)qy;
+        }
+    }
+    if (tid == 0) {
+        TileDesc d;
+        d.i0w = wrap(box_ok ? x0 : 0, a.nx);
+        d.j0 = box_ok ? y0 : 0;
+        d.w = box_ok ? w : 0;
+        d.h = box_ok ? h : 0;
+        d.scale = scale;
+        d.active = spread_ok ? 1 : 0;
+        d.i0u = box_ok ? x0 : 0;
+        d.pad = 0;
+        *a.desc = d;
+        if (a.check_zone) {
+            const TileDesc z = a.zone[a.parity_in];
+            // the concurrent sweep of the nodes outside the predicted box is only valid when
+            // the prediction equals this box
+            if (!z.active || z.i0w != d.i0w || z.j0 != d.j0 || z.w != d.w || z.h != d.h) flags |= FLAG_TILE;
+        }
+    }
+
+    // ---- probe loads (eq 7-8) and wall distances ---------------------------------------
+    double TX[MPT], TY[MPT], D[MPT];
+    bool PRB[MPT];
+    int nprobe = 0;
+#pragma unroll
+    for (int k = 0; k < MPT; ++k) {
+        const int l = tid + k * PB;
+        TX[k] = TY[k] = 0.0;
+        D[k] = 0.0;
+        PRB[k] = false;
+        if (l < nl) {
+            Mls m;
+            const bool ok = box_ok && mls_shape(PX[k], PY[k], a.ny, m, true);
+            if (ok) {
+                double rp = 0.0, gxx = 0.0, gxy = 0.0, gyx = 0.0, gyy = 0.0;
+#pragma unroll
+                for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc) {
+                        if (bb < m.nys && cc < m.nxs) {
+                            const int e = 3 * bb + cc;
+                            const int n = (m.j0 + bb - y0) * w + (m.i0 + cc - x0);
+                            double vx = B.ux[n], vy = B.uy[n];
+                            if (spread_ok) {
+                                unsigned long long qx, qy;
+                                if (LDS) {
+                                    qx = B.fx[n];
+                                    qy = B.fy[n];
+                                } else {
+                                    qx = __hip_atomic_load(B.fx + n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                    qy = __hip_atomic_load(B.fy + n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                }
+                                const double hinv = 0.5 * B.inv[n];
+                                vx += ldexp((double)(int64_t)qx, -scale) * hinv;
+                                vy += ldexp((double)(int64_t)qy, -scale) * hinv;
+                            }
+                            rp += m.phi[e] * B.rho[n];
+                            gxx += m.psx[e] * vx;
+                            gxy += m.psy[e] * vx;
+                            gyx += m.psx[e] * vy;
+                            gyy += m.psy[e] * vy;
+                        }
+                    }
+                const double p = (rp - 1.0) * (1.0 / 3.0);
+                const double sxx = rp * a.nu * (2.0 * gxx), syy = rp * a.nu * (2.0 * gyy);
+                const double sxy = rp * a.nu * (gxy + gyx);
+                TX[k] = (-p * NX[k] + sxx * NX[k] + sxy * NY[k]) * S[k];
+                TY[k] = (-p * NY[k] + sxy * NX[k] + syy * NY[k]) * S[k];
+            } else if (box_ok) {
+                flags |= FLAG_MLS;
+            }
+            D[k] = Y[k] + 0.5;
+            PRB[k] = LIG[k] && D[k] < a.y_cr;
+            nprobe += PRB[k] ? 1 : 0;
+        }
+    }
+    {
+        int v[1] = {nprobe};
+        const int op[1] = {0};
+        block_int<1>(v, op, shi);
+        nprobe = v[0];
+    }
+
+    // ---- bonds (eq 9-11) and the partial sums of the loads ----------------------------
+    const double Pf = -expm1(-a.k_f * ((double)nprobe / (double)nl));
+    const uint64_t Tf = prob_threshold(Pf);
+    const BondParams bp{a.y_cr, a.y_eq, a.sigma, a.sigma_star, a.k_f, a.k_r0, a.kBT};
+    double acc[6] = {0, 0, 0, 0, 0, 0};  // hydro x, y, moment; bond x, y, moment
+    int nb = 0;
+#pragma unroll
+    for (int k = 0; k < MPT; ++k) {
+        const int l = tid + k * PB;
+        if (l < nl) {
+            const double rx = X[k] - xc, ry = Y[k] - yc;
+            const uint8_t b = bond_update(LIG[k], BND[k], D[k], Tf, bp, a.seed, step, (uint32_t)l, a.pid);
+            a.bond[l] = b;
+            acc[0] += TX[k];
+            acc[1] += TY[k];
+            acc[2] += rx * TY[k] - ry * TX[k];
+            if (b) {
+                const double mag = a.sigma * (D[k] - a.y_eq);
+                const double fx = mag * NX[k], fy = mag * NY[k];
+                acc[3] += fx;
+                acc[4] += fy;
+                acc[5] += rx * fy - ry * fx;
+                ++nb;
+            }
+        }
+    }
+    block_sum<6>(acc, shd);
+    {
+        int v[2] = {nb, flags};
+        const int op[2] = {0, 1};
+        block_int<2>(v, op, shi);
+        nb = v[0];
+        flags = v[1];
+    }
+
+    // ---- wall force (eq 12), totals and the rigid-body update (eq 13-16) --------------
+    if (tid == 0) {
+        const double hx = acc[0], hy = acc[1], hm = acc[2], bx_ = acc[3], by_ = acc[4], bm = acc[5];
+        const double gap = yc + 0.5 - sqrt(a.b * a.b * sth * sth + a.a * a.a * cth * cth);
+        int32_t fl = flags;
+        if (!(gap > 0.0)) fl |= FLAG_CONTACT;
+        const double eps = gap > 1e-3 ? gap : 1e-3;
+        const double fw = a.hamaker / (8.0 * sqrt(2.0)) * sqrt(sqrt(a.a * a.b) / (eps * eps * eps * eps * eps));
+        const double Fx = hx + bx_, Fy = hy + by_ + fw, M = hm + bm;
+        const double nux = (2.0 / 3.0) * (2.0 * ux - 0.5 * st->ux1 + Fx / a.mass);
+        const double nuy = (2.0 / 3.0) * (2.0 * uy - 0.5 * st->uy1 + Fy / a.mass);
+        const double nom = (2.0 / 3.0) * (2.0 * om - 0.5 * st->om1 + M / a.inertia);
+        const double nxc = (2.0 / 3.0) * (2.0 * xc - 0.5 * st->xc1 + nux);
+        const double nyc = (2.0 / 3.0) * (2.0 * yc - 0.5 * st->yc1 + nuy);
+        const double nth = (2.0 / 3.0) * (2.0 * th - 0.5 * st->th1 + nom);
+        if (!(isfinite(Fx) && isfinite(Fy) && isfinite(M) && isfinite(nux) && isfinite(nuy) && isfinite(nom)))
+            fl |= FLAG_NONFINITE;
+        st->xc1 = xc;
+        st->yc1 = yc;
+        st->th1 = th;
+        st->ux1 = ux;
+        st->uy1 = uy;
+        st->om1 = om;
+        st->xc = nxc;
+        st->yc = nyc;
+        st->th = nth;
+        st->ux = nux;
+        st->uy = nuy;
+        st->om = nom;
+        st->step = step + 1;
+        lbib_particle_state rec;
+        rec.step = step;
+        rec.xc = nxc;
+        rec.yc = nyc;
+        rec.theta = nth;
+        rec.ux = nux;
+        rec.uy = nuy;
+        rec.omega = nom;
+        rec.fx = Fx;
+        rec.fy = Fy;
+        rec.torque = M;
+        rec.fx_hydro = hx;
+        rec.fy_hydro = hy;
+        rec.m_hydro = hm;
+        rec.fx_bond = bx_;
+        rec.fy_bond = by_;
+        rec.m_bond = bm;
+        rec.fy_wall = fw;
+        rec.gap = gap;
+        rec.n_bonds = nb;
+        rec.n_probing = nprobe;
+        st->last = rec;
+        const int64_t kk = step - a.trace_start;
+        if (a.trace && kk >= 0 && kk < a.trace_cap) a.trace[kk] = rec;
+        if (fl) atomicOr(a.flags, fl);
+        shd[0][0] = nxc;
+        shd[1][0] = nyc;
+        shd[2][0] = nth;
+    }
+    __syncthreads();
+
+    // ---- the box of the next step (the sweep of the nodes outside it may then run while
+    // the next particle phase does) -------------------------------------------------------
+    {
+        const double nxc = shd[0][0], nyc = shd[1][0], nth = shd[2][0];
+        int rn[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
+        accumulate_bounds<T, MPT>(a, nxc, nyc, cos(nth), sin(nth), rn);
+        const int op[4] = {2, 2, 2, 2};
+        block_int<4>(rn, op, shi);
+        if (tid == 0) {
+            const int nw = (rn[0] != 0x7fffffff) ? -rn[1] - rn[0] + 1 : 0;
+            const int nh = (rn[2] != 0x7fffffff) ? -rn[3] - rn[2] + 1 : 0;
+            TileDesc z;
+            z.i0w = wrap(rn[0] != 0x7fffffff ? rn[0] : 0, a.nx);
+            z.j0 = rn[2] != 0x7fffffff ? rn[2] : 0;
+            z.w = nw;
+            z.h = nh;
+            z.scale = 0;
+            z.active = (nw > 0 && nh > 0 && nw <= a.nx && (int64_t)nw * nh <= cap) ? 1 : 0;
+            z.i0u = rn[0] != 0x7fffffff ? rn[0] : 0;
+            z.pad = 0;
+            a.zone[a.parity_out] = z;
+        }
+    }
+}
+
+template <typename T, int MPT>
+hipError_t launch_particle_mpt(const ParticleArgs<T>& a, hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
+{
+    const size_t lds = particle_lds_bytes(a.box_cap);
+    if (lds) {
+        static bool attr_set = false;  // once per instantiation, for the largest box allowed
+        if (!attr_set) {
+            hipError_t e = hipFuncSetAttribute((const void*)particle_kernel<T, MPT, true>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, 158 * 1024);
+            if (e != hipSuccess) return e;
+            attr_set = true;
+        }
+        hipExtLaunchKernelGGL(particle_kernel<T, MPT, true>, dim3(1), dim3(PB), (uint32_t)lds, stream, t0, t1, 0u, a);
+    } else {
+        hipExtLaunchKernelGGL(particle_kernel<T, MPT, false>, dim3(1), dim3(PB), 0u, stream, t0, t1, 0u, a);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_particle(const ParticleArgs<T>& a, hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
+{
+    if (a.nl <= PB) return launch_particle_mpt<T, 1>(a, stream, t0, t1);
+    if (a.nl <= 2 * PB) return launch_particle_mpt<T, 2>(a, stream, t0, t1);
+    if (a.nl <= 4 * PB) return launch_particle_mpt<T, 4>(a, stream, t0, t1);
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------------------
+// Kernel-level entry points (same device functions as the time step)
+// ---------------------------------------------------------------------------------------
+__global__ void philox_kernel(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    uint32_t c0 = ctr[4 * k], c1 = ctr[4 * k + 1], c2 = ctr[4 * k + 2], c3 = ctr[4 * k + 3];
+    philox4x32_10(c0, c1, c2, c3, key[2 * k], key[2 * k + 1]);
+    out[4 * k] = c0;
+    out[4 * k + 1] = c1;
+    out[4 * k + 2] = c2;
+    out[4 * k + 3] = c3;
+}
+
+hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(philox_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, ctr, key, out, n);
+    return hipGetLastError();
+}
+
+__global__ void mls_kernel(const double* pts, int64_t n, int nx, int ny, int32_t* node, double* phi, double* psix,
+                           double* psiy)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    Mls m;
+    const bool ok = mls_shape(pts[2 * k], pts[2 * k + 1], ny, m, true);
+    for (int b = 0; b < 3; ++b)
+        for (int a = 0; a < 3; ++a) {
+            const int e = 3 * b + a;
+            const bool in = ok && a < m.nxs && b < m.nys;
+            node[2 * (9 * k + e)] = in ? wrap(m.i0 + a, nx) : -1;
+            node[2 * (9 * k + e) + 1] = in ? m.j0 + b : -1;
+            phi[9 * k + e] = in ? m.phi[e] : 0.0;
+            psix[9 * k + e] = in ? m.psx[e] : 0.0;
+            psiy[9 * k + e] = in ? m.psy[e] : 0.0;
+        }
+}
+
+hipError_t launch_mls(const double* pts, int64_t n, int32_t nx, int32_t ny, int32_t* node, double* phi, double* psix,
+                      double* psiy, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(mls_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, pts, n, nx, ny, node, phi,
+                       psix, psiy);
+    return hipGetLastError();
+}
+
+// One workgroup per set: count the probing ligands, then update every element.
+__global__ __launch_bounds__(PB) void bonds_kernel(const uint8_t* ligand, const double* d, const uint8_t* b_in,
+                                                   uint8_t* b_out, const int64_t* step, int32_t* n_bonds,
+                                                   int32_t* n_probing, int nl, BondParams p, uint64_t seed,
+                                                   uint32_t pid)
+{
+    __shared__ int shi[1][NW];
+    const int s = blockIdx.x;
+    const size_t base = (size_t)s * nl;
+    int np = 0;
+    for (int l = threadIdx.x; l < nl; l += PB) np += (ligand[base + l] && d[base + l] < p.y_cr) ? 1 : 0;
+    {
+        int v[1] = {np};
+        const int op[1] = {0};
+        block_int<1>(v, op, shi);
+        np = v[0];
+    }
+    const uint64_t Tf = prob_threshold(-expm1(-p.k_f * ((double)np / (double)nl)));
+    int nb = 0;
+    for (int l = threadIdx.x; l < nl; l += PB) {
+        const uint8_t b = bond_update(ligand[base + l] != 0, b_in[base + l] != 0, d[base + l], Tf, p, seed, step[s],
+                                      (uint32_t)l, pid);
+        b_out[base + l] = b;
+        nb += b;
+    }
+    {
+        int v[1] = {nb};
+        const int op[1] = {0};
+        block_int<1>(v, op, shi);
+        nb = v[0];
+    }
+    if (threadIdx.x == 0) {
+        n_bonds[s] = nb;
+        n_probing[s] = np;
+    }
+}
+
+hipError_t launch_bonds(const uint8_t* ligand, const double* d, const uint8_t* b_in, uint8_t* b_out,
+                        const int64_t* step, int32_t* n_bonds, int32_t* n_probing, int32_t nl, int32_t n_sets,
+                        const double* q, uint64_t seed, uint32_t pid, hipStream_t stream)
+{
+    if (n_sets <= 0) return hipSuccess;
+    BondParams p{q[0], q[1], q[2], q[3], q[4], q[5], q[6]};
+    hipLaunchKernelGGL(bonds_kernel, dim3(n_sets), dim3(PB), 0, stream, ligand, d, b_in, b_out, step, n_bonds,
+                       n_probing, nl, p, seed, pid);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) dst[k] = src[k];
+}
+
+hipError_t launch_copy(const float4* src, float4* dst, int64_t n, hipStream_t stream)
+{
+    hipLaunchKernelGGL(copy_kernel, dim3(256 * 64), dim3(256), 0, stream, src, dst, n);
+    return hipGetLastError();
+}
+
+template hipError_t launch_particle<float>(const ParticleArgs<float>&, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_particle<double>(const ParticleArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
+
+}  // namespace lbib

@@ -40,18 +40,22 @@ struct Particle {
     double *d_xi = nullptr, *d_nuv = nullptr, *d_S = nullptr;
     uint8_t *d_lig = nullptr, *d_bond = nullptr;
     int64_t* d_tile = nullptr;
-    int cap_w = 0, cap_h = 0;
+    double* d_box = nullptr;  // box node fields when they do not fit in LDS
+    int box_cap = 0;
     TileDesc* d_desc = nullptr;
+    TileDesc* d_zone = nullptr;  // two slots, by step parity
     DevParticle* d_st = nullptr;
     lbib_particle_state* d_trace = nullptr;
     int64_t trace_cap = 0, trace_start = 0;
 };
 
+constexpr int kKinds = 3;  // 0 lattice sweep (all or outside the box), 1 particle phase, 2 box sweep
+
 struct Timing {
     bool on = false;
-    std::vector<hipEvent_t> ev[2];
-    size_t used[2] = {0, 0};
-    int64_t launches[2] = {0, 0};
+    std::vector<hipEvent_t> ev[kKinds];
+    size_t used[kKinds] = {0, 0, 0};
+    int64_t launches[kKinds] = {0, 0, 0};
 };
 
 }  // namespace
@@ -60,6 +64,10 @@ struct lbib_sim {
     lbib_lattice_desc desc{};
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    hipStream_t stream2 = nullptr;  // particle chain of the overlapped schedule
+    hipEvent_t evA = nullptr, evB = nullptr;
+    int overlap = 2;  // 0 serial, 1 overlapped, 2 chosen by lattice size
+    bool zone_valid = false;  // the zone slot of the next step holds its box
     int state = 0;  // 0 created, 1 running, 2 failed
     std::string err;
     int pitch = 0;
@@ -121,7 +129,9 @@ void free_particle(Particle& p)
     dfree(p.d_lig);
     dfree(p.d_bond);
     dfree(p.d_tile);
+    dfree(p.d_box);
     dfree(p.d_desc);
+    dfree(p.d_zone);
     dfree(p.d_st);
     dfree(p.d_trace);
 }
@@ -133,10 +143,15 @@ void free_all(lbib_sim* h)
     if (h->fB) (void)hipFree(h->fB);
     h->fA = h->fB = nullptr;
     dfree(h->d_flags);
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < kKinds; ++k) {
         for (auto e : h->timing.ev[k]) (void)hipEventDestroy(e);
         h->timing.ev[k].clear();
     }
+    if (h->evA) (void)hipEventDestroy(h->evA);
+    if (h->evB) (void)hipEventDestroy(h->evB);
+    h->evA = h->evB = nullptr;
+    if (h->stream2) (void)hipStreamDestroy(h->stream2);
+    h->stream2 = nullptr;
 }
 
 template <typename T>
@@ -192,9 +207,10 @@ ParticleArgs<T> particle_args(lbib_sim* h, Particle& p)
     a.seed = h->desc.seed;
     a.pid = 0;
     a.tile = p.d_tile;
-    a.cap_w = p.cap_w;
-    a.cap_h = p.cap_h;
+    a.box_global = p.d_box;
+    a.box_cap = p.box_cap;
     a.desc = p.d_desc;
+    a.zone = p.d_zone;
     a.st = p.d_st;
     a.trace = p.d_trace;
     a.trace_cap = p.trace_cap;
@@ -217,42 +233,83 @@ SweepArgs sweep_args(lbib_sim* h)
     return a;
 }
 
-hipError_t record(lbib_sim* h, int kind, bool start)
+// Event pair that brackets the next launch of kernel `kind` (null when timing is off or the
+// pool is used up).
+struct EvPair {
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+};
+
+EvPair timing_events(lbib_sim* h, int kind)
 {
     Timing& t = h->timing;
-    if (!t.on) return hipSuccess;
-    if (start) {
-        if (t.used[kind] + 2 > t.ev[kind].size()) return hipSuccess;
-        return hipEventRecord(t.ev[kind][t.used[kind]], h->stream);
-    }
-    if (t.used[kind] + 2 > t.ev[kind].size()) {
-        return hipSuccess;
-    }
-    hipError_t e = hipEventRecord(t.ev[kind][t.used[kind] + 1], h->stream);
+    EvPair p;
+    if (!t.on || t.used[kind] + 2 > t.ev[kind].size()) return p;
+    p.t0 = t.ev[kind][t.used[kind]];
+    p.t1 = t.ev[kind][t.used[kind] + 1];
     t.used[kind] += 2;
     t.launches[kind] += 1;
-    return e;
+    return p;
 }
 
+// One time step is the particle phase then the lattice sweep.  Serial schedule: both on the
+// caller's stream.  Overlapped schedule (when the previous step has predicted this step's
+// box): the particle phase runs on the second stream while the caller's stream sweeps the
+// nodes outside the box (they carry no spread force); the box is swept after the particle
+// phase.  Both schedules compute every node with the same arithmetic.
 template <typename T>
 lbib_status enqueue_steps(lbib_sim* h, int64_t n)
 {
     const SweepArgs sa = sweep_args(h);
+    bool joined = true;
     for (int64_t s = 0; s < n; ++s) {
-        const TileDesc* desc = nullptr;
-        const int64_t* tile = nullptr;
-        for (auto& p : h->parts) {
-            HIPCHK(h, record(h, 1, true));
-            HIPCHK(h, launch_particle<T>(particle_args<T>(h, p), h->stream));
-            HIPCHK(h, record(h, 1, false));
-            desc = p.d_desc;
-            tile = p.d_tile;
+        const T* fin = (const T*)h->fA;
+        T* fout = (T*)h->fB;
+        if (h->parts.empty()) {
+            const EvPair e0 = timing_events(h, 0);
+            HIPCHK(h, launch_sweep<T>(fin, fout, sa, SWEEP_ALL, nullptr, nullptr, 0, h->stream, e0.t0, e0.t1));
+        } else {
+            Particle& p = h->parts[0];
+            ParticleArgs<T> pa = particle_args<T>(h, p);
+            const int par = (int)(h->steps & 1);
+            pa.parity_in = par;
+            pa.parity_out = par ^ 1;
+            // the overlapped schedule pays two cross-stream waits per step (~10 us); it wins
+            // once a sweep moves more than ~64 MiB (the particle phase then hides behind it)
+            const bool overlap =
+                h->overlap == 1 || (h->overlap == 2 && (double)h->desc.nx * h->desc.ny * 18.0 * h->elem >= 64.0 * 1048576.0);
+            if (!overlap || !h->zone_valid) {
+                pa.check_zone = 0;
+                const EvPair e1 = timing_events(h, 1);
+                HIPCHK(h, launch_particle<T>(pa, h->stream, e1.t0, e1.t1));
+                const EvPair e0 = timing_events(h, 0);
+                HIPCHK(h, launch_sweep<T>(fin, fout, sa, SWEEP_ALL, p.d_desc, p.d_tile, p.box_cap, h->stream, e0.t0,
+                                          e0.t1));
+                HIPCHK(h, hipEventRecord(h->evA, h->stream));
+                h->zone_valid = true;
+            } else {
+                pa.check_zone = 1;
+                HIPCHK(h, hipStreamWaitEvent(h->stream2, h->evA, 0));
+                const EvPair e1 = timing_events(h, 1);
+                HIPCHK(h, launch_particle<T>(pa, h->stream2, e1.t0, e1.t1));
+                HIPCHK(h, hipStreamWaitEvent(h->stream, h->evB, 0));
+                const EvPair e0 = timing_events(h, 0);
+                HIPCHK(h, launch_sweep<T>(fin, fout, sa, SWEEP_OUTSIDE, p.d_zone + par, nullptr, 0, h->stream, e0.t0,
+                                          e0.t1));
+                HIPCHK(h, hipEventRecord(h->evA, h->stream));
+                const EvPair e2 = timing_events(h, 2);
+                HIPCHK(h, launch_sweep<T>(fin, fout, sa, SWEEP_BOX, p.d_desc, p.d_tile, p.box_cap, h->stream2, e2.t0,
+                                          e2.t1));
+                HIPCHK(h, hipEventRecord(h->evB, h->stream2));
+                joined = false;
+            }
         }
-        HIPCHK(h, record(h, 0, true));
-        HIPCHK(h, launch_sweep<T>((const T*)h->fA, (T*)h->fB, sa, desc, tile, h->stream));
-        HIPCHK(h, record(h, 0, false));
         std::swap(h->fA, h->fB);
         h->steps += 1;
+    }
+    if (!joined) {
+        // everything enqueued is ordered before later work on the caller's stream
+        HIPCHK(h, hipStreamWaitEvent(h->stream, h->evB, 0));
+        HIPCHK(h, hipEventRecord(h->evA, h->stream));
     }
     return LBIB_OK;
 }
@@ -410,8 +467,11 @@ lbib_status lbib_particle_add(lbib_handle h, const lbib_particle_desc* d, int32_
             return fail(h, LBIB_E_INVALID, "lbib_particle_add: marker spacing below 0.25 lattice units");
         p.mass = d->rho_p * M_PI * a * b;
         p.inertia = p.mass * (a * a + b * b) / 4.0;
-        // the spread footprint of any orientation fits (2 amax + 6)^2 nodes
-        p.cap_w = p.cap_h = (int)std::ceil(2.0 * amax) + 6;
+        // every marker lies within amax of the centroid and every probe within amax + 1.2;
+        // an MLS support reaches 1.5 further, so any orientation's box has at most
+        // ceil(2 amax + 2.4) + 4 nodes per side (one more kept as margin)
+        const int side = (int)std::ceil(2.0 * amax + 2.4) + 5;
+        p.box_cap = side * side;
         h->parts.push_back(std::move(p));
         *pid = (int32_t)h->parts.size() - 1;
         return LBIB_OK;
@@ -473,10 +533,12 @@ lbib_status lbib_init(lbib_handle h)
     }
     for (auto& p : h->parts) {
         const int nl = p.nl;
-        const size_t tile = (size_t)2 * p.cap_w * p.cap_h;
+        const size_t tile = (size_t)2 * p.box_cap;
+        const size_t boxg = particle_lds_bytes(p.box_cap) ? 0 : (size_t)6 * p.box_cap;
         if ((e = dalloc(&p.d_xi, 2 * nl)) != hipSuccess || (e = dalloc(&p.d_nuv, 2 * nl)) != hipSuccess ||
             (e = dalloc(&p.d_S, nl)) != hipSuccess || (e = dalloc(&p.d_lig, nl)) != hipSuccess ||
-            (e = dalloc(&p.d_bond, nl)) != hipSuccess || (e = dalloc(&p.d_tile, tile)) != hipSuccess || (e = dalloc(&p.d_desc, 1)) != hipSuccess ||
+            (e = dalloc(&p.d_bond, nl)) != hipSuccess || (e = dalloc(&p.d_tile, tile)) != hipSuccess ||
+            (boxg && (e = dalloc(&p.d_box, boxg)) != hipSuccess) || (e = dalloc(&p.d_zone, 2)) != hipSuccess || (e = dalloc(&p.d_desc, 1)) != hipSuccess ||
             (e = dalloc(&p.d_st, 1)) != hipSuccess) {
             free_all(h);
             return fail(h, e == hipErrorOutOfMemory ? LBIB_E_NOMEM : LBIB_E_DEVICE,
@@ -508,19 +570,26 @@ lbib_status lbib_init(lbib_handle h)
         st.last.yc = st.yc;
         st.last.theta = st.th;
         st.last.gap = st.yc + 0.5 - support_h(p.a, p.b, st.th);
-        TileDesc td{};
-        if ((e = hipMemcpy(p.d_xi, p.surf.xi.data(), 2 * nl * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+        TileDesc td[2] = {};
+        if ((e = hipMemcpy(p.d_zone, td, sizeof(td), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(p.d_xi, p.surf.xi.data(), 2 * nl * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
             (e = hipMemcpy(p.d_nuv, p.surf.nu.data(), 2 * nl * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
             (e = hipMemcpy(p.d_S, p.surf.S.data(), nl * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
             (e = hipMemcpy(p.d_lig, p.ligand.data(), nl, hipMemcpyHostToDevice)) != hipSuccess ||
             (e = hipMemcpy(p.d_bond, zeros.data(), nl, hipMemcpyHostToDevice)) != hipSuccess ||
             (e = hipMemcpy(p.d_st, &st, sizeof(st), hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = hipMemcpy(p.d_desc, &td, sizeof(td), hipMemcpyHostToDevice)) != hipSuccess)
+            (e = hipMemcpy(p.d_desc, td, sizeof(TileDesc), hipMemcpyHostToDevice)) != hipSuccess)
             return bail(e, "lbib_init: upload");
     }
+    if ((e = hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking)) != hipSuccess)
+        return bail(e, "lbib_init: second stream");
+    if ((e = hipEventCreateWithFlags(&h->evA, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&h->evB, hipEventDisableTiming)) != hipSuccess)
+        return bail(e, "lbib_init: events");
     if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return bail(e, "lbib_init: sync");
     h->state = 1;
     h->steps = 0;
+    h->zone_valid = false;
     return LBIB_OK;
 }
 
@@ -694,6 +763,7 @@ lbib_status lbib_write_particle(lbib_handle h, int32_t pid, const double* v)
     st.uy1 = v[10];
     st.om1 = v[11];
     HIPCHK(h, hipMemcpy(p->d_st, &st, sizeof(st), hipMemcpyHostToDevice));
+    h->zone_valid = false;  // the predicted box no longer matches the particle
     return LBIB_OK;
 }
 
@@ -810,6 +880,7 @@ lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size)
     HIPCHK(h, hipMemcpy(h->d_flags, &zero, sizeof(zero), hipMemcpyHostToDevice));
     h->steps = hd.steps;
     h->state = 1;
+    h->zone_valid = false;
     return LBIB_OK;
 }
 
@@ -819,7 +890,7 @@ lbib_status lbib_kernel_timing(lbib_handle h, int32_t enable)
     HIPCHK(h, hipStreamSynchronize(h->stream));
     Timing& t = h->timing;
     if (enable) {
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < kKinds; ++k) {
             while (t.ev[k].size() < (size_t)2 * kTimingPool) {
                 hipEvent_t e;
                 HIPCHK(h, hipEventCreate(&e));
@@ -836,8 +907,8 @@ lbib_status lbib_kernel_timing(lbib_handle h, int32_t enable)
 lbib_status lbib_kernel_time(lbib_handle h, int32_t kernel, double* total_ms, int64_t* launches)
 {
     if (!h) return fail(nullptr, LBIB_E_INVALID, "lbib_kernel_time: NULL handle");
-    if (kernel < 0 || kernel > 1 || !total_ms || !launches)
-        return fail(h, LBIB_E_INVALID, "lbib_kernel_time: kernel must be 0 or 1 and outputs non-NULL");
+    if (kernel < 0 || kernel >= kKinds || !total_ms || !launches)
+        return fail(h, LBIB_E_INVALID, "lbib_kernel_time: kernel must be 0, 1 or 2 and outputs non-NULL");
     HIPCHK(h, hipStreamSynchronize(h->stream));
     Timing& t = h->timing;
     double acc = 0.0;
@@ -848,6 +919,14 @@ lbib_status lbib_kernel_time(lbib_handle h, int32_t kernel, double* total_ms, in
     }
     *total_ms = acc;
     *launches = t.launches[kernel];
+    return LBIB_OK;
+}
+
+lbib_status lbib_set_overlap(lbib_handle h, int32_t mode)
+{
+    if (!h) return fail(nullptr, LBIB_E_INVALID, "lbib_set_overlap: NULL handle");
+    if (mode < 0 || mode > 2) return fail(h, LBIB_E_INVALID, "lbib_set_overlap: mode must be 0, 1 or 2");
+    h->overlap = mode;
     return LBIB_OK;
 }
 

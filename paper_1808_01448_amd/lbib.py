@@ -84,6 +84,7 @@ _SIGS = {
     "lbib_save": (C.c_int, [_P, _P, _I64]),
     "lbib_load": (C.c_int, [_P, _P, C.c_int64]),
     "lbib_kernel_timing": (C.c_int, [_P, C.c_int32]),
+    "lbib_set_overlap": (C.c_int, [_P, C.c_int32]),
     "lbib_kernel_time": (C.c_int, [_P, C.c_int32, _D, _I64]),
     "lbib_bytes_per_update": (C.c_int, [_P, _I64]),
     "lbib_last_error": (C.c_char_p, [_P]),
@@ -285,12 +286,17 @@ class Sim:
         buf = C.create_string_buffer(blob, len(blob))
         self._call(lib().lbib_load, buf, len(blob))
 
+    def set_overlap(self, mode):
+        """0 / False: serial; 1 / True: overlapped; 2: chosen by lattice size (default)."""
+        self._call(lib().lbib_set_overlap, int(mode))
+
     # -- timing --------------------------------------------------------------------------
     def kernel_timing(self, enable: bool):
         self._call(lib().lbib_kernel_timing, 1 if enable else 0)
 
     def kernel_time(self, kernel: int):
-        """(total milliseconds, launches) of kernel 0 (lattice sweep) or 1 (particle phase)."""
+        """(total milliseconds, launches) of kernel 0 (lattice sweep: all nodes, or the nodes
+        outside the particle's box), 1 (particle phase) or 2 (sweep of the box)."""
         ms = C.c_double()
         n = C.c_int64()
         self._call(lib().lbib_kernel_time, int(kernel), C.byref(ms), C.byref(n))

@@ -274,6 +274,31 @@ def test_full_size_channel_fp32(L, orc):
 # Determinism, checkpoints, failure handling
 # ----------------------------------------------------------------------------------------
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_overlapped_schedule_is_bit_identical(L, prec):
+    """The overlapped schedule (particle phase concurrent with the sweep outside its box)
+    equals the serial one bit for bit, also across a state overwrite that invalidates the
+    predicted box."""
+    w = W.channel_small_binding(prec)
+    a = L.Sim(w)
+    b = L.Sim(w)
+    a.set_overlap(True)
+    b.set_overlap(False)
+    a.trace_enable(400)
+    b.trace_enable(400)
+    for sim in (a, b):
+        sim.step(150)
+        st = np.array([64.3, 7.8, 0.05, 1e-5, 0, 0, 64.3, 7.8, 0.05, 1e-5, 0, 0])
+        sim.write_particle(st)
+        sim.step(250)
+        sim.sync()
+    np.testing.assert_array_equal(a.trace(400), b.trace(400))
+    np.testing.assert_array_equal(a.f, b.f)
+    np.testing.assert_array_equal(a.bonds()[0], b.bonds()[0])
+    a.close()
+    b.close()
+
+
 def test_bitwise_determinism(L):
     w = W.channel_small_binding("fp32")
     a, ta = run_gpu(L, w, 300)
@@ -342,11 +367,14 @@ def test_kernel_timing_and_step_zero(L):
     s = L.Sim(w)
     s.step(0)
     assert s.particle()["step"] == -1
+    s.set_overlap(True)
     s.kernel_timing(True)
     s.step(20)
     ms0, n0 = s.kernel_time(0)
     ms1, n1 = s.kernel_time(1)
-    say("timing", ms0, n0, ms1, n1)
-    assert n0 == 20 and n1 == 20 and ms0 > 0 and ms1 > 0
+    ms2, n2 = s.kernel_time(2)
+    say("timing", ms0, n0, ms1, n1, ms2, n2)
+    # the first step is serial (no predicted box yet), the others overlapped
+    assert n0 == 20 and n1 == 20 and n2 == 19 and ms0 > 0 and ms1 > 0 and ms2 > 0
     assert s.bytes_per_update == 144
     s.close()
