@@ -80,8 +80,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the single-simulation path has no multi-GPU form in this build "
-              "(see the sharding notes in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: a single simulation of this path runs on one device and the "
+              "benchmark has no multi-GPU form; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -9,8 +9,7 @@
  * constants, geometry, moving-least-squares, Philox generator and rigid-body step.
  *
  * Every function cites the passage of the paper it follows.  Where the paper is silent or
- * garbled the reading taken is named in the comment (the same readings are listed with
- * their justification in the design notes of the repository).
+ * garbled the reading taken is named in the comment.
  *
  * Units: lattice units, dx = dt = 1 (section "Fluid-structure interaction strategy").
  * Storage: plain populations f[q][j][i] (x fastest), FP64.
