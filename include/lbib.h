@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define LBIB_ABI_VERSION 1
+#define LBIB_ABI_VERSION 2
 
 typedef struct lbib_sim* lbib_handle;
 
@@ -58,7 +58,8 @@ typedef enum {
     LBIB_E_NOMEM = -3,       /* device or host allocation failed */
     LBIB_E_DEVICE = -4,      /* a HIP runtime call failed */
     LBIB_E_NUMERIC = -5,     /* the GPU watchdog raised a numerical failure */
-    LBIB_E_UNSUPPORTED = -6  /* valid request this build does not implement */
+    LBIB_E_UNSUPPORTED = -6, /* valid request this build does not implement */
+    LBIB_E_FULL = -7         /* a pool's memory budget or member count would be exceeded */
 } lbib_status;
 
 /* Precision of the population storage: f - w_q in double (FP64) or in float (FP32).  The
@@ -235,6 +236,96 @@ const char* lbib_last_error(lbib_handle h);
 
 /* Release everything the handle owns.  NULL-safe. */
 void lbib_destroy(lbib_handle h);
+
+/* ---------------------------------------------------------------------------------------
+ * Pools: many independent simulations stepped together.
+ *
+ * A parameter study (the results section sweeps particle shape, ligand density, bond
+ * strength and flow rate, with several seeds each) runs many small simulations of the
+ * same method.  Stepped one by one, each pays two kernel launches and their gaps per step
+ * on a lattice too small to fill the GPU.  A pool runs one launch of the particle phase
+ * (one workgroup per member) and one launch of the lattice sweep (the tiles of every
+ * member) per time step.  Members may differ in lattice size, tau, Re, particle, ligands
+ * and seed; all share the pool's storage precision.  Each member runs until it has done
+ * its own n_steps (then idles on the GPU at no sweep cost) or until its watchdog fires
+ * (then it stays frozen at the failing step; the others go on).  A member's populations,
+ * particle records, bonds and trace are bit-identical to the same descriptors run alone
+ * through lbib_create / lbib_init / lbib_step with lbib_set_overlap(h, 0).
+ *
+ * Members join (lbib_pool_add) and leave (lbib_pool_remove) between calls; admission is
+ * by device-memory footprint against the budget given at creation, and is refused with
+ * LBIB_E_FULL rather than over-committing HBM.  lbib_pool_add and lbib_pool_remove wait for
+ * the pool's stream; lbib_pool_step only enqueues.  Threading and stream rules are those of
+ * a simulation handle.
+ * ------------------------------------------------------------------------------------- */
+
+typedef struct lbib_pool* lbib_pool_handle;
+
+/* Member states. */
+enum { LBIB_POOL_RUNNING = 0, LBIB_POOL_FINISHED = 1, LBIB_POOL_FAILED = 2 };
+
+/* Create a pool.  precision: LBIB_FP64 or LBIB_FP32 storage for every member;
+ * hbm_budget_bytes: device memory the members may occupy together (the pool's own tables
+ * come on top: about 16 bytes per 256 lattice nodes and 1 KB per member); max_members in
+ * [1, 65536]; hip_stream as for lbib_create. */
+lbib_status lbib_pool_create(int32_t precision, int64_t hbm_budget_bytes, int32_t max_members, void* hip_stream,
+                             lbib_pool_handle* out);
+
+/* Device bytes a member with these descriptors occupies (populations, particle buffers);
+ * the admission test of lbib_pool_add. */
+lbib_status lbib_pool_footprint(const lbib_lattice_desc* lattice, const lbib_particle_desc* particle,
+                                int64_t* bytes);
+
+/* Add a member: one particle with its ligands on the given lattice (descriptors validated
+ * as by lbib_create / lbib_particle_add / lbib_ligands_set; lattice->precision must match
+ * the pool's), initialised as by lbib_init, to run n_steps steps.  *slot receives its id
+ * (ids are never reused within a pool).  LBIB_E_FULL when the budget or max_members would
+ * be exceeded; nothing is changed then. */
+lbib_status lbib_pool_add(lbib_pool_handle p, const lbib_lattice_desc* lattice, const lbib_particle_desc* particle,
+                          const lbib_ligand_desc* ligands, int64_t n_steps, int32_t* slot);
+
+/* Enqueue n pool steps: every running member advances by one step per pool step until it
+ * reaches its n_steps. */
+lbib_status lbib_pool_step(lbib_pool_handle p, int64_t n);
+
+/* Wait for the enqueued steps and list (up to capacity) the slots that have finished or
+ * failed since the previous poll; *count receives how many were written.  Slots beyond
+ * capacity are returned by the next poll. */
+lbib_status lbib_pool_poll(lbib_pool_handle p, int32_t* slots, int32_t capacity, int32_t* count);
+
+/* Wait, then give a member's completed step count and state (LBIB_POOL_*).  For a failed
+ * member, lbib_pool_last_error() then names the watchdog's reason. */
+lbib_status lbib_pool_status(lbib_pool_handle p, int32_t slot, int64_t* steps_done, int32_t* state);
+
+/* Read-outs of one member, as the lbib_read_* calls of a simulation handle (they wait for
+ * the pool's stream). */
+lbib_status lbib_pool_read_particle(lbib_pool_handle p, int32_t slot, lbib_particle_state* out);
+lbib_status lbib_pool_read_bonds(lbib_pool_handle p, int32_t slot, uint8_t* bonded, uint8_t* ligand,
+                                 int32_t capacity);
+lbib_status lbib_pool_read_field(lbib_pool_handle p, int32_t slot, int32_t which, double* out, int64_t capacity);
+
+/* Per-step particle records of one member, as lbib_trace_enable / lbib_read_trace
+ * (recording starts with the member's next step). */
+lbib_status lbib_pool_trace_enable(lbib_pool_handle p, int32_t slot, int64_t capacity);
+lbib_status lbib_pool_read_trace(lbib_pool_handle p, int32_t slot, lbib_particle_state* out, int64_t capacity,
+                                 int64_t* count);
+
+/* Remove a member (finished, failed or still running) and release its device memory. */
+lbib_status lbib_pool_remove(lbib_pool_handle p, int32_t slot);
+
+/* Members held, members still running (as of the last wait) and bytes of the budget in use. */
+lbib_status lbib_pool_usage(lbib_pool_handle p, int32_t* members, int32_t* running, int64_t* bytes_in_use);
+
+/* Kernel timing of the pool's launches: kernel 0 the lattice sweep, kernel 1 the particle
+ * phase (as lbib_kernel_timing / lbib_kernel_time). */
+lbib_status lbib_pool_kernel_timing(lbib_pool_handle p, int32_t enable);
+lbib_status lbib_pool_kernel_time(lbib_pool_handle p, int32_t kernel, double* total_ms, int64_t* launches);
+
+/* Description of the last failure on this pool (NULL: of the last call with a NULL pool). */
+const char* lbib_pool_last_error(lbib_pool_handle p);
+
+/* Release everything the pool owns.  NULL-safe. */
+void lbib_pool_destroy(lbib_pool_handle p);
 
 /* ---------------------------------------------------------------------------------------
  * Kernel-level entry points.  They run the same device functions as the time step on

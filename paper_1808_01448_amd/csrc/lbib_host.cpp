@@ -1,0 +1,307 @@
+// lbib_host.cpp -- host pieces shared by the single-simulation handle and the pool.
+#include "lbib_host.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+namespace lbib {
+
+namespace {
+
+constexpr double kWq[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
+                           1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+constexpr int kExq[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int kEyq[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+// Ligand-bearing elements: with rho_l = p/q in lowest terms, element l carries a ligand when
+// floor((l+1) p/q) - floor(l p/q) = 1 -- floor(nl p/q) ligands spread evenly.
+std::vector<uint8_t> ligand_layout(int nl, int p, int q)
+{
+    const int g = std::gcd(p, q);
+    p /= g;
+    q /= g;
+    std::vector<uint8_t> out(nl);
+    for (int l = 0; l < nl; ++l) out[l] = (uint8_t)((((int64_t)(l + 1) * p) / q - ((int64_t)l * p) / q) == 1);
+    return out;
+}
+
+}  // namespace
+
+lbib_status check_lattice(const lbib_lattice_desc& d, std::string& msg)
+{
+    if (d.nx < 4 || d.ny < 4) return msg = "nx and ny must be >= 4", LBIB_E_INVALID;
+    if ((int64_t)d.nx * d.ny > (int64_t)1 << 31) return msg = "more than 2^31 nodes", LBIB_E_INVALID;
+    if (!is_finite(d.tau) || !(d.tau > 0.5)) return msg = "tau must be > 1/2", LBIB_E_INVALID;
+    if (!is_finite(d.re) || d.re < 0) return msg = "Re must be >= 0", LBIB_E_INVALID;
+    if (d.drive != 0) return msg = "only drive 0 (body-force Poiseuille) is built", LBIB_E_UNSUPPORTED;
+    if (d.precision != LBIB_FP64 && d.precision != LBIB_FP32)
+        return msg = "precision must be LBIB_FP64 or LBIB_FP32", LBIB_E_UNSUPPORTED;
+    return LBIB_OK;
+}
+
+LatticeGeom lattice_geom(const lbib_lattice_desc& d)
+{
+    LatticeGeom g;
+    g.nx = d.nx;
+    g.ny = d.ny;
+    g.elem = d.precision == LBIB_FP64 ? 8 : 4;
+    const int align = (int)(256 / g.elem);  // rows start on 256-byte boundaries
+    g.pitch = (d.nx + align - 1) / align * align;
+    g.plane = (int64_t)g.pitch * d.ny;
+    const double H = (double)d.ny;
+    g.tau = d.tau;
+    g.nu = (d.tau - 0.5) / 3.0;
+    g.umax = d.re * g.nu / H;
+    g.gx = 8.0 * g.nu * g.umax / (H * H);
+    g.gy = 0.0;
+    return g;
+}
+
+lbib_status check_ligands(const lbib_ligand_desc& d, std::string& msg)
+{
+    if (d.rho_l_den <= 0 || d.rho_l_num < 0 || d.rho_l_num > d.rho_l_den)
+        return msg = "ligand density must be a fraction in [0, 1]", LBIB_E_INVALID;
+    const double v[] = {d.sigma_hat, d.sigma_star_ratio, d.y_cr_hat, d.y_eq_ratio,
+                        d.k_f,       d.k_r0,             d.kbt_hat,  d.hamaker_hat};
+    for (double x : v)
+        if (!is_finite(x)) return msg = "non-finite parameter", LBIB_E_INVALID;
+    if (d.sigma_hat < 0 || d.y_cr_hat < 0 || d.y_eq_ratio < 0 || d.k_f < 0 || d.k_r0 < 0 || d.hamaker_hat < 0)
+        return msg = "negative rate, length or constant", LBIB_E_INVALID;
+    if (!(d.kbt_hat > 0)) return msg = "kbt_hat must be > 0", LBIB_E_INVALID;
+    return LBIB_OK;
+}
+
+void set_ligands(Particle& p, const lbib_ligand_desc& d)
+{
+    p.ligand = ligand_layout(p.nl, d.rho_l_num, d.rho_l_den);
+    p.lig = d;
+    p.has_ligands = true;
+}
+
+lbib_status prepare_particle(const lbib_lattice_desc& lat, const lbib_particle_desc& d, Particle& p, std::string& msg)
+{
+    if (d.shape != 0 && d.shape != 1) return msg = "shape must be 0 or 1", LBIB_E_INVALID;
+    const double a = d.a_major, b = d.shape == 0 ? d.a_major : d.b_minor;
+    if (!is_finite(a) || !is_finite(b) || !(a > 0) || !(b > 0)) return msg = "semi-axes must be positive", LBIB_E_INVALID;
+    if (!is_finite(d.xc) || !is_finite(d.yc) || !is_finite(d.theta0)) return msg = "non-finite position", LBIB_E_INVALID;
+    if (!is_finite(d.rho_p) || !(d.rho_p > 0)) return msg = "rho_p must be > 0", LBIB_E_INVALID;
+    if (d.n_markers < 8 || d.n_markers > kMaxMarkers) return msg = "n_markers must be in [8, 1024]", LBIB_E_INVALID;
+    const double amax = std::max(a, b);
+    if (2.0 * amax + 6.0 > lat.nx) return msg = "particle too wide for the channel (2a + 6 > nx)", LBIB_E_INVALID;
+    const double hs = support_h(a, b, d.theta0);
+    if (!(d.yc - hs + 0.5 > 0.0) || !(d.yc + hs < lat.ny - 0.5))
+        return msg = "particle must lie inside the channel with a positive gap", LBIB_E_INVALID;
+    p.desc = d;
+    p.nl = d.n_markers;
+    p.a = a;
+    p.b = b;
+    if (!build_surface(d.shape, a, b, p.nl, p.surf)) return msg = "surface construction failed", LBIB_E_INVALID;
+    if (p.surf.perimeter / p.nl < 0.25) return msg = "marker spacing below 0.25 lattice units", LBIB_E_INVALID;
+    p.mass = d.rho_p * M_PI * a * b;
+    p.inertia = p.mass * (a * a + b * b) / 4.0;
+    // every marker lies within amax of the centroid and every probe within amax + 1.2; an
+    // MLS support reaches 1.5 further, so any orientation's box has at most
+    // ceil(2 amax + 2.4) + 4 nodes per side (one more kept as margin)
+    const int side = (int)std::ceil(2.0 * amax + 2.4) + 5;
+    p.box_cap = side * side;
+    return LBIB_OK;
+}
+
+int64_t footprint_bytes(const lbib_lattice_desc& lat, const Particle* p)
+{
+    const LatticeGeom g = lattice_geom(lat);
+    int64_t bytes = 2 * 9 * g.plane * (int64_t)g.elem;
+    if (p) {
+        const int64_t nl = p->nl;
+        bytes += nl * (5 * 8 + 2) + 2 * 8 * (int64_t)p->box_cap + 3 * (int64_t)sizeof(TileDesc) + (int64_t)sizeof(DevParticle);
+        if (!particle_lds_bytes(p->box_cap)) bytes += 6 * 8 * (int64_t)p->box_cap;
+    }
+    return bytes;
+}
+
+hipError_t alloc_particle(Particle& p)
+{
+    const int nl = p.nl;
+    const size_t tile = (size_t)2 * p.box_cap;
+    const size_t boxg = particle_lds_bytes(p.box_cap) ? 0 : (size_t)6 * p.box_cap;
+    hipError_t e;
+    if ((e = dalloc(&p.d_xi, 2 * nl)) != hipSuccess || (e = dalloc(&p.d_nuv, 2 * nl)) != hipSuccess ||
+        (e = dalloc(&p.d_S, nl)) != hipSuccess || (e = dalloc(&p.d_lig, nl)) != hipSuccess ||
+        (e = dalloc(&p.d_bond, nl)) != hipSuccess || (e = dalloc(&p.d_tile, tile)) != hipSuccess ||
+        (boxg && (e = dalloc(&p.d_box, boxg)) != hipSuccess) || (e = dalloc(&p.d_zone, 2)) != hipSuccess ||
+        (e = dalloc(&p.d_desc, 1)) != hipSuccess || (e = dalloc(&p.d_st, 1)) != hipSuccess) {
+        free_particle(p);
+        return e;
+    }
+    return hipSuccess;
+}
+
+void free_particle(Particle& p)
+{
+    dfree(p.d_xi);
+    dfree(p.d_nuv);
+    dfree(p.d_S);
+    dfree(p.d_lig);
+    dfree(p.d_bond);
+    dfree(p.d_tile);
+    dfree(p.d_box);
+    dfree(p.d_desc);
+    dfree(p.d_zone);
+    dfree(p.d_st);
+    dfree(p.d_trace);
+    p.trace_cap = 0;
+}
+
+hipError_t upload_particle(Particle& p)
+{
+    const int nl = p.nl;
+    std::vector<uint8_t> zeros(nl, 0);
+    DevParticle st{};
+    st.xc = st.xc1 = p.desc.xc;
+    st.yc = st.yc1 = p.desc.yc;
+    st.th = st.th1 = p.desc.theta0;
+    st.step = 0;
+    st.last.step = -1;
+    st.last.xc = st.xc;
+    st.last.yc = st.yc;
+    st.last.theta = st.th;
+    st.last.gap = st.yc + 0.5 - support_h(p.a, p.b, st.th);
+    TileDesc td[2] = {};
+    hipError_t e;
+    if ((e = hipMemcpy(p.d_zone, td, sizeof(td), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p.d_xi, p.surf.xi.data(), 2 * nl * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p.d_nuv, p.surf.nu.data(), 2 * nl * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p.d_S, p.surf.S.data(), nl * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p.d_lig, p.ligand.data(), nl, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p.d_bond, zeros.data(), nl, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p.d_st, &st, sizeof(st), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p.d_desc, td, sizeof(TileDesc), hipMemcpyHostToDevice)) != hipSuccess)
+        return e;
+    return hipSuccess;
+}
+
+template <typename T>
+void fill_particle_args(ParticleArgs<T>& a, const LatticeGeom& g, uint64_t seed, const Particle& p, int32_t* flags)
+{
+    a = ParticleArgs<T>{};
+    a.target_steps = INT64_MAX;
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.pitch = g.pitch;
+    a.plane = g.plane;
+    a.gx = g.gx;
+    a.gy = g.gy;
+    a.nu = g.nu;
+    a.xi = p.d_xi;
+    a.nuv = p.d_nuv;
+    a.S = p.d_S;
+    a.ligand = p.d_lig;
+    a.bond = p.d_bond;
+    a.nl = p.nl;
+    a.a = p.a;
+    a.b = p.b;
+    a.mass = p.mass;
+    a.inertia = p.inertia;
+    // Table 1 dimensionless groups to lattice units (rho_ref = 1, length H = ny)
+    const double H = (double)g.ny, nu2 = g.nu * g.nu;
+    const lbib_ligand_desc& L = p.lig;
+    a.sigma = L.sigma_hat * nu2 / H;
+    a.sigma_star = L.sigma_star_ratio * a.sigma;
+    a.y_cr = L.y_cr_hat * H;
+    a.y_eq = L.y_eq_ratio * a.y_cr;
+    a.k_f = L.k_f;
+    a.k_r0 = L.k_r0;
+    a.kBT = L.kbt_hat * nu2 * H;
+    a.hamaker = L.hamaker_hat * nu2 * H;
+    a.seed = seed;
+    a.pid = 0;
+    a.tile = p.d_tile;
+    a.box_global = p.d_box;
+    a.box_cap = p.box_cap;
+    a.desc = p.d_desc;
+    a.zone = p.d_zone;
+    a.st = p.d_st;
+    a.trace = p.d_trace;
+    a.trace_cap = p.trace_cap;
+    a.trace_start = p.trace_start;
+    a.flags = flags;
+}
+
+template void fill_particle_args<float>(ParticleArgs<float>&, const LatticeGeom&, uint64_t, const Particle&, int32_t*);
+template void fill_particle_args<double>(ParticleArgs<double>&, const LatticeGeom&, uint64_t, const Particle&,
+                                         int32_t*);
+
+hipError_t init_populations(void* f, const LatticeGeom& g, hipStream_t s)
+{
+    const size_t bytes = (size_t)9 * g.plane * g.elem;
+    hipError_t e = hipMemsetAsync(f, 0, bytes, s);
+    if (e != hipSuccess) return e;
+    if (g.elem == 8) return launch_init<double>((double*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, s);
+    return launch_init<float>((float*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, s);
+}
+
+hipError_t download_populations(const void* fdev, const LatticeGeom& g, std::vector<double>& f)
+{
+    const int nx = g.nx, ny = g.ny;
+    const size_t n = (size_t)9 * g.plane;
+    f.assign((size_t)9 * nx * ny, 0.0);
+    hipError_t e;
+    if (g.elem == 8) {
+        std::vector<double> raw(n);
+        if ((e = hipMemcpy(raw.data(), fdev, n * 8, hipMemcpyDeviceToHost)) != hipSuccess) return e;
+        for (int q = 0; q < 9; ++q)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i)
+                    f[((size_t)q * ny + j) * nx + i] = kWq[q] + raw[q * g.plane + (size_t)j * g.pitch + i];
+    } else {
+        std::vector<float> raw(n);
+        if ((e = hipMemcpy(raw.data(), fdev, n * 4, hipMemcpyDeviceToHost)) != hipSuccess) return e;
+        for (int q = 0; q < 9; ++q)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i)
+                    f[((size_t)q * ny + j) * nx + i] = kWq[q] + (double)raw[q * g.plane + (size_t)j * g.pitch + i];
+    }
+    return hipSuccess;
+}
+
+hipError_t upload_populations(void* fdev, const LatticeGeom& g, const double* f)
+{
+    const int nx = g.nx, ny = g.ny;
+    const size_t n = (size_t)9 * g.plane;
+    if (g.elem == 8) {
+        std::vector<double> raw(n, 0.0);
+        for (int q = 0; q < 9; ++q)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i)
+                    raw[q * g.plane + (size_t)j * g.pitch + i] = f[((size_t)q * ny + j) * nx + i] - kWq[q];
+        return hipMemcpy(fdev, raw.data(), n * 8, hipMemcpyHostToDevice);
+    }
+    std::vector<float> raw(n, 0.0f);
+    for (int q = 0; q < 9; ++q)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i)
+                raw[q * g.plane + (size_t)j * g.pitch + i] = (float)(f[((size_t)q * ny + j) * nx + i] - kWq[q]);
+    return hipMemcpy(fdev, raw.data(), n * 4, hipMemcpyHostToDevice);
+}
+
+void field_from_populations(const std::vector<double>& f, const LatticeGeom& g, int which, double* out)
+{
+    const size_t N = (size_t)g.nx * g.ny;
+    if (which == 3) {
+        std::memcpy(out, f.data(), f.size() * sizeof(double));
+        return;
+    }
+    for (size_t c = 0; c < N; ++c) {
+        double r = 0, jx = 0, jy = 0;
+        for (int q = 0; q < 9; ++q) {
+            const double v = f[q * N + c];
+            r += v;
+            jx += v * kExq[q];
+            jy += v * kEyq[q];
+        }
+        out[c] = which == 0 ? r : which == 1 ? (jx + 0.5 * g.gx) / r : (jy + 0.5 * g.gy) / r;
+    }
+}
+
+}  // namespace lbib

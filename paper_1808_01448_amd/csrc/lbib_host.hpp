@@ -1,0 +1,101 @@
+// lbib_host.hpp -- host pieces shared by the single-simulation handle and the pool:
+// descriptor validation, unit conversion (Table 1 groups to lattice units), particle
+// preparation, device buffers of a particle and the population download.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "lbib.h"
+#include "lbib_geometry.hpp"
+#include "lbib_internal.hpp"
+
+namespace lbib {
+
+constexpr int kMaxMarkers = 1024;
+
+// Lattice constants derived from a descriptor.
+struct LatticeGeom {
+    int nx = 0, ny = 0, pitch = 0;
+    int64_t plane = 0;  // elements per population plane
+    size_t elem = 0;    // bytes per stored population
+    double tau = 0, nu = 0, umax = 0, gx = 0, gy = 0;
+};
+
+// One particle: host description, surface, ligand layout and its device buffers.
+struct Particle {
+    lbib_particle_desc desc{};
+    lbib_ligand_desc lig{};
+    bool has_ligands = false;
+    int nl = 0;
+    double a = 0, b = 0, mass = 0, inertia = 0;
+    Surface surf;
+    std::vector<uint8_t> ligand;
+    double *d_xi = nullptr, *d_nuv = nullptr, *d_S = nullptr;
+    uint8_t *d_lig = nullptr, *d_bond = nullptr;
+    int64_t* d_tile = nullptr;
+    double* d_box = nullptr;  // box node fields when they do not fit in LDS
+    int box_cap = 0;
+    TileDesc* d_desc = nullptr;
+    TileDesc* d_zone = nullptr;  // two slots, by step parity
+    DevParticle* d_st = nullptr;
+    lbib_particle_state* d_trace = nullptr;
+    int64_t trace_cap = 0, trace_start = 0;
+};
+
+inline bool is_finite(double v) { return std::isfinite(v); }
+
+// Support function of the ellipse along the wall normal: its lowest point is h below the
+// centroid.
+inline double support_h(double a, double b, double th)
+{
+    const double s = std::sin(th), c = std::cos(th);
+    return std::sqrt(b * b * s * s + a * a * c * c);
+}
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count)
+{
+    return hipMalloc((void**)p, (count ? count : 1) * sizeof(T));
+}
+
+template <typename T>
+void dfree(T*& p)
+{
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+// Validation: LBIB_OK, or an error status with the reason in msg.
+lbib_status check_lattice(const lbib_lattice_desc& d, std::string& msg);
+lbib_status check_ligands(const lbib_ligand_desc& d, std::string& msg);
+// Validates the particle against the lattice and fills the host part of p.
+lbib_status prepare_particle(const lbib_lattice_desc& lat, const lbib_particle_desc& d, Particle& p, std::string& msg);
+void set_ligands(Particle& p, const lbib_ligand_desc& d);
+LatticeGeom lattice_geom(const lbib_lattice_desc& d);
+
+// Device bytes a simulation of this lattice and particle (or none) needs.
+int64_t footprint_bytes(const lbib_lattice_desc& lat, const Particle* p);
+
+hipError_t alloc_particle(Particle& p);
+void free_particle(Particle& p);
+// Geometry, ligands, no bonds and the particle at rest at its initial placement.
+hipError_t upload_particle(Particle& p);
+
+template <typename T>
+void fill_particle_args(ParticleArgs<T>& a, const LatticeGeom& g, uint64_t seed, const Particle& p, int32_t* flags);
+
+// Initial populations f = f_eq(1, u_poiseuille(y)) (shifted), padding zeroed.
+hipError_t init_populations(void* f, const LatticeGeom& g, hipStream_t s);
+
+// Plain FP64 populations [9][ny][nx] from a device buffer of shifted ones.
+hipError_t download_populations(const void* fdev, const LatticeGeom& g, std::vector<double>& f);
+// Overwrite a device buffer with plain FP64 populations [9][ny][nx].
+hipError_t upload_populations(void* fdev, const LatticeGeom& g, const double* f);
+// rho (which 0), u_x (1), u_y (2) or the populations (3) from plain populations.
+void field_from_populations(const std::vector<double>& f, const LatticeGeom& g, int which, double* out);
+
+}  // namespace lbib

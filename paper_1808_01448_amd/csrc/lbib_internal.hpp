@@ -23,7 +23,8 @@ struct DevParticle {
     double xc, yc, th, ux, uy, om;        // level n
     double xc1, yc1, th1, ux1, uy1, om1;  // level n-1
     int64_t step;                         // n: the next step to run
-    int32_t pad0, pad1;
+    int32_t did_step;                     // the last particle phase advanced the particle
+    int32_t pad0;
     lbib_particle_state last;             // record of the last completed step
 };
 
@@ -51,7 +52,9 @@ struct SweepArgs {
 // Everything the particle phase needs; passed by value.
 template <typename T>
 struct ParticleArgs {
-    const T* f;  // populations f - w_q at level n
+    const T* f;   // populations f - w_q at level n (a pool passes the even-step buffer)
+    const T* fB;  // a pool's odd-step buffer
+    int64_t target_steps;  // a pool member stops at this step count
     int32_t nx, ny, pitch;
     int64_t plane;
     double gx, gy, nu;
@@ -98,6 +101,27 @@ size_t particle_lds_bytes(int32_t box_cap);
 template <typename T>
 hipError_t launch_particle(const ParticleArgs<T>& a, hipStream_t stream, hipEvent_t t0 = nullptr,
                            hipEvent_t t1 = nullptr);
+
+// A pool of independent simulations stepped together (one launch per kernel per step).
+// The sweep's blocks are listed in `table`: (simulation, tile) per block, tiles of 64 x 4
+// nodes; a block of a simulation whose particle phase did not step does nothing.
+template <typename T>
+struct PoolSweep {
+    SweepArgs a;
+    T* fA;  // buffer of the even steps
+    T* fB;  // buffer of the odd steps
+    const TileDesc* desc;
+    const int64_t* tile;
+    const DevParticle* st;
+    int32_t gx;  // 64-node tiles along x
+    int32_t pad;
+};
+template <typename T>
+hipError_t launch_pool_particle(const ParticleArgs<T>* args, const int32_t* active, int32_t n_active, int32_t max_nl,
+                                int32_t lds_cap, hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+template <typename T>
+hipError_t launch_pool_sweep(const PoolSweep<T>* sims, const int2* table, int32_t n_blocks, hipStream_t stream,
+                             hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
 hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n, hipStream_t stream);
 hipError_t launch_mls(const double* pts, int64_t n, int32_t nx, int32_t ny, int32_t* node, double* phi, double* psix,

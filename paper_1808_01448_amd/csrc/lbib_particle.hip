@@ -205,13 +205,12 @@ __device__ __forceinline__ void force_add(unsigned long long* p, int64_t v)
         __hip_atomic_fetch_add(p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// MPT markers per thread (nl <= MPT * PB).  LDS: the box lives in dynamic LDS, else in the
-// global scratch a.box_global (plain loads and stores ordered by the workgroup barriers,
-// device-scope atomics for the force).
+// One particle's phase, run by one workgroup.  MPT markers per thread (nl <= MPT * PB).
+// LDS: the box lives in dynamic LDS (`base`), else in the global scratch a.box_global (plain
+// loads and stores ordered by the workgroup barriers, device-scope atomics for the force).
 template <typename T, int MPT, bool LDS>
-__global__ __launch_bounds__(PB) void particle_kernel(ParticleArgs<T> a)
+__device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, double* lds_box)
 {
-    extern __shared__ double lds_box[];
     __shared__ double shd[8][NW];
     __shared__ int shi[8][NW];
     const int tid = threadIdx.x;
@@ -526,6 +525,7 @@ __global__ __launch_bounds__(PB) void particle_kernel(ParticleArgs<T> a)
         st->uy = nuy;
         st->om = nom;
         st->step = step + 1;
+        st->did_step = 1;
         lbib_particle_state rec;
         rec.step = step;
         rec.xc = nxc;
@@ -580,6 +580,67 @@ __global__ __launch_bounds__(PB) void particle_kernel(ParticleArgs<T> a)
             a.zone[a.parity_out] = z;
         }
     }
+}
+
+template <typename T, int MPT, bool LDS>
+__global__ __launch_bounds__(PB) void particle_kernel(ParticleArgs<T> a)
+{
+    extern __shared__ double lds_box[];
+    particle_phase<T, MPT, LDS>(a, lds_box);
+}
+
+// Particle phases of a pool of independent simulations: workgroup b runs simulation
+// active[b].  A simulation whose step counter has reached its target, or whose watchdog
+// has raised a flag, does nothing and clears its did_step flag (its sweep then does
+// nothing either), so a failed member stays frozen at the step that failed.  The
+// population buffer of step n is f for even n and fB for odd n.  Boxes up to lds_cap nodes
+// are staged in LDS, larger ones in their global scratch.
+template <typename T, int MPT>
+__global__ __launch_bounds__(PB) void pool_particle_kernel(const ParticleArgs<T>* __restrict__ args,
+                                                           const int32_t* __restrict__ active, int32_t lds_cap)
+{
+    extern __shared__ double lds_box[];
+    ParticleArgs<T> a = args[active[blockIdx.x]];
+    const int64_t n = a.st->step;
+    if (n >= a.target_steps || *a.flags != 0) {
+        if (threadIdx.x == 0) a.st->did_step = 0;
+        return;
+    }
+    a.f = (n & 1) ? a.fB : a.f;
+    if (a.box_cap <= lds_cap)
+        particle_phase<T, MPT, true>(a, lds_box);
+    else
+        particle_phase<T, MPT, false>(a, lds_box);
+}
+
+template <typename T>
+hipError_t launch_pool_particle(const ParticleArgs<T>* args, const int32_t* active, int32_t n_active, int32_t max_nl,
+                                int32_t lds_cap, hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
+{
+    if (n_active <= 0) return hipSuccess;
+    const size_t lds = (size_t)lds_cap * kBoxDoubles * 8;
+    static bool attr[3] = {false, false, false};
+#define LBIB_POOL_LAUNCH(M, IDX)                                                                                      \
+    do {                                                                                                               \
+        if (!attr[IDX]) {                                                                                              \
+            hipError_t e = hipFuncSetAttribute((const void*)pool_particle_kernel<T, M>,                                \
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, 158 * 1024);                \
+            if (e != hipSuccess) return e;                                                                             \
+            attr[IDX] = true;                                                                                          \
+        }                                                                                                              \
+        hipExtLaunchKernelGGL((pool_particle_kernel<T, M>), dim3(n_active), dim3(PB), (uint32_t)lds, stream, t0, t1, 0u, \
+                              args, active, lds_cap);                                                              \
+    } while (0)
+    if (max_nl <= PB)
+        LBIB_POOL_LAUNCH(1, 0);
+    else if (max_nl <= 2 * PB)
+        LBIB_POOL_LAUNCH(2, 1);
+    else if (max_nl <= 4 * PB)
+        LBIB_POOL_LAUNCH(4, 2);
+    else
+        return hipErrorInvalidValue;
+#undef LBIB_POOL_LAUNCH
+    return hipGetLastError();
 }
 
 template <typename T, int MPT>
@@ -720,6 +781,10 @@ hipError_t launch_copy(const float4* src, float4* dst, int64_t n, hipStream_t st
     return hipGetLastError();
 }
 
+template hipError_t launch_pool_particle<float>(const ParticleArgs<float>*, const int32_t*, int32_t, int32_t, int32_t,
+                                                hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_pool_particle<double>(const ParticleArgs<double>*, const int32_t*, int32_t, int32_t, int32_t,
+                                                 hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_particle<float>(const ParticleArgs<float>&, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_particle<double>(const ParticleArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
 

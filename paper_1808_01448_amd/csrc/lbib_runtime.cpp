@@ -13,41 +13,14 @@
 #include <vector>
 
 #include "lbib.h"
-#include "lbib_geometry.hpp"
+#include "lbib_host.hpp"
 #include "lbib_internal.hpp"
 
 using namespace lbib;
 
 namespace {
 
-constexpr double kWq[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
-                           1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
-constexpr int kExq[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-constexpr int kEyq[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-
-constexpr int kMaxMarkers = 1024;
 constexpr int kTimingPool = 8192;  // event pairs per kernel kind
-
-struct Particle {
-    lbib_particle_desc desc{};
-    lbib_ligand_desc lig{};
-    bool has_ligands = false;
-    int nl = 0;
-    double a = 0, b = 0, mass = 0, inertia = 0;
-    Surface surf;
-    std::vector<uint8_t> ligand;
-    // device
-    double *d_xi = nullptr, *d_nuv = nullptr, *d_S = nullptr;
-    uint8_t *d_lig = nullptr, *d_bond = nullptr;
-    int64_t* d_tile = nullptr;
-    double* d_box = nullptr;  // box node fields when they do not fit in LDS
-    int box_cap = 0;
-    TileDesc* d_desc = nullptr;
-    TileDesc* d_zone = nullptr;  // two slots, by step parity
-    DevParticle* d_st = nullptr;
-    lbib_particle_state* d_trace = nullptr;
-    int64_t trace_cap = 0, trace_start = 0;
-};
 
 constexpr int kKinds = 3;  // 0 lattice sweep (all or outside the box), 1 particle phase, 2 box sweep
 
@@ -70,12 +43,9 @@ struct lbib_sim {
     bool zone_valid = false;  // the zone slot of the next step holds its box
     int state = 0;  // 0 created, 1 running, 2 failed
     std::string err;
-    int pitch = 0;
-    int64_t plane = 0;
-    size_t elem = 0;
+    LatticeGeom g;
     void* fA = nullptr;
     void* fB = nullptr;
-    double nu = 0, umax = 0, gx = 0, gy = 0;
     std::vector<Particle> parts;
     int32_t* d_flags = nullptr;
     int64_t steps = 0;
@@ -106,36 +76,6 @@ lbib_status hip_fail(lbib_sim* h, hipError_t e, const char* what)
         if (e_ != hipSuccess) return hip_fail((h), e_, #call);      \
     } while (0)
 
-bool is_finite(double v) { return std::isfinite(v); }
-
-double support_h(double a, double b, double th)
-{
-    const double s = std::sin(th), c = std::cos(th);
-    return std::sqrt(b * b * s * s + a * a * c * c);
-}
-
-template <typename T>
-void dfree(T*& p)
-{
-    if (p) (void)hipFree((void*)p);
-    p = nullptr;
-}
-
-void free_particle(Particle& p)
-{
-    dfree(p.d_xi);
-    dfree(p.d_nuv);
-    dfree(p.d_S);
-    dfree(p.d_lig);
-    dfree(p.d_bond);
-    dfree(p.d_tile);
-    dfree(p.d_box);
-    dfree(p.d_desc);
-    dfree(p.d_zone);
-    dfree(p.d_st);
-    dfree(p.d_trace);
-}
-
 void free_all(lbib_sim* h)
 {
     for (auto& p : h->parts) free_particle(p);
@@ -155,67 +95,11 @@ void free_all(lbib_sim* h)
 }
 
 template <typename T>
-hipError_t dalloc(T** p, size_t count)
-{
-    return hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
-}
-
-// Ligand-bearing elements: with rho_l = p/q in lowest terms, element l carries a ligand when
-// floor((l+1) p/q) - floor(l p/q) = 1 -- floor(nl p/q) ligands spread evenly.
-std::vector<uint8_t> ligand_layout(int nl, int p, int q)
-{
-    const int g = std::gcd(p, q);
-    p /= g;
-    q /= g;
-    std::vector<uint8_t> out(nl);
-    for (int l = 0; l < nl; ++l) out[l] = (uint8_t)((((int64_t)(l + 1) * p) / q - ((int64_t)l * p) / q) == 1);
-    return out;
-}
-
-template <typename T>
 ParticleArgs<T> particle_args(lbib_sim* h, Particle& p)
 {
-    ParticleArgs<T> a{};
+    ParticleArgs<T> a;
+    fill_particle_args<T>(a, h->g, h->desc.seed, p, h->d_flags);
     a.f = (const T*)h->fA;
-    a.nx = h->desc.nx;
-    a.ny = h->desc.ny;
-    a.pitch = h->pitch;
-    a.plane = h->plane;
-    a.gx = h->gx;
-    a.gy = h->gy;
-    a.nu = h->nu;
-    a.xi = p.d_xi;
-    a.nuv = p.d_nuv;
-    a.S = p.d_S;
-    a.ligand = p.d_lig;
-    a.bond = p.d_bond;
-    a.nl = p.nl;
-    a.a = p.a;
-    a.b = p.b;
-    a.mass = p.mass;
-    a.inertia = p.inertia;
-    const double H = (double)h->desc.ny, nu2 = h->nu * h->nu;
-    const lbib_ligand_desc& L = p.lig;
-    a.sigma = L.sigma_hat * nu2 / H;
-    a.sigma_star = L.sigma_star_ratio * a.sigma;
-    a.y_cr = L.y_cr_hat * H;
-    a.y_eq = L.y_eq_ratio * a.y_cr;
-    a.k_f = L.k_f;
-    a.k_r0 = L.k_r0;
-    a.kBT = L.kbt_hat * nu2 * H;
-    a.hamaker = L.hamaker_hat * nu2 * H;
-    a.seed = h->desc.seed;
-    a.pid = 0;
-    a.tile = p.d_tile;
-    a.box_global = p.d_box;
-    a.box_cap = p.box_cap;
-    a.desc = p.d_desc;
-    a.zone = p.d_zone;
-    a.st = p.d_st;
-    a.trace = p.d_trace;
-    a.trace_cap = p.trace_cap;
-    a.trace_start = p.trace_start;
-    a.flags = h->d_flags;
     return a;
 }
 
@@ -224,12 +108,12 @@ SweepArgs sweep_args(lbib_sim* h)
     SweepArgs a{};
     a.nx = h->desc.nx;
     a.ny = h->desc.ny;
-    a.pitch = h->pitch;
-    a.plane = h->plane;
+    a.pitch = h->g.pitch;
+    a.plane = h->g.plane;
     a.omega = 1.0 / h->desc.tau;
     a.guo = 1.0 - 1.0 / (2.0 * h->desc.tau);
-    a.gx = h->gx;
-    a.gy = h->gy;
+    a.gx = h->g.gx;
+    a.gy = h->g.gy;
     return a;
 }
 
@@ -276,7 +160,7 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
             // the overlapped schedule pays two cross-stream waits per step (~10 us); it wins
             // once a sweep moves more than ~64 MiB (the particle phase then hides behind it)
             const bool overlap =
-                h->overlap == 1 || (h->overlap == 2 && (double)h->desc.nx * h->desc.ny * 18.0 * h->elem >= 64.0 * 1048576.0);
+                h->overlap == 1 || (h->overlap == 2 && (double)h->desc.nx * h->desc.ny * 18.0 * h->g.elem >= 64.0 * 1048576.0);
             if (!overlap || !h->zone_valid) {
                 pa.check_zone = 0;
                 const EvPair e1 = timing_events(h, 1);
@@ -345,24 +229,7 @@ Particle* get_particle(lbib_sim* h, int32_t pid)
 // Populations on the device -> plain FP64 f (host, [9][ny][nx]).
 lbib_status download_f(lbib_sim* h, std::vector<double>& f)
 {
-    const int nx = h->desc.nx, ny = h->desc.ny;
-    const size_t n = (size_t)9 * h->plane;
-    f.assign((size_t)9 * nx * ny, 0.0);
-    if (h->elem == 8) {
-        std::vector<double> raw(n);
-        HIPCHK(h, hipMemcpy(raw.data(), h->fA, n * 8, hipMemcpyDeviceToHost));
-        for (int q = 0; q < 9; ++q)
-            for (int j = 0; j < ny; ++j)
-                for (int i = 0; i < nx; ++i)
-                    f[((size_t)q * ny + j) * nx + i] = kWq[q] + raw[q * h->plane + (size_t)j * h->pitch + i];
-    } else {
-        std::vector<float> raw(n);
-        HIPCHK(h, hipMemcpy(raw.data(), h->fA, n * 4, hipMemcpyDeviceToHost));
-        for (int q = 0; q < 9; ++q)
-            for (int j = 0; j < ny; ++j)
-                for (int i = 0; i < nx; ++i)
-                    f[((size_t)q * ny + j) * nx + i] = kWq[q] + (double)raw[q * h->plane + (size_t)j * h->pitch + i];
-    }
+    HIPCHK(h, download_populations(h->fA, h->g, f));
     return LBIB_OK;
 }
 
@@ -374,7 +241,7 @@ struct BlobHeader {
 
 size_t blob_size(lbib_sim* h)
 {
-    size_t s = sizeof(BlobHeader) + (size_t)9 * h->plane * h->elem;
+    size_t s = sizeof(BlobHeader) + (size_t)9 * h->g.plane * h->g.elem;
     for (auto& p : h->parts) s += sizeof(DevParticle) + (size_t)p.nl;
     return s;
 }
@@ -395,15 +262,9 @@ lbib_status lbib_create(const lbib_lattice_desc* d, void* hip_stream, lbib_handl
 {
     try {
         if (!d || !out) return fail(nullptr, LBIB_E_INVALID, "lbib_create: NULL argument");
-        if (d->nx < 4 || d->ny < 4) return fail(nullptr, LBIB_E_INVALID, "lbib_create: nx and ny must be >= 4");
-        if ((int64_t)d->nx * d->ny > (int64_t)1 << 31)
-            return fail(nullptr, LBIB_E_INVALID, "lbib_create: more than 2^31 nodes");
-        if (!is_finite(d->tau) || !(d->tau > 0.5)) return fail(nullptr, LBIB_E_INVALID, "lbib_create: tau must be > 1/2");
-        if (!is_finite(d->re) || d->re < 0) return fail(nullptr, LBIB_E_INVALID, "lbib_create: Re must be >= 0");
-        if (d->drive != 0)
-            return fail(nullptr, LBIB_E_UNSUPPORTED, "lbib_create: only drive 0 (body-force Poiseuille) is built");
-        if (d->precision != LBIB_FP64 && d->precision != LBIB_FP32)
-            return fail(nullptr, LBIB_E_UNSUPPORTED, "lbib_create: precision must be LBIB_FP64 or LBIB_FP32");
+        std::string msg;
+        const lbib_status v = check_lattice(*d, msg);
+        if (v != LBIB_OK) return fail(nullptr, v, "lbib_create: " + msg);
         lbib_sim* h = new lbib_sim();
         h->desc = *d;
         if (hip_stream) {
@@ -416,15 +277,7 @@ lbib_status lbib_create(const lbib_lattice_desc* d, void* hip_stream, lbib_handl
             }
             h->own_stream = true;
         }
-        h->elem = d->precision == LBIB_FP64 ? 8 : 4;
-        const int align = (int)(256 / h->elem);  // rows start on 256-byte boundaries
-        h->pitch = (d->nx + align - 1) / align * align;
-        h->plane = (int64_t)h->pitch * d->ny;
-        const double H = (double)d->ny;
-        h->nu = (d->tau - 0.5) / 3.0;
-        h->umax = d->re * h->nu / H;
-        h->gx = 8.0 * h->nu * h->umax / (H * H);
-        h->gy = 0.0;
+        h->g = lattice_geom(*d);
         *out = h;
         return LBIB_OK;
     } catch (const std::bad_alloc&) {
@@ -441,37 +294,10 @@ lbib_status lbib_particle_add(lbib_handle h, const lbib_particle_desc* d, int32_
         if (!d || !pid) return fail(h, LBIB_E_INVALID, "lbib_particle_add: NULL argument");
         if (h->state != 0) return fail(h, LBIB_E_STATE, "lbib_particle_add: must precede lbib_init");
         if (!h->parts.empty()) return fail(h, LBIB_E_UNSUPPORTED, "lbib_particle_add: one particle per simulation");
-        if (d->shape != 0 && d->shape != 1) return fail(h, LBIB_E_INVALID, "lbib_particle_add: shape must be 0 or 1");
-        const double a = d->a_major, b = d->shape == 0 ? d->a_major : d->b_minor;
-        if (!is_finite(a) || !is_finite(b) || !(a > 0) || !(b > 0))
-            return fail(h, LBIB_E_INVALID, "lbib_particle_add: semi-axes must be positive");
-        if (!is_finite(d->xc) || !is_finite(d->yc) || !is_finite(d->theta0))
-            return fail(h, LBIB_E_INVALID, "lbib_particle_add: non-finite position");
-        if (!is_finite(d->rho_p) || !(d->rho_p > 0)) return fail(h, LBIB_E_INVALID, "lbib_particle_add: rho_p must be > 0");
-        if (d->n_markers < 8 || d->n_markers > kMaxMarkers)
-            return fail(h, LBIB_E_INVALID, "lbib_particle_add: n_markers must be in [8, 1024]");
-        const double amax = std::max(a, b);
-        if (2.0 * amax + 6.0 > h->desc.nx)
-            return fail(h, LBIB_E_INVALID, "lbib_particle_add: particle too wide for the channel (2a + 6 > nx)");
-        const double hs = support_h(a, b, d->theta0);
-        if (!(d->yc - hs + 0.5 > 0.0) || !(d->yc + hs < h->desc.ny - 0.5))
-            return fail(h, LBIB_E_INVALID, "lbib_particle_add: particle must lie inside the channel with a positive gap");
         Particle p;
-        p.desc = *d;
-        p.nl = d->n_markers;
-        p.a = a;
-        p.b = b;
-        if (!build_surface(d->shape, a, b, p.nl, p.surf))
-            return fail(h, LBIB_E_INVALID, "lbib_particle_add: surface construction failed");
-        if (p.surf.perimeter / p.nl < 0.25)
-            return fail(h, LBIB_E_INVALID, "lbib_particle_add: marker spacing below 0.25 lattice units");
-        p.mass = d->rho_p * M_PI * a * b;
-        p.inertia = p.mass * (a * a + b * b) / 4.0;
-        // every marker lies within amax of the centroid and every probe within amax + 1.2;
-        // an MLS support reaches 1.5 further, so any orientation's box has at most
-        // ceil(2 amax + 2.4) + 4 nodes per side (one more kept as margin)
-        const int side = (int)std::ceil(2.0 * amax + 2.4) + 5;
-        p.box_cap = side * side;
+        std::string msg;
+        const lbib_status v = prepare_particle(h->desc, *d, p, msg);
+        if (v != LBIB_OK) return fail(h, v, "lbib_particle_add: " + msg);
         h->parts.push_back(std::move(p));
         *pid = (int32_t)h->parts.size() - 1;
         return LBIB_OK;
@@ -487,22 +313,14 @@ lbib_status lbib_ligands_set(lbib_handle h, int32_t pid, const lbib_ligand_desc*
     if (h->state != 0) return fail(h, LBIB_E_STATE, "lbib_ligands_set: must precede lbib_init");
     Particle* p = get_particle(h, pid);
     if (!p) return fail(h, LBIB_E_INVALID, "lbib_ligands_set: unknown particle id");
-    if (d->rho_l_den <= 0 || d->rho_l_num < 0 || d->rho_l_num > d->rho_l_den)
-        return fail(h, LBIB_E_INVALID, "lbib_ligands_set: ligand density must be a fraction in [0, 1]");
-    const double v[] = {d->sigma_hat, d->sigma_star_ratio, d->y_cr_hat, d->y_eq_ratio,
-                        d->k_f,       d->k_r0,             d->kbt_hat,  d->hamaker_hat};
-    for (double x : v)
-        if (!is_finite(x)) return fail(h, LBIB_E_INVALID, "lbib_ligands_set: non-finite parameter");
-    if (d->sigma_hat < 0 || d->y_cr_hat < 0 || d->y_eq_ratio < 0 || d->k_f < 0 || d->k_r0 < 0 || d->hamaker_hat < 0)
-        return fail(h, LBIB_E_INVALID, "lbib_ligands_set: negative rate, length or constant");
-    if (!(d->kbt_hat > 0)) return fail(h, LBIB_E_INVALID, "lbib_ligands_set: kbt_hat must be > 0");
+    std::string msg;
+    const lbib_status v = check_ligands(*d, msg);
+    if (v != LBIB_OK) return fail(h, v, "lbib_ligands_set: " + msg);
     try {
-        p->ligand = ligand_layout(p->nl, d->rho_l_num, d->rho_l_den);
+        set_ligands(*p, *d);
     } catch (const std::bad_alloc&) {
         return fail(h, LBIB_E_NOMEM, "lbib_ligands_set: host allocation failed");
     }
-    p->lig = *d;
-    p->has_ligands = true;
     return LBIB_OK;
 }
 
@@ -522,8 +340,7 @@ lbib_status lbib_init(lbib_handle h)
     if (h->state != 0) return fail(h, LBIB_E_STATE, "lbib_init: already initialised");
     for (auto& p : h->parts)
         if (!p.has_ligands) return fail(h, LBIB_E_STATE, "lbib_init: lbib_ligands_set missing for a particle");
-    const int nx = h->desc.nx, ny = h->desc.ny;
-    const size_t bytes = (size_t)9 * h->plane * h->elem;
+    const size_t bytes = (size_t)9 * h->g.plane * h->g.elem;
     hipError_t e;
     if ((e = hipMalloc(&h->fA, bytes)) != hipSuccess || (e = hipMalloc(&h->fB, bytes)) != hipSuccess ||
         (e = dalloc(&h->d_flags, 1)) != hipSuccess) {
@@ -532,14 +349,7 @@ lbib_status lbib_init(lbib_handle h)
                     std::string("lbib_init: device allocation: ") + hipGetErrorString(e));
     }
     for (auto& p : h->parts) {
-        const int nl = p.nl;
-        const size_t tile = (size_t)2 * p.box_cap;
-        const size_t boxg = particle_lds_bytes(p.box_cap) ? 0 : (size_t)6 * p.box_cap;
-        if ((e = dalloc(&p.d_xi, 2 * nl)) != hipSuccess || (e = dalloc(&p.d_nuv, 2 * nl)) != hipSuccess ||
-            (e = dalloc(&p.d_S, nl)) != hipSuccess || (e = dalloc(&p.d_lig, nl)) != hipSuccess ||
-            (e = dalloc(&p.d_bond, nl)) != hipSuccess || (e = dalloc(&p.d_tile, tile)) != hipSuccess ||
-            (boxg && (e = dalloc(&p.d_box, boxg)) != hipSuccess) || (e = dalloc(&p.d_zone, 2)) != hipSuccess || (e = dalloc(&p.d_desc, 1)) != hipSuccess ||
-            (e = dalloc(&p.d_st, 1)) != hipSuccess) {
+        if ((e = alloc_particle(p)) != hipSuccess) {
             free_all(h);
             return fail(h, e == hipErrorOutOfMemory ? LBIB_E_NOMEM : LBIB_E_DEVICE,
                         std::string("lbib_init: device allocation: ") + hipGetErrorString(e));
@@ -549,38 +359,12 @@ lbib_status lbib_init(lbib_handle h)
         free_all(h);
         return hip_fail(h, err, what);
     };
-    if ((e = hipMemsetAsync(h->fA, 0, bytes, h->stream)) != hipSuccess) return bail(e, "hipMemset");
     if ((e = hipMemsetAsync(h->fB, 0, bytes, h->stream)) != hipSuccess) return bail(e, "hipMemset");
     if ((e = hipMemsetAsync(h->d_flags, 0, sizeof(int32_t), h->stream)) != hipSuccess) return bail(e, "hipMemset");
-    if (h->elem == 8)
-        e = launch_init<double>((double*)h->fA, nx, ny, h->pitch, h->plane, h->umax, h->stream);
-    else
-        e = launch_init<float>((float*)h->fA, nx, ny, h->pitch, h->plane, h->umax, h->stream);
-    if (e != hipSuccess) return bail(e, "init kernel");
-    for (auto& p : h->parts) {
-        const int nl = p.nl;
-        std::vector<uint8_t> zeros(nl, 0);
-        DevParticle st{};
-        st.xc = st.xc1 = p.desc.xc;
-        st.yc = st.yc1 = p.desc.yc;
-        st.th = st.th1 = p.desc.theta0;
-        st.step = 0;
-        st.last.step = -1;
-        st.last.xc = st.xc;
-        st.last.yc = st.yc;
-        st.last.theta = st.th;
-        st.last.gap = st.yc + 0.5 - support_h(p.a, p.b, st.th);
-        TileDesc td[2] = {};
-        if ((e = hipMemcpy(p.d_zone, td, sizeof(td), hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = hipMemcpy(p.d_xi, p.surf.xi.data(), 2 * nl * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = hipMemcpy(p.d_nuv, p.surf.nu.data(), 2 * nl * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = hipMemcpy(p.d_S, p.surf.S.data(), nl * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = hipMemcpy(p.d_lig, p.ligand.data(), nl, hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = hipMemcpy(p.d_bond, zeros.data(), nl, hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = hipMemcpy(p.d_st, &st, sizeof(st), hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = hipMemcpy(p.d_desc, td, sizeof(TileDesc), hipMemcpyHostToDevice)) != hipSuccess)
-            return bail(e, "lbib_init: upload");
-    }
+    if ((e = init_populations(h->fA, h->g, h->stream)) != hipSuccess) return bail(e, "init kernel");
+    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return bail(e, "lbib_init: sync");
+    for (auto& p : h->parts)
+        if ((e = upload_particle(p)) != hipSuccess) return bail(e, "lbib_init: upload");
     if ((e = hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking)) != hipSuccess)
         return bail(e, "lbib_init: second stream");
     if ((e = hipEventCreateWithFlags(&h->evA, hipEventDisableTiming)) != hipSuccess ||
@@ -599,7 +383,7 @@ lbib_status lbib_step(lbib_handle h, int64_t n)
     if (n < 0) return fail(h, LBIB_E_INVALID, "lbib_step: negative step count");
     if (h->state == 0) return fail(h, LBIB_E_STATE, "lbib_step: lbib_init first");
     if (h->state == 2) return fail(h, LBIB_E_STATE, "lbib_step: simulation failed; lbib_load a good state");
-    if (h->elem == 8) return enqueue_steps<double>(h, n);
+    if (h->g.elem == 8) return enqueue_steps<double>(h, n);
     return enqueue_steps<float>(h, n);
 }
 
@@ -677,29 +461,14 @@ lbib_status lbib_read_field(lbib_handle h, int32_t which, double* out, int64_t c
     if (!out) return fail(h, LBIB_E_INVALID, "lbib_read_field: NULL output");
     if (which < 0 || which > 3) return fail(h, LBIB_E_INVALID, "lbib_read_field: which must be 0..3");
     if (h->state == 0) return fail(h, LBIB_E_STATE, "lbib_read_field: lbib_init first");
-    const int nx = h->desc.nx, ny = h->desc.ny;
-    const int64_t need = (which == 3 ? 9 : 1) * (int64_t)nx * ny;
+    const int64_t need = (which == 3 ? 9 : 1) * (int64_t)h->desc.nx * h->desc.ny;
     if (capacity < need) return fail(h, LBIB_E_INVALID, "lbib_read_field: capacity must be >= " + std::to_string(need));
     try {
         HIPCHK(h, hipStreamSynchronize(h->stream));
         std::vector<double> f;
         lbib_status s = download_f(h, f);
         if (s != LBIB_OK) return s;
-        if (which == 3) {
-            std::memcpy(out, f.data(), f.size() * sizeof(double));
-        } else {
-            const size_t N = (size_t)nx * ny;
-            for (size_t c = 0; c < N; ++c) {
-                double r = 0, jx = 0, jy = 0;
-                for (int q = 0; q < 9; ++q) {
-                    const double v = f[q * N + c];
-                    r += v;
-                    jx += v * kExq[q];
-                    jy += v * kEyq[q];
-                }
-                out[c] = which == 0 ? r : which == 1 ? (jx + 0.5 * h->gx) / r : (jy + 0.5 * h->gy) / r;
-            }
-        }
+        field_from_populations(f, h->g, which, out);
     } catch (const std::bad_alloc&) {
         return fail(h, LBIB_E_NOMEM, "lbib_read_field: host allocation failed");
     }
@@ -711,28 +480,11 @@ lbib_status lbib_write_populations(lbib_handle h, const double* f, int64_t count
     if (!h) return fail(nullptr, LBIB_E_INVALID, "lbib_write_populations: NULL handle");
     if (!f) return fail(h, LBIB_E_INVALID, "lbib_write_populations: NULL input");
     if (h->state == 0) return fail(h, LBIB_E_STATE, "lbib_write_populations: lbib_init first");
-    const int nx = h->desc.nx, ny = h->desc.ny;
-    if (count != (int64_t)9 * nx * ny)
+    if (count != (int64_t)9 * h->desc.nx * h->desc.ny)
         return fail(h, LBIB_E_INVALID, "lbib_write_populations: count must be 9 nx ny");
     try {
-        const size_t n = (size_t)9 * h->plane;
         HIPCHK(h, hipStreamSynchronize(h->stream));
-        if (h->elem == 8) {
-            std::vector<double> raw(n, 0.0);
-            for (int q = 0; q < 9; ++q)
-                for (int j = 0; j < ny; ++j)
-                    for (int i = 0; i < nx; ++i)
-                        raw[q * h->plane + (size_t)j * h->pitch + i] = f[((size_t)q * ny + j) * nx + i] - kWq[q];
-            HIPCHK(h, hipMemcpy(h->fA, raw.data(), n * 8, hipMemcpyHostToDevice));
-        } else {
-            std::vector<float> raw(n, 0.0f);
-            for (int q = 0; q < 9; ++q)
-                for (int j = 0; j < ny; ++j)
-                    for (int i = 0; i < nx; ++i)
-                        raw[q * h->plane + (size_t)j * h->pitch + i] =
-                            (float)(f[((size_t)q * ny + j) * nx + i] - kWq[q]);
-            HIPCHK(h, hipMemcpy(h->fA, raw.data(), n * 4, hipMemcpyHostToDevice));
-        }
+        HIPCHK(h, upload_populations(h->fA, h->g, f));
     } catch (const std::bad_alloc&) {
         return fail(h, LBIB_E_NOMEM, "lbib_write_populations: host allocation failed");
     }
@@ -838,7 +590,7 @@ lbib_status lbib_save(lbib_handle h, void* blob, int64_t* size)
     hd.n_particles = (int32_t)h->parts.size();
     hd.nl = h->parts.empty() ? 0 : h->parts[0].nl;
     hd.steps = h->steps;
-    hd.pop_bytes = (int64_t)9 * h->plane * (int64_t)h->elem;
+    hd.pop_bytes = (int64_t)9 * h->g.plane * (int64_t)h->g.elem;
     std::memcpy(w, &hd, sizeof(hd));
     w += sizeof(hd);
     HIPCHK(h, hipMemcpy(w, h->fA, (size_t)hd.pop_bytes, hipMemcpyDeviceToHost));
@@ -863,7 +615,7 @@ lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size)
     std::memcpy(&hd, blob, sizeof(hd));
     if (std::memcmp(hd.magic, "LBIBCKP1", 8) != 0 || hd.version != LBIB_ABI_VERSION || hd.nx != h->desc.nx ||
         hd.ny != h->desc.ny || hd.precision != h->desc.precision || hd.n_particles != (int32_t)h->parts.size() ||
-        (hd.n_particles && hd.nl != h->parts[0].nl) || hd.pop_bytes != (int64_t)9 * h->plane * (int64_t)h->elem)
+        (hd.n_particles && hd.nl != h->parts[0].nl) || hd.pop_bytes != (int64_t)9 * h->g.plane * (int64_t)h->g.elem)
         return fail(h, LBIB_E_INVALID, "lbib_load: checkpoint was made with different descriptors");
     const char* r = (const char*)blob + sizeof(hd);
     HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -933,7 +685,7 @@ lbib_status lbib_set_overlap(lbib_handle h, int32_t mode)
 lbib_status lbib_bytes_per_update(lbib_handle h, int64_t* bytes)
 {
     if (!h || !bytes) return fail(h, LBIB_E_INVALID, "lbib_bytes_per_update: NULL argument");
-    *bytes = (int64_t)(18 * h->elem);
+    *bytes = (int64_t)(18 * h->g.elem);
     return LBIB_OK;
 }
 

@@ -175,6 +175,53 @@ __global__ __launch_bounds__(256) void sweep_box_kernel(const T* __restrict__ fi
     collide_push<T>(fin, fout, a, i, j, a.gx + ldexp((double)t[0], -d.scale), a.gy + ldexp((double)t[1], -d.scale));
 }
 
+// Sweep of a pool of independent simulations in one launch.  Block b covers tile table[b].y
+// (64 x 4 nodes) of simulation table[b].x; the table lists each simulation's tiles
+// contiguously, so after the XCD remap a simulation's tiles share one XCD's L2.  The
+// particle phase that precedes it has advanced the member to step n + 1 (did_step set) or
+// left it idle (did_step clear, nothing to do here); step n reads fA for even n.
+template <typename T>
+__global__ __launch_bounds__(256) void pool_sweep_kernel(const PoolSweep<T>* __restrict__ sims,
+                                                         const int2* __restrict__ table, int nblocks)
+{
+    int b = blockIdx.x;
+    {
+        const int q = nblocks >> 3, r = nblocks & 7, x = b & 7, k = b >> 3;
+        b = (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+    }
+    const int2 e = table[b];
+    const PoolSweep<T>& ps = sims[e.x];
+    const DevParticle* st = ps.st;
+    if (!st->did_step) return;
+    const bool odd = ((st->step - 1) & 1) != 0;
+    const T* fin = odd ? ps.fB : ps.fA;
+    T* fout = odd ? ps.fA : ps.fB;
+    const SweepArgs a = ps.a;
+    const int i = (e.y % ps.gx) * 64 + (int)(threadIdx.x & 63);
+    const int j = (e.y / ps.gx) * 4 + (int)(threadIdx.x >> 6);
+    if (i >= a.nx || j >= a.ny) return;
+    double Fx = a.gx, Fy = a.gy;
+    const TileDesc d = *ps.desc;
+    if (d.active && in_box(d, i, j, a.nx)) {
+        int di = i - d.i0w;
+        if (di < 0) di += a.nx;
+        const int64_t* t = ps.tile + 2 * ((size_t)(j - d.j0) * d.w + di);
+        Fx += ldexp((double)t[0], -d.scale);
+        Fy += ldexp((double)t[1], -d.scale);
+    }
+    collide_push<T>(fin, fout, a, i, j, Fx, Fy);
+}
+
+template <typename T>
+hipError_t launch_pool_sweep(const PoolSweep<T>* sims, const int2* table, int32_t n_blocks, hipStream_t stream,
+                             hipEvent_t t0, hipEvent_t t1)
+{
+    if (n_blocks <= 0) return hipSuccess;
+    hipExtLaunchKernelGGL(pool_sweep_kernel<T>, dim3(n_blocks), dim3(256), 0u, stream, t0, t1, 0u, sims, table,
+                          n_blocks);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_sweep(const T* fin, T* fout, const SweepArgs& a, int mode, const TileDesc* desc,
                         const int64_t* tile, int32_t box_cap, hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
@@ -200,5 +247,9 @@ template hipError_t launch_sweep<float>(const float*, float*, const SweepArgs&, 
                                         int32_t, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_sweep<double>(const double*, double*, const SweepArgs&, int, const TileDesc*,
                                          const int64_t*, int32_t, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_pool_sweep<float>(const PoolSweep<float>*, const int2*, int32_t, hipStream_t, hipEvent_t,
+                                             hipEvent_t);
+template hipError_t launch_pool_sweep<double>(const PoolSweep<double>*, const int2*, int32_t, hipStream_t, hipEvent_t,
+                                              hipEvent_t);
 
 }  // namespace lbib

@@ -15,10 +15,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "liblbib.so")
 
-OK, E_INVALID, E_STATE, E_NOMEM, E_DEVICE, E_NUMERIC, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+OK, E_INVALID, E_STATE, E_NOMEM, E_DEVICE, E_NUMERIC, E_UNSUPPORTED, E_FULL = 0, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_STATE", -3: "E_NOMEM", -4: "E_DEVICE", -5: "E_NUMERIC",
-                -6: "E_UNSUPPORTED"}
+                -6: "E_UNSUPPORTED", -7: "E_FULL"}
 FP64, FP32 = 0, 1
+POOL_RUNNING, POOL_FINISHED, POOL_FAILED = 0, 1, 2
 
 
 class LbibError(RuntimeError):
@@ -94,6 +95,24 @@ _SIGS = {
     "lbib_kernel_bonds": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, C.c_int32, C.c_int32, _D, C.c_uint64,
                                     C.c_uint32, _P]),
     "lbib_bandwidth_probe": (C.c_int, [C.c_int64, C.c_int32, _P, _D]),
+    "lbib_pool_create": (C.c_int, [C.c_int32, C.c_int64, C.c_int32, _P, C.POINTER(_P)]),
+    "lbib_pool_footprint": (C.c_int, [C.POINTER(LatticeDesc), C.POINTER(ParticleDesc), _I64]),
+    "lbib_pool_add": (C.c_int, [_P, C.POINTER(LatticeDesc), C.POINTER(ParticleDesc), C.POINTER(LigandDesc),
+                                C.c_int64, C.POINTER(C.c_int32)]),
+    "lbib_pool_step": (C.c_int, [_P, C.c_int64]),
+    "lbib_pool_poll": (C.c_int, [_P, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)]),
+    "lbib_pool_status": (C.c_int, [_P, C.c_int32, _I64, C.POINTER(C.c_int32)]),
+    "lbib_pool_read_particle": (C.c_int, [_P, C.c_int32, C.POINTER(ParticleState)]),
+    "lbib_pool_read_bonds": (C.c_int, [_P, C.c_int32, _U8, _U8, C.c_int32]),
+    "lbib_pool_read_field": (C.c_int, [_P, C.c_int32, C.c_int32, _D, C.c_int64]),
+    "lbib_pool_trace_enable": (C.c_int, [_P, C.c_int32, C.c_int64]),
+    "lbib_pool_read_trace": (C.c_int, [_P, C.c_int32, C.POINTER(ParticleState), C.c_int64, _I64]),
+    "lbib_pool_remove": (C.c_int, [_P, C.c_int32]),
+    "lbib_pool_usage": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _I64]),
+    "lbib_pool_kernel_timing": (C.c_int, [_P, C.c_int32]),
+    "lbib_pool_kernel_time": (C.c_int, [_P, C.c_int32, _D, _I64]),
+    "lbib_pool_last_error": (C.c_char_p, [_P]),
+    "lbib_pool_destroy": (None, [_P]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -115,9 +134,9 @@ def lib():
     return _lib
 
 
-def _check(status: int, handle=None):
+def _check(status: int, handle=None, pool: bool = False):
     if status != OK:
-        msg = lib().lbib_last_error(handle)
+        msg = (lib().lbib_pool_last_error if pool else lib().lbib_last_error)(handle)
         raise LbibError(status, msg.decode() if msg else "")
 
 
@@ -130,6 +149,27 @@ def _stream_ptr(stream):
 def _ptr(t):
     """Device pointer of a torch tensor."""
     return C.c_void_p(t.data_ptr())
+
+
+def _lattice_desc(lat: dict) -> LatticeDesc:
+    return LatticeDesc(int(lat["nx"]), int(lat["ny"]), float(lat["tau"]), float(lat["re"]), int(lat.get("drive", 0)),
+                       int(lat.get("precision", FP64)), int(lat.get("seed", 0)))
+
+
+def _particle_desc(part: dict) -> ParticleDesc:
+    return ParticleDesc(int(part["shape"]), float(part["a_major"]), float(part["b_minor"]), float(part["xc"]),
+                        float(part["yc"]), float(part["theta0"]), float(part["rho_p"]), int(part["n_markers"]))
+
+
+def _ligand_desc(g: dict) -> LigandDesc:
+    return LigandDesc(int(g["rho_l_num"]), int(g["rho_l_den"]), float(g["sigma_hat"]), float(g["sigma_star_ratio"]),
+                      float(g["y_cr_hat"]), float(g["y_eq_ratio"]), float(g["k_f"]), float(g["k_r0"]),
+                      float(g["kbt_hat"]), float(g["hamaker_hat"]))
+
+
+def _trace_array(buf, count: int) -> np.ndarray:
+    return np.array([[float(getattr(buf[k], n)) for n in STATE_FIELDS] for k in range(count)]).reshape(
+        count, len(STATE_FIELDS))
 
 
 # ----------------------------------------------------------------------------------------
@@ -145,8 +185,7 @@ class Sim:
         self.workload = workload
         self.nx, self.ny = int(lat["nx"]), int(lat["ny"])
         self.precision = int(lat.get("precision", FP64))
-        d = LatticeDesc(self.nx, self.ny, float(lat["tau"]), float(lat["re"]), int(lat.get("drive", 0)),
-                        self.precision, int(lat.get("seed", 0)))
+        d = _lattice_desc(lat)
         self._h = C.c_void_p()
         self.stream = stream
         _check(L.lbib_create(C.byref(d), _stream_ptr(stream), C.byref(self._h)))
@@ -154,16 +193,11 @@ class Sim:
         try:
             part = workload.get("particle")
             if part is not None:
-                pd = ParticleDesc(int(part["shape"]), float(part["a_major"]), float(part["b_minor"]),
-                                  float(part["xc"]), float(part["yc"]), float(part["theta0"]),
-                                  float(part["rho_p"]), int(part["n_markers"]))
+                pd = _particle_desc(part)
                 pid = C.c_int32()
                 self._call(L.lbib_particle_add, C.byref(pd), C.byref(pid))
                 self.nl = int(part["n_markers"])
-                g = workload["ligand"]
-                ld = LigandDesc(int(g["rho_l_num"]), int(g["rho_l_den"]), float(g["sigma_hat"]),
-                                float(g["sigma_star_ratio"]), float(g["y_cr_hat"]), float(g["y_eq_ratio"]),
-                                float(g["k_f"]), float(g["k_r0"]), float(g["kbt_hat"]), float(g["hamaker_hat"]))
+                ld = _ligand_desc(workload["ligand"])
                 self._call(L.lbib_ligands_set, 0, C.byref(ld))
                 r = workload.get("receptor", {"wall": 0, "density": 1.0})
                 rd = ReceptorDesc(int(r["wall"]), float(r["density"]))
@@ -271,8 +305,7 @@ class Sim:
         buf = (ParticleState * max(1, capacity))()
         cnt = C.c_int64()
         self._call(lib().lbib_read_trace, pid, buf, int(capacity), C.byref(cnt))
-        return np.array([[float(getattr(buf[k], n)) for n in STATE_FIELDS] for k in range(cnt.value)]).reshape(
-            cnt.value, len(STATE_FIELDS))
+        return _trace_array(buf, cnt.value)
 
     # -- checkpoints ---------------------------------------------------------------------
     def save(self) -> bytes:
@@ -300,6 +333,127 @@ class Sim:
         ms = C.c_double()
         n = C.c_int64()
         self._call(lib().lbib_kernel_time, int(kernel), C.byref(ms), C.byref(n))
+        return ms.value, n.value
+
+
+# ----------------------------------------------------------------------------------------
+# Pool of simulations stepped together
+# ----------------------------------------------------------------------------------------
+
+class Pool:
+    """Many independent simulations (one particle each) stepped with one particle-phase launch
+    and one sweep launch per time step.  Members join with add() and leave with remove()."""
+
+    def __init__(self, precision: int = FP32, budget_bytes: int = 64 << 30, max_members: int = 4096, stream=None):
+        self._h = C.c_void_p()
+        self.stream = stream
+        self.precision = int(precision)
+        self._shape = {}
+        _check(lib().lbib_pool_create(self.precision, int(budget_bytes), int(max_members), _stream_ptr(stream),
+                                      C.byref(self._h)), None, pool=True)
+
+    def _call(self, fn, *args):
+        _check(fn(self._h, *args), self._h, pool=True)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().lbib_pool_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @staticmethod
+    def footprint(workload: dict) -> int:
+        v = C.c_int64()
+        _check(lib().lbib_pool_footprint(C.byref(_lattice_desc(workload["lattice"])),
+                                         C.byref(_particle_desc(workload["particle"])), C.byref(v)), None, pool=True)
+        return v.value
+
+    def add(self, workload: dict, n_steps: int) -> int:
+        """Add a simulation (lattice + particle + ligands) to run n_steps steps; returns its slot."""
+        lat, part = workload["lattice"], workload["particle"]
+        slot = C.c_int32()
+        self._call(lib().lbib_pool_add, C.byref(_lattice_desc(lat)), C.byref(_particle_desc(part)),
+                   C.byref(_ligand_desc(workload["ligand"])), int(n_steps), C.byref(slot))
+        self._shape[slot.value] = (int(lat["nx"]), int(lat["ny"]), int(part["n_markers"]))
+        return slot.value
+
+    def remove(self, slot: int):
+        self._call(lib().lbib_pool_remove, int(slot))
+        self._shape.pop(slot, None)
+
+    def step(self, n: int = 1):
+        self._call(lib().lbib_pool_step, int(n))
+
+    def poll(self, capacity: int = 65536) -> list:
+        """Wait for the enqueued steps; slots that finished or failed since the last poll."""
+        buf = (C.c_int32 * max(1, capacity))()
+        cnt = C.c_int32()
+        self._call(lib().lbib_pool_poll, buf, int(capacity), C.byref(cnt))
+        return [buf[k] for k in range(cnt.value)]
+
+    def status(self, slot: int):
+        """(steps done, state) with state POOL_RUNNING / POOL_FINISHED / POOL_FAILED."""
+        n = C.c_int64()
+        st = C.c_int32()
+        self._call(lib().lbib_pool_status, int(slot), C.byref(n), C.byref(st))
+        return n.value, st.value
+
+    def last_error(self) -> str:
+        m = lib().lbib_pool_last_error(self._h)
+        return m.decode() if m else ""
+
+    def usage(self):
+        """(members, running, bytes in use)."""
+        m, r, b = C.c_int32(), C.c_int32(), C.c_int64()
+        self._call(lib().lbib_pool_usage, C.byref(m), C.byref(r), C.byref(b))
+        return m.value, r.value, b.value
+
+    def particle(self, slot: int) -> dict:
+        s = ParticleState()
+        self._call(lib().lbib_pool_read_particle, int(slot), C.byref(s))
+        return {n: getattr(s, n) for n in STATE_FIELDS}
+
+    def bonds(self, slot: int):
+        nl = self._shape[slot][2]
+        b = np.zeros(nl, np.uint8)
+        lg = np.zeros(nl, np.uint8)
+        self._call(lib().lbib_pool_read_bonds, int(slot), b.ctypes.data_as(_U8), lg.ctypes.data_as(_U8), nl)
+        return b, lg
+
+    def field(self, slot: int, which: int) -> np.ndarray:
+        nx, ny, _ = self._shape[slot]
+        out = np.zeros((9, ny, nx) if which == 3 else (ny, nx))
+        self._call(lib().lbib_pool_read_field, int(slot), int(which), out.ctypes.data_as(_D), out.size)
+        return out
+
+    def trace_enable(self, slot: int, capacity: int):
+        self._call(lib().lbib_pool_trace_enable, int(slot), int(capacity))
+
+    def trace(self, slot: int, capacity: int) -> np.ndarray:
+        buf = (ParticleState * max(1, capacity))()
+        cnt = C.c_int64()
+        self._call(lib().lbib_pool_read_trace, int(slot), buf, int(capacity), C.byref(cnt))
+        return _trace_array(buf, cnt.value)
+
+    def kernel_timing(self, enable: bool):
+        self._call(lib().lbib_pool_kernel_timing, 1 if enable else 0)
+
+    def kernel_time(self, kernel: int):
+        """(total milliseconds, launches) of kernel 0 (pool sweep) or 1 (pool particle phase)."""
+        ms = C.c_double()
+        n = C.c_int64()
+        self._call(lib().lbib_pool_kernel_time, int(kernel), C.byref(ms), C.byref(n))
         return ms.value, n.value
 
 

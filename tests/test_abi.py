@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_abi_version(L):
-    assert L.lbib_abi_version() == 1
+    assert L.lbib_abi_version() == 2
 
 
 def test_struct_layout_matches_c(tmp_path):
@@ -147,3 +147,40 @@ def test_kernel_entry_points_validate_sizes(L):
     assert L.lbib_kernel_bonds(None, None, None, None, None, None, None, 0, 1, p, 0, 0, None) == lbib.E_INVALID
     v = C.c_double()
     assert L.lbib_bandwidth_probe(17, 1, None, C.byref(v)) == lbib.E_INVALID
+
+
+def test_pool_host_validation(L):
+    h = C.c_void_p()
+    assert L.lbib_pool_create(2, 1 << 30, 16, FAKE_STREAM, C.byref(h)) == lbib.E_UNSUPPORTED
+    assert L.lbib_pool_create(1, 0, 16, FAKE_STREAM, C.byref(h)) == lbib.E_INVALID
+    assert L.lbib_pool_create(1, 1 << 30, 0, FAKE_STREAM, C.byref(h)) == lbib.E_INVALID
+    assert L.lbib_pool_create(1, 1 << 30, 70000, FAKE_STREAM, C.byref(h)) == lbib.E_INVALID
+    assert L.lbib_pool_last_error(None)
+    assert h.value is None
+    assert L.lbib_pool_step(None, 1) == lbib.E_INVALID
+    n = C.c_int32()
+    assert L.lbib_pool_poll(None, None, 0, C.byref(n)) == lbib.E_INVALID
+    assert L.lbib_pool_remove(None, 0) == lbib.E_INVALID
+    L.lbib_pool_destroy(None)
+
+
+def test_pool_footprint(L):
+    """Two population buffers of 9 planes (rows padded to 256 bytes) plus the particle's
+    buffers; refused for descriptors lbib_create / lbib_particle_add would refuse."""
+    def fp(nx, ny, prec, **kw):
+        d = lbib.LatticeDesc(nx, ny, 0.8, 0.1, 0, prec, 0)
+        v = C.c_int64(-1)
+        st = L.lbib_pool_footprint(C.byref(d), C.byref(_pdesc(**kw)), C.byref(v))
+        return st, v.value
+
+    for nx, ny, prec, elem in [(64, 32, 1, 4), (100, 40, 1, 4), (100, 40, 0, 8), (1000, 300, 1, 4)]:
+        st, v = fp(nx, ny, prec)
+        assert st == lbib.OK
+        pitch = -(-nx * elem // 256) * 256 // elem
+        pop = 2 * 9 * pitch * ny * elem
+        assert pop < v < pop + 200_000, (nx, ny, prec, v - pop)
+    # more markers or a larger particle never cost less
+    assert fp(64, 32, 1, n_markers=64)[1] > fp(64, 32, 1)[1]
+    assert fp(200, 64, 1, a_major=20.0, yc=30.0)[1] > fp(200, 64, 1)[1]
+    assert fp(64, 32, 1, n_markers=7)[0] == lbib.E_INVALID
+    assert fp(3, 32, 1)[0] == lbib.E_INVALID
