@@ -70,6 +70,40 @@ def cpu_baseline(workload: dict, steps: int):
     }
 
 
+def batched_leg(steps: int, stream) -> dict:
+    """The 216-simulation parameter sweep (FP32): the pool against the plain loops."""
+    from paper_1808_01448_amd import lbib, measure
+    from paper_1808_01448_amd import workloads as W
+
+    ws = W.batched_sweep(0)
+    cells = sum(w["lattice"]["nx"] * w["lattice"]["ny"] for w in ws)
+    log(f"bench: batched sweep, {len(ws)} simulations, {cells / 1e6:.1f} M nodes, pool {steps} steps")
+    pool = measure.pool_throughput(ws, steps, 20, stream=stream, autotune=10)
+    log(f"bench: pool {pool['mlups']:.0f} MLUPS; plain loop")
+    seq = measure.plain_sequential(ws, steps, 5, stream=stream)
+    log(f"bench: plain sequential {seq['mlups']:.0f} MLUPS; plain concurrent")
+    conc = measure.plain_concurrent(ws, steps, 5)
+    log(f"bench: plain concurrent {conc['mlups']:.0f} MLUPS")
+    sweep_gbs = 72.0 * cells / (pool["sweep_avg_us"] * 1e-6) / 1e9
+    return {
+        "workload": "parameter sweep: 216 simulations (shape x ligand density x bond strength x Re x seed), "
+                    "grids nx U[512,2048] x ny U[128,256], FP32, tau 0.8",
+        "simulations": len(ws), "nodes": cells, "steps": steps, "unit": "MLUPS",
+        "pool": round(pool["mlups"], 1),
+        "plain_sequential": round(seq["mlups"], 1),
+        "plain_concurrent_streams": round(conc["mlups"], 1),
+        "speedup_vs_plain_sequential": round(pool["mlups"] / seq["mlups"], 3),
+        "speedup_vs_plain_concurrent": round(pool["mlups"] / conc["mlups"], 3),
+        "pool_ms_per_step": round(pool["ms_per_step"], 4),
+        "pool_config": dict(zip(("tile_x", "tiles_per_block", "graph_steps"), pool["config"])),
+        "pool_sweep_avg_us": round(pool["sweep_avg_us"], 2),
+        "pool_particle_avg_us": round(pool["particle_avg_us"], 2),
+        "pool_sweep_roofline": {"bound": "hbm", "achieved": round(sweep_gbs, 1), "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": round(sweep_gbs / HBM_PEAK_GBS, 4)},
+        "accuracy": "each pooled simulation bit-identical to its plain run",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +111,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=60, help="oracle steps of the CPU baseline (0: skip)")
     ap.add_argument("--no-timing-events", action="store_true", help="time only the whole steps")
+    ap.add_argument("--batched-steps", type=int, default=200,
+                    help="steps of the 216-simulation sweep, pooled and plain (0: skip)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -143,6 +179,10 @@ def main():
     p = sim.particle()
     sim.close()
 
+    batched = None
+    if args.batched_steps > 0:
+        batched = batched_leg(args.batched_steps, stream)
+
     cpu = None
     if args.cpu_steps > 0:
         log(f"bench: CPU oracle baseline, {args.cpu_steps} steps")
@@ -170,6 +210,7 @@ def main():
         "roofline": roofline,
         "copy_bandwidth_gbs": round(copy_gbs, 1),
         "cpu_baseline": cpu,
+        "batched": batched,
         "final_particle": {k: p[k] for k in ("step", "xc", "yc", "theta", "n_bonds")},
     }
     print(json.dumps(out), flush=True)

@@ -321,6 +321,21 @@ lbib_status lbib_pool_usage(lbib_pool_handle p, int32_t* members, int32_t* runni
 lbib_status lbib_pool_kernel_timing(lbib_pool_handle p, int32_t enable);
 lbib_status lbib_pool_kernel_time(lbib_pool_handle p, int32_t kernel, double* total_ms, int64_t* launches);
 
+/* Launch shape of the pool's lattice sweep: tiles of tile_x nodes (64, 128 or 256) by
+ * 256 / tile_x rows, tiles_per_block consecutive tiles (1, 2, 4 or 8) per workgroup, and,
+ * when graph_steps > 0, runs of graph_steps steps replayed as one captured HIP graph
+ * (graph_steps <= 4096; kernel timing, when on, uses direct launches).  Results do not
+ * depend on these choices.  The default is 64, 4, 0. */
+lbib_status lbib_pool_set_config(lbib_pool_handle p, int32_t tile_x, int32_t tiles_per_block, int32_t graph_steps);
+lbib_status lbib_pool_get_config(lbib_pool_handle p, int32_t* tile_x, int32_t* tiles_per_block, int32_t* graph_steps);
+
+/* Autotuner: times steps_per_trial pool steps (wall clock, after untimed warm-up steps)
+ * for each tile shape, then graph replay of the fastest, and keeps the fastest
+ * configuration; *best_step_us (may be NULL) receives its time per step.  The trials are
+ * ordinary steps of the running members: about 16 (steps_per_trial + 2) + 64 steps in
+ * total. */
+lbib_status lbib_pool_autotune(lbib_pool_handle p, int32_t steps_per_trial, double* best_step_us);
+
 /* Description of the last failure on this pool (NULL: of the last call with a NULL pool). */
 const char* lbib_pool_last_error(lbib_pool_handle p);
 

@@ -23,8 +23,7 @@ struct DevParticle {
     double xc, yc, th, ux, uy, om;        // level n
     double xc1, yc1, th1, ux1, uy1, om1;  // level n-1
     int64_t step;                         // n: the next step to run
-    int32_t did_step;                     // the last particle phase advanced the particle
-    int32_t pad0;
+    int32_t pad0, pad1;
     lbib_particle_state last;             // record of the last completed step
 };
 
@@ -103,8 +102,11 @@ hipError_t launch_particle(const ParticleArgs<T>& a, hipStream_t stream, hipEven
                            hipEvent_t t1 = nullptr);
 
 // A pool of independent simulations stepped together (one launch per kernel per step).
-// The sweep's blocks are listed in `table`: (simulation, tile) per block, tiles of 64 x 4
-// nodes; a block of a simulation whose particle phase did not step does nothing.
+// The particle launch runs member active[b] in workgroup b and writes ctl[member]: the
+// parity of the step it ran (its input buffer: 0 fA, 1 fB), or -1 when the member did not
+// step (target reached, or frozen by its watchdog).  The sweep's blocks are listed in
+// `table`: (member, first tile); a block sweeps up to TPB consecutive tiles of BX x 256/BX
+// nodes of that member.
 template <typename T>
 struct PoolSweep {
     SweepArgs a;
@@ -112,16 +114,21 @@ struct PoolSweep {
     T* fB;  // buffer of the odd steps
     const TileDesc* desc;
     const int64_t* tile;
-    const DevParticle* st;
-    int32_t gx;  // 64-node tiles along x
-    int32_t pad;
+    int32_t gx;      // tiles along x
+    int32_t ntiles;  // tiles of this member
+};
+// Sweep configurations a pool can use: tile width BX in {64, 128, 256} nodes (256/BX rows),
+// TPB in {1, 2, 4, 8} tiles per block.
+struct PoolSweepConfig {
+    int32_t bx, tpb;
 };
 template <typename T>
-hipError_t launch_pool_particle(const ParticleArgs<T>* args, const int32_t* active, int32_t n_active, int32_t max_nl,
-                                int32_t lds_cap, hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+hipError_t launch_pool_particle(const ParticleArgs<T>* args, const int32_t* active, int32_t* ctl, int32_t n_active,
+                                int32_t max_nl, int32_t lds_cap, hipStream_t stream, hipEvent_t t0 = nullptr,
+                                hipEvent_t t1 = nullptr);
 template <typename T>
-hipError_t launch_pool_sweep(const PoolSweep<T>* sims, const int2* table, int32_t n_blocks, hipStream_t stream,
-                             hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+hipError_t launch_pool_sweep(const PoolSweep<T>* sims, const int32_t* ctl, const int2* table, int32_t n_blocks,
+                             PoolSweepConfig cfg, hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
 hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n, hipStream_t stream);
 hipError_t launch_mls(const double* pts, int64_t n, int32_t nx, int32_t ny, int32_t* node, double* phi, double* psix,

@@ -525,7 +525,6 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, double*
         st->uy = nuy;
         st->om = nom;
         st->step = step + 1;
-        st->did_step = 1;
         lbib_particle_state rec;
         rec.step = step;
         rec.xc = nxc;
@@ -589,21 +588,23 @@ __global__ __launch_bounds__(PB) void particle_kernel(ParticleArgs<T> a)
     particle_phase<T, MPT, LDS>(a, lds_box);
 }
 
-// Particle phases of a pool of independent simulations: workgroup b runs simulation
-// active[b].  A simulation whose step counter has reached its target, or whose watchdog
-// has raised a flag, does nothing and clears its did_step flag (its sweep then does
-// nothing either), so a failed member stays frozen at the step that failed.  The
-// population buffer of step n is f for even n and fB for odd n.  Boxes up to lds_cap nodes
-// are staged in LDS, larger ones in their global scratch.
+// Particle phases of a pool of independent simulations: workgroup b runs member
+// k = active[b].  A member whose step counter has reached its target, or whose watchdog
+// has raised a flag, does nothing (ctl[k] = -1: its sweep does nothing either), so a
+// failed member stays frozen at the step that failed.  Otherwise ctl[k] receives the
+// parity of step n: its populations are f for even n and fB for odd n.  Boxes up to
+// lds_cap nodes are staged in LDS, larger ones in their global scratch.
 template <typename T, int MPT>
 __global__ __launch_bounds__(PB) void pool_particle_kernel(const ParticleArgs<T>* __restrict__ args,
-                                                           const int32_t* __restrict__ active, int32_t lds_cap)
+                                                           const int32_t* __restrict__ active,
+                                                           int32_t* __restrict__ ctl, int32_t lds_cap)
 {
     extern __shared__ double lds_box[];
-    ParticleArgs<T> a = args[active[blockIdx.x]];
+    const int k = active[blockIdx.x];
+    ParticleArgs<T> a = args[k];
     const int64_t n = a.st->step;
     if (n >= a.target_steps || *a.flags != 0) {
-        if (threadIdx.x == 0) a.st->did_step = 0;
+        if (threadIdx.x == 0) ctl[k] = -1;
         return;
     }
     a.f = (n & 1) ? a.fB : a.f;
@@ -611,11 +612,12 @@ __global__ __launch_bounds__(PB) void pool_particle_kernel(const ParticleArgs<T>
         particle_phase<T, MPT, true>(a, lds_box);
     else
         particle_phase<T, MPT, false>(a, lds_box);
+    if (threadIdx.x == 0) ctl[k] = (int32_t)(n & 1);
 }
 
 template <typename T>
-hipError_t launch_pool_particle(const ParticleArgs<T>* args, const int32_t* active, int32_t n_active, int32_t max_nl,
-                                int32_t lds_cap, hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
+hipError_t launch_pool_particle(const ParticleArgs<T>* args, const int32_t* active, int32_t* ctl, int32_t n_active,
+                                int32_t max_nl, int32_t lds_cap, hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
 {
     if (n_active <= 0) return hipSuccess;
     const size_t lds = (size_t)lds_cap * kBoxDoubles * 8;
@@ -628,8 +630,12 @@ hipError_t launch_pool_particle(const ParticleArgs<T>* args, const int32_t* acti
             if (e != hipSuccess) return e;                                                                             \
             attr[IDX] = true;                                                                                          \
         }                                                                                                              \
-        hipExtLaunchKernelGGL((pool_particle_kernel<T, M>), dim3(n_active), dim3(PB), (uint32_t)lds, stream, t0, t1, 0u, \
-                              args, active, lds_cap);                                                              \
+        if (t0 || t1)                                                                                                  \
+            hipExtLaunchKernelGGL((pool_particle_kernel<T, M>), dim3(n_active), dim3(PB), (uint32_t)lds, stream, t0, t1, \
+                                  0u, args, active, ctl, lds_cap);                                                     \
+        else                                                                                                           \
+            hipLaunchKernelGGL((pool_particle_kernel<T, M>), dim3(n_active), dim3(PB), lds, stream, args, active, ctl,   \
+                               lds_cap);                                                                               \
     } while (0)
     if (max_nl <= PB)
         LBIB_POOL_LAUNCH(1, 0);
@@ -781,10 +787,10 @@ hipError_t launch_copy(const float4* src, float4* dst, int64_t n, hipStream_t st
     return hipGetLastError();
 }
 
-template hipError_t launch_pool_particle<float>(const ParticleArgs<float>*, const int32_t*, int32_t, int32_t, int32_t,
-                                                hipStream_t, hipEvent_t, hipEvent_t);
-template hipError_t launch_pool_particle<double>(const ParticleArgs<double>*, const int32_t*, int32_t, int32_t, int32_t,
-                                                 hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_pool_particle<float>(const ParticleArgs<float>*, const int32_t*, int32_t*, int32_t, int32_t,
+                                                int32_t, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_pool_particle<double>(const ParticleArgs<double>*, const int32_t*, int32_t*, int32_t, int32_t,
+                                                 int32_t, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_particle<float>(const ParticleArgs<float>&, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_particle<double>(const ParticleArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
 

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -67,7 +68,13 @@ struct lbib_pool {
     size_t sims_cap = 0;
     int2* d_table = nullptr;
     size_t table_cap = 0;
+    int32_t* d_ctl = nullptr;
+    size_t ctl_cap = 0;
     int32_t n_active = 0, n_blocks = 0, max_nl = 0, lds_cap = 0;
+    PoolSweepConfig cfg{64, 4};
+    // optional replay of graph_steps steps as one HIP graph (rebuilt with the tables)
+    int32_t graph_steps = 0;
+    hipGraphExec_t graph = nullptr;
     int64_t pool_steps = 0;
     // kernel timing: kind 0 sweep, 1 particle phase
     bool timing = false;
@@ -162,11 +169,12 @@ lbib_status rebuild(lbib_pool* h)
         s.fB = (T*)m.fB;
         s.desc = m.p.d_desc;
         s.tile = m.p.d_tile;
-        s.st = m.p.d_st;
-        s.gx = (m.g.nx + 63) / 64;
-        const int32_t nt = s.gx * ((m.g.ny + 3) / 4);
-        if ((int64_t)table.size() + nt > 0x7fffffff) return fail(h, LBIB_E_INVALID, "pool: more than 2^31 tiles");
-        for (int32_t t = 0; t < nt; ++t) table.push_back(make_int2((int)k, t));
+        const int by = 256 / h->cfg.bx;
+        s.gx = (m.g.nx + h->cfg.bx - 1) / h->cfg.bx;
+        s.ntiles = s.gx * ((m.g.ny + by - 1) / by);
+        if ((int64_t)table.size() + s.ntiles / h->cfg.tpb + 1 > 0x7fffffff)
+            return fail(h, LBIB_E_INVALID, "pool: more than 2^31 sweep blocks");
+        for (int32_t t = 0; t < s.ntiles; t += h->cfg.tpb) table.push_back(make_int2((int)k, t));
     }
     hipError_t e = hipSuccess;
     ParticleArgs<T>* dargs = (ParticleArgs<T>*)h->d_args;
@@ -177,6 +185,7 @@ lbib_status rebuild(lbib_pool* h)
     ensure(dsims, h->sims_cap, sims.size(), e);
     h->d_sims = dsims;
     ensure(h->d_table, h->table_cap, table.size(), e);
+    ensure(h->d_ctl, h->ctl_cap, run.size(), e);
     if (e != hipSuccess) return hip_fail(h, e, "pool: table allocation");
     if (!run.empty()) {
         PCHK(h, hipMemcpy(h->d_args, args.data(), args.size() * sizeof(ParticleArgs<T>), hipMemcpyHostToDevice));
@@ -189,6 +198,8 @@ lbib_status rebuild(lbib_pool* h)
     h->max_nl = max_nl;
     h->lds_cap = lds_cap;
     h->dirty = false;
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
     return LBIB_OK;
 }
 
@@ -208,6 +219,38 @@ EvPair next_events(lbib_pool* h, int kind)
 }
 
 template <typename T>
+hipError_t launch_step(lbib_pool* h, EvPair e1, EvPair e0)
+{
+    hipError_t e = launch_pool_particle<T>((const ParticleArgs<T>*)h->d_args, h->d_active, h->d_ctl, h->n_active,
+                                           h->max_nl, h->lds_cap, h->stream, e1.t0, e1.t1);
+    if (e != hipSuccess) return e;
+    return launch_pool_sweep<T>((const PoolSweep<T>*)h->d_sims, h->d_ctl, h->d_table, h->n_blocks, h->cfg, h->stream,
+                                e0.t0, e0.t1);
+}
+
+// Capture graph_steps steps of direct launches into one executable graph.
+template <typename T>
+lbib_status build_graph(lbib_pool* h)
+{
+    hipGraph_t g = nullptr;
+    PCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int32_t k = 0; k < h->graph_steps && e == hipSuccess; ++k) e = launch_step<T>(h, EvPair{}, EvPair{});
+    hipError_t e2 = hipStreamEndCapture(h->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(h, e != hipSuccess ? e : e2, "pool: graph capture");
+    }
+    e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        h->graph = nullptr;
+        return hip_fail(h, e, "pool: graph instantiation");
+    }
+    return LBIB_OK;
+}
+
+template <typename T>
 lbib_status enqueue(lbib_pool* h, int64_t n)
 {
     if (h->dirty) {
@@ -216,15 +259,26 @@ lbib_status enqueue(lbib_pool* h, int64_t n)
         if (s != LBIB_OK) return s;
     }
     if (h->n_active == 0) return LBIB_OK;
-    for (int64_t k = 0; k < n; ++k) {
+    int64_t k = 0;
+    if (h->graph_steps > 0 && !h->timing && n >= h->graph_steps) {
+        if (!h->graph) {
+            lbib_status s = build_graph<T>(h);
+            if (s != LBIB_OK) return s;
+        }
+        for (; k + h->graph_steps <= n; k += h->graph_steps) PCHK(h, hipGraphLaunch(h->graph, h->stream));
+    }
+    for (; k < n; ++k) {
         const EvPair e1 = next_events(h, 1);
-        PCHK(h, launch_pool_particle<T>((const ParticleArgs<T>*)h->d_args, h->d_active, h->n_active, h->max_nl,
-                                        h->lds_cap, h->stream, e1.t0, e1.t1));
         const EvPair e0 = next_events(h, 0);
-        PCHK(h, launch_pool_sweep<T>((const PoolSweep<T>*)h->d_sims, h->d_table, h->n_blocks, h->stream, e0.t0, e0.t1));
+        PCHK(h, launch_step<T>(h, e1, e0));
     }
     h->pool_steps += n;
     return LBIB_OK;
+}
+
+bool valid_config(int32_t bx, int32_t tpb)
+{
+    return (bx == 64 || bx == 128 || bx == 256) && (tpb == 1 || tpb == 2 || tpb == 4 || tpb == 8);
 }
 
 Member* get_member(lbib_pool* h, int32_t slot)
@@ -591,6 +645,85 @@ lbib_status lbib_pool_kernel_time(lbib_pool_handle h, int32_t kernel, double* to
     return LBIB_OK;
 }
 
+lbib_status lbib_pool_set_config(lbib_pool_handle h, int32_t tile_x, int32_t tiles_per_block, int32_t graph_steps)
+{
+    if (!h) return fail(nullptr, LBIB_E_INVALID, "lbib_pool_set_config: NULL handle");
+    if (!valid_config(tile_x, tiles_per_block) || graph_steps < 0 || graph_steps > 4096)
+        return fail(h, LBIB_E_INVALID,
+                    "lbib_pool_set_config: tile_x in {64, 128, 256}, tiles_per_block in {1, 2, 4, 8}, "
+                    "graph_steps in [0, 4096]");
+    PCHK(h, hipStreamSynchronize(h->stream));
+    h->cfg = PoolSweepConfig{tile_x, tiles_per_block};
+    h->graph_steps = graph_steps;
+    h->dirty = true;
+    return LBIB_OK;
+}
+
+lbib_status lbib_pool_get_config(lbib_pool_handle h, int32_t* tile_x, int32_t* tiles_per_block, int32_t* graph_steps)
+{
+    if (!h || !tile_x || !tiles_per_block || !graph_steps)
+        return fail(h, LBIB_E_INVALID, "lbib_pool_get_config: NULL argument");
+    *tile_x = h->cfg.bx;
+    *tiles_per_block = h->cfg.tpb;
+    *graph_steps = h->graph_steps;
+    return LBIB_OK;
+}
+
+lbib_status lbib_pool_autotune(lbib_pool_handle h, int32_t steps_per_trial, double* best_step_us)
+{
+    if (!h) return fail(nullptr, LBIB_E_INVALID, "lbib_pool_autotune: NULL handle");
+    if (steps_per_trial < 1 || steps_per_trial > 100000)
+        return fail(h, LBIB_E_INVALID, "lbib_pool_autotune: steps_per_trial must be in [1, 100000]");
+    const bool timing_was = h->timing;
+    auto run_trial = [&](PoolSweepConfig c, int32_t gsteps, double& us) -> lbib_status {
+        PCHK(h, hipStreamSynchronize(h->stream));
+        h->cfg = c;
+        h->graph_steps = gsteps;
+        h->dirty = true;
+        h->timing = false;
+        lbib_status s = lbib_pool_step(h, 2);  // rebuild, first launches, graph capture outside the clock
+        if (s != LBIB_OK) return s;
+        PCHK(h, hipStreamSynchronize(h->stream));
+        if (gsteps > 0) {
+            s = lbib_pool_step(h, gsteps);  // instantiate the graph outside the clock
+            if (s != LBIB_OK) return s;
+            PCHK(h, hipStreamSynchronize(h->stream));
+        }
+        const auto t0 = std::chrono::steady_clock::now();
+        s = lbib_pool_step(h, steps_per_trial);
+        if (s != LBIB_OK) return s;
+        PCHK(h, hipStreamSynchronize(h->stream));
+        us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count() /
+             steps_per_trial;
+        return LBIB_OK;
+    };
+    // tile shapes first (direct launches), then graph replay of the best shape
+    static const PoolSweepConfig cand[] = {{64, 1},  {64, 2},  {64, 4},  {64, 8},  {128, 1}, {128, 2},
+                                           {128, 4}, {128, 8}, {256, 1}, {256, 2}, {256, 4}, {256, 8}};
+    PoolSweepConfig best = h->cfg;
+    double best_us = 1e300;
+    for (const PoolSweepConfig& c : cand) {
+        double us = 0;
+        lbib_status s = run_trial(c, 0, us);
+        if (s != LBIB_OK) return s;
+        if (us < best_us) best_us = us, best = c;
+    }
+    int32_t best_graph = 0;
+    {
+        const int32_t g = std::min<int32_t>(steps_per_trial, 64);
+        double us = 0;
+        lbib_status s = run_trial(best, g, us);
+        if (s != LBIB_OK) return s;
+        if (us < best_us) best_us = us, best_graph = g;
+    }
+    h->cfg = best;
+    h->graph_steps = best_graph;
+    h->dirty = true;
+    h->timing = timing_was;
+    if (best_step_us) *best_step_us = best_us;
+    return LBIB_OK;
+}
+
 const char* lbib_pool_last_error(lbib_pool_handle h) { return h ? h->err.c_str() : g_pool_null_err.c_str(); }
 
 void lbib_pool_destroy(lbib_pool_handle h)
@@ -605,6 +738,8 @@ void lbib_pool_destroy(lbib_pool_handle h)
     if (h->d_sims) (void)hipFree(h->d_sims);
     dfree(h->d_active);
     dfree(h->d_table);
+    dfree(h->d_ctl);
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
     for (int k = 0; k < 2; ++k)
         for (auto e : h->ev[k]) (void)hipEventDestroy(e);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);

@@ -175,51 +175,78 @@ __global__ __launch_bounds__(256) void sweep_box_kernel(const T* __restrict__ fi
     collide_push<T>(fin, fout, a, i, j, a.gx + ldexp((double)t[0], -d.scale), a.gy + ldexp((double)t[1], -d.scale));
 }
 
-// Sweep of a pool of independent simulations in one launch.  Block b covers tile table[b].y
-// (64 x 4 nodes) of simulation table[b].x; the table lists each simulation's tiles
-// contiguously, so after the XCD remap a simulation's tiles share one XCD's L2.  The
-// particle phase that precedes it has advanced the member to step n + 1 (did_step set) or
-// left it idle (did_step clear, nothing to do here); step n reads fA for even n.
-template <typename T>
+// Sweep of a pool of independent simulations in one launch.  Block b sweeps up to TPB
+// consecutive tiles (BX x 256/BX nodes each) of member table[b].x, starting at tile
+// table[b].y; the table lists each member's tiles in order, so after the XCD remap a
+// member's tiles share one XCD's L2.  ctl[member] says which buffer the member's particle
+// phase just read (0: fA, 1: fB) or that it did not step (-1: nothing to do).  A block pays
+// its member lookups once for TPB tiles.
+template <typename T, int BX, int TPB>
 __global__ __launch_bounds__(256) void pool_sweep_kernel(const PoolSweep<T>* __restrict__ sims,
+                                                         const int32_t* __restrict__ ctl,
                                                          const int2* __restrict__ table, int nblocks)
 {
+    constexpr int BY = 256 / BX;
     int b = blockIdx.x;
     {
         const int q = nblocks >> 3, r = nblocks & 7, x = b & 7, k = b >> 3;
         b = (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
     }
     const int2 e = table[b];
+    const int par = ctl[e.x];
+    if (par < 0) return;
     const PoolSweep<T>& ps = sims[e.x];
-    const DevParticle* st = ps.st;
-    if (!st->did_step) return;
-    const bool odd = ((st->step - 1) & 1) != 0;
-    const T* fin = odd ? ps.fB : ps.fA;
-    T* fout = odd ? ps.fA : ps.fB;
+    const T* fin = par ? ps.fB : ps.fA;
+    T* fout = par ? ps.fA : ps.fB;
     const SweepArgs a = ps.a;
-    const int i = (e.y % ps.gx) * 64 + (int)(threadIdx.x & 63);
-    const int j = (e.y / ps.gx) * 4 + (int)(threadIdx.x >> 6);
-    if (i >= a.nx || j >= a.ny) return;
-    double Fx = a.gx, Fy = a.gy;
     const TileDesc d = *ps.desc;
-    if (d.active && in_box(d, i, j, a.nx)) {
-        int di = i - d.i0w;
-        if (di < 0) di += a.nx;
-        const int64_t* t = ps.tile + 2 * ((size_t)(j - d.j0) * d.w + di);
-        Fx += ldexp((double)t[0], -d.scale);
-        Fy += ldexp((double)t[1], -d.scale);
+    const int tx = (int)(threadIdx.x % BX), ty = (int)(threadIdx.x / BX);
+    const int tend = min(e.y + TPB, ps.ntiles);
+    for (int t = e.y; t < tend; ++t) {
+        const int i = (t % ps.gx) * BX + tx;
+        const int j = (t / ps.gx) * BY + ty;
+        if (i >= a.nx || j >= a.ny) continue;
+        double Fx = a.gx, Fy = a.gy;
+        if (d.active && in_box(d, i, j, a.nx)) {
+            int di = i - d.i0w;
+            if (di < 0) di += a.nx;
+            const int64_t* tl = ps.tile + 2 * ((size_t)(j - d.j0) * d.w + di);
+            Fx += ldexp((double)tl[0], -d.scale);
+            Fy += ldexp((double)tl[1], -d.scale);
+        }
+        collide_push<T>(fin, fout, a, i, j, Fx, Fy);
     }
-    collide_push<T>(fin, fout, a, i, j, Fx, Fy);
 }
 
 template <typename T>
-hipError_t launch_pool_sweep(const PoolSweep<T>* sims, const int2* table, int32_t n_blocks, hipStream_t stream,
-                             hipEvent_t t0, hipEvent_t t1)
+hipError_t launch_pool_sweep(const PoolSweep<T>* sims, const int32_t* ctl, const int2* table, int32_t n_blocks,
+                             PoolSweepConfig cfg, hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
 {
     if (n_blocks <= 0) return hipSuccess;
-    hipExtLaunchKernelGGL(pool_sweep_kernel<T>, dim3(n_blocks), dim3(256), 0u, stream, t0, t1, 0u, sims, table,
-                          n_blocks);
-    return hipGetLastError();
+#define LBIB_POOL_SWEEP(BX_, TPB_)                                                                                     \
+    if (cfg.bx == BX_ && cfg.tpb == TPB_) {                                                                            \
+        if (t0 || t1)                                                                                                  \
+            hipExtLaunchKernelGGL(pool_sweep_kernel<T, BX_, TPB_>, dim3(n_blocks), dim3(256), 0u, stream, t0, t1, 0u,  \
+                                  sims, ctl, table, n_blocks);                                                         \
+        else                                                                                                           \
+            hipLaunchKernelGGL((pool_sweep_kernel<T, BX_, TPB_>), dim3(n_blocks), dim3(256), 0, stream, sims, ctl,     \
+                               table, n_blocks);                                                                       \
+        return hipGetLastError();                                                                                      \
+    }
+    LBIB_POOL_SWEEP(64, 1)
+    LBIB_POOL_SWEEP(64, 2)
+    LBIB_POOL_SWEEP(64, 4)
+    LBIB_POOL_SWEEP(64, 8)
+    LBIB_POOL_SWEEP(128, 1)
+    LBIB_POOL_SWEEP(128, 2)
+    LBIB_POOL_SWEEP(128, 4)
+    LBIB_POOL_SWEEP(128, 8)
+    LBIB_POOL_SWEEP(256, 1)
+    LBIB_POOL_SWEEP(256, 2)
+    LBIB_POOL_SWEEP(256, 4)
+    LBIB_POOL_SWEEP(256, 8)
+#undef LBIB_POOL_SWEEP
+    return hipErrorInvalidValue;
 }
 
 template <typename T>
@@ -247,9 +274,9 @@ template hipError_t launch_sweep<float>(const float*, float*, const SweepArgs&, 
                                         int32_t, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_sweep<double>(const double*, double*, const SweepArgs&, int, const TileDesc*,
                                          const int64_t*, int32_t, hipStream_t, hipEvent_t, hipEvent_t);
-template hipError_t launch_pool_sweep<float>(const PoolSweep<float>*, const int2*, int32_t, hipStream_t, hipEvent_t,
-                                             hipEvent_t);
-template hipError_t launch_pool_sweep<double>(const PoolSweep<double>*, const int2*, int32_t, hipStream_t, hipEvent_t,
-                                              hipEvent_t);
+template hipError_t launch_pool_sweep<float>(const PoolSweep<float>*, const int32_t*, const int2*, int32_t,
+                                             PoolSweepConfig, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_pool_sweep<double>(const PoolSweep<double>*, const int32_t*, const int2*, int32_t,
+                                              PoolSweepConfig, hipStream_t, hipEvent_t, hipEvent_t);
 
 }  // namespace lbib

@@ -111,6 +111,9 @@ _SIGS = {
     "lbib_pool_usage": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _I64]),
     "lbib_pool_kernel_timing": (C.c_int, [_P, C.c_int32]),
     "lbib_pool_kernel_time": (C.c_int, [_P, C.c_int32, _D, _I64]),
+    "lbib_pool_set_config": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32]),
+    "lbib_pool_get_config": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "lbib_pool_autotune": (C.c_int, [_P, C.c_int32, _D]),
     "lbib_pool_last_error": (C.c_char_p, [_P]),
     "lbib_pool_destroy": (None, [_P]),
 }
@@ -445,6 +448,22 @@ class Pool:
         cnt = C.c_int64()
         self._call(lib().lbib_pool_read_trace, int(slot), buf, int(capacity), C.byref(cnt))
         return _trace_array(buf, cnt.value)
+
+    def set_config(self, tile_x: int = 64, tiles_per_block: int = 4, graph_steps: int = 0):
+        self._call(lib().lbib_pool_set_config, int(tile_x), int(tiles_per_block), int(graph_steps))
+
+    def config(self):
+        """(tile_x, tiles_per_block, graph_steps)."""
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        self._call(lib().lbib_pool_get_config, C.byref(a), C.byref(b), C.byref(c))
+        return a.value, b.value, c.value
+
+    def autotune(self, steps_per_trial: int = 20) -> float:
+        """Pick the fastest sweep launch shape (and graph replay) on real steps; returns the
+        best time per step in microseconds."""
+        v = C.c_double()
+        self._call(lib().lbib_pool_autotune, int(steps_per_trial), C.byref(v))
+        return v.value
 
     def kernel_timing(self, enable: bool):
         self._call(lib().lbib_pool_kernel_timing, 1 if enable else 0)

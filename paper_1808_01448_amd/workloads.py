@@ -120,6 +120,69 @@ def with_precision(w: dict, precision: str) -> dict:
 
 
 # ----------------------------------------------------------------------------------------
+# Parameter sweeps of the results section (many small simulations)
+# ----------------------------------------------------------------------------------------
+
+SWEEP_SHAPES = ("circle", "ar2", "ar3")
+SWEEP_RHO_L = ((3, 10), (1, 2), (7, 10), (9, 10))
+SWEEP_STRENGTH = (1, 2)
+SWEEP_RE = (0.01, 0.1, 1.0)
+SWEEP_SEEDS = (0, 1, 2)
+
+
+def _semi_axes(shape: str, H: float, area_frac: float = 0.025):
+    """Semi-axes (a, b) of a particle of area area_frac H^2 (the results section keeps the
+    particle area fixed while the aspect ratio varies)."""
+    A = area_frac * H * H
+    ar = {"circle": 1.0, "ar2": 2.0, "ar3": 3.0}[shape]
+    a = math.sqrt(ar * A / math.pi)
+    return a, a / ar
+
+
+def _n_markers(shape: str, a: float, b: float) -> int:
+    """Marker count for a spacing of about 0.785 lattice units (that of the 256 x 64 case),
+    rounded up to a multiple of 64."""
+    h = ((a - b) / (a + b)) ** 2
+    perim = math.pi * (a + b) * (1 + 3 * h / (10 + math.sqrt(4 - 3 * h)))
+    return 64 * math.ceil(perim / (0.785 * 64))
+
+
+def sweep_member(nx: int, ny: int, shape: str, rho_l: tuple[int, int], strength: int, re: float, seed: int,
+                 *, precision: str = "fp32", steps: int = 10_000, gap_frac: float = 3e-3) -> dict:
+    """One simulation of a parameter sweep: tau 0.8, the particle (area 0.025 H^2, major axis
+    normal to the wall) a gap of gap_frac H above the receptor wall at x = nx / 4."""
+    H = float(ny)
+    a, b = _semi_axes(shape, H)
+    return dict(
+        name=f"sweep_{nx}x{ny}_{shape}_rl{rho_l[0]}-{rho_l[1]}_s{strength}_re{re}_seed{seed}",
+        lattice=dict(nx=nx, ny=ny, tau=0.8, re=re, drive=0, precision=PRECISION[precision], seed=seed),
+        particle=dict(shape=0 if shape == "circle" else 1, a_major=a, b_minor=b, xc=nx / 4.0,
+                      yc=-0.5 + gap_frac * H + a, theta0=0.0, rho_p=1.0, n_markers=_n_markers(shape, a, b)),
+        ligand=_ligand(rho_l, strength),
+        receptor=dict(wall=0, density=1.0),
+        steps=steps,
+    )
+
+
+def batched_sweep(seed: int = 0, *, precision: str = "fp32", steps: int = 10_000) -> list[dict]:
+    """The 216-simulation sweep: shape {circle, AR2, AR3} x ligand density {0.3, 0.5, 0.7, 0.9}
+    x bond strength {1, 2} x Re {0.01, 0.1, 1} x seed {0, 1, 2}; each grid drawn (in this
+    order) with nx ~ U_int[512, 2048] and ny ~ U_int[128, 256] from a generator seeded
+    with `seed`."""
+    g = rng(seed)
+    out = []
+    for shape in SWEEP_SHAPES:
+        for rl in SWEEP_RHO_L:
+            for st in SWEEP_STRENGTH:
+                for re in SWEEP_RE:
+                    for sd in SWEEP_SEEDS:
+                        nx = int(g.integers(512, 2049))
+                        ny = int(g.integers(128, 257))
+                        out.append(sweep_member(nx, ny, shape, rl, st, re, sd, precision=precision, steps=steps))
+    return out
+
+
+# ----------------------------------------------------------------------------------------
 # Seeded random arrays (for unit-level parity tests)
 # ----------------------------------------------------------------------------------------
 

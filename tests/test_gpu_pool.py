@@ -60,7 +60,17 @@ def mix(precision):
     ]
 
 
+_ALONE = {}
+
+
 def alone(L, w, steps):
+    key = (w["name"], w["lattice"]["precision"], steps)
+    if key not in _ALONE:
+        _ALONE[key] = _alone(L, w, steps)
+    return _ALONE[key]
+
+
+def _alone(L, w, steps):
     s = L.Sim(w)
     s.set_overlap(0)
     s.trace_enable(steps)
@@ -243,4 +253,42 @@ def test_pool_kernel_timing(L):
     ms1, n1 = P.kernel_time(1)
     say("pool timing: sweep", ms0, n0, "particle", ms1, n1)
     assert n0 == 10 and n1 == 10 and ms0 > 0 and ms1 > 0
+    P.close()
+
+
+@pytest.mark.parametrize("cfg", [(64, 1, 0), (128, 2, 0), (256, 8, 0), (64, 4, 8), (128, 4, 16)])
+def test_pool_launch_shapes_and_graph_replay_are_bit_identical(L, cfg):
+    """Every sweep launch shape, and steps replayed from a captured HIP graph (several
+    replays with host reads and ordinary launches in between), give the stand-alone result."""
+    cases = mix("fp32")
+    P = L.Pool(L.FP32)
+    P.set_config(*cfg)
+    assert P.config() == cfg
+    slots = [P.add(w, n) for w, n in cases]
+    done = []
+    for _ in range(3):
+        P.step(16)
+        done += P.poll()
+        P.particle(slots[0])
+    P.step(3)
+    P.step(60)
+    done += P.poll()
+    assert sorted(done) == sorted(slots)
+    for (w, n), s in zip(cases, slots):
+        assert_same(pooled(P, s, 0), dict(alone(L, w, n), trace=np.zeros((0, 20))), f"{w['name']} {cfg}")
+    P.close()
+
+
+def test_pool_autotune(L):
+    cases = mix("fp32")
+    P = L.Pool(L.FP32)
+    slots = [P.add(w, 400) for w, _ in cases]
+    us = P.autotune(5)
+    cfg = P.config()
+    say("autotune picked", cfg, f"{us:.1f} us/step")
+    assert us > 0 and cfg[0] in (64, 128, 256) and cfg[1] in (1, 2, 4, 8) and cfg[2] in (0, 5)
+    P.step(400)
+    assert sorted(P.poll()) == sorted(slots)
+    w, _ = cases[2]
+    assert_same(pooled(P, slots[2], 0), dict(alone(L, w, 400), trace=np.zeros((0, 20))), "after autotune")
     P.close()
