@@ -220,10 +220,26 @@ lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size);
  * than they hide.  Both schedules give bit-identical results. */
 lbib_status lbib_set_overlap(lbib_handle h, int32_t mode);
 
-/* Kernel timing: when enabled, HIP events bracket every launch of the lattice sweep of all
- * nodes or of the nodes outside the particle's box (kernel 0), of the particle phase
- * (kernel 1) and of the sweep of the box (kernel 2).  lbib_kernel_time synchronises and
- * returns the summed milliseconds and launch counts since the last enable. */
+/* Storage layout of the population buffers, chosen before lbib_init: mode 0 push (the
+ * buffers hold the streamed populations; the update collides a node and scatters its
+ * results to the neighbours), 1 pull (the buffers hold the post-collision populations; the
+ * update gathers a node's inflow from the neighbours, collides and stores at the node),
+ * 2 (default) pull when the two buffers together exceed 512 MiB, push otherwise.  Push's
+ * shifted stores cost little while the buffers fit the GPU's 256 MB last-level cache (MALL);
+ * beyond it the aligned stores of pull move HBM traffic ~25% faster.  The layout is
+ * invisible at this interface (read-outs, writes and the oracle's populations are the
+ * streamed values either way) and results are bit-identical; checkpoints record it and load
+ * only into a handle with the same layout.  lbib_get_layout (after lbib_init) gives 1 for
+ * pull. */
+lbib_status lbib_set_layout(lbib_handle h, int32_t mode);
+lbib_status lbib_get_layout(lbib_handle h, int32_t* pull);
+
+/* Kernel timing: HIP events bracket every launch of the kernels selected by the bit mask
+ * `enable` (0 switches timing off): bit 0 the lattice sweep of all nodes or of the nodes
+ * outside the particle's box (kernel 0), bit 1 the particle phase (kernel 1), bit 2 the
+ * sweep of the box (kernel 2).  lbib_kernel_time synchronises and returns the summed
+ * milliseconds and launch counts since the last enable.  The events delay the hand-over
+ * between the two streams of the overlapped schedule: time whole steps without them. */
 lbib_status lbib_kernel_timing(lbib_handle h, int32_t enable);
 lbib_status lbib_kernel_time(lbib_handle h, int32_t kernel, double* total_ms, int64_t* launches);
 
@@ -325,15 +341,17 @@ lbib_status lbib_pool_kernel_time(lbib_pool_handle p, int32_t kernel, double* to
  * 256 / tile_x rows, tiles_per_block consecutive tiles (1, 2, 4 or 8) per workgroup, and,
  * when graph_steps > 0, runs of graph_steps steps replayed as one captured HIP graph
  * (graph_steps <= 4096; kernel timing, when on, uses direct launches).  Results do not
- * depend on these choices.  The default is 64, 4, 0. */
+ * depend on these choices.  The default is 256, 4, 0. */
 lbib_status lbib_pool_set_config(lbib_pool_handle p, int32_t tile_x, int32_t tiles_per_block, int32_t graph_steps);
 lbib_status lbib_pool_get_config(lbib_pool_handle p, int32_t* tile_x, int32_t* tiles_per_block, int32_t* graph_steps);
 
-/* Autotuner: times steps_per_trial pool steps (wall clock, after untimed warm-up steps)
- * for each tile shape, then graph replay of the fastest, and keeps the fastest
- * configuration; *best_step_us (may be NULL) receives its time per step.  The trials are
- * ordinary steps of the running members: about 16 (steps_per_trial + 2) + 64 steps in
- * total. */
+/* Autotuner: for each tile shape, the sweep's average duration over steps_per_trial steps
+ * (HIP events around the sweep launches, best of two rounds); then, for the fastest
+ * shape, whole steps with direct launches against graph replay (wall clock, best of two
+ * rounds).  Keeps the fastest configuration; *best_step_us (may be NULL) receives its time
+ * per step.  The trials are ordinary steps of the running members: about
+ * 30 steps_per_trial + 60 steps in total.  Kernel timing is switched off and its counts
+ * are reset. */
 lbib_status lbib_pool_autotune(lbib_pool_handle p, int32_t steps_per_trial, double* best_step_us);
 
 /* Description of the last failure on this pool (NULL: of the last call with a NULL pool). */

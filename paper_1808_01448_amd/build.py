@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "liblbib.so")
-SOURCES = ["lbib_sweep.hip", "lbib_particle.hip", "lbib_runtime.cpp", "lbib_pool.cpp", "lbib_host.cpp",
+SOURCES = ["lbib_sweep.hip", "lbib_pool_sweep.hip", "lbib_particle.hip", "lbib_runtime.cpp", "lbib_pool.cpp", "lbib_host.cpp",
            "lbib_geometry.cpp"]
 ARCH = "gfx950"
 
@@ -23,12 +23,11 @@ FLAGS = [
 ]
 
 
-# The particle phase is compiled without FMA contraction: its arithmetic is then exactly the
-# written sequence in every kernel that inlines it (the stand-alone launch and the pool
-# launch, with any number of markers per thread), so a simulation gives bit-identical
-# results in either.  It is latency-bound, so the separate multiply and add cost nothing
-# measurable.
-PER_SOURCE = {"lbib_particle.hip": ["-ffp-contract=off"]}
+# Device code is compiled without FMA contraction: the arithmetic of every kernel is then
+# exactly the written sequence (with the fused operations written out where they pay), so a
+# simulation gives bit-identical results whichever kernel variant runs it (one simulation
+# or a pool, push or pull layout, any number of markers per thread).
+PER_SOURCE = {src: ["-ffp-contract=off"] for src in ("lbib_sweep.hip", "lbib_pool_sweep.hip", "lbib_particle.hip")}
 
 
 def hipcc() -> str:

@@ -21,6 +21,26 @@ constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 constexpr double kW[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
                           1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 
+// Element index of population q of node (i, j) at the start of a step, in the two storage
+// layouts of a population buffer (planes [q][j][i], row pitch `pitch`, plane `plane`):
+//  - push: the buffer holds the streamed populations, each at its own node;
+//  - pull: the buffer holds the previous step's post-collision populations at the node that
+//    emitted them; population q of (i, j) is the one emitted along e_q by (i - e_x, j - e_y)
+//    (x periodic), or, when that link crosses a wall, the opposite population emitted by
+//    (i, j) itself (half-way bounce-back).
+// Streaming is a permutation, so both layouts present the same values.
+__device__ __forceinline__ int64_t pop_index(int q, int i, int j, int nx, int ny, int pitch, int64_t plane, bool pull)
+{
+    if (pull) {
+        const int sj = j - kEy[q];
+        if (sj < 0 || sj >= ny) return kOpp[q] * plane + (int64_t)j * pitch + i;
+        int si = i - kEx[q];
+        si = si < 0 ? si + nx : (si >= nx ? si - nx : si);
+        return q * plane + (int64_t)sj * pitch + si;
+    }
+    return q * plane + (int64_t)j * pitch + i;
+}
+
 // Density and momentum of shifted populations g_q = f_q - w_q: rho = 1 + sum g (the weights
 // sum to one), j = sum g e (the weights carry no momentum).
 template <typename R, typename S>

@@ -13,6 +13,7 @@ constexpr double kWq[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 
                            1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 constexpr int kExq[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 constexpr int kEyq[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr int kOppq[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 
 // Ligand-bearing elements: with rho_l = p/q in lowest terms, element l carries a ligand when
 // floor((l+1) p/q) - floor(l p/q) = 1 -- floor(nl p/q) ligands spread evenly.
@@ -27,6 +28,18 @@ std::vector<uint8_t> ligand_layout(int nl, int p, int q)
 }
 
 }  // namespace
+
+int64_t host_pop_index(const LatticeGeom& g, int q, int i, int j)
+{
+    if (g.pull) {
+        const int sj = j - kEyq[q];
+        if (sj < 0 || sj >= g.ny) return kOppq[q] * g.plane + (int64_t)j * g.pitch + i;
+        int si = i - kExq[q];
+        si = si < 0 ? si + g.nx : (si >= g.nx ? si - g.nx : si);
+        return q * g.plane + (int64_t)sj * g.pitch + si;
+    }
+    return q * g.plane + (int64_t)j * g.pitch + i;
+}
 
 lbib_status check_lattice(const lbib_lattice_desc& d, std::string& msg)
 {
@@ -189,6 +202,7 @@ void fill_particle_args(ParticleArgs<T>& a, const LatticeGeom& g, uint64_t seed,
     a.nx = g.nx;
     a.ny = g.ny;
     a.pitch = g.pitch;
+    a.pull = g.pull ? 1 : 0;
     a.plane = g.plane;
     a.gx = g.gx;
     a.gy = g.gy;
@@ -237,8 +251,8 @@ hipError_t init_populations(void* f, const LatticeGeom& g, hipStream_t s)
     const size_t bytes = (size_t)9 * g.plane * g.elem;
     hipError_t e = hipMemsetAsync(f, 0, bytes, s);
     if (e != hipSuccess) return e;
-    if (g.elem == 8) return launch_init<double>((double*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, s);
-    return launch_init<float>((float*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, s);
+    if (g.elem == 8) return launch_init<double>((double*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, g.pull, s);
+    return launch_init<float>((float*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, g.pull, s);
 }
 
 hipError_t download_populations(const void* fdev, const LatticeGeom& g, std::vector<double>& f)
@@ -253,14 +267,14 @@ hipError_t download_populations(const void* fdev, const LatticeGeom& g, std::vec
         for (int q = 0; q < 9; ++q)
             for (int j = 0; j < ny; ++j)
                 for (int i = 0; i < nx; ++i)
-                    f[((size_t)q * ny + j) * nx + i] = kWq[q] + raw[q * g.plane + (size_t)j * g.pitch + i];
+                    f[((size_t)q * ny + j) * nx + i] = kWq[q] + raw[host_pop_index(g, q, i, j)];
     } else {
         std::vector<float> raw(n);
         if ((e = hipMemcpy(raw.data(), fdev, n * 4, hipMemcpyDeviceToHost)) != hipSuccess) return e;
         for (int q = 0; q < 9; ++q)
             for (int j = 0; j < ny; ++j)
                 for (int i = 0; i < nx; ++i)
-                    f[((size_t)q * ny + j) * nx + i] = kWq[q] + (double)raw[q * g.plane + (size_t)j * g.pitch + i];
+                    f[((size_t)q * ny + j) * nx + i] = kWq[q] + (double)raw[host_pop_index(g, q, i, j)];
     }
     return hipSuccess;
 }
@@ -274,14 +288,14 @@ hipError_t upload_populations(void* fdev, const LatticeGeom& g, const double* f)
         for (int q = 0; q < 9; ++q)
             for (int j = 0; j < ny; ++j)
                 for (int i = 0; i < nx; ++i)
-                    raw[q * g.plane + (size_t)j * g.pitch + i] = f[((size_t)q * ny + j) * nx + i] - kWq[q];
+                    raw[host_pop_index(g, q, i, j)] = f[((size_t)q * ny + j) * nx + i] - kWq[q];
         return hipMemcpy(fdev, raw.data(), n * 8, hipMemcpyHostToDevice);
     }
     std::vector<float> raw(n, 0.0f);
     for (int q = 0; q < 9; ++q)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i)
-                raw[q * g.plane + (size_t)j * g.pitch + i] = (float)(f[((size_t)q * ny + j) * nx + i] - kWq[q]);
+                raw[host_pop_index(g, q, i, j)] = (float)(f[((size_t)q * ny + j) * nx + i] - kWq[q]);
     return hipMemcpy(fdev, raw.data(), n * 4, hipMemcpyHostToDevice);
 }
 

@@ -22,8 +22,13 @@ struct LatticeGeom {
     int nx = 0, ny = 0, pitch = 0;
     int64_t plane = 0;  // elements per population plane
     size_t elem = 0;    // bytes per stored population
+    bool pull = false;  // buffer layout (push: streamed values; pull: post-collision values)
     double tau = 0, nu = 0, umax = 0, gx = 0, gy = 0;
 };
+
+// Element index of population q of node (i, j) in a buffer of this geometry (the host
+// mirror of the device's pop_index).
+int64_t host_pop_index(const LatticeGeom& g, int q, int i, int j);
 
 // One particle: host description, surface, ligand layout and its device buffers.
 struct Particle {
@@ -88,7 +93,8 @@ hipError_t upload_particle(Particle& p);
 template <typename T>
 void fill_particle_args(ParticleArgs<T>& a, const LatticeGeom& g, uint64_t seed, const Particle& p, int32_t* flags);
 
-// Initial populations f = f_eq(1, u_poiseuille(y)) (shifted), padding zeroed.
+// Initial populations f = f_eq(1, u_poiseuille(y)) (shifted, in the geometry's layout),
+// padding zeroed.
 hipError_t init_populations(void* f, const LatticeGeom& g, hipStream_t s);
 
 // Plain FP64 populations [9][ny][nx] from a device buffer of shifted ones.

@@ -55,6 +55,7 @@ struct ParticleArgs {
     const T* fB;  // a pool's odd-step buffer
     int64_t target_steps;  // a pool member stops at this step count
     int32_t nx, ny, pitch;
+    int32_t pull;  // layout of f: 0 push, 1 pull
     int64_t plane;
     double gx, gy, nu;
     // body-frame surface: centroids xi[2l], outward normals nuv[2l], lengths S[l]
@@ -84,15 +85,17 @@ struct ParticleArgs {
 
 // Launchers (lbib_sweep.hip, lbib_particle.hip).  All enqueue on `stream` and return the launch status.
 template <typename T>
-hipError_t launch_init(T* f, int32_t nx, int32_t ny, int32_t pitch, int64_t plane, double umax, hipStream_t stream);
+hipError_t launch_init(T* f, int32_t nx, int32_t ny, int32_t pitch, int64_t plane, double umax, bool pull,
+                       hipStream_t stream);
 // Sweep modes: every node (forces from desc/tile when desc != NULL); only nodes outside
 // the box in `desc` (which carry no spread force); only the nodes of the box in `desc`
 // (box_cap bounds the launch).
 enum SweepMode { SWEEP_ALL = 0, SWEEP_OUTSIDE = 1, SWEEP_BOX = 2 };
 // t0 / t1 (optional) receive the kernel's own start and end times.
+// pull selects the layout of the population buffers (pop_index in lbib_device.hpp).
 template <typename T>
 hipError_t launch_sweep(const T* fin, T* fout, const SweepArgs& a, int mode, const TileDesc* desc,
-                        const int64_t* tile, int32_t box_cap, hipStream_t stream, hipEvent_t t0 = nullptr,
+                        const int64_t* tile, int32_t box_cap, bool pull, hipStream_t stream, hipEvent_t t0 = nullptr,
                         hipEvent_t t1 = nullptr);
 // Bytes of dynamic LDS the particle phase needs for a box of box_cap nodes, or 0 when the
 // box is kept in global memory instead.
@@ -102,17 +105,17 @@ hipError_t launch_particle(const ParticleArgs<T>& a, hipStream_t stream, hipEven
                            hipEvent_t t1 = nullptr);
 
 // A pool of independent simulations stepped together (one launch per kernel per step).
-// The particle launch runs member active[b] in workgroup b and writes ctl[member]: the
-// parity of the step it ran (its input buffer: 0 fA, 1 fB), or -1 when the member did not
-// step (target reached, or frozen by its watchdog).  The sweep's blocks are listed in
-// `table`: (member, first tile); a block sweeps up to TPB consecutive tiles of BX x 256/BX
-// nodes of that member.
+// The particle launch runs member active[b] in workgroup b and copies the member's box
+// descriptor of the step into ctl[member], with `pad` set to the parity of the step it ran
+// (its input buffer: 0 fA, 1 fB), or only pad = -1 when the member did not step (target
+// reached, or frozen by its watchdog).  The sweep's blocks are listed in `table`: (member,
+// first tile); a block sweeps up to TPB consecutive tiles of BX x 256/BX nodes of that
+// member, reading ctl[member] and the member's record side by side.
 template <typename T>
 struct PoolSweep {
     SweepArgs a;
     T* fA;  // buffer of the even steps
     T* fB;  // buffer of the odd steps
-    const TileDesc* desc;
     const int64_t* tile;
     int32_t gx;      // tiles along x
     int32_t ntiles;  // tiles of this member
@@ -123,11 +126,11 @@ struct PoolSweepConfig {
     int32_t bx, tpb;
 };
 template <typename T>
-hipError_t launch_pool_particle(const ParticleArgs<T>* args, const int32_t* active, int32_t* ctl, int32_t n_active,
+hipError_t launch_pool_particle(const ParticleArgs<T>* args, const int32_t* active, TileDesc* ctl, int32_t n_active,
                                 int32_t max_nl, int32_t lds_cap, hipStream_t stream, hipEvent_t t0 = nullptr,
                                 hipEvent_t t1 = nullptr);
 template <typename T>
-hipError_t launch_pool_sweep(const PoolSweep<T>* sims, const int32_t* ctl, const int2* table, int32_t n_blocks,
+hipError_t launch_pool_sweep(const PoolSweep<T>* sims, const TileDesc* ctl, const int2* table, int32_t n_blocks,
                              PoolSweepConfig cfg, hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
 hipError_t launch_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n, hipStream_t stream);

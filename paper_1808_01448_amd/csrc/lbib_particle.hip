@@ -253,9 +253,9 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, double*
         for (int u = 0; u < U; ++u) {
             const int k = min(k0 + u * PB, nbox - 1);  // clamped: duplicates are recomputed, not stored
             const int j = y0 + k / w;
-            const size_t c = (size_t)j * a.pitch + wrap(x0 + k % w, a.nx);
+            const int i = wrap(x0 + k % w, a.nx);
 #pragma unroll
-            for (int q = 0; q < 9; ++q) v[u][q] = a.f[q * a.plane + c];
+            for (int q = 0; q < 9; ++q) v[u][q] = a.f[pop_index(q, i, j, a.nx, a.ny, a.pitch, a.plane, a.pull != 0)];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -590,21 +590,22 @@ __global__ __launch_bounds__(PB) void particle_kernel(ParticleArgs<T> a)
 
 // Particle phases of a pool of independent simulations: workgroup b runs member
 // k = active[b].  A member whose step counter has reached its target, or whose watchdog
-// has raised a flag, does nothing (ctl[k] = -1: its sweep does nothing either), so a
-// failed member stays frozen at the step that failed.  Otherwise ctl[k] receives the
-// parity of step n: its populations are f for even n and fB for odd n.  Boxes up to
-// lds_cap nodes are staged in LDS, larger ones in their global scratch.
+// has raised a flag, does nothing (ctl[k].pad = -1: its sweep does nothing either), so a
+// failed member stays frozen at the step that failed.  Otherwise ctl[k] receives the box
+// descriptor of step n with pad = the parity of n: the populations of step n are in f for
+// even n and in fB for odd n.  Boxes up to lds_cap nodes are staged in LDS, larger ones in
+// their global scratch.
 template <typename T, int MPT>
 __global__ __launch_bounds__(PB) void pool_particle_kernel(const ParticleArgs<T>* __restrict__ args,
                                                            const int32_t* __restrict__ active,
-                                                           int32_t* __restrict__ ctl, int32_t lds_cap)
+                                                           TileDesc* __restrict__ ctl, int32_t lds_cap)
 {
     extern __shared__ double lds_box[];
     const int k = active[blockIdx.x];
     ParticleArgs<T> a = args[k];
     const int64_t n = a.st->step;
     if (n >= a.target_steps || *a.flags != 0) {
-        if (threadIdx.x == 0) ctl[k] = -1;
+        if (threadIdx.x == 0) ctl[k].pad = -1;
         return;
     }
     a.f = (n & 1) ? a.fB : a.f;
@@ -612,11 +613,15 @@ __global__ __launch_bounds__(PB) void pool_particle_kernel(const ParticleArgs<T>
         particle_phase<T, MPT, true>(a, lds_box);
     else
         particle_phase<T, MPT, false>(a, lds_box);
-    if (threadIdx.x == 0) ctl[k] = (int32_t)(n & 1);
+    if (threadIdx.x == 0) {  // the thread that wrote *a.desc in the particle phase
+        TileDesc d = *a.desc;
+        d.pad = (int32_t)(n & 1);
+        ctl[k] = d;
+    }
 }
 
 template <typename T>
-hipError_t launch_pool_particle(const ParticleArgs<T>* args, const int32_t* active, int32_t* ctl, int32_t n_active,
+hipError_t launch_pool_particle(const ParticleArgs<T>* args, const int32_t* active, TileDesc* ctl, int32_t n_active,
                                 int32_t max_nl, int32_t lds_cap, hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
 {
     if (n_active <= 0) return hipSuccess;
@@ -775,21 +780,34 @@ hipError_t launch_bonds(const uint8_t* ligand, const double* d, const uint8_t* b
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst, int64_t n)
+// Plain streaming copy: each thread moves four 16-byte vectors, all loads issued before
+// the stores, loads and stores past the caches (data touched once).
+typedef float lbib_v4f __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void copy_kernel(const lbib_v4f* __restrict__ src, lbib_v4f* __restrict__ dst,
+                                                   int64_t n)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) dst[k] = src[k];
+    const int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    lbib_v4f v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (base + 256 * u < n) v[u] = __builtin_nontemporal_load(src + base + 256 * u);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (base + 256 * u < n) __builtin_nontemporal_store(v[u], dst + base + 256 * u);
 }
 
 hipError_t launch_copy(const float4* src, float4* dst, int64_t n, hipStream_t stream)
 {
-    hipLaunchKernelGGL(copy_kernel, dim3(256 * 64), dim3(256), 0, stream, src, dst, n);
+    const int64_t blocks = (n + 1023) / 1024;
+    if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(copy_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, (const lbib_v4f*)src,
+                       (lbib_v4f*)dst, n);
     return hipGetLastError();
 }
 
-template hipError_t launch_pool_particle<float>(const ParticleArgs<float>*, const int32_t*, int32_t*, int32_t, int32_t,
+template hipError_t launch_pool_particle<float>(const ParticleArgs<float>*, const int32_t*, TileDesc*, int32_t, int32_t,
                                                 int32_t, hipStream_t, hipEvent_t, hipEvent_t);
-template hipError_t launch_pool_particle<double>(const ParticleArgs<double>*, const int32_t*, int32_t*, int32_t, int32_t,
+template hipError_t launch_pool_particle<double>(const ParticleArgs<double>*, const int32_t*, TileDesc*, int32_t, int32_t,
                                                  int32_t, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_particle<float>(const ParticleArgs<float>&, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_particle<double>(const ParticleArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);

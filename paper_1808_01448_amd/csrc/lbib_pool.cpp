@@ -68,10 +68,10 @@ struct lbib_pool {
     size_t sims_cap = 0;
     int2* d_table = nullptr;
     size_t table_cap = 0;
-    int32_t* d_ctl = nullptr;
+    TileDesc* d_ctl = nullptr;  // per running member: its box of the step and the step parity
     size_t ctl_cap = 0;
     int32_t n_active = 0, n_blocks = 0, max_nl = 0, lds_cap = 0;
-    PoolSweepConfig cfg{64, 4};
+    PoolSweepConfig cfg{256, 4};
     // optional replay of graph_steps steps as one HIP graph (rebuilt with the tables)
     int32_t graph_steps = 0;
     hipGraphExec_t graph = nullptr;
@@ -167,7 +167,6 @@ lbib_status rebuild(lbib_pool* h)
         s.a.gy = m.g.gy;
         s.fA = (T*)m.fA;
         s.fB = (T*)m.fB;
-        s.desc = m.p.d_desc;
         s.tile = m.p.d_tile;
         const int by = 256 / h->cfg.bx;
         s.gx = (m.g.nx + h->cfg.bx - 1) / h->cfg.bx;
@@ -414,6 +413,7 @@ lbib_status lbib_pool_add(lbib_pool_handle h, const lbib_lattice_desc* lat, cons
     }
     m->lat = *lat;
     m->g = lattice_geom(*lat);
+    m->g.pull = true;  // the pool sweep runs the pull update
     m->target = n_steps;
     m->bytes = footprint_bytes(*lat, &m->p);
     if (h->free_lanes.empty()) return fail(h, LBIB_E_FULL, "lbib_pool_add: max_members members already in the pool");
@@ -674,53 +674,71 @@ lbib_status lbib_pool_autotune(lbib_pool_handle h, int32_t steps_per_trial, doub
     if (!h) return fail(nullptr, LBIB_E_INVALID, "lbib_pool_autotune: NULL handle");
     if (steps_per_trial < 1 || steps_per_trial > 100000)
         return fail(h, LBIB_E_INVALID, "lbib_pool_autotune: steps_per_trial must be in [1, 100000]");
-    const bool timing_was = h->timing;
-    auto run_trial = [&](PoolSweepConfig c, int32_t gsteps, double& us) -> lbib_status {
+    // sweep duration of one configuration: HIP events around each sweep launch (they do not
+    // change a kernel's own duration), after 2 untimed steps for the table rebuild
+    auto sweep_trial = [&](PoolSweepConfig c, double& us) -> lbib_status {
         PCHK(h, hipStreamSynchronize(h->stream));
         h->cfg = c;
+        h->graph_steps = 0;
+        h->dirty = true;
+        h->timing = false;
+        lbib_status s = lbib_pool_step(h, 2);
+        if (s != LBIB_OK) return s;
+        if ((s = lbib_pool_kernel_timing(h, 1)) != LBIB_OK) return s;
+        if ((s = lbib_pool_step(h, steps_per_trial)) != LBIB_OK) return s;
+        double ms = 0;
+        int64_t n = 0;
+        if ((s = lbib_pool_kernel_time(h, 0, &ms, &n)) != LBIB_OK) return s;
+        h->timing = false;
+        us = n > 0 ? ms * 1e3 / n : 1e300;
+        return LBIB_OK;
+    };
+    // whole steps, wall clock, with or without graph replay
+    auto step_trial = [&](int32_t gsteps, double& us) -> lbib_status {
+        PCHK(h, hipStreamSynchronize(h->stream));
         h->graph_steps = gsteps;
         h->dirty = true;
         h->timing = false;
-        lbib_status s = lbib_pool_step(h, 2);  // rebuild, first launches, graph capture outside the clock
+        lbib_status s = lbib_pool_step(h, std::max<int32_t>(2, gsteps));  // rebuild and capture off the clock
         if (s != LBIB_OK) return s;
         PCHK(h, hipStreamSynchronize(h->stream));
-        if (gsteps > 0) {
-            s = lbib_pool_step(h, gsteps);  // instantiate the graph outside the clock
-            if (s != LBIB_OK) return s;
-            PCHK(h, hipStreamSynchronize(h->stream));
-        }
+        const int64_t n = gsteps > 0 ? (steps_per_trial + gsteps - 1) / gsteps * gsteps : steps_per_trial;
         const auto t0 = std::chrono::steady_clock::now();
-        s = lbib_pool_step(h, steps_per_trial);
-        if (s != LBIB_OK) return s;
+        if ((s = lbib_pool_step(h, n)) != LBIB_OK) return s;
         PCHK(h, hipStreamSynchronize(h->stream));
-        us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count() /
-             steps_per_trial;
+        us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count() / n;
         return LBIB_OK;
     };
-    // tile shapes first (direct launches), then graph replay of the best shape
     static const PoolSweepConfig cand[] = {{64, 1},  {64, 2},  {64, 4},  {64, 8},  {128, 1}, {128, 2},
                                            {128, 4}, {128, 8}, {256, 1}, {256, 2}, {256, 4}, {256, 8}};
-    PoolSweepConfig best = h->cfg;
-    double best_us = 1e300;
-    for (const PoolSweepConfig& c : cand) {
+    constexpr int kCand = sizeof(cand) / sizeof(cand[0]);
+    double best_sweep[kCand];
+    for (int c = 0; c < kCand; ++c) best_sweep[c] = 1e300;
+    for (int round = 0; round < 2; ++round)  // two rounds, best of each: drifts in clock hit every shape
+        for (int c = 0; c < kCand; ++c) {
+            double us = 0;
+            lbib_status s = sweep_trial(cand[c], us);
+            if (s != LBIB_OK) return s;
+            best_sweep[c] = std::min(best_sweep[c], us);
+        }
+    int bi = 0;
+    for (int c = 1; c < kCand; ++c)
+        if (best_sweep[c] < best_sweep[bi]) bi = c;
+    h->cfg = cand[bi];
+    const int32_t g = std::min<int32_t>(steps_per_trial, 64);
+    double direct = 1e300, graphed = 1e300;
+    for (int round = 0; round < 2; ++round) {
         double us = 0;
-        lbib_status s = run_trial(c, 0, us);
+        lbib_status s = step_trial(0, us);
         if (s != LBIB_OK) return s;
-        if (us < best_us) best_us = us, best = c;
+        direct = std::min(direct, us);
+        if ((s = step_trial(g, us)) != LBIB_OK) return s;
+        graphed = std::min(graphed, us);
     }
-    int32_t best_graph = 0;
-    {
-        const int32_t g = std::min<int32_t>(steps_per_trial, 64);
-        double us = 0;
-        lbib_status s = run_trial(best, g, us);
-        if (s != LBIB_OK) return s;
-        if (us < best_us) best_us = us, best_graph = g;
-    }
-    h->cfg = best;
-    h->graph_steps = best_graph;
+    h->graph_steps = graphed < direct ? g : 0;
     h->dirty = true;
-    h->timing = timing_was;
-    if (best_step_us) *best_step_us = best_us;
+    h->timing = false;
+    if (best_step_us) *best_step_us = std::min(direct, graphed);
     return LBIB_OK;
 }
 

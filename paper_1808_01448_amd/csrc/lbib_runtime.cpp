@@ -25,7 +25,7 @@ constexpr int kTimingPool = 8192;  // event pairs per kernel kind
 constexpr int kKinds = 3;  // 0 lattice sweep (all or outside the box), 1 particle phase, 2 box sweep
 
 struct Timing {
-    bool on = false;
+    int32_t mask = 0;  // bit k: time kernel kind k
     std::vector<hipEvent_t> ev[kKinds];
     size_t used[kKinds] = {0, 0, 0};
     int64_t launches[kKinds] = {0, 0, 0};
@@ -40,6 +40,7 @@ struct lbib_sim {
     hipStream_t stream2 = nullptr;  // particle chain of the overlapped schedule
     hipEvent_t evA = nullptr, evB = nullptr;
     int overlap = 2;  // 0 serial, 1 overlapped, 2 chosen by lattice size
+    int layout = 2;   // 0 push, 1 pull, 2 chosen by lattice size (at lbib_init)
     bool zone_valid = false;  // the zone slot of the next step holds its box
     int state = 0;  // 0 created, 1 running, 2 failed
     std::string err;
@@ -127,7 +128,7 @@ EvPair timing_events(lbib_sim* h, int kind)
 {
     Timing& t = h->timing;
     EvPair p;
-    if (!t.on || t.used[kind] + 2 > t.ev[kind].size()) return p;
+    if (!(t.mask >> kind & 1) || t.used[kind] + 2 > t.ev[kind].size()) return p;
     p.t0 = t.ev[kind][t.used[kind]];
     p.t1 = t.ev[kind][t.used[kind] + 1];
     t.used[kind] += 2;
@@ -150,7 +151,7 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
         T* fout = (T*)h->fB;
         if (h->parts.empty()) {
             const EvPair e0 = timing_events(h, 0);
-            HIPCHK(h, launch_sweep<T>(fin, fout, sa, SWEEP_ALL, nullptr, nullptr, 0, h->stream, e0.t0, e0.t1));
+            HIPCHK(h, launch_sweep<T>(fin, fout, sa, SWEEP_ALL, nullptr, nullptr, 0, h->g.pull, h->stream, e0.t0, e0.t1));
         } else {
             Particle& p = h->parts[0];
             ParticleArgs<T> pa = particle_args<T>(h, p);
@@ -166,7 +167,7 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
                 const EvPair e1 = timing_events(h, 1);
                 HIPCHK(h, launch_particle<T>(pa, h->stream, e1.t0, e1.t1));
                 const EvPair e0 = timing_events(h, 0);
-                HIPCHK(h, launch_sweep<T>(fin, fout, sa, SWEEP_ALL, p.d_desc, p.d_tile, p.box_cap, h->stream, e0.t0,
+                HIPCHK(h, launch_sweep<T>(fin, fout, sa, SWEEP_ALL, p.d_desc, p.d_tile, p.box_cap, h->g.pull, h->stream, e0.t0,
                                           e0.t1));
                 HIPCHK(h, hipEventRecord(h->evA, h->stream));
                 h->zone_valid = true;
@@ -177,11 +178,11 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
                 HIPCHK(h, launch_particle<T>(pa, h->stream2, e1.t0, e1.t1));
                 HIPCHK(h, hipStreamWaitEvent(h->stream, h->evB, 0));
                 const EvPair e0 = timing_events(h, 0);
-                HIPCHK(h, launch_sweep<T>(fin, fout, sa, SWEEP_OUTSIDE, p.d_zone + par, nullptr, 0, h->stream, e0.t0,
+                HIPCHK(h, launch_sweep<T>(fin, fout, sa, SWEEP_OUTSIDE, p.d_zone + par, nullptr, 0, h->g.pull, h->stream, e0.t0,
                                           e0.t1));
                 HIPCHK(h, hipEventRecord(h->evA, h->stream));
                 const EvPair e2 = timing_events(h, 2);
-                HIPCHK(h, launch_sweep<T>(fin, fout, sa, SWEEP_BOX, p.d_desc, p.d_tile, p.box_cap, h->stream2, e2.t0,
+                HIPCHK(h, launch_sweep<T>(fin, fout, sa, SWEEP_BOX, p.d_desc, p.d_tile, p.box_cap, h->g.pull, h->stream2, e2.t0,
                                           e2.t1));
                 HIPCHK(h, hipEventRecord(h->evB, h->stream2));
                 joined = false;
@@ -235,7 +236,7 @@ lbib_status download_f(lbib_sim* h, std::vector<double>& f)
 
 struct BlobHeader {
     char magic[8];
-    int32_t version, nx, ny, precision, n_particles, nl;
+    int32_t version, nx, ny, precision, n_particles, nl, layout;
     int64_t steps, pop_bytes;
 };
 
@@ -341,6 +342,9 @@ lbib_status lbib_init(lbib_handle h)
     for (auto& p : h->parts)
         if (!p.has_ligands) return fail(h, LBIB_E_STATE, "lbib_init: lbib_ligands_set missing for a particle");
     const size_t bytes = (size_t)9 * h->g.plane * h->g.elem;
+    // the push update's shifted stores are cheap while both buffers fit the 256 MB MALL
+    // beside the rest of the working set; far above it the pull update's aligned stores win
+    h->g.pull = h->layout == 1 || (h->layout == 2 && 2.0 * bytes > 512.0 * 1048576.0);
     hipError_t e;
     if ((e = hipMalloc(&h->fA, bytes)) != hipSuccess || (e = hipMalloc(&h->fB, bytes)) != hipSuccess ||
         (e = dalloc(&h->d_flags, 1)) != hipSuccess) {
@@ -582,13 +586,14 @@ lbib_status lbib_save(lbib_handle h, void* blob, int64_t* size)
     HIPCHK(h, hipStreamSynchronize(h->stream));
     char* w = (char*)blob;
     BlobHeader hd{};
-    std::memcpy(hd.magic, "LBIBCKP1", 8);
+    std::memcpy(hd.magic, "LBIBCKP2", 8);
     hd.version = LBIB_ABI_VERSION;
     hd.nx = h->desc.nx;
     hd.ny = h->desc.ny;
     hd.precision = h->desc.precision;
     hd.n_particles = (int32_t)h->parts.size();
     hd.nl = h->parts.empty() ? 0 : h->parts[0].nl;
+    hd.layout = h->g.pull ? 1 : 0;
     hd.steps = h->steps;
     hd.pop_bytes = (int64_t)9 * h->g.plane * (int64_t)h->g.elem;
     std::memcpy(w, &hd, sizeof(hd));
@@ -613,7 +618,8 @@ lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size)
     if (size != (int64_t)blob_size(h)) return fail(h, LBIB_E_INVALID, "lbib_load: blob size does not match this simulation");
     BlobHeader hd;
     std::memcpy(&hd, blob, sizeof(hd));
-    if (std::memcmp(hd.magic, "LBIBCKP1", 8) != 0 || hd.version != LBIB_ABI_VERSION || hd.nx != h->desc.nx ||
+    if (std::memcmp(hd.magic, "LBIBCKP2", 8) != 0 || hd.version != LBIB_ABI_VERSION || hd.nx != h->desc.nx ||
+        hd.layout != (h->g.pull ? 1 : 0) ||
         hd.ny != h->desc.ny || hd.precision != h->desc.precision || hd.n_particles != (int32_t)h->parts.size() ||
         (hd.n_particles && hd.nl != h->parts[0].nl) || hd.pop_bytes != (int64_t)9 * h->g.plane * (int64_t)h->g.elem)
         return fail(h, LBIB_E_INVALID, "lbib_load: checkpoint was made with different descriptors");
@@ -652,7 +658,7 @@ lbib_status lbib_kernel_timing(lbib_handle h, int32_t enable)
             t.launches[k] = 0;
         }
     }
-    t.on = enable != 0;
+    t.mask = enable & 7;
     return LBIB_OK;
 }
 
@@ -679,6 +685,23 @@ lbib_status lbib_set_overlap(lbib_handle h, int32_t mode)
     if (!h) return fail(nullptr, LBIB_E_INVALID, "lbib_set_overlap: NULL handle");
     if (mode < 0 || mode > 2) return fail(h, LBIB_E_INVALID, "lbib_set_overlap: mode must be 0, 1 or 2");
     h->overlap = mode;
+    return LBIB_OK;
+}
+
+lbib_status lbib_set_layout(lbib_handle h, int32_t mode)
+{
+    if (!h) return fail(nullptr, LBIB_E_INVALID, "lbib_set_layout: NULL handle");
+    if (mode < 0 || mode > 2) return fail(h, LBIB_E_INVALID, "lbib_set_layout: mode must be 0, 1 or 2");
+    if (h->state != 0) return fail(h, LBIB_E_STATE, "lbib_set_layout: must precede lbib_init");
+    h->layout = mode;
+    return LBIB_OK;
+}
+
+lbib_status lbib_get_layout(lbib_handle h, int32_t* pull)
+{
+    if (!h || !pull) return fail(h, LBIB_E_INVALID, "lbib_get_layout: NULL argument");
+    if (h->state == 0) return fail(h, LBIB_E_STATE, "lbib_get_layout: the layout is chosen by lbib_init");
+    *pull = h->g.pull ? 1 : 0;
     return LBIB_OK;
 }
 

@@ -86,6 +86,8 @@ _SIGS = {
     "lbib_load": (C.c_int, [_P, _P, C.c_int64]),
     "lbib_kernel_timing": (C.c_int, [_P, C.c_int32]),
     "lbib_set_overlap": (C.c_int, [_P, C.c_int32]),
+    "lbib_set_layout": (C.c_int, [_P, C.c_int32]),
+    "lbib_get_layout": (C.c_int, [_P, C.POINTER(C.c_int32)]),
     "lbib_kernel_time": (C.c_int, [_P, C.c_int32, _D, _I64]),
     "lbib_bytes_per_update": (C.c_int, [_P, _I64]),
     "lbib_last_error": (C.c_char_p, [_P]),
@@ -182,7 +184,7 @@ def _trace_array(buf, count: int) -> np.ndarray:
 class Sim:
     """One simulation: lattice, at most one particle, ligands, receptors."""
 
-    def __init__(self, workload: dict, stream=None, *, init: bool = True):
+    def __init__(self, workload: dict, stream=None, *, init: bool = True, layout: int = 2):
         L = lib()
         lat = workload["lattice"]
         self.workload = workload
@@ -205,6 +207,7 @@ class Sim:
                 r = workload.get("receptor", {"wall": 0, "density": 1.0})
                 rd = ReceptorDesc(int(r["wall"]), float(r["density"]))
                 self._call(L.lbib_receptors_set, C.byref(rd))
+            self._call(L.lbib_set_layout, int(layout))
             if init:
                 self._call(L.lbib_init)
         except Exception:
@@ -322,13 +325,22 @@ class Sim:
         buf = C.create_string_buffer(blob, len(blob))
         self._call(lib().lbib_load, buf, len(blob))
 
+    @property
+    def pull(self) -> bool:
+        """True when the population buffers use the pull layout."""
+        v = C.c_int32()
+        self._call(lib().lbib_get_layout, C.byref(v))
+        return bool(v.value)
+
     def set_overlap(self, mode):
         """0 / False: serial; 1 / True: overlapped; 2: chosen by lattice size (default)."""
         self._call(lib().lbib_set_overlap, int(mode))
 
     # -- timing --------------------------------------------------------------------------
-    def kernel_timing(self, enable: bool):
-        self._call(lib().lbib_kernel_timing, 1 if enable else 0)
+    def kernel_timing(self, enable=True):
+        """True: time all three kernels; False: off; an int: bit mask of the kernels to time."""
+        mask = 7 if enable is True else 0 if enable is False else int(enable)
+        self._call(lib().lbib_kernel_timing, mask)
 
     def kernel_time(self, kernel: int):
         """(total milliseconds, launches) of kernel 0 (lattice sweep: all nodes, or the nodes
@@ -449,7 +461,7 @@ class Pool:
         self._call(lib().lbib_pool_read_trace, int(slot), buf, int(capacity), C.byref(cnt))
         return _trace_array(buf, cnt.value)
 
-    def set_config(self, tile_x: int = 64, tiles_per_block: int = 4, graph_steps: int = 0):
+    def set_config(self, tile_x: int = 256, tiles_per_block: int = 4, graph_steps: int = 0):
         self._call(lib().lbib_pool_set_config, int(tile_x), int(tiles_per_block), int(graph_steps))
 
     def config(self):

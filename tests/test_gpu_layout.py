@@ -1,0 +1,158 @@
+"""GPU tests of the two population-buffer layouts (push and pull streaming).
+
+Streaming is a permutation of values, so the pull layout (buffers hold post-collision
+values, each node gathers its inflow) must reproduce the push layout (buffers hold the
+streamed values, each node scatters its outflow) bit for bit: fields, particle records,
+bonds, through the overlapped schedule, checkpoints and population overwrites.  The push
+layout is held to the FP64 oracle by test_gpu_sim.py; the pull layout is also compared with
+the oracle directly here."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1808_01448_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_1808_01448_amd import lbib
+
+    lbib.lib()
+    return lbib
+
+
+def run(L, w, steps, layout, overlap=0):
+    s = L.Sim(w, layout=layout)
+    assert s.pull == (layout == 1)
+    s.set_overlap(overlap)
+    s.trace_enable(steps)
+    s.step(steps)
+    s.sync()
+    out = dict(trace=s.trace(steps), f=s.f, bonds=s.bonds()[0], particle=s.particle())
+    return s, out
+
+
+def same(a, b, what):
+    np.testing.assert_array_equal(a["trace"], b["trace"], err_msg=what)
+    np.testing.assert_array_equal(a["f"], b["f"], err_msg=what)
+    np.testing.assert_array_equal(a["bonds"], b["bonds"], err_msg=what)
+    assert a["particle"] == b["particle"], what
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("overlap", [0, 1])
+def test_pull_equals_push(L, prec, overlap):
+    w = W.channel_small_binding(prec)
+    sa, a = run(L, w, 300, 0, overlap)
+    sb, b = run(L, w, 300, 1, overlap)
+    say("layouts", prec, "overlap", overlap, "bonds", int(a["bonds"].sum()))
+    same(a, b, f"{prec} overlap {overlap}")
+    sa.close()
+    sb.close()
+
+
+def test_pull_ragged_lattice_and_seam(L):
+    """Padded rows, partial tiles and a particle across the periodic seam."""
+    w = W.channel_small_binding("fp64")
+    w["lattice"].update(nx=100, ny=37)
+    w["particle"].update(shape=1, a_major=7.0, b_minor=3.5, xc=1.2, yc=-0.5 + 0.15 + 7.0, theta0=0.4)
+    sa, a = run(L, w, 200, 0)
+    sb, b = run(L, w, 200, 1)
+    same(a, b, "ragged")
+    sa.close()
+    sb.close()
+
+
+def test_pull_against_oracle(L, orc):
+    w = W.channel_small_binding("fp64")
+    steps = 400
+    s, g = run(L, w, steps, 1)
+    o = orc.Sim.from_workload(w)
+    _, to = o.step(steps, trace=True)
+    x0 = np.array([w["particle"]["xc"], w["particle"]["yc"]])
+    eX = np.linalg.norm(g["trace"][:, 1:3] - to[:, 1:3]) / np.linalg.norm(to[:, 1:3] - x0)
+    eU = np.linalg.norm(g["trace"][:, 4:6] - to[:, 4:6]) / np.linalg.norm(to[:, 4:6])
+    ef = np.linalg.norm(g["f"] - o.f) / np.linalg.norm(o.f - orc.lattice()[2][:, None, None])
+    say(f"pull vs oracle: displacement {eX:.2e} velocity {eU:.2e} populations {ef:.2e}")
+    assert max(eX, eU) < 1e-10
+    # populations are compared by their deviation from the weights (~1e-5 here): the oracle
+    # stores plain f ~ 0.4, whose FP64 rounding is ~5e-12 of that deviation per step, a random
+    # walk of ~1e-10 after 400 steps; the GPU stores f - w and does not add it
+    assert ef < 2e-9
+    np.testing.assert_array_equal(g["trace"][:, -2], to[:, -2])
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_pull_populations_roundtrip_and_overwrite(L, orc, prec):
+    """write_populations / read-outs are layout-independent: the same plain populations
+    written into both layouts read back identically and evolve identically."""
+    w = W.with_precision(W.channel_small_binding(prec), prec)
+    f0 = None
+    out = []
+    for layout in (0, 1):
+        s = L.Sim(w, layout=layout)
+        s.step(20)
+        if f0 is None:
+            f0 = s.f + W.random_perturbation(5, (9, w["lattice"]["ny"], w["lattice"]["nx"]), 1e-6)
+        s.write_populations(f0)
+        back = s.f
+        s.step(30)
+        out.append((back, s.f, s.particle()))
+        s.close()
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    assert out[0][2] == out[1][2]
+    if prec == "fp64":
+        np.testing.assert_allclose(out[0][0], f0, rtol=0, atol=1e-15)
+
+
+def test_pull_checkpoint_resume(L):
+    w = W.channel_small_binding("fp32")
+    a = L.Sim(w, layout=1)
+    a.step(120)
+    blob = a.save()
+    a.step(80)
+    b = L.Sim(w, layout=1)
+    b.load(blob)
+    b.step(80)
+    np.testing.assert_array_equal(a.f, b.f)
+    assert a.particle() == b.particle()
+    c = L.Sim(w, layout=0)
+    with pytest.raises(L.LbibError) as ei:
+        c.load(blob)  # a checkpoint loads only into the layout it was made in
+    assert ei.value.status == L.E_INVALID
+    for s in (a, b, c):
+        s.close()
+
+
+def test_full_size_layouts_agree(L):
+    """The 4096 x 1024 FP32 workload in both layouts, overlapped schedule: 30 steps, particle
+    trace bit-identical and sampled populations equal."""
+    w = W.channel_large_fp32()
+    sa, a = run_light(L, w, 30, 0)
+    sb, b = run_light(L, w, 30, 1)
+    np.testing.assert_array_equal(a["trace"], b["trace"])
+    np.testing.assert_array_equal(a["u"], b["u"])
+    sa.close()
+    sb.close()
+
+
+def run_light(L, w, steps, layout):
+    s = L.Sim(w, layout=layout)
+    s.set_overlap(1)
+    s.trace_enable(steps)
+    s.step(steps)
+    s.sync()
+    _, ux, uy = s.fields()
+    return s, dict(trace=s.trace(steps), u=np.stack([ux[::7, ::5], uy[::7, ::5]]))

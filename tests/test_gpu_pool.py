@@ -282,13 +282,14 @@ def test_pool_launch_shapes_and_graph_replay_are_bit_identical(L, cfg):
 def test_pool_autotune(L):
     cases = mix("fp32")
     P = L.Pool(L.FP32)
-    slots = [P.add(w, 400) for w, _ in cases]
+    slots = [P.add(w, 1000) for w, _ in cases]
     us = P.autotune(5)
     cfg = P.config()
     say("autotune picked", cfg, f"{us:.1f} us/step")
     assert us > 0 and cfg[0] in (64, 128, 256) and cfg[1] in (1, 2, 4, 8) and cfg[2] in (0, 5)
-    P.step(400)
+    assert all(P.status(s)[0] < 1000 for s in slots)
+    P.step(1000)
     assert sorted(P.poll()) == sorted(slots)
     w, _ = cases[2]
-    assert_same(pooled(P, slots[2], 0), dict(alone(L, w, 400), trace=np.zeros((0, 20))), "after autotune")
+    assert_same(pooled(P, slots[2], 0), dict(alone(L, w, 1000), trace=np.zeros((0, 20))), "after autotune")
     P.close()
