@@ -105,6 +105,47 @@ def batched_leg(steps: int, stream) -> dict:
     }
 
 
+def serving_leg(n: int, full: bool, stream) -> dict:
+    """Poisson arrivals of single-particle solves at 0.7 x the server's measured capacity,
+    served by continuous batching, against the plain one-simulation-at-a-time server on the
+    same arrival trace."""
+    import numpy as np
+
+    from paper_1808_01448_amd import measure
+    from paper_1808_01448_amd import workloads as W
+
+    steps_range = (5_000, 50_000) if full else (1_000, 5_000)
+    ws = W.serving_requests(n, 0, steps_range=steps_range)
+    mean_lu = float(np.mean([w["lattice"]["nx"] * w["lattice"]["ny"] * w["steps"] for w in ws]))
+    # pilot: the first half of the requests at a quarter of their steps, all arriving at once
+    pilot_ws = [dict(w, steps=max(1, w["steps"] // 4)) for w in ws[: max(1, n // 2)]]
+    log(f"bench: serving pilot, {len(pilot_ws)} requests arriving together")
+    pilot = measure.serve_trace(pilot_ws, np.zeros(len(pilot_ws)), stream=stream)
+    capacity = pilot["mlups"] * 1e6 / mean_lu
+    rate = 0.7 * capacity
+    arrivals = W.poisson_arrivals(n, rate, seed=0)
+    log(f"bench: serving {n} requests at {rate:.2f}/s (capacity {capacity:.2f}/s)")
+    srv = measure.serve_trace(ws, arrivals, stream=stream)
+    log(f"bench: served in {srv['makespan_s']:.2f} s; plain server on the same trace")
+    plain = measure.plain_fifo(ws, arrivals, stream=stream)
+    same = all(r["final_state"] == p for r, p in zip(srv["results"], plain["finals"]))
+    ls, lp = measure.percentiles(srv["latency_s"]), measure.percentiles(plain["latency_s"])
+    return {
+        "workload": f"{n} single-particle solves, nx log-U[256,4096] x ny log-U[64,512], steps U[{steps_range[0]},"
+                    f"{steps_range[1]}], shape/ligand density/bond strength/Re from the sweep's sets, FP32"
+                    + ("" if full else " (step counts 1/10 of the full mix)"),
+        "arrival_rate_per_s": round(rate, 3), "capacity_per_s": round(capacity, 3), "load": 0.7,
+        "unit": "MLUPS", "served": round(srv["mlups"], 1), "plain": round(plain["mlups"], 1),
+        "speedup_vs_plain": round(srv["mlups"] / plain["mlups"], 3),
+        "latency_s": {"served": {k: round(v, 4) for k, v in ls.items()},
+                      "plain": {k: round(v, 4) for k, v in lp.items()}},
+        "wait_s_served": {k: round(v, 4) for k, v in measure.percentiles(srv["wait_s"]).items()},
+        "makespan_s": {"served": round(srv["makespan_s"], 3), "plain": round(plain["makespan_s"], 3)},
+        "chunk_steps": 200, "chunks": srv["chunks"], "failed": srv["failed"],
+        "results_equal_plain": bool(same),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +155,9 @@ def main():
     ap.add_argument("--no-timing-events", action="store_true", help="time only the whole steps")
     ap.add_argument("--batched-steps", type=int, default=200,
                     help="steps of the 216-simulation sweep, pooled and plain (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=64, help="requests of the serving leg (0: skip)")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="serving leg at the full request mix: 256 requests of 5k-50k steps (several minutes)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -196,6 +240,10 @@ def main():
     if args.batched_steps > 0:
         batched = batched_leg(args.batched_steps, stream)
 
+    served = None
+    if args.serve_requests > 0 or args.serve_full:
+        served = serving_leg(256 if args.serve_full else args.serve_requests, args.serve_full, stream)
+
     cpu = None
     if args.cpu_steps > 0:
         log(f"bench: CPU oracle baseline, {args.cpu_steps} steps")
@@ -224,6 +272,7 @@ def main():
         "copy_bandwidth_gbs": round(copy_gbs, 1),
         "cpu_baseline": cpu,
         "batched": batched,
+        "served": served,
         "final_particle": {k: p[k] for k in ("step", "xc", "yc", "theta", "n_bonds")},
     }
     print(json.dumps(out), flush=True)

@@ -281,9 +281,10 @@ typedef struct lbib_pool* lbib_pool_handle;
 enum { LBIB_POOL_RUNNING = 0, LBIB_POOL_FINISHED = 1, LBIB_POOL_FAILED = 2 };
 
 /* Create a pool.  precision: LBIB_FP64 or LBIB_FP32 storage for every member;
- * hbm_budget_bytes: device memory the members may occupy together (the pool's own tables
- * come on top: about 16 bytes per 256 lattice nodes and 1 KB per member); max_members in
- * [1, 65536]; hip_stream as for lbib_create. */
+ * hbm_budget_bytes: device memory the members may occupy together, allocated here in one
+ * piece (members are placed in it first fit, so joining and leaving never allocate or free
+ * device memory; the pool's own tables come on top: about 8 bytes per 256 lattice nodes and
+ * 1 KB per member); max_members in [1, 65536]; hip_stream as for lbib_create. */
 lbib_status lbib_pool_create(int32_t precision, int64_t hbm_budget_bytes, int32_t max_members, void* hip_stream,
                              lbib_pool_handle* out);
 
@@ -296,7 +297,9 @@ lbib_status lbib_pool_footprint(const lbib_lattice_desc* lattice, const lbib_par
  * as by lbib_create / lbib_particle_add / lbib_ligands_set; lattice->precision must match
  * the pool's), initialised as by lbib_init, to run n_steps steps.  *slot receives its id
  * (ids are never reused within a pool).  LBIB_E_FULL when the budget or max_members would
- * be exceeded; nothing is changed then. */
+ * be exceeded, or when no contiguous free part of the budget is large enough; nothing is
+ * changed then.  The member's initialisation is enqueued on the pool's stream (the call
+ * does not wait for the GPU). */
 lbib_status lbib_pool_add(lbib_pool_handle p, const lbib_lattice_desc* lattice, const lbib_particle_desc* particle,
                           const lbib_ligand_desc* ligands, int64_t n_steps, int32_t* slot);
 
@@ -359,6 +362,70 @@ const char* lbib_pool_last_error(lbib_pool_handle p);
 
 /* Release everything the pool owns.  NULL-safe. */
 void lbib_pool_destroy(lbib_pool_handle p);
+
+/* ---------------------------------------------------------------------------------------
+ * Server: continuous batching of adhesion solves.
+ *
+ * A request is one solve (lattice, particle, ligands, n_steps).  Requests wait on the host
+ * in arrival order and join a pool of the server's as soon as a slot and enough of the
+ * memory budget are free, while earlier requests keep stepping: admission is first fit in
+ * arrival order, but the request at the head of the queue is passed over by later, smaller
+ * ones at most max_bypass times (0: strict arrival order).  The pool steps chunk_steps
+ * steps per lbib_server_progress call; a request that completes inside a chunk waits for
+ * the chunk's end.  Completed requests leave the pool at once and keep their result until
+ * lbib_server_release.  A request's result is bit-identical to the same solve run alone
+ * (the bond draws are keyed by the lattice seed, never by the slot).  Times are seconds on
+ * the server's clock (a host steady clock started by lbib_server_create).
+ * ------------------------------------------------------------------------------------- */
+
+typedef struct lbib_server* lbib_server_handle;
+
+enum { LBIB_REQ_QUEUED = 0, LBIB_REQ_RUNNING = 1, LBIB_REQ_DONE = 2, LBIB_REQ_FAILED = 3 };
+
+typedef struct {
+    int64_t id;
+    int32_t state; /* LBIB_REQ_* */
+    int32_t slot;  /* pool slot while running, else -1 */
+    int64_t steps, steps_done;
+    int64_t bytes; /* device footprint */
+    double t_arrival, t_submit, t_admit, t_done;
+    lbib_particle_state final_state; /* the last step's particle record (step -1 before any) */
+} lbib_request_result;
+
+/* Create a server: a pool of the given precision, memory budget and member count (as
+ * lbib_pool_create), chunk_steps in [1, 10^6] steps per progress call, max_bypass >= 0. */
+lbib_status lbib_server_create(int32_t precision, int64_t hbm_budget_bytes, int32_t max_members, int32_t chunk_steps,
+                               int32_t max_bypass, void* hip_stream, lbib_server_handle* out);
+
+/* Queue a request (descriptors validated now); arrival_s is its arrival time on the
+ * server's clock (negative: now).  LBIB_E_FULL when it alone exceeds the budget. */
+lbib_status lbib_server_submit(lbib_server_handle s, const lbib_lattice_desc* lattice,
+                               const lbib_particle_desc* particle, const lbib_ligand_desc* ligands, int64_t n_steps,
+                               double arrival_s, int64_t* id);
+
+/* One scheduling round: admit what fits, step the pool chunk_steps steps (if anything
+ * runs), collect the completed requests.  *n_completed (may be NULL) receives how many
+ * completed requests await lbib_server_take_completed. */
+lbib_status lbib_server_progress(lbib_server_handle s, int32_t* n_completed);
+
+/* Ids of completed requests, oldest first (up to capacity; the rest stay for the next call). */
+lbib_status lbib_server_take_completed(lbib_server_handle s, int64_t* ids, int32_t capacity, int32_t* count);
+
+/* A request's current record; lbib_server_release frees a completed one. */
+lbib_status lbib_server_result(lbib_server_handle s, int64_t id, lbib_request_result* out);
+lbib_status lbib_server_release(lbib_server_handle s, int64_t id);
+
+/* Requests waiting and running, pool bytes in use, chunks stepped so far. */
+lbib_status lbib_server_stats(lbib_server_handle s, int32_t* queued, int32_t* running, int64_t* bytes_in_use,
+                              int64_t* chunks);
+
+/* The server's pool (for kernel timing and launch configuration; do not add or remove
+ * members through it) and its clock. */
+lbib_pool_handle lbib_server_pool(lbib_server_handle s);
+double lbib_server_clock(lbib_server_handle s);
+
+const char* lbib_server_last_error(lbib_server_handle s);
+void lbib_server_destroy(lbib_server_handle s);
 
 /* ---------------------------------------------------------------------------------------
  * Kernel-level entry points.  They run the same device functions as the time step on

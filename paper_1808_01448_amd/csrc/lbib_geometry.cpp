@@ -46,12 +46,14 @@ ArcSeries make_series(double a, double b)
     for (int k = 0; k < N; ++k) s0 += v[k];
     S.c0 = s0 / N;
     const double scale = std::fabs(S.c0);
+    // the coefficients fall geometrically, as ((a - b) / (a + b))^m; below ~1e-14 of the mean
+    // they are the trapezoid sums' round-off, so the series stops there
     for (int m = 1; m < N / 2; ++m) {
         double cm = 0.0;
         for (int k = 0; k < N; ++k) cm += v[k] * std::cos(2.0 * m * M_PI * k / N);
         cm *= 2.0 / N;
+        if (m > 8 && std::fabs(cm) < 1e-14 * scale) break;
         S.c.push_back(cm);
-        if (m > 8 && std::fabs(cm) < 1e-19 * scale) break;
     }
     return S;
 }
@@ -84,10 +86,10 @@ bool build_surface(int shape, double a, double b, int nl, Surface& out)
         for (int k = 1; k < nl; ++k) {
             const double target = P * k / nl;
             double t = 2.0 * M_PI * k / nl;
-            for (int it = 0; it < 60; ++it) {
+            for (int it = 0; it < 60; ++it) {  // quadratic convergence: a few steps reach round-off
                 const double dt = (S.arc(t) - target) / S.speed(t);
                 t -= dt;
-                if (std::fabs(dt) < 1e-16 * (1.0 + std::fabs(t))) break;
+                if (std::fabs(dt) < 1e-15 * (1.0 + std::fabs(t))) break;
             }
             vx[k] = b * std::sin(t);
             vy[k] = -a * std::cos(t);

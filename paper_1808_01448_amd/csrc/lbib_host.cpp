@@ -117,60 +117,84 @@ lbib_status prepare_particle(const lbib_lattice_desc& lat, const lbib_particle_d
     // MLS support reaches 1.5 further, so any orientation's box has at most
     // ceil(2 amax + 2.4) + 4 nodes per side (one more kept as margin)
     const int side = (int)std::ceil(2.0 * amax + 2.4) + 5;
+    if ((double)side * side > 1.0e6) return msg = "particle too large (box of more than 10^6 nodes)", LBIB_E_INVALID;
     p.box_cap = side * side;
+    if (!particle_lds_bytes(p.box_cap) && particle_lds_aux_bytes(p.box_cap) > 158 * 1024)
+        return msg = "particle too large for the node mask in LDS", LBIB_E_INVALID;
     return LBIB_OK;
+}
+
+size_t particle_block_bytes(const Particle& p)
+{
+    const size_t nl = (size_t)p.nl, cap = (size_t)p.box_cap;
+    const bool global_box = !particle_lds_bytes(p.box_cap);
+    return 2 * align_up(2 * nl * 8) + align_up(nl * 8) + 2 * align_up(nl) + align_up(2 * cap * 8) +
+           (global_box ? align_up(6 * cap * 8) : 0) + align_up(sizeof(TileDesc)) + align_up(2 * sizeof(TileDesc)) +
+           align_up(sizeof(DevParticle));
+}
+
+void carve_particle(Particle& p, char* block)
+{
+    const size_t nl = (size_t)p.nl, cap = (size_t)p.box_cap;
+    char* c = block;
+    auto take = [&](size_t bytes) {
+        char* r = c;
+        c += align_up(bytes);
+        return r;
+    };
+    p.d_xi = (double*)take(2 * nl * 8);
+    p.d_nuv = (double*)take(2 * nl * 8);
+    p.d_S = (double*)take(nl * 8);
+    p.d_lig = (uint8_t*)take(nl);
+    p.d_bond = (uint8_t*)take(nl);
+    p.d_tile = (int64_t*)take(2 * cap * 8);
+    p.d_box = particle_lds_bytes(p.box_cap) ? nullptr : (double*)take(6 * cap * 8);
+    p.d_desc = (TileDesc*)take(sizeof(TileDesc));
+    p.d_zone = (TileDesc*)take(2 * sizeof(TileDesc));
+    p.d_st = (DevParticle*)take(sizeof(DevParticle));
+    p.block = block;
+    p.own_block = false;
 }
 
 int64_t footprint_bytes(const lbib_lattice_desc& lat, const Particle* p)
 {
     const LatticeGeom g = lattice_geom(lat);
-    int64_t bytes = 2 * 9 * g.plane * (int64_t)g.elem;
-    if (p) {
-        const int64_t nl = p->nl;
-        bytes += nl * (5 * 8 + 2) + 2 * 8 * (int64_t)p->box_cap + 3 * (int64_t)sizeof(TileDesc) + (int64_t)sizeof(DevParticle);
-        if (!particle_lds_bytes(p->box_cap)) bytes += 6 * 8 * (int64_t)p->box_cap;
-    }
+    int64_t bytes = 2 * (int64_t)align_up((size_t)9 * g.plane * g.elem);
+    if (p) bytes += (int64_t)particle_block_bytes(*p);
     return bytes;
 }
 
 hipError_t alloc_particle(Particle& p)
 {
-    const int nl = p.nl;
-    const size_t tile = (size_t)2 * p.box_cap;
-    const size_t boxg = particle_lds_bytes(p.box_cap) ? 0 : (size_t)6 * p.box_cap;
-    hipError_t e;
-    if ((e = dalloc(&p.d_xi, 2 * nl)) != hipSuccess || (e = dalloc(&p.d_nuv, 2 * nl)) != hipSuccess ||
-        (e = dalloc(&p.d_S, nl)) != hipSuccess || (e = dalloc(&p.d_lig, nl)) != hipSuccess ||
-        (e = dalloc(&p.d_bond, nl)) != hipSuccess || (e = dalloc(&p.d_tile, tile)) != hipSuccess ||
-        (boxg && (e = dalloc(&p.d_box, boxg)) != hipSuccess) || (e = dalloc(&p.d_zone, 2)) != hipSuccess ||
-        (e = dalloc(&p.d_desc, 1)) != hipSuccess || (e = dalloc(&p.d_st, 1)) != hipSuccess) {
-        free_particle(p);
-        return e;
-    }
+    char* block = nullptr;
+    hipError_t e = hipMalloc((void**)&block, particle_block_bytes(p));
+    if (e != hipSuccess) return e;
+    carve_particle(p, block);
+    p.own_block = true;
     return hipSuccess;
 }
 
 void free_particle(Particle& p)
 {
-    dfree(p.d_xi);
-    dfree(p.d_nuv);
-    dfree(p.d_S);
-    dfree(p.d_lig);
-    dfree(p.d_bond);
-    dfree(p.d_tile);
-    dfree(p.d_box);
-    dfree(p.d_desc);
-    dfree(p.d_zone);
-    dfree(p.d_st);
+    if (p.own_block && p.block) (void)hipFree(p.block);
+    p.block = nullptr;
+    p.own_block = false;
+    p.d_xi = p.d_nuv = p.d_S = nullptr;
+    p.d_lig = p.d_bond = nullptr;
+    p.d_tile = nullptr;
+    p.d_box = nullptr;
+    p.d_desc = p.d_zone = nullptr;
+    p.d_st = nullptr;
     dfree(p.d_trace);
     p.trace_cap = 0;
 }
 
-hipError_t upload_particle(Particle& p)
+hipError_t upload_particle(Particle& p, hipStream_t s)
 {
     const int nl = p.nl;
-    std::vector<uint8_t> zeros(nl, 0);
-    DevParticle st{};
+    p.zeros.assign(nl, 0);
+    DevParticle& st = p.st0;
+    st = DevParticle{};
     st.xc = st.xc1 = p.desc.xc;
     st.yc = st.yc1 = p.desc.yc;
     st.th = st.th1 = p.desc.theta0;
@@ -180,16 +204,17 @@ hipError_t upload_particle(Particle& p)
     st.last.yc = st.yc;
     st.last.theta = st.th;
     st.last.gap = st.yc + 0.5 - support_h(p.a, p.b, st.th);
-    TileDesc td[2] = {};
+    p.td0[0] = p.td0[1] = TileDesc{};
     hipError_t e;
-    if ((e = hipMemcpy(p.d_zone, td, sizeof(td), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(p.d_xi, p.surf.xi.data(), 2 * nl * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(p.d_nuv, p.surf.nu.data(), 2 * nl * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(p.d_S, p.surf.S.data(), nl * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(p.d_lig, p.ligand.data(), nl, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(p.d_bond, zeros.data(), nl, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(p.d_st, &st, sizeof(st), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(p.d_desc, td, sizeof(TileDesc), hipMemcpyHostToDevice)) != hipSuccess)
+    if ((e = hipMemcpyAsync(p.d_zone, p.td0, 2 * sizeof(TileDesc), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(p.d_xi, p.surf.xi.data(), 2 * nl * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(p.d_nuv, p.surf.nu.data(), 2 * nl * sizeof(double), hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(p.d_S, p.surf.S.data(), nl * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(p.d_lig, p.ligand.data(), nl, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(p.d_bond, p.zeros.data(), nl, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(p.d_st, &p.st0, sizeof(DevParticle), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(p.d_desc, p.td0, sizeof(TileDesc), hipMemcpyHostToDevice, s)) != hipSuccess)
         return e;
     return hipSuccess;
 }

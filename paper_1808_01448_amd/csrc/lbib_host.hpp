@@ -49,6 +49,14 @@ struct Particle {
     DevParticle* d_st = nullptr;
     lbib_particle_state* d_trace = nullptr;
     int64_t trace_cap = 0, trace_start = 0;
+    // the device buffers above (trace aside) are carved from one block: owned (freed by
+    // free_particle) or provided by the caller (a pool's arena)
+    char* block = nullptr;
+    bool own_block = false;
+    // host staging of the initial upload (kept until the stream-ordered copies have run)
+    DevParticle st0{};
+    TileDesc td0[2] = {};
+    std::vector<uint8_t> zeros;
 };
 
 inline bool is_finite(double v) { return std::isfinite(v); }
@@ -85,10 +93,19 @@ LatticeGeom lattice_geom(const lbib_lattice_desc& d);
 // Device bytes a simulation of this lattice and particle (or none) needs.
 int64_t footprint_bytes(const lbib_lattice_desc& lat, const Particle* p);
 
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
+
+// Bytes of the particle's device block (every buffer aligned to 256 bytes).
+size_t particle_block_bytes(const Particle& p);
+// Point the particle's buffers into `block` (particle_block_bytes(p) bytes, not owned).
+void carve_particle(Particle& p, char* block);
+// One owned device block for the particle's buffers.
 hipError_t alloc_particle(Particle& p);
 void free_particle(Particle& p);
-// Geometry, ligands, no bonds and the particle at rest at its initial placement.
-hipError_t upload_particle(Particle& p);
+// Geometry, ligands, no bonds and the particle at rest at its initial placement, enqueued
+// on `s` (stream-ordered copies from the particle's own staging).
+hipError_t upload_particle(Particle& p, hipStream_t s);
 
 template <typename T>
 void fill_particle_args(ParticleArgs<T>& a, const LatticeGeom& g, uint64_t seed, const Particle& p, int32_t* flags);

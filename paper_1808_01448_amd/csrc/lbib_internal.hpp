@@ -97,9 +97,11 @@ template <typename T>
 hipError_t launch_sweep(const T* fin, T* fout, const SweepArgs& a, int mode, const TileDesc* desc,
                         const int64_t* tile, int32_t box_cap, bool pull, hipStream_t stream, hipEvent_t t0 = nullptr,
                         hipEvent_t t1 = nullptr);
-// Bytes of dynamic LDS the particle phase needs for a box of box_cap nodes, or 0 when the
-// box is kept in global memory instead.
+// Bytes of dynamic LDS the particle phase needs for a box of box_cap nodes kept in LDS, or
+// 0 when the box is kept in global memory instead; then it still needs
+// particle_lds_aux_bytes (the node mask and the fill queues), which must not exceed 158 KB.
 size_t particle_lds_bytes(int32_t box_cap);
+size_t particle_lds_aux_bytes(int32_t box_cap);
 template <typename T>
 hipError_t launch_particle(const ParticleArgs<T>& a, hipStream_t stream, hipEvent_t t0 = nullptr,
                            hipEvent_t t1 = nullptr);
@@ -126,9 +128,11 @@ struct PoolSweepConfig {
     int32_t bx, tpb;
 };
 template <typename T>
+// lds_cap: the largest box kept in LDS; lds: the dynamic LDS of the launch (the most any
+// member needs).
 hipError_t launch_pool_particle(const ParticleArgs<T>* args, const int32_t* active, TileDesc* ctl, int32_t n_active,
-                                int32_t max_nl, int32_t lds_cap, hipStream_t stream, hipEvent_t t0 = nullptr,
-                                hipEvent_t t1 = nullptr);
+                                int32_t max_nl, int32_t lds_cap, size_t lds, hipStream_t stream,
+                                hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 template <typename T>
 hipError_t launch_pool_sweep(const PoolSweep<T>* sims, const TileDesc* ctl, const int2* table, int32_t n_blocks,
                              PoolSweepConfig cfg, hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);

@@ -189,11 +189,120 @@ struct BoxView {
 };
 
 constexpr int kBoxDoubles = 6;  // 4 doubles + 2 64-bit integers per node
+constexpr int kFillU = 4;       // marked nodes per lane in flight while filling the box
+constexpr int kQueue = 64 * kFillU + 64;  // per-wave queue of marked nodes (LDS ints)
+
+// LDS beside the box fields: one bit per box node (marked when some support reaches it) and
+// the per-wave queues of the fill.
+size_t particle_lds_aux_bytes(int32_t box_cap)
+{
+    return (size_t)((box_cap + 31) / 32) * 4 + (size_t)NW * kQueue * 4;
+}
 
 size_t particle_lds_bytes(int32_t box_cap)
 {
-    const size_t bytes = (size_t)box_cap * kBoxDoubles * 8;
+    const size_t bytes = (size_t)box_cap * kBoxDoubles * 8 + particle_lds_aux_bytes(box_cap);
     return bytes <= 158 * 1024 ? bytes : 0;  // gfx950: 160 KB of LDS per workgroup
+}
+
+// Set the bit of every box node in the support window of a marker or probe of this step (the
+// full window of mls_shape: nodes of zero weight are read too, multiplied by zero).
+template <typename T, int MPT>
+__device__ __forceinline__ void mark_supports(const ParticleArgs<T>& a, double xc, double yc, double cth, double sth,
+                                              int x0, int y0, int w, int h, uint32_t* mask)
+{
+#pragma unroll
+    for (int k = 0; k < MPT; ++k) {
+        const int l = threadIdx.x + k * PB;
+        if (l >= a.nl) continue;
+        const MarkerGeo g = marker_geo(a.xi, a.nuv, l, xc, yc, cth, sth, a.ny);
+#pragma unroll
+        for (int pt = 0; pt < 2; ++pt) {
+            int ilo, ihi, jlo, jhi;
+            const bool ok = pt == 0 ? support_range(g.X, fluid_row(g.Y, a.ny), a.ny, ilo, ihi, jlo, jhi)
+                                    : support_range(g.px, g.py, a.ny, ilo, ihi, jlo, jhi);
+            if (!ok) continue;
+            for (int j = jlo; j <= jhi; ++j)
+                for (int i = ilo; i <= ihi; ++i) {
+                    const int di = i - x0, dj = j - y0;
+                    if (di < 0 || di >= w || dj < 0 || dj >= h) continue;
+                    const int n = dj * w + di;
+                    atomicOr(mask + (n >> 5), 1u << (n & 31));
+                }
+        }
+    }
+}
+
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Node fields at the marked nodes of the box.  Each wave walks its share of the box (64
+// consecutive nodes per round), appends the marked ones to its LDS queue (ballot + prefix
+// count) and, whenever 64 U are queued, loads and reduces them U per lane; so the loads in
+// flight stay full while only the ring of nodes next to the surface is read.
+template <typename T, bool LDS>
+__device__ __forceinline__ void fill_marked(const ParticleArgs<T>& a, const BoxView& B, const uint32_t* mask, int nbox,
+                                            int x0, int y0, int w, int* q)
+{
+    const int lane = threadIdx.x & 63;
+    int qn = 0;  // wave-uniform
+    for (int k0 = threadIdx.x & ~63;; k0 += PB) {
+        const bool more = k0 < nbox;
+        if (more) {
+            const int k = k0 + lane;
+            const bool m = k < nbox && ((mask[k >> 5] >> (k & 31)) & 1u);
+            const unsigned long long bal = __ballot(m);
+            const int below = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            if (m) q[qn + below] = k;
+            qn += __popcll(bal);
+        }
+        if (qn >= 64 * kFillU || (!more && qn > 0)) {
+            wave_sync_lds();
+            const int take = min(qn, 64 * kFillU);
+            int kk[kFillU];
+            T v[kFillU][9];
+#pragma unroll
+            for (int u = 0; u < kFillU; ++u) {
+                const int e = lane + 64 * u;
+                kk[u] = e < take ? q[e] : -1;
+                if (kk[u] >= 0) {
+                    const int j = y0 + kk[u] / w;
+                    const int i = wrap(x0 + kk[u] % w, a.nx);
+#pragma unroll
+                    for (int c = 0; c < 9; ++c)
+                        v[u][c] = a.f[pop_index(c, i, j, a.nx, a.ny, a.pitch, a.plane, a.pull != 0)];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kFillU; ++u) {
+                if (kk[u] < 0) continue;
+                double dr, jx, jy;
+                shifted_moments<double, T>(v[u], dr, jx, jy);
+                const double rho = 1.0 + dr;
+                const double inv = 1.0 / rho;
+                const int k = kk[u];
+                B.rho[k] = rho;
+                B.inv[k] = inv;
+                B.ux[k] = (jx + 0.5 * a.gx) * inv;
+                B.uy[k] = (jy + 0.5 * a.gy) * inv;
+                B.fx[k] = 0ull;
+                B.fy[k] = 0ull;
+            }
+            const int rest = qn - take;  // < 64, moved to the front (no overlap: take >= 256)
+            wave_sync_lds();
+            const int mv = lane < rest ? q[take + lane] : 0;
+            wave_sync_lds();
+            if (lane < rest) q[lane] = mv;
+            wave_sync_lds();
+            qn = rest;
+        }
+        if (!more && qn == 0) break;
+    }
 }
 
 template <bool LDS>
@@ -217,6 +326,8 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, double*
     const int nl = a.nl;
     const int cap = a.box_cap;
     double* base = LDS ? lds_box : a.box_global;
+    uint32_t* mask = (uint32_t*)(LDS ? lds_box + (size_t)cap * kBoxDoubles : lds_box);
+    int* queue = (int*)(mask + (cap + 31) / 32) + (tid >> 6) * kQueue;
     BoxView B;
     B.rho = base;
     B.ux = base + cap;
@@ -244,36 +355,13 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, double*
     const bool box_ok = w > 0 && h > 0 && w <= a.nx && (int64_t)w * h <= cap;
     if (!box_ok && tid == 0) flags |= FLAG_TILE;
 
-    // ---- node fields of the box, several nodes per thread in flight --------------------
+    // ---- the box nodes some support reaches this step, then their node fields ----------
     const int nbox = box_ok ? w * h : 0;
-    constexpr int U = 4;
-    for (int k0 = tid; k0 < nbox; k0 += U * PB) {
-        T v[U][9];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int k = min(k0 + u * PB, nbox - 1);  // clamped: duplicates are recomputed, not stored
-            const int j = y0 + k / w;
-            const int i = wrap(x0 + k % w, a.nx);
-#pragma unroll
-            for (int q = 0; q < 9; ++q) v[u][q] = a.f[pop_index(q, i, j, a.nx, a.ny, a.pitch, a.plane, a.pull != 0)];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int k = k0 + u * PB;
-            if (k < nbox) {
-                double dr, jx, jy;
-                shifted_moments<double, T>(v[u], dr, jx, jy);
-                const double rho = 1.0 + dr;
-                const double inv = 1.0 / rho;
-                B.rho[k] = rho;
-                B.inv[k] = inv;
-                B.ux[k] = (jx + 0.5 * a.gx) * inv;
-                B.uy[k] = (jy + 0.5 * a.gy) * inv;
-                B.fx[k] = 0ull;
-                B.fy[k] = 0ull;
-            }
-        }
-    }
+    for (int k = tid; k < (nbox + 31) / 32; k += PB) mask[k] = 0u;
+    __syncthreads();
+    if (box_ok) mark_supports<T, MPT>(a, xc, yc, cth, sth, x0, y0, w, h, mask);
+    __syncthreads();
+    fill_marked<T, LDS>(a, B, mask, nbox, x0, y0, w, queue);
     __syncthreads();
 
     // ---- markers: MLS interpolation and direct forcing ----------------------------------
@@ -366,13 +454,15 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, double*
     __syncthreads();
     if (spread_ok) {
         for (int k = tid; k < nbox; k += PB) {
-            unsigned long long qx, qy;
-            if (LDS) {
-                qx = B.fx[k];
-                qy = B.fy[k];
-            } else {
-                qx = __hip_atomic_load(B.fx + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                qy = __hip_atomic_load(B.fy + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            unsigned long long qx = 0, qy = 0;  // no support reaches an unmarked node
+            if ((mask[k >> 5] >> (k & 31)) & 1u) {
+                if (LDS) {
+                    qx = B.fx[k];
+                    qy = B.fy[k];
+                } else {
+                    qx = __hip_atomic_load(B.fx + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    qy = __hip_atomic_load(B.fy + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
             }
             a.tile[2 * k] = (int64_t)qx;
             a.tile[2 * k + 1] = (int64_t)qy;
@@ -622,10 +712,11 @@ __global__ __launch_bounds__(PB) void pool_particle_kernel(const ParticleArgs<T>
 
 template <typename T>
 hipError_t launch_pool_particle(const ParticleArgs<T>* args, const int32_t* active, TileDesc* ctl, int32_t n_active,
-                                int32_t max_nl, int32_t lds_cap, hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
+                                int32_t max_nl, int32_t lds_cap, size_t lds, hipStream_t stream, hipEvent_t t0,
+                                hipEvent_t t1)
 {
     if (n_active <= 0) return hipSuccess;
-    const size_t lds = (size_t)lds_cap * kBoxDoubles * 8;
+    if (lds > 158 * 1024) return hipErrorInvalidValue;
     static bool attr[3] = {false, false, false};
 #define LBIB_POOL_LAUNCH(M, IDX)                                                                                      \
     do {                                                                                                               \
@@ -657,18 +748,24 @@ hipError_t launch_pool_particle(const ParticleArgs<T>* args, const int32_t* acti
 template <typename T, int MPT>
 hipError_t launch_particle_mpt(const ParticleArgs<T>& a, hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
 {
+    static bool attr_set = false;  // once per instantiation, for the largest LDS request allowed
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)particle_kernel<T, MPT, true>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 158 * 1024);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)particle_kernel<T, MPT, false>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 158 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
     const size_t lds = particle_lds_bytes(a.box_cap);
     if (lds) {
-        static bool attr_set = false;  // once per instantiation, for the largest box allowed
-        if (!attr_set) {
-            hipError_t e = hipFuncSetAttribute((const void*)particle_kernel<T, MPT, true>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, 158 * 1024);
-            if (e != hipSuccess) return e;
-            attr_set = true;
-        }
         hipExtLaunchKernelGGL(particle_kernel<T, MPT, true>, dim3(1), dim3(PB), (uint32_t)lds, stream, t0, t1, 0u, a);
     } else {
-        hipExtLaunchKernelGGL(particle_kernel<T, MPT, false>, dim3(1), dim3(PB), 0u, stream, t0, t1, 0u, a);
+        const size_t aux = particle_lds_aux_bytes(a.box_cap);
+        if (aux > 158 * 1024) return hipErrorInvalidValue;
+        hipExtLaunchKernelGGL(particle_kernel<T, MPT, false>, dim3(1), dim3(PB), (uint32_t)aux, stream, t0, t1, 0u,
+                              a);
     }
     return hipGetLastError();
 }
@@ -806,9 +903,9 @@ hipError_t launch_copy(const float4* src, float4* dst, int64_t n, hipStream_t st
 }
 
 template hipError_t launch_pool_particle<float>(const ParticleArgs<float>*, const int32_t*, TileDesc*, int32_t, int32_t,
-                                                int32_t, hipStream_t, hipEvent_t, hipEvent_t);
+                                                int32_t, size_t, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_pool_particle<double>(const ParticleArgs<double>*, const int32_t*, TileDesc*, int32_t, int32_t,
-                                                 int32_t, hipStream_t, hipEvent_t, hipEvent_t);
+                                                 int32_t, size_t, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_particle<float>(const ParticleArgs<float>&, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_particle<double>(const ParticleArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
 

@@ -27,6 +27,68 @@ namespace {
 
 constexpr int kPoolTimingPool = 8192;  // event pairs per kernel kind
 
+// First-fit sub-allocator over one device allocation made when the pool is created, so a
+// member joins and leaves without a device allocation or free (each of which would wait for
+// the whole device).  Blocks are multiples of 256 bytes; freed blocks merge with free
+// neighbours.
+class Arena {
+  public:
+    hipError_t init(size_t bytes)
+    {
+        size_ = align_up(bytes);
+        hipError_t e = hipMalloc((void**)&base_, size_);
+        if (e != hipSuccess) {
+            base_ = nullptr;
+            size_ = 0;
+            return e;
+        }
+        free_[0] = size_;
+        return hipSuccess;
+    }
+    void release()
+    {
+        if (base_) (void)hipFree(base_);
+        base_ = nullptr;
+        size_ = 0;
+        free_.clear();
+    }
+    // nullptr when no free block is large enough
+    char* alloc(size_t bytes)
+    {
+        bytes = align_up(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            const size_t off = it->first, len = it->second;
+            free_.erase(it);
+            if (len > bytes) free_[off + bytes] = len - bytes;
+            return base_ + off;
+        }
+        return nullptr;
+    }
+    void free(char* p, size_t bytes)
+    {
+        size_t off = (size_t)(p - base_), len = align_up(bytes);
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && off + len == next->first) {
+            len += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                prev->second += len;
+                return;
+            }
+        }
+        free_[off] = len;
+    }
+
+  private:
+    char* base_ = nullptr;
+    size_t size_ = 0;
+    std::map<size_t, size_t> free_;  // offset -> length
+};
+
 struct Member {
     int32_t slot = -1;
     int32_t lane = -1;  // index into the pool-wide state and flag arrays
@@ -35,6 +97,7 @@ struct Member {
     Particle p;
     void* fA = nullptr;
     void* fB = nullptr;
+    char* block = nullptr;  // the member's arena block: fA, fB, then the particle's buffers
     int64_t target = 0;
     int64_t bytes = 0;
     int32_t state = LBIB_POOL_RUNNING;
@@ -58,6 +121,12 @@ struct lbib_pool {
     // pool-wide device arrays, one entry per lane
     DevParticle* d_st = nullptr;
     int32_t* d_flags = nullptr;
+    Arena arena;  // members' device memory
+    // host snapshot of every lane's particle state and flags, valid while nothing has been
+    // enqueued since it was taken
+    std::vector<DevParticle> st_cache;
+    std::vector<int32_t> fl_cache;
+    bool cache_valid = false;
     // launch tables (rebuilt when the set of running members changes)
     bool dirty = true;
     void* d_args = nullptr;
@@ -71,6 +140,7 @@ struct lbib_pool {
     TileDesc* d_ctl = nullptr;  // per running member: its box of the step and the step parity
     size_t ctl_cap = 0;
     int32_t n_active = 0, n_blocks = 0, max_nl = 0, lds_cap = 0;
+    size_t lds_bytes = 0;
     PoolSweepConfig cfg{256, 4};
     // optional replay of graph_steps steps as one HIP graph (rebuilt with the tables)
     int32_t graph_steps = 0;
@@ -107,12 +177,12 @@ lbib_status hip_fail(lbib_pool* h, hipError_t e, const std::string& what)
         if (e_ != hipSuccess) return hip_fail((h), e_, #call);      \
     } while (0)
 
-void free_member(Member& m)
+// The stream must be idle (no enqueued step may still use the block).
+void free_member(lbib_pool* h, Member& m)
 {
-    m.p.d_st = nullptr;  // lanes of the pool-wide array, not owned by the particle
-    free_particle(m.p);
-    if (m.fA) (void)hipFree(m.fA);
-    if (m.fB) (void)hipFree(m.fB);
+    free_particle(m.p);  // the block is the arena's; only an optional trace buffer is freed
+    if (m.block) h->arena.free(m.block, (size_t)m.bytes);
+    m.block = nullptr;
     m.fA = m.fB = nullptr;
 }
 
@@ -142,6 +212,7 @@ lbib_status rebuild(lbib_pool* h)
     std::vector<PoolSweep<T>> sims(run.size());
     std::vector<int2> table;
     int32_t max_nl = 0, lds_cap = 0;
+    size_t lds_bytes = 0;
     for (size_t k = 0; k < run.size(); ++k) {
         Member& m = *run[k];
         ParticleArgs<T>& a = args[k];
@@ -154,7 +225,12 @@ lbib_status rebuild(lbib_pool* h)
         a.parity_out = 1;
         active[k] = (int32_t)k;
         max_nl = std::max(max_nl, m.p.nl);
-        if (particle_lds_bytes(m.p.box_cap)) lds_cap = std::max(lds_cap, m.p.box_cap);
+        if (particle_lds_bytes(m.p.box_cap)) {
+            lds_cap = std::max(lds_cap, m.p.box_cap);
+            lds_bytes = std::max(lds_bytes, particle_lds_bytes(m.p.box_cap));
+        } else {
+            lds_bytes = std::max(lds_bytes, particle_lds_aux_bytes(m.p.box_cap));
+        }
         PoolSweep<T>& s = sims[k];
         s = PoolSweep<T>{};
         s.a.nx = m.g.nx;
@@ -196,6 +272,7 @@ lbib_status rebuild(lbib_pool* h)
     h->n_blocks = (int32_t)table.size();
     h->max_nl = max_nl;
     h->lds_cap = lds_cap;
+    h->lds_bytes = lds_bytes;
     h->dirty = false;
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
     h->graph = nullptr;
@@ -221,7 +298,7 @@ template <typename T>
 hipError_t launch_step(lbib_pool* h, EvPair e1, EvPair e0)
 {
     hipError_t e = launch_pool_particle<T>((const ParticleArgs<T>*)h->d_args, h->d_active, h->d_ctl, h->n_active,
-                                           h->max_nl, h->lds_cap, h->stream, e1.t0, e1.t1);
+                                           h->max_nl, h->lds_cap, h->lds_bytes, h->stream, e1.t0, e1.t1);
     if (e != hipSuccess) return e;
     return launch_pool_sweep<T>((const PoolSweep<T>*)h->d_sims, h->d_ctl, h->d_table, h->n_blocks, h->cfg, h->stream,
                                 e0.t0, e0.t1);
@@ -258,6 +335,7 @@ lbib_status enqueue(lbib_pool* h, int64_t n)
         if (s != LBIB_OK) return s;
     }
     if (h->n_active == 0) return LBIB_OK;
+    h->cache_valid = false;
     int64_t k = 0;
     if (h->graph_steps > 0 && !h->timing && n >= h->graph_steps) {
         if (!h->graph) {
@@ -286,17 +364,23 @@ Member* get_member(lbib_pool* h, int32_t slot)
     return it == h->members.end() ? nullptr : it->second.get();
 }
 
-// Synchronise and refresh every member's step count and state from the device.
+// Synchronise and refresh every member's step count and state from the device (a no-op
+// while the last snapshot is still current).
 lbib_status refresh(lbib_pool* h)
 {
+    if (h->cache_valid) return LBIB_OK;
     PCHK(h, hipStreamSynchronize(h->stream));
-    if (h->members.empty()) return LBIB_OK;
     int32_t top = 0;
     for (auto& kv : h->members) top = std::max(top, kv.second->lane + 1);
-    std::vector<DevParticle> st(top);
-    std::vector<int32_t> fl(top);
-    PCHK(h, hipMemcpy(st.data(), h->d_st, top * sizeof(DevParticle), hipMemcpyDeviceToHost));
-    PCHK(h, hipMemcpy(fl.data(), h->d_flags, top * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<DevParticle>& st = h->st_cache;
+    std::vector<int32_t>& fl = h->fl_cache;
+    st.resize(top);
+    fl.resize(top);
+    if (top > 0) {
+        PCHK(h, hipMemcpy(st.data(), h->d_st, top * sizeof(DevParticle), hipMemcpyDeviceToHost));
+        PCHK(h, hipMemcpy(fl.data(), h->d_flags, top * sizeof(int32_t), hipMemcpyDeviceToHost));
+    }
+    h->cache_valid = true;
     for (auto& kv : h->members) {
         Member& m = *kv.second;
         m.steps_done = st[m.lane].step;
@@ -353,11 +437,12 @@ lbib_status lbib_pool_create(int32_t precision, int64_t hbm_budget_bytes, int32_
         return hip_fail(nullptr, e, "lbib_pool_create: device allocation");
     }
     if ((e = hipMemset(h->d_flags, 0, (size_t)max_members * sizeof(int32_t))) != hipSuccess ||
-        (e = hipMemset(h->d_st, 0, (size_t)max_members * sizeof(DevParticle))) != hipSuccess) {
+        (e = hipMemset(h->d_st, 0, (size_t)max_members * sizeof(DevParticle))) != hipSuccess ||
+        (e = h->arena.init((size_t)hbm_budget_bytes)) != hipSuccess) {
         dfree(h->d_st);
         dfree(h->d_flags);
         delete h;
-        return hip_fail(nullptr, e, "lbib_pool_create: hipMemset");
+        return hip_fail(nullptr, e, "lbib_pool_create: device allocation of the budget");
     }
     if (hip_stream) {
         h->stream = (hipStream_t)hip_stream;
@@ -421,28 +506,27 @@ lbib_status lbib_pool_add(lbib_pool_handle h, const lbib_lattice_desc* lat, cons
         return fail(h, LBIB_E_FULL,
                     "lbib_pool_add: needs " + std::to_string(m->bytes) + " bytes, " +
                         std::to_string(h->budget - h->in_use) + " left in the budget");
-    // the stream must be idle: device buffers are uploaded synchronously below
-    PCHK(h, hipStreamSynchronize(h->stream));
-    const size_t pop = (size_t)9 * m->g.plane * m->g.elem;
-    hipError_t e;
-    if ((e = hipMalloc(&m->fA, pop)) != hipSuccess || (e = hipMalloc(&m->fB, pop)) != hipSuccess ||
-        (e = alloc_particle(m->p)) != hipSuccess) {
-        free_member(*m);
-        return hip_fail(h, e, "lbib_pool_add: device allocation");
-    }
+    m->block = h->arena.alloc((size_t)m->bytes);
+    if (!m->block) return fail(h, LBIB_E_FULL, "lbib_pool_add: no contiguous free block of the budget is large enough");
+    const size_t pop = align_up((size_t)9 * m->g.plane * m->g.elem);
+    m->fA = m->block;
+    m->fB = m->block + pop;
+    carve_particle(m->p, m->block + 2 * pop);
     m->lane = h->free_lanes.back();
-    (void)hipFree(m->p.d_st);
-    m->p.d_st = h->d_st + m->lane;
+    m->p.d_st = h->d_st + m->lane;  // the pool-wide lane replaces the block's own state slot
+    // everything below is stream-ordered: the member's first step sees it complete
+    hipError_t e;
     auto bail = [&](hipError_t err, const char* what) {
-        free_member(*m);
+        (void)hipStreamSynchronize(h->stream);
+        free_member(h, *m);
         return hip_fail(h, err, what);
     };
     if ((e = hipMemsetAsync(m->fB, 0, pop, h->stream)) != hipSuccess) return bail(e, "lbib_pool_add: hipMemset");
     if ((e = hipMemsetAsync(h->d_flags + m->lane, 0, sizeof(int32_t), h->stream)) != hipSuccess)
         return bail(e, "lbib_pool_add: hipMemset");
     if ((e = init_populations(m->fA, m->g, h->stream)) != hipSuccess) return bail(e, "lbib_pool_add: init kernel");
-    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return bail(e, "lbib_pool_add: sync");
-    if ((e = upload_particle(m->p)) != hipSuccess) return bail(e, "lbib_pool_add: upload");
+    if ((e = upload_particle(m->p, h->stream)) != hipSuccess) return bail(e, "lbib_pool_add: upload");
+    h->cache_valid = false;
     h->free_lanes.pop_back();
     m->slot = h->next_slot++;
     m->state = n_steps > 0 ? LBIB_POOL_RUNNING : LBIB_POOL_FINISHED;
@@ -489,11 +573,8 @@ lbib_status lbib_pool_status(lbib_pool_handle h, int32_t slot, int64_t* steps_do
     Member* m = get_member(h, slot);
     *steps_done = m->steps_done;
     *state = m->state;
-    if (m->state == LBIB_POOL_FAILED) {
-        int32_t fl = 0;
-        PCHK(h, hipMemcpy(&fl, h->d_flags + m->lane, sizeof(fl), hipMemcpyDeviceToHost));
-        h->err = "lbib_pool_status: slot " + std::to_string(slot) + " failed:" + flag_text(fl);
-    }
+    if (m->state == LBIB_POOL_FAILED)
+        h->err = "lbib_pool_status: slot " + std::to_string(slot) + " failed:" + flag_text(h->fl_cache[m->lane]);
     return LBIB_OK;
 }
 
@@ -502,10 +583,9 @@ lbib_status lbib_pool_read_particle(lbib_pool_handle h, int32_t slot, lbib_parti
     if (!h) return fail(nullptr, LBIB_E_INVALID, "lbib_pool_read_particle: NULL handle");
     Member* m = get_member(h, slot);
     if (!m || !out) return fail(h, LBIB_E_INVALID, "lbib_pool_read_particle: unknown slot or NULL output");
-    PCHK(h, hipStreamSynchronize(h->stream));
-    DevParticle st;
-    PCHK(h, hipMemcpy(&st, m->p.d_st, sizeof(st), hipMemcpyDeviceToHost));
-    *out = st.last;
+    lbib_status s = refresh(h);
+    if (s != LBIB_OK) return s;
+    *out = h->st_cache[m->lane].last;
     return LBIB_OK;
 }
 
@@ -589,7 +669,7 @@ lbib_status lbib_pool_remove(lbib_pool_handle h, int32_t slot)
     if (it == h->members.end()) return fail(h, LBIB_E_INVALID, "lbib_pool_remove: unknown slot");
     PCHK(h, hipStreamSynchronize(h->stream));  // no enqueued step may still use its buffers
     Member& m = *it->second;
-    free_member(m);
+    free_member(h, m);
     h->free_lanes.push_back(m.lane);
     h->in_use -= m.bytes;
     h->members.erase(it);
@@ -748,8 +828,9 @@ void lbib_pool_destroy(lbib_pool_handle h)
 {
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
-    for (auto& kv : h->members) free_member(*kv.second);
+    for (auto& kv : h->members) free_member(h, *kv.second);
     h->members.clear();
+    h->arena.release();
     dfree(h->d_st);
     dfree(h->d_flags);
     if (h->d_args) (void)hipFree(h->d_args);

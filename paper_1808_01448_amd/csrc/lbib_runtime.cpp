@@ -368,7 +368,7 @@ lbib_status lbib_init(lbib_handle h)
     if ((e = init_populations(h->fA, h->g, h->stream)) != hipSuccess) return bail(e, "init kernel");
     if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return bail(e, "lbib_init: sync");
     for (auto& p : h->parts)
-        if ((e = upload_particle(p)) != hipSuccess) return bail(e, "lbib_init: upload");
+        if ((e = upload_particle(p, h->stream)) != hipSuccess) return bail(e, "lbib_init: upload");
     if ((e = hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking)) != hipSuccess)
         return bail(e, "lbib_init: second stream");
     if ((e = hipEventCreateWithFlags(&h->evA, hipEventDisableTiming)) != hipSuccess ||

@@ -58,6 +58,14 @@ class ParticleState(C.Structure):
 
 STATE_FIELDS = [n for n, _ in ParticleState._fields_]
 
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
+
+
+class RequestResult(C.Structure):
+    _fields_ = [("id", C.c_int64), ("state", C.c_int32), ("slot", C.c_int32), ("steps", C.c_int64),
+                ("steps_done", C.c_int64), ("bytes", C.c_int64), ("t_arrival", C.c_double), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double), ("final_state", ParticleState)]
+
 _P = C.c_void_p
 _D = C.POINTER(C.c_double)
 _U8 = C.POINTER(C.c_uint8)
@@ -118,6 +126,18 @@ _SIGS = {
     "lbib_pool_autotune": (C.c_int, [_P, C.c_int32, _D]),
     "lbib_pool_last_error": (C.c_char_p, [_P]),
     "lbib_pool_destroy": (None, [_P]),
+    "lbib_server_create": (C.c_int, [C.c_int32, C.c_int64, C.c_int32, C.c_int32, C.c_int32, _P, C.POINTER(_P)]),
+    "lbib_server_submit": (C.c_int, [_P, C.POINTER(LatticeDesc), C.POINTER(ParticleDesc), C.POINTER(LigandDesc),
+                                     C.c_int64, C.c_double, _I64]),
+    "lbib_server_progress": (C.c_int, [_P, C.POINTER(C.c_int32)]),
+    "lbib_server_take_completed": (C.c_int, [_P, _I64, C.c_int32, C.POINTER(C.c_int32)]),
+    "lbib_server_result": (C.c_int, [_P, C.c_int64, C.POINTER(RequestResult)]),
+    "lbib_server_release": (C.c_int, [_P, C.c_int64]),
+    "lbib_server_stats": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _I64, _I64]),
+    "lbib_server_pool": (_P, [_P]),
+    "lbib_server_clock": (C.c_double, [_P]),
+    "lbib_server_last_error": (C.c_char_p, [_P]),
+    "lbib_server_destroy": (None, [_P]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -139,9 +159,11 @@ def lib():
     return _lib
 
 
-def _check(status: int, handle=None, pool: bool = False):
+def _check(status: int, handle=None, pool: bool = False, server: bool = False):
     if status != OK:
-        msg = (lib().lbib_pool_last_error if pool else lib().lbib_last_error)(handle)
+        L = lib()
+        err = L.lbib_server_last_error if server else L.lbib_pool_last_error if pool else L.lbib_last_error
+        msg = err(handle)
         raise LbibError(status, msg.decode() if msg else "")
 
 
@@ -357,9 +379,10 @@ class Sim:
 
 class Pool:
     """Many independent simulations (one particle each) stepped with one particle-phase launch
-    and one sweep launch per time step.  Members join with add() and leave with remove()."""
+    and one sweep launch per time step.  Members join with add() and leave with remove().
+    The whole memory budget is allocated on the device when the pool is created."""
 
-    def __init__(self, precision: int = FP32, budget_bytes: int = 64 << 30, max_members: int = 4096, stream=None):
+    def __init__(self, precision: int = FP32, budget_bytes: int = 16 << 30, max_members: int = 4096, stream=None):
         self._h = C.c_void_p()
         self.stream = stream
         self.precision = int(precision)
@@ -486,6 +509,79 @@ class Pool:
         n = C.c_int64()
         self._call(lib().lbib_pool_kernel_time, int(kernel), C.byref(ms), C.byref(n))
         return ms.value, n.value
+
+
+# ----------------------------------------------------------------------------------------
+# Server: continuous batching of adhesion solves
+# ----------------------------------------------------------------------------------------
+
+class Server:
+    """Requests (one adhesion solve each) queue in arrival order and join a pool as slots and
+    memory free up; progress() runs one scheduling round (admit, step a chunk, collect)."""
+
+    def __init__(self, precision: int = FP32, budget_bytes: int = 16 << 30, max_members: int = 4096,
+                 chunk_steps: int = 200, max_bypass: int = 8, stream=None):
+        self._h = C.c_void_p()
+        self.stream = stream
+        _check(lib().lbib_server_create(int(precision), int(budget_bytes), int(max_members), int(chunk_steps),
+                                        int(max_bypass), _stream_ptr(stream), C.byref(self._h)), None, server=True)
+
+    def _call(self, fn, *args):
+        _check(fn(self._h, *args), self._h, server=True)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().lbib_server_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def clock(self) -> float:
+        return lib().lbib_server_clock(self._h)
+
+    def submit(self, workload: dict, n_steps: int, arrival_s: float = -1.0) -> int:
+        rid = C.c_int64()
+        self._call(lib().lbib_server_submit, C.byref(_lattice_desc(workload["lattice"])),
+                   C.byref(_particle_desc(workload["particle"])), C.byref(_ligand_desc(workload["ligand"])),
+                   int(n_steps), float(arrival_s), C.byref(rid))
+        return rid.value
+
+    def progress(self) -> int:
+        n = C.c_int32()
+        self._call(lib().lbib_server_progress, C.byref(n))
+        return n.value
+
+    def take_completed(self, capacity: int = 65536) -> list:
+        buf = (C.c_int64 * max(1, capacity))()
+        n = C.c_int32()
+        self._call(lib().lbib_server_take_completed, buf, int(capacity), C.byref(n))
+        return [buf[k] for k in range(n.value)]
+
+    def result(self, rid: int) -> dict:
+        r = RequestResult()
+        self._call(lib().lbib_server_result, int(rid), C.byref(r))
+        out = {n: getattr(r, n) for n, _ in RequestResult._fields_ if n != "final_state"}
+        out["final_state"] = {n: getattr(r.final_state, n) for n in STATE_FIELDS}
+        return out
+
+    def release(self, rid: int):
+        self._call(lib().lbib_server_release, int(rid))
+
+    def stats(self):
+        """(queued, running, bytes in use, chunks stepped)."""
+        q, r, b, c = C.c_int32(), C.c_int32(), C.c_int64(), C.c_int64()
+        self._call(lib().lbib_server_stats, C.byref(q), C.byref(r), C.byref(b), C.byref(c))
+        return q.value, r.value, b.value, c.value
 
 
 # ----------------------------------------------------------------------------------------

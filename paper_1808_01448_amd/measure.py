@@ -9,6 +9,8 @@ from __future__ import annotations
 
 import time
 
+import numpy as np
+
 from . import lbib
 
 
@@ -22,7 +24,7 @@ def pool_throughput(ws: list, steps: int, warmup: int, *, precision: int = lbib.
     with autotune > 0, the autotuner's trials of that many steps each).  The timed run uses
     the chosen launch configuration as it is (graph replay included); a second, shorter run
     with kernel timing on gives the per-kernel averages."""
-    budget = 200 << 30
+    budget = sum(lbib.Pool.footprint(w) for w in ws) + (256 << 20)
     P = lbib.Pool(precision, budget_bytes=budget, max_members=max(len(ws), 1), stream=stream)
     try:
         for w in ws:
@@ -94,3 +96,76 @@ def plain_concurrent(ws: list, steps: int, warmup: int) -> dict:
             s.close()
     cells = sum(_cells(w) for w in ws)
     return {"mlups": cells * steps / dt / 1e6, "seconds": dt}
+
+
+def _lu(w: dict) -> int:
+    return _cells(w) * int(w["steps"])
+
+
+def serve_trace(ws: list, arrivals, *, chunk_steps: int = 200, max_bypass: int = 8, budget_bytes: int = 16 << 30,
+                max_members: int = 4096, stream=None, autotune: bool = False) -> dict:
+    """Run the requests through the server in real time: request k is submitted when the
+    server's clock passes arrivals[k] (seconds after the start) and stamped with that arrival
+    time.  Returns per-request latencies (arrival -> result) and the aggregate throughput."""
+    S = lbib.Server(lbib.FP32, budget_bytes=budget_bytes, max_members=max_members, chunk_steps=chunk_steps,
+                    max_bypass=max_bypass, stream=stream)
+    try:
+        n = len(ws)
+        t0 = S.clock()
+        i = 0
+        res = {}
+        ids = {}
+        while len(res) < n:
+            now = S.clock() - t0
+            while i < n and arrivals[i] <= now:
+                ids[S.submit(ws[i], int(ws[i]["steps"]), t0 + float(arrivals[i]))] = i
+                i += 1
+            q, r, _, _ = S.stats()
+            if q == 0 and r == 0:
+                if i < n:
+                    time.sleep(max(0.0, min(0.05, arrivals[i] - (S.clock() - t0))))
+                continue
+            S.progress()
+            for rid in S.take_completed():
+                res[ids[rid]] = S.result(rid)
+                S.release(rid)
+        t_end = S.clock()
+        lat = np.array([res[k]["t_done"] - res[k]["t_arrival"] for k in range(n)])
+        wait = np.array([res[k]["t_admit"] - res[k]["t_arrival"] for k in range(n)])
+        makespan = t_end - t0
+        lu = sum(_lu(w) for w in ws)
+        _, _, _, chunks = S.stats()
+        return {"latency_s": lat, "wait_s": wait, "makespan_s": makespan, "mlups": lu / makespan / 1e6,
+                "results": [res[k] for k in range(n)], "chunks": chunks,
+                "failed": sum(1 for k in range(n) if res[k]["state"] != lbib.REQ_DONE)}
+    finally:
+        S.close()
+
+
+def plain_fifo(ws: list, arrivals, *, stream=None) -> dict:
+    """The plain server: one simulation at a time in arrival order, each created when the
+    previous one has finished (or at its arrival), stepped to completion and read."""
+    t0 = time.perf_counter()
+    lat = np.zeros(len(ws))
+    finals = []
+    for k, w in enumerate(ws):
+        now = time.perf_counter() - t0
+        if arrivals[k] > now:
+            time.sleep(arrivals[k] - now)
+        s = lbib.Sim(w, stream=stream)
+        try:
+            s.step(int(w["steps"]))
+            s.sync()
+            finals.append(s.particle())
+        finally:
+            s.close()
+        lat[k] = time.perf_counter() - t0 - arrivals[k]
+    makespan = time.perf_counter() - t0
+    lu = sum(_lu(w) for w in ws)
+    return {"latency_s": lat, "makespan_s": makespan, "mlups": lu / makespan / 1e6, "finals": finals}
+
+
+def percentiles(x) -> dict:
+    x = np.asarray(x, float)
+    return {"p50": float(np.percentile(x, 50)), "p99": float(np.percentile(x, 99)), "mean": float(x.mean()),
+            "max": float(x.max())}

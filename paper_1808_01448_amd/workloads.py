@@ -182,6 +182,33 @@ def batched_sweep(seed: int = 0, *, precision: str = "fp32", steps: int = 10_000
     return out
 
 
+def serving_requests(n: int, seed: int = 0, *, steps_range=(5_000, 50_000), nx_range=(256, 4096),
+                     ny_range=(64, 512), precision: str = "fp32") -> list[dict]:
+    """n single-particle adhesion solves for the serving loop: nx and ny log-uniform over
+    their ranges (independently, rounded), shape, ligand density, bond strength and Re
+    uniform over the sweep's sets, the step count uniform over steps_range; request k uses
+    seed k for its bond draws.  Each workload's "steps" is its step count."""
+    g = rng(seed)
+    out = []
+    for k in range(n):
+        nx = int(round(math.exp(g.uniform(math.log(nx_range[0]), math.log(nx_range[1])))))
+        ny = int(round(math.exp(g.uniform(math.log(ny_range[0]), math.log(ny_range[1])))))
+        shape = SWEEP_SHAPES[int(g.integers(len(SWEEP_SHAPES)))]
+        rl = SWEEP_RHO_L[int(g.integers(len(SWEEP_RHO_L)))]
+        st = SWEEP_STRENGTH[int(g.integers(len(SWEEP_STRENGTH)))]
+        re = SWEEP_RE[int(g.integers(len(SWEEP_RE)))]
+        steps = int(g.integers(steps_range[0], steps_range[1] + 1))
+        w = sweep_member(nx, ny, shape, rl, st, re, k, precision=precision, steps=steps)
+        w["name"] = f"request{k}_" + w["name"]
+        out.append(w)
+    return out
+
+
+def poisson_arrivals(n: int, rate: float, seed: int = 0) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process of the given rate."""
+    return np.cumsum(rng(seed + 1_000_003).exponential(1.0 / rate, n))
+
+
 # ----------------------------------------------------------------------------------------
 # Seeded random arrays (for unit-level parity tests)
 # ----------------------------------------------------------------------------------------

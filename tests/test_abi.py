@@ -47,7 +47,7 @@ def test_struct_layout_matches_c(tmp_path):
     structs = {
         "lbib_lattice_desc": lbib.LatticeDesc, "lbib_particle_desc": lbib.ParticleDesc,
         "lbib_ligand_desc": lbib.LigandDesc, "lbib_receptor_desc": lbib.ReceptorDesc,
-        "lbib_particle_state": lbib.ParticleState,
+        "lbib_particle_state": lbib.ParticleState, "lbib_request_result": lbib.RequestResult,
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbib.h"', "int main(void){"]
     for cname, py in structs.items():
@@ -184,3 +184,13 @@ def test_pool_footprint(L):
     assert fp(200, 64, 1, a_major=20.0, yc=30.0)[1] > fp(200, 64, 1)[1]
     assert fp(64, 32, 1, n_markers=7)[0] == lbib.E_INVALID
     assert fp(3, 32, 1)[0] == lbib.E_INVALID
+
+
+def test_server_host_validation(L):
+    h = C.c_void_p()
+    assert L.lbib_server_create(1, 1 << 30, 16, 0, 0, FAKE_STREAM, C.byref(h)) == lbib.E_INVALID
+    assert L.lbib_server_create(1, 1 << 30, 16, 10, -1, FAKE_STREAM, C.byref(h)) == lbib.E_INVALID
+    assert L.lbib_server_create(7, 1 << 30, 16, 10, 0, FAKE_STREAM, C.byref(h)) == lbib.E_UNSUPPORTED
+    assert L.lbib_server_last_error(None)
+    assert L.lbib_server_progress(None, None) == lbib.E_INVALID
+    L.lbib_server_destroy(None)
