@@ -62,12 +62,17 @@ typedef enum {
     LBIB_E_FULL = -7         /* a pool's memory budget or member count would be exceeded */
 } lbib_status;
 
-/* Precision of the population storage: f - w_q in double (FP64) or in float (FP32).  The
- * collision is evaluated in FP64 for both (in FP32 arithmetic its rounding breaks the
+/* Precision of the population storage: f - w_q in double (FP64), float (FP32), IEEE
+ * binary16 (FP16, stored as (f - w_q) 2^S, S = floor(log2(8192 / d)) clamped to [0, 40],
+ * d = (4/9)(3u + 4.5u^2), u = max(4 u_max, 1e-6): the largest deviation expected lands near
+ * 2^13, far from both the binary16 maximum and its subnormals) or bfloat16 (BF16).  Values
+ * are rounded to nearest even (FP16 through float: (float)(f - w) * 2^S).  The collision is evaluated
+ * in FP64 for the FP64 and FP32 storages (in FP32 arithmetic its rounding breaks the
  * momentum balance at a level that accumulates over thousands of steps at the small
- * velocities of capillary flow).  The particle phase (MLS solves, interpolation, loads,
- * bonds, reductions, rigid body) is FP64 in both. */
-enum { LBIB_FP64 = 0, LBIB_FP32 = 1 };
+ * velocities of capillary flow) and in FP32 for the 16-bit storages, whose rounding is far
+ * coarser.  The particle phase (MLS solves, interpolation, loads, bonds, reductions, rigid
+ * body) is FP64 for every storage.  Bytes per lattice update: 144, 72, 36, 36. */
+enum { LBIB_FP64 = 0, LBIB_FP32 = 1, LBIB_FP16 = 2, LBIB_BF16 = 3 };
 
 /* Lattice (section "Modeling the adhesion dynamics ..."; Table 1).  drive must be 0
  * (body-force Poiseuille with resting bounce-back walls).  Requirements: nx >= 4, ny >= 4,
@@ -244,7 +249,7 @@ lbib_status lbib_kernel_timing(lbib_handle h, int32_t enable);
 lbib_status lbib_kernel_time(lbib_handle h, int32_t kernel, double* total_ms, int64_t* launches);
 
 /* Bytes of HBM the algorithm moves per lattice update (9 populations read + 9 written):
- * 144 for FP64 storage, 72 for FP32. */
+ * 144 for FP64 storage, 72 for FP32, 36 for FP16 and BF16. */
 lbib_status lbib_bytes_per_update(lbib_handle h, int64_t* bytes);
 
 /* Description of the last failure on this handle; valid until the next call on it. */

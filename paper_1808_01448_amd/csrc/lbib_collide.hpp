@@ -23,29 +23,30 @@ using namespace dev;
 // O(1) density to the O(1e-5) deviations.  Device code is compiled without FMA
 // contraction and the fused operations below are explicit, so every kernel that runs this
 // update (either layout, one simulation or a pool) computes the same sequence and gives
-// bit-identical results.
+// bit-identical results.  The compute type C is FP64 for the FP64 and FP32 storages and
+// FP32 for the 16-bit ones, whose storage rounding is far coarser than FP32 arithmetic.
 // ---------------------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void collide_node(const T gs[9], const SweepArgs& a, double Fx, double Fy, T post[9])
+template <typename C>
+__device__ __forceinline__ void collide_node(const C g[9], const SweepArgs& a, C Fx, C Fy, C post[9])
 {
-    double g[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) g[q] = (double)gs[q];
-    double drho, jx, jy;
-    shifted_moments<double, double>(g, drho, jx, jy);
-    const double r = drho / (1.0 + drho);
-    const double jxF = fma(0.5, Fx, jx), jyF = fma(0.5, Fy, jy);
-    const double ux = fma(-jxF, r, jxF), uy = fma(-jyF, r, jyF);
-    const double uu = fma(ux, ux, uy * uy);
-    const double uF = fma(ux, Fx, uy * Fy);
+    C drho, jx, jy;
+    shifted_moments<C, C>(g, drho, jx, jy);
+    const C half = 0.5, c3 = 3.0, c45 = 4.5, c15 = 1.5, c9 = 9.0;
+    const C omega = (C)a.omega, guo = (C)a.guo;
+    const C r = drho / ((C)1 + drho);
+    const C jxF = fma(half, Fx, jx), jyF = fma(half, Fy, jy);
+    const C ux = fma(-jxF, r, jxF), uy = fma(-jyF, r, jyF);
+    const C uu = fma(ux, ux, uy * uy);
+    const C uF = fma(ux, Fx, uy * Fy);
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-        const double eu = kEx[q] * ux + kEy[q] * uy;
-        const double eF = kEx[q] * Fx + kEy[q] * Fy;
-        const double A = fma(4.5 * eu, eu, fma(-1.5, uu, 3.0 * eu));
-        const double geq = kW[q] * fma(drho, A, drho + A);
-        const double src = a.guo * kW[q] * fma(9.0 * eu, eF, 3.0 * (eF - uF));
-        post[q] = (T)(fma(-a.omega, g[q] - geq, g[q]) + src);
+        const C eu = (C)kEx[q] * ux + (C)kEy[q] * uy;
+        const C eF = (C)kEx[q] * Fx + (C)kEy[q] * Fy;
+        const C w = (C)kW[q];
+        const C A = fma(c45 * eu, eu, fma(-c15, uu, c3 * eu));
+        const C geq = w * fma(drho, A, drho + A);
+        const C src = guo * w * fma(c9 * eu, eF, c3 * (eF - uF));
+        post[q] = fma(-omega, g[q] - geq, g[q]) + src;
     }
 }
 
@@ -55,40 +56,42 @@ template <typename T>
 __device__ __forceinline__ void collide_push(const T* __restrict__ fin, T* __restrict__ fout, const SweepArgs& a,
                                              int i, int j, double Fx, double Fy)
 {
+    using C = typename St<T>::C;
     const int64_t P = a.plane;
     const size_t c = (size_t)j * a.pitch + i;
     // populations are read exactly once per step: stream them past the caches
-    T gs[9];
+    C g[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) gs[q] = __builtin_nontemporal_load(fin + q * P + c);
-    T post[9];
-    collide_node<T>(gs, a, Fx, Fy, post);
+    for (int q = 0; q < 9; ++q) g[q] = st_load(fin, q * P + c, a.inv_scale, true);
+    C post[9];
+    collide_node<C>(g, a, (C)Fx, (C)Fy, post);
 
     const int ip = (i + 1 == a.nx) ? 0 : i + 1;
     const int im = (i == 0) ? a.nx - 1 : i - 1;
     const size_t up = (size_t)(j + 1) * a.pitch, dn = (size_t)(j - 1) * a.pitch, row = (size_t)j * a.pitch;
     const bool top = (j + 1 == a.ny), bot = (j == 0);
+    const double sc = a.scale;
     // shifted values reflect unchanged: w_q = w_opp(q)
-    fout[0 * P + c] = post[0];
-    fout[1 * P + row + ip] = post[1];
-    fout[3 * P + row + im] = post[3];
+    st_store(fout, 0 * P + c, post[0], sc, false);
+    st_store(fout, 1 * P + row + ip, post[1], sc, false);
+    st_store(fout, 3 * P + row + im, post[3], sc, false);
     if (!top) {
-        fout[2 * P + up + i] = post[2];
-        fout[5 * P + up + ip] = post[5];
-        fout[6 * P + up + im] = post[6];
+        st_store(fout, 2 * P + up + i, post[2], sc, false);
+        st_store(fout, 5 * P + up + ip, post[5], sc, false);
+        st_store(fout, 6 * P + up + im, post[6], sc, false);
     } else {
-        fout[4 * P + c] = post[2];
-        fout[7 * P + c] = post[5];
-        fout[8 * P + c] = post[6];
+        st_store(fout, 4 * P + c, post[2], sc, false);
+        st_store(fout, 7 * P + c, post[5], sc, false);
+        st_store(fout, 8 * P + c, post[6], sc, false);
     }
     if (!bot) {
-        fout[4 * P + dn + i] = post[4];
-        fout[7 * P + dn + im] = post[7];
-        fout[8 * P + dn + ip] = post[8];
+        st_store(fout, 4 * P + dn + i, post[4], sc, false);
+        st_store(fout, 7 * P + dn + im, post[7], sc, false);
+        st_store(fout, 8 * P + dn + ip, post[8], sc, false);
     } else {
-        fout[2 * P + c] = post[4];
-        fout[5 * P + c] = post[7];
-        fout[6 * P + c] = post[8];
+        st_store(fout, 2 * P + c, post[4], sc, false);
+        st_store(fout, 5 * P + c, post[7], sc, false);
+        st_store(fout, 6 * P + c, post[8], sc, false);
     }
 }
 
@@ -100,15 +103,16 @@ template <typename T>
 __device__ __forceinline__ void collide_pull(const T* __restrict__ fin, T* __restrict__ fout, const SweepArgs& a,
                                              int i, int j, double Fx, double Fy)
 {
+    using C = typename St<T>::C;
     const int64_t P = a.plane;
     const size_t c = (size_t)j * a.pitch + i;
-    T gs[9];
+    C g[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) gs[q] = __builtin_nontemporal_load(fin + pop_index(q, i, j, a.nx, a.ny, a.pitch, P, true));
-    T post[9];
-    collide_node<T>(gs, a, Fx, Fy, post);
+    for (int q = 0; q < 9; ++q) g[q] = st_load(fin, pop_index(q, i, j, a.nx, a.ny, a.pitch, P, true), a.inv_scale, true);
+    C post[9];
+    collide_node<C>(g, a, (C)Fx, (C)Fy, post);
 #pragma unroll
-    for (int q = 0; q < 9; ++q) __builtin_nontemporal_store(post[q], fout + q * P + c);
+    for (int q = 0; q < 9; ++q) st_store(fout, q * P + c, post[q], a.scale, true);
 }
 
 // Node update in either layout.

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lbib_internal.hpp"
+
 namespace lbib {
 namespace dev {
 
@@ -39,6 +41,65 @@ __device__ __forceinline__ int64_t pop_index(int q, int i, int j, int nx, int ny
         return q * plane + (int64_t)sj * pitch + si;
     }
     return q * plane + (int64_t)j * pitch + i;
+}
+
+// Loads and stores of one stored population (f - w, in the compute type of the storage),
+// optionally past the caches (nt).
+__device__ __forceinline__ double st_load(const double* p, int64_t i, double, bool nt)
+{
+    return nt ? __builtin_nontemporal_load(p + i) : p[i];
+}
+__device__ __forceinline__ double st_load(const float* p, int64_t i, double, bool nt)
+{
+    return (double)(nt ? __builtin_nontemporal_load(p + i) : p[i]);
+}
+__device__ __forceinline__ float st_load(const half_t* p, int64_t i, double inv_scale, bool nt)
+{
+    const uint16_t* r = (const uint16_t*)p;
+    const uint16_t b = nt ? __builtin_nontemporal_load(r + i) : r[i];
+    return (float)__builtin_bit_cast(_Float16, b) * (float)inv_scale;
+}
+__device__ __forceinline__ float st_load(const bf16_t* p, int64_t i, double, bool nt)
+{
+    const uint16_t* r = (const uint16_t*)p;
+    const uint16_t b = nt ? __builtin_nontemporal_load(r + i) : r[i];
+    return __builtin_bit_cast(float, (uint32_t)b << 16);
+}
+
+__device__ __forceinline__ void st_store(double* p, int64_t i, double v, double, bool nt)
+{
+    if (nt)
+        __builtin_nontemporal_store(v, p + i);
+    else
+        p[i] = v;
+}
+__device__ __forceinline__ void st_store(float* p, int64_t i, double v, double, bool nt)
+{
+    if (nt)
+        __builtin_nontemporal_store((float)v, p + i);
+    else
+        p[i] = (float)v;
+}
+__device__ __forceinline__ void st_store(half_t* p, int64_t i, float v, double scale, bool nt)
+{
+    const uint16_t b = __builtin_bit_cast(uint16_t, (_Float16)(v * (float)scale));
+    uint16_t* r = (uint16_t*)p;
+    if (nt)
+        __builtin_nontemporal_store(b, r + i);
+    else
+        r[i] = b;
+}
+__device__ __forceinline__ void st_store(bf16_t* p, int64_t i, float v, double, bool nt)
+{
+    uint32_t x = __builtin_bit_cast(uint32_t, v);
+    // round to nearest even on the 16 dropped bits; NaN stays a quiet NaN
+    x = (x & 0x7fffffffu) > 0x7f800000u ? 0x7fc00000u : x + 0x7fffu + ((x >> 16) & 1u);
+    const uint16_t b = (uint16_t)(x >> 16);
+    uint16_t* r = (uint16_t*)p;
+    if (nt)
+        __builtin_nontemporal_store(b, r + i);
+    else
+        r[i] = b;
 }
 
 // Density and momentum of shifted populations g_q = f_q - w_q: rho = 1 + sum g (the weights

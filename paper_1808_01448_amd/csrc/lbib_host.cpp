@@ -29,6 +29,63 @@ std::vector<uint8_t> ligand_layout(int nl, int p, int q)
 
 }  // namespace
 
+uint16_t f32_to_f16(float f)
+{
+    uint32_t x;
+    std::memcpy(&x, &f, 4);
+    const uint32_t sign = (x >> 16) & 0x8000u, ax = x & 0x7fffffffu;
+    if (ax >= 0x7f800000u) return (uint16_t)(sign | (ax > 0x7f800000u ? 0x7e00u : 0x7c00u));
+    if (ax >= 0x477ff000u) return (uint16_t)(sign | 0x7c00u);  // rounds to infinity (>= 65520)
+    if (ax < 0x33000000u) return (uint16_t)sign;                 // below 2^-25: rounds to zero
+    const int e = (int)(ax >> 23) - 127 + 15;
+    uint32_t m = ax & 0x7fffffu;
+    if (e <= 0) {  // subnormal result: m_h = M 2^(e - 14), M the 24-bit significand
+        m |= 0x800000u;
+        const int shift = 14 - e;
+        uint32_t r = m >> shift;
+        const uint32_t rem = m & ((1u << shift) - 1u), halfway = 1u << (shift - 1);
+        if (rem > halfway || (rem == halfway && (r & 1u))) ++r;
+        return (uint16_t)(sign | r);
+    }
+    uint32_t r = ((uint32_t)e << 10) | (m >> 13);
+    const uint32_t rem = m & 0x1fffu;
+    if (rem > 0x1000u || (rem == 0x1000u && (r & 1u))) ++r;  // a carry moves into the exponent
+    return (uint16_t)(sign | r);
+}
+
+float f16_to_f32(uint16_t h)
+{
+    const uint32_t sign = (uint32_t)(h & 0x8000u) << 16, e = (h >> 10) & 0x1fu, m = h & 0x3ffu;
+    uint32_t x;
+    if (e == 0) {
+        const float v = std::ldexp((float)m, -24);  // zero or subnormal, exact
+        return sign ? -v : v;
+    }
+    if (e == 31)
+        x = sign | 0x7f800000u | (m << 13);
+    else
+        x = sign | ((e + 112u) << 23) | (m << 13);
+    float f;
+    std::memcpy(&f, &x, 4);
+    return f;
+}
+
+uint16_t f32_to_bf16(float f)
+{
+    uint32_t x;
+    std::memcpy(&x, &f, 4);
+    x = (x & 0x7fffffffu) > 0x7f800000u ? 0x7fc00000u : x + 0x7fffu + ((x >> 16) & 1u);
+    return (uint16_t)(x >> 16);
+}
+
+float bf16_to_f32(uint16_t h)
+{
+    const uint32_t x = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &x, 4);
+    return f;
+}
+
 int64_t host_pop_index(const LatticeGeom& g, int q, int i, int j)
 {
     if (g.pull) {
@@ -48,8 +105,8 @@ lbib_status check_lattice(const lbib_lattice_desc& d, std::string& msg)
     if (!is_finite(d.tau) || !(d.tau > 0.5)) return msg = "tau must be > 1/2", LBIB_E_INVALID;
     if (!is_finite(d.re) || d.re < 0) return msg = "Re must be >= 0", LBIB_E_INVALID;
     if (d.drive != 0) return msg = "only drive 0 (body-force Poiseuille) is built", LBIB_E_UNSUPPORTED;
-    if (d.precision != LBIB_FP64 && d.precision != LBIB_FP32)
-        return msg = "precision must be LBIB_FP64 or LBIB_FP32", LBIB_E_UNSUPPORTED;
+    if (d.precision != LBIB_FP64 && d.precision != LBIB_FP32 && d.precision != LBIB_FP16 && d.precision != LBIB_BF16)
+        return msg = "precision must be LBIB_FP64, LBIB_FP32, LBIB_FP16 or LBIB_BF16", LBIB_E_UNSUPPORTED;
     return LBIB_OK;
 }
 
@@ -58,7 +115,8 @@ LatticeGeom lattice_geom(const lbib_lattice_desc& d)
     LatticeGeom g;
     g.nx = d.nx;
     g.ny = d.ny;
-    g.elem = d.precision == LBIB_FP64 ? 8 : 4;
+    g.precision = d.precision;
+    g.elem = d.precision == LBIB_FP64 ? 8 : d.precision == LBIB_FP32 ? 4 : 2;
     const int align = (int)(256 / g.elem);  // rows start on 256-byte boundaries
     g.pitch = (d.nx + align - 1) / align * align;
     g.plane = (int64_t)g.pitch * d.ny;
@@ -68,6 +126,14 @@ LatticeGeom lattice_geom(const lbib_lattice_desc& d)
     g.umax = d.re * g.nu / H;
     g.gx = 8.0 * g.nu * g.umax / (H * H);
     g.gy = 0.0;
+    if (d.precision == LBIB_FP16) {
+        // the largest deviation f - w to expect is that of the rest population at a few times
+        // u_max; a power of two maps it to ~2^13, far below the binary16 maximum (65504) and
+        // far above its subnormal range (< 2^-14)
+        const double u = std::max(4.0 * g.umax, 1e-6);
+        const double dev = (4.0 / 9.0) * (3.0 * u + 4.5 * u * u);
+        g.scale = std::ldexp(1.0, std::min(40, std::max(0, (int)std::floor(std::log2(8192.0 / dev)))));
+    }
     return g;
 }
 
@@ -229,6 +295,7 @@ void fill_particle_args(ParticleArgs<T>& a, const LatticeGeom& g, uint64_t seed,
     a.pitch = g.pitch;
     a.pull = g.pull ? 1 : 0;
     a.plane = g.plane;
+    a.inv_scale = 1.0 / g.scale;
     a.gx = g.gx;
     a.gy = g.gy;
     a.nu = g.nu;
@@ -270,14 +337,22 @@ void fill_particle_args(ParticleArgs<T>& a, const LatticeGeom& g, uint64_t seed,
 template void fill_particle_args<float>(ParticleArgs<float>&, const LatticeGeom&, uint64_t, const Particle&, int32_t*);
 template void fill_particle_args<double>(ParticleArgs<double>&, const LatticeGeom&, uint64_t, const Particle&,
                                          int32_t*);
+template void fill_particle_args<half_t>(ParticleArgs<half_t>&, const LatticeGeom&, uint64_t, const Particle&,
+                                         int32_t*);
+template void fill_particle_args<bf16_t>(ParticleArgs<bf16_t>&, const LatticeGeom&, uint64_t, const Particle&,
+                                         int32_t*);
 
 hipError_t init_populations(void* f, const LatticeGeom& g, hipStream_t s)
 {
     const size_t bytes = (size_t)9 * g.plane * g.elem;
     hipError_t e = hipMemsetAsync(f, 0, bytes, s);
     if (e != hipSuccess) return e;
-    if (g.elem == 8) return launch_init<double>((double*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, g.pull, s);
-    return launch_init<float>((float*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, g.pull, s);
+    switch (g.precision) {
+        case LBIB_FP64: return launch_init<double>((double*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, g.scale, g.pull, s);
+        case LBIB_FP32: return launch_init<float>((float*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, g.scale, g.pull, s);
+        case LBIB_FP16: return launch_init<half_t>((half_t*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, g.scale, g.pull, s);
+        default: return launch_init<bf16_t>((bf16_t*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, g.scale, g.pull, s);
+    }
 }
 
 hipError_t download_populations(const void* fdev, const LatticeGeom& g, std::vector<double>& f)
@@ -285,22 +360,23 @@ hipError_t download_populations(const void* fdev, const LatticeGeom& g, std::vec
     const int nx = g.nx, ny = g.ny;
     const size_t n = (size_t)9 * g.plane;
     f.assign((size_t)9 * nx * ny, 0.0);
-    hipError_t e;
-    if (g.elem == 8) {
-        std::vector<double> raw(n);
-        if ((e = hipMemcpy(raw.data(), fdev, n * 8, hipMemcpyDeviceToHost)) != hipSuccess) return e;
-        for (int q = 0; q < 9; ++q)
-            for (int j = 0; j < ny; ++j)
-                for (int i = 0; i < nx; ++i)
-                    f[((size_t)q * ny + j) * nx + i] = kWq[q] + raw[host_pop_index(g, q, i, j)];
-    } else {
-        std::vector<float> raw(n);
-        if ((e = hipMemcpy(raw.data(), fdev, n * 4, hipMemcpyDeviceToHost)) != hipSuccess) return e;
-        for (int q = 0; q < 9; ++q)
-            for (int j = 0; j < ny; ++j)
-                for (int i = 0; i < nx; ++i)
-                    f[((size_t)q * ny + j) * nx + i] = kWq[q] + (double)raw[host_pop_index(g, q, i, j)];
-    }
+    std::vector<unsigned char> raw(n * g.elem);
+    hipError_t e = hipMemcpy(raw.data(), fdev, raw.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    const double inv = 1.0 / g.scale;
+    for (int q = 0; q < 9; ++q)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const int64_t k = host_pop_index(g, q, i, j);
+                double v;
+                switch (g.precision) {
+                    case LBIB_FP64: v = ((const double*)raw.data())[k]; break;
+                    case LBIB_FP32: v = (double)((const float*)raw.data())[k]; break;
+                    case LBIB_FP16: v = (double)f16_to_f32(((const uint16_t*)raw.data())[k]) * inv; break;
+                    default: v = (double)bf16_to_f32(((const uint16_t*)raw.data())[k]); break;
+                }
+                f[((size_t)q * ny + j) * nx + i] = kWq[q] + v;
+            }
     return hipSuccess;
 }
 
@@ -308,20 +384,20 @@ hipError_t upload_populations(void* fdev, const LatticeGeom& g, const double* f)
 {
     const int nx = g.nx, ny = g.ny;
     const size_t n = (size_t)9 * g.plane;
-    if (g.elem == 8) {
-        std::vector<double> raw(n, 0.0);
-        for (int q = 0; q < 9; ++q)
-            for (int j = 0; j < ny; ++j)
-                for (int i = 0; i < nx; ++i)
-                    raw[host_pop_index(g, q, i, j)] = f[((size_t)q * ny + j) * nx + i] - kWq[q];
-        return hipMemcpy(fdev, raw.data(), n * 8, hipMemcpyHostToDevice);
-    }
-    std::vector<float> raw(n, 0.0f);
+    std::vector<unsigned char> raw(n * g.elem, 0);
     for (int q = 0; q < 9; ++q)
         for (int j = 0; j < ny; ++j)
-            for (int i = 0; i < nx; ++i)
-                raw[host_pop_index(g, q, i, j)] = (float)(f[((size_t)q * ny + j) * nx + i] - kWq[q]);
-    return hipMemcpy(fdev, raw.data(), n * 4, hipMemcpyHostToDevice);
+            for (int i = 0; i < nx; ++i) {
+                const int64_t k = host_pop_index(g, q, i, j);
+                const double v = f[((size_t)q * ny + j) * nx + i] - kWq[q];
+                switch (g.precision) {
+                    case LBIB_FP64: ((double*)raw.data())[k] = v; break;
+                    case LBIB_FP32: ((float*)raw.data())[k] = (float)v; break;
+                    case LBIB_FP16: ((uint16_t*)raw.data())[k] = f32_to_f16((float)v * (float)g.scale); break;
+                    default: ((uint16_t*)raw.data())[k] = f32_to_bf16((float)v); break;
+                }
+            }
+    return hipMemcpy(fdev, raw.data(), raw.size(), hipMemcpyHostToDevice);
 }
 
 void field_from_populations(const std::vector<double>& f, const LatticeGeom& g, int which, double* out)

@@ -23,8 +23,16 @@ struct LatticeGeom {
     int64_t plane = 0;  // elements per population plane
     size_t elem = 0;    // bytes per stored population
     bool pull = false;  // buffer layout (push: streamed values; pull: post-collision values)
+    int precision = LBIB_FP64;
+    double scale = 1.0;  // stored value = (f - w) scale (a power of two; 1 but for FP16)
     double tau = 0, nu = 0, umax = 0, gx = 0, gy = 0;
 };
+
+// Host conversions of the 16-bit storages (round to nearest even).
+uint16_t f32_to_f16(float f);
+float f16_to_f32(uint16_t h);
+uint16_t f32_to_bf16(float f);
+float bf16_to_f32(uint16_t h);
 
 // Element index of population q of node (i, j) in a buffer of this geometry (the host
 // mirror of the device's pop_index).

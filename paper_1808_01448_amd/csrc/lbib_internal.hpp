@@ -38,14 +38,49 @@ struct TileDesc {
     int32_t i0u, pad;
 };
 
-// Lattice constants of one sweep (the collision is evaluated in FP64 for both storage
-// precisions).
+// 16-bit storage types of the shifted populations: IEEE binary16 (of (f - w) 2^S, S a
+// power-of-two scale chosen per simulation) and bfloat16 (of f - w).  Plain bit containers:
+// every conversion is explicit (round to nearest even).
+struct half_t {
+    uint16_t b;
+};
+struct bf16_t {
+    uint16_t b;
+};
+
+// Storage traits: the bits in memory and the type the collision computes in (FP64 for the
+// FP64 and FP32 storages, FP32 for the 16-bit ones).
+template <typename T>
+struct St;
+template <>
+struct St<double> {
+    using raw = double;
+    using C = double;
+};
+template <>
+struct St<float> {
+    using raw = float;
+    using C = double;
+};
+template <>
+struct St<half_t> {
+    using raw = uint16_t;
+    using C = float;
+};
+template <>
+struct St<bf16_t> {
+    using raw = uint16_t;
+    using C = float;
+};
+
+// Lattice constants of one sweep.
 struct SweepArgs {
     int32_t nx, ny, pitch;
     int64_t plane;  // elements per population plane (pitch * ny)
     double omega;   // 1 / tau
     double guo;     // 1 - 1 / (2 tau)
     double gx, gy;  // uniform body force
+    double scale, inv_scale;  // stored value = (f - w) scale (a power of two; 1 but for FP16)
 };
 
 // Everything the particle phase needs; passed by value.
@@ -57,6 +92,7 @@ struct ParticleArgs {
     int32_t nx, ny, pitch;
     int32_t pull;  // layout of f: 0 push, 1 pull
     int64_t plane;
+    double inv_scale;  // f - w = stored value * inv_scale
     double gx, gy, nu;
     // body-frame surface: centroids xi[2l], outward normals nuv[2l], lengths S[l]
     const double* xi;
@@ -85,8 +121,8 @@ struct ParticleArgs {
 
 // Launchers (lbib_sweep.hip, lbib_particle.hip).  All enqueue on `stream` and return the launch status.
 template <typename T>
-hipError_t launch_init(T* f, int32_t nx, int32_t ny, int32_t pitch, int64_t plane, double umax, bool pull,
-                       hipStream_t stream);
+hipError_t launch_init(T* f, int32_t nx, int32_t ny, int32_t pitch, int64_t plane, double umax, double scale,
+                       bool pull, hipStream_t stream);
 // Sweep modes: every node (forces from desc/tile when desc != NULL); only nodes outside
 // the box in `desc` (which carry no spread force); only the nodes of the box in `desc`
 // (box_cap bounds the launch).

@@ -265,7 +265,7 @@ __device__ __forceinline__ void fill_marked(const ParticleArgs<T>& a, const BoxV
             wave_sync_lds();
             const int take = min(qn, 64 * kFillU);
             int kk[kFillU];
-            T v[kFillU][9];
+            double v[kFillU][9];
 #pragma unroll
             for (int u = 0; u < kFillU; ++u) {
                 const int e = lane + 64 * u;
@@ -275,14 +275,15 @@ __device__ __forceinline__ void fill_marked(const ParticleArgs<T>& a, const BoxV
                     const int i = wrap(x0 + kk[u] % w, a.nx);
 #pragma unroll
                     for (int c = 0; c < 9; ++c)
-                        v[u][c] = a.f[pop_index(c, i, j, a.nx, a.ny, a.pitch, a.plane, a.pull != 0)];
+                        v[u][c] = (double)st_load(a.f, pop_index(c, i, j, a.nx, a.ny, a.pitch, a.plane, a.pull != 0),
+                                                  a.inv_scale, false);
                 }
             }
 #pragma unroll
             for (int u = 0; u < kFillU; ++u) {
                 if (kk[u] < 0) continue;
                 double dr, jx, jy;
-                shifted_moments<double, T>(v[u], dr, jx, jy);
+                shifted_moments<double, double>(v[u], dr, jx, jy);
                 const double rho = 1.0 + dr;
                 const double inv = 1.0 / rho;
                 const int k = kk[u];
@@ -902,11 +903,14 @@ hipError_t launch_copy(const float4* src, float4* dst, int64_t n, hipStream_t st
     return hipGetLastError();
 }
 
-template hipError_t launch_pool_particle<float>(const ParticleArgs<float>*, const int32_t*, TileDesc*, int32_t, int32_t,
-                                                int32_t, size_t, hipStream_t, hipEvent_t, hipEvent_t);
-template hipError_t launch_pool_particle<double>(const ParticleArgs<double>*, const int32_t*, TileDesc*, int32_t, int32_t,
-                                                 int32_t, size_t, hipStream_t, hipEvent_t, hipEvent_t);
-template hipError_t launch_particle<float>(const ParticleArgs<float>&, hipStream_t, hipEvent_t, hipEvent_t);
-template hipError_t launch_particle<double>(const ParticleArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
+#define LBIB_PARTICLE_INSTANTIATE(T)                                                                        \
+    template hipError_t launch_pool_particle<T>(const ParticleArgs<T>*, const int32_t*, TileDesc*, int32_t,      \
+                                                int32_t, int32_t, size_t, hipStream_t, hipEvent_t, hipEvent_t); \
+    template hipError_t launch_particle<T>(const ParticleArgs<T>&, hipStream_t, hipEvent_t, hipEvent_t);
+LBIB_PARTICLE_INSTANTIATE(double)
+LBIB_PARTICLE_INSTANTIATE(float)
+LBIB_PARTICLE_INSTANTIATE(half_t)
+LBIB_PARTICLE_INSTANTIATE(bf16_t)
+#undef LBIB_PARTICLE_INSTANTIATE
 
 }  // namespace lbib

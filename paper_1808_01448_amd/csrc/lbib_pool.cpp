@@ -241,6 +241,8 @@ lbib_status rebuild(lbib_pool* h)
         s.a.guo = 1.0 - 1.0 / (2.0 * m.g.tau);
         s.a.gx = m.g.gx;
         s.a.gy = m.g.gy;
+        s.a.scale = m.g.scale;
+        s.a.inv_scale = 1.0 / m.g.scale;
         s.fA = (T*)m.fA;
         s.fB = (T*)m.fB;
         s.tile = m.p.d_tile;
@@ -412,8 +414,9 @@ lbib_status lbib_pool_create(int32_t precision, int64_t hbm_budget_bytes, int32_
                              lbib_pool_handle* out)
 {
     if (!out) return fail(nullptr, LBIB_E_INVALID, "lbib_pool_create: NULL output");
-    if (precision != LBIB_FP64 && precision != LBIB_FP32)
-        return fail(nullptr, LBIB_E_UNSUPPORTED, "lbib_pool_create: precision must be LBIB_FP64 or LBIB_FP32");
+    if (precision != LBIB_FP64 && precision != LBIB_FP32 && precision != LBIB_FP16 && precision != LBIB_BF16)
+        return fail(nullptr, LBIB_E_UNSUPPORTED,
+                    "lbib_pool_create: precision must be LBIB_FP64, LBIB_FP32, LBIB_FP16 or LBIB_BF16");
     if (hbm_budget_bytes <= 0) return fail(nullptr, LBIB_E_INVALID, "lbib_pool_create: budget must be positive");
     if (max_members < 1 || max_members > 65536)
         return fail(nullptr, LBIB_E_INVALID, "lbib_pool_create: max_members must be in [1, 65536]");
@@ -421,7 +424,7 @@ lbib_status lbib_pool_create(int32_t precision, int64_t hbm_budget_bytes, int32_
     try {
         h = new lbib_pool();
         h->precision = precision;
-        h->elem = precision == LBIB_FP64 ? 8 : 4;
+        h->elem = precision == LBIB_FP64 ? 8 : precision == LBIB_FP32 ? 4 : 2;
         h->budget = hbm_budget_bytes;
         h->max_members = max_members;
         for (int32_t l = max_members - 1; l >= 0; --l) h->free_lanes.push_back(l);
@@ -541,8 +544,12 @@ lbib_status lbib_pool_step(lbib_pool_handle h, int64_t n)
 {
     if (!h) return fail(nullptr, LBIB_E_INVALID, "lbib_pool_step: NULL handle");
     if (n < 0) return fail(h, LBIB_E_INVALID, "lbib_pool_step: negative step count");
-    if (h->elem == 8) return enqueue<double>(h, n);
-    return enqueue<float>(h, n);
+    switch (h->precision) {
+        case LBIB_FP64: return enqueue<double>(h, n);
+        case LBIB_FP32: return enqueue<float>(h, n);
+        case LBIB_FP16: return enqueue<half_t>(h, n);
+        default: return enqueue<bf16_t>(h, n);
+    }
 }
 
 lbib_status lbib_pool_poll(lbib_pool_handle h, int32_t* slots, int32_t capacity, int32_t* count)

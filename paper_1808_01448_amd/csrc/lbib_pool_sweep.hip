@@ -88,9 +88,13 @@ hipError_t launch_pool_sweep(const PoolSweep<T>* sims, const TileDesc* ctl, cons
     return hipErrorInvalidValue;
 }
 
-template hipError_t launch_pool_sweep<float>(const PoolSweep<float>*, const TileDesc*, const int2*, int32_t,
+#define LBIB_POOL_SWEEP_INSTANTIATE(T)                                                                      \
+    template hipError_t launch_pool_sweep<T>(const PoolSweep<T>*, const TileDesc*, const int2*, int32_t,         \
                                              PoolSweepConfig, hipStream_t, hipEvent_t, hipEvent_t);
-template hipError_t launch_pool_sweep<double>(const PoolSweep<double>*, const TileDesc*, const int2*, int32_t,
-                                              PoolSweepConfig, hipStream_t, hipEvent_t, hipEvent_t);
+LBIB_POOL_SWEEP_INSTANTIATE(double)
+LBIB_POOL_SWEEP_INSTANTIATE(float)
+LBIB_POOL_SWEEP_INSTANTIATE(half_t)
+LBIB_POOL_SWEEP_INSTANTIATE(bf16_t)
+#undef LBIB_POOL_SWEEP_INSTANTIATE
 
 }  // namespace lbib

@@ -115,6 +115,8 @@ SweepArgs sweep_args(lbib_sim* h)
     a.guo = 1.0 - 1.0 / (2.0 * h->desc.tau);
     a.gx = h->g.gx;
     a.gy = h->g.gy;
+    a.scale = h->g.scale;
+    a.inv_scale = 1.0 / h->g.scale;
     return a;
 }
 
@@ -387,8 +389,12 @@ lbib_status lbib_step(lbib_handle h, int64_t n)
     if (n < 0) return fail(h, LBIB_E_INVALID, "lbib_step: negative step count");
     if (h->state == 0) return fail(h, LBIB_E_STATE, "lbib_step: lbib_init first");
     if (h->state == 2) return fail(h, LBIB_E_STATE, "lbib_step: simulation failed; lbib_load a good state");
-    if (h->g.elem == 8) return enqueue_steps<double>(h, n);
-    return enqueue_steps<float>(h, n);
+    switch (h->g.precision) {
+        case LBIB_FP64: return enqueue_steps<double>(h, n);
+        case LBIB_FP32: return enqueue_steps<float>(h, n);
+        case LBIB_FP16: return enqueue_steps<half_t>(h, n);
+        default: return enqueue_steps<bf16_t>(h, n);
+    }
 }
 
 lbib_status lbib_sync(lbib_handle h)

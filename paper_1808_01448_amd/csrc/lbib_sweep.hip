@@ -39,7 +39,8 @@ __device__ __forceinline__ double init_value(int q, int j, int ny, double umax)
 }
 
 template <typename T, bool PULL>
-__global__ __launch_bounds__(256) void init_kernel(T* f, int nx, int ny, int pitch, int64_t plane, double umax)
+__global__ __launch_bounds__(256) void init_kernel(T* f, int nx, int ny, int pitch, int64_t plane, double umax,
+                                                   double scale)
 {
     const int i = blockIdx.x * 64 + threadIdx.x;
     const int j = blockIdx.y * 4 + threadIdx.y;
@@ -52,19 +53,19 @@ __global__ __launch_bounds__(256) void init_kernel(T* f, int nx, int ny, int pit
         const int dj = j + kEy[q];
         const double v = !PULL ? init_value(q, j, ny, umax)
                                : (dj >= 0 && dj < ny ? init_value(q, dj, ny, umax) : init_value(kOpp[q], j, ny, umax));
-        f[q * plane + c] = (T)v;
+        st_store(f, q * plane + c, (typename St<T>::C)v, scale, false);
     }
 }
 
 template <typename T>
-hipError_t launch_init(T* f, int32_t nx, int32_t ny, int32_t pitch, int64_t plane, double umax, bool pull,
-                       hipStream_t stream)
+hipError_t launch_init(T* f, int32_t nx, int32_t ny, int32_t pitch, int64_t plane, double umax, double scale,
+                       bool pull, hipStream_t stream)
 {
     dim3 block(64, 4), grid((nx + 63) / 64, (ny + 3) / 4);
     if (pull)
-        hipLaunchKernelGGL((init_kernel<T, true>), grid, block, 0, stream, f, nx, ny, pitch, plane, umax);
+        hipLaunchKernelGGL((init_kernel<T, true>), grid, block, 0, stream, f, nx, ny, pitch, plane, umax, scale);
     else
-        hipLaunchKernelGGL((init_kernel<T, false>), grid, block, 0, stream, f, nx, ny, pitch, plane, umax);
+        hipLaunchKernelGGL((init_kernel<T, false>), grid, block, 0, stream, f, nx, ny, pitch, plane, umax, scale);
     return hipGetLastError();
 }
 
@@ -147,11 +148,14 @@ hipError_t launch_sweep(const T* fin, T* fout, const SweepArgs& a, int mode, con
     return launch_sweep_layout<T, false>(fin, fout, a, mode, desc, tile, box_cap, stream, t0, t1);
 }
 
-template hipError_t launch_init<float>(float*, int32_t, int32_t, int32_t, int64_t, double, bool, hipStream_t);
-template hipError_t launch_init<double>(double*, int32_t, int32_t, int32_t, int64_t, double, bool, hipStream_t);
-template hipError_t launch_sweep<float>(const float*, float*, const SweepArgs&, int, const TileDesc*, const int64_t*,
+#define LBIB_SWEEP_INSTANTIATE(T)                                                                               \
+    template hipError_t launch_init<T>(T*, int32_t, int32_t, int32_t, int64_t, double, double, bool, hipStream_t); \
+    template hipError_t launch_sweep<T>(const T*, T*, const SweepArgs&, int, const TileDesc*, const int64_t*,      \
                                         int32_t, bool, hipStream_t, hipEvent_t, hipEvent_t);
-template hipError_t launch_sweep<double>(const double*, double*, const SweepArgs&, int, const TileDesc*,
-                                         const int64_t*, int32_t, bool, hipStream_t, hipEvent_t, hipEvent_t);
+LBIB_SWEEP_INSTANTIATE(double)
+LBIB_SWEEP_INSTANTIATE(float)
+LBIB_SWEEP_INSTANTIATE(half_t)
+LBIB_SWEEP_INSTANTIATE(bf16_t)
+#undef LBIB_SWEEP_INSTANTIATE
 
 }  // namespace lbib

@@ -81,7 +81,7 @@ def _create(L, **kw):
 @pytest.mark.parametrize("kw,status", [
     (dict(nx=3), lbib.E_INVALID), (dict(ny=2), lbib.E_INVALID), (dict(tau=0.5), lbib.E_INVALID),
     (dict(tau=float("nan")), lbib.E_INVALID), (dict(re=-1.0), lbib.E_INVALID),
-    (dict(drive=1), lbib.E_UNSUPPORTED), (dict(precision=2), lbib.E_UNSUPPORTED),
+    (dict(drive=1), lbib.E_UNSUPPORTED), (dict(precision=4), lbib.E_UNSUPPORTED), (dict(precision=-1), lbib.E_UNSUPPORTED),
 ])
 def test_create_rejects(L, kw, status):
     st, h = _create(L, **kw)
@@ -151,7 +151,7 @@ def test_kernel_entry_points_validate_sizes(L):
 
 def test_pool_host_validation(L):
     h = C.c_void_p()
-    assert L.lbib_pool_create(2, 1 << 30, 16, FAKE_STREAM, C.byref(h)) == lbib.E_UNSUPPORTED
+    assert L.lbib_pool_create(9, 1 << 30, 16, FAKE_STREAM, C.byref(h)) == lbib.E_UNSUPPORTED
     assert L.lbib_pool_create(1, 0, 16, FAKE_STREAM, C.byref(h)) == lbib.E_INVALID
     assert L.lbib_pool_create(1, 1 << 30, 0, FAKE_STREAM, C.byref(h)) == lbib.E_INVALID
     assert L.lbib_pool_create(1, 1 << 30, 70000, FAKE_STREAM, C.byref(h)) == lbib.E_INVALID

@@ -1,0 +1,135 @@
+"""GPU tests of the 16-bit population storages (FP16 with a power-of-two scale, BF16).
+
+Populations are stored as f - w_q in IEEE binary16 (times 2^S) or bfloat16 and collided in
+FP32; the particle phase stays FP64.  The error against the FP64 oracle is set by the
+storage's unit roundoff u (2^-11 for FP16, 2^-8 for BF16): every stored deviation carries a
+relative rounding of up to u/2 each step, and the flow's velocity (a sum of deviations)
+inherits a few u.  Measured on the 256 x 64 cases: velocity 1.0-1.6e-3 (FP16) and 2.5e-2
+(BF16), displacement 1.6-2.2e-4 and 1.7-3.8e-3, hydrodynamic force 7.8e-3 and 0.14 (a
+derivative of the field), field 1.2e-3 and 1.1e-2.  The bars below are about 3x those."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1808_01448_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {  # velocity series, displacement series, force series, final velocity field
+    "fp16": dict(U=5e-3, X=1e-3, F=3e-2, field=4e-3),
+    "bf16": dict(U=8e-2, X=1.5e-2, F=0.4, field=4e-2),
+}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_1808_01448_amd import lbib
+
+    lbib.lib()
+    return lbib
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_16bit_storage_against_oracle(L, orc, prec):
+    w0 = W.channel_small_binding("fp64")
+    steps = 1500
+    o = orc.Sim.from_workload(w0)
+    _, to = o.step(steps, trace=True)
+    _, uxo, uyo = o.fields()
+    w = W.with_precision(w0, prec)
+    s = L.Sim(w)
+    assert s.bytes_per_update == 36
+    s.trace_enable(steps)
+    s.step(steps)
+    s.sync()
+    tg = s.trace(steps)
+    _, ux, uy = s.fields()
+    x0 = np.array([w0["particle"]["xc"], w0["particle"]["yc"]])
+    e = dict(U=rel(tg[:, 4:6], to[:, 4:6]), X=rel(tg[:, 1:3] - x0, to[:, 1:3] - x0), F=rel(tg[:, 7:9], to[:, 7:9]),
+             field=rel(np.stack([ux, uy]), np.stack([uxo, uyo])))
+    say(prec, " ".join(f"{k}={v:.2e}" for k, v in e.items()))
+    for k, v in e.items():
+        assert v <= TOL[prec][k], (prec, k, v)
+    # bond counts: the decisions use FP64 distances, which move by ~1e-4 (FP16) to 1e-3 (BF16)
+    # of the gap; a draw near its threshold may flip, so allow a handful of differing steps
+    diff = np.abs(tg[:, -2] - to[:, -2])
+    say("  bond-count steps differing:", int((diff > 0).sum()), "of", steps)
+    assert (diff > 0).mean() <= 0.01 and diff.max() <= 2
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_16bit_layouts_and_schedules_agree(L, prec):
+    w = W.channel_small_binding(prec)
+    out = []
+    for layout, overlap in ((0, 0), (1, 0), (1, 1)):
+        s = L.Sim(w, layout=layout)
+        s.set_overlap(overlap)
+        s.trace_enable(300)
+        s.step(300)
+        s.sync()
+        out.append((s.trace(300), s.f))
+        s.close()
+    for t, f in out[1:]:
+        np.testing.assert_array_equal(t, out[0][0])
+        np.testing.assert_array_equal(f, out[0][1])
+
+
+def fp16_scale(w):
+    """The FP16 storage scale of a lattice, by the rule lbib.h states."""
+    lat = w["lattice"]
+    nu = (lat["tau"] - 0.5) / 3.0
+    u = max(4.0 * lat["re"] * nu / lat["ny"], 1e-6)
+    d = (4.0 / 9.0) * (3.0 * u + 4.5 * u * u)
+    return 2.0 ** min(40, max(0, int(np.floor(np.log2(8192.0 / d)))))
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_16bit_population_roundtrip(L, prec):
+    """Written populations read back as the storage's rounding (to nearest even) of f - w,
+    FP16 after its power-of-two scale, for deviations from 1e-9 to 1e-3."""
+    w = W.channel_small_binding(prec)
+    s = L.Sim(w)
+    f = s.f
+    wq = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)[:, None, None]
+    dev = W.random_perturbation(11, f.shape, 1.0) * np.logspace(-9, -3, f.shape[2])[None, None, :]
+    s.write_populations(wq + dev)
+    v = (wq + dev) - wq
+    if prec == "fp16":
+        sc = fp16_scale(w)
+        h = (v.astype(np.float32) * np.float32(sc)).astype(np.float16)
+        back = h.astype(np.float64) * (1.0 / sc)
+    else:
+        u = v.astype(np.float32).view(np.uint32).astype(np.uint64)
+        back = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+    np.testing.assert_array_equal(s.f, wq + back)
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_16bit_pool_member_equals_standalone(L, prec):
+    w = W.channel_small_binding(prec)
+    s = L.Sim(w)
+    s.step(120)
+    s.sync()
+    ref = (s.particle(), s.f)
+    s.close()
+    P = L.Pool(W.PRECISION[prec], budget_bytes=1 << 30)
+    k = P.add(w, 120)
+    P.step(130)
+    assert P.poll() == [k]
+    assert P.particle(k) == ref[0]
+    np.testing.assert_array_equal(P.field(k, 3), ref[1])
+    P.close()
