@@ -56,6 +56,17 @@ class Params(C.Structure):
     ]
 
 
+class ParticleParams(C.Structure):
+    _fields_ = [
+        ("shape", C.c_int32), ("a", C.c_double), ("b", C.c_double), ("xc", C.c_double), ("yc", C.c_double),
+        ("theta0", C.c_double), ("rho_p", C.c_double), ("nl", C.c_int32),
+        ("rho_l_num", C.c_int32), ("rho_l_den", C.c_int32),
+        ("sigma_hat", C.c_double), ("sigma_star_ratio", C.c_double), ("y_cr_hat", C.c_double),
+        ("y_eq_ratio", C.c_double), ("k_f", C.c_double), ("k_r0", C.c_double),
+        ("kbt_hat", C.c_double), ("hamaker_hat", C.c_double),
+    ]
+
+
 _lib = None
 
 _D = C.POINTER(C.c_double)
@@ -110,6 +121,13 @@ def lib():
             "orc_sim_set_bonds": (None, [C.c_void_p, _U8]),
             "orc_sim_get_geometry": (None, [C.c_void_p, _D, _D, _D]),
             "orc_sim_get_markers": (None, [C.c_void_p, _D, _D]),
+            "orc_sim_add_particle": (C.c_int32, [C.c_void_p, C.POINTER(ParticleParams)]),
+            "orc_sim_num_particles": (C.c_int32, [C.c_void_p]),
+            "orc_sim_step_all": (C.c_int32, [C.c_void_p, C.c_int64, _D]),
+            "orc_sim_get_particle_k": (None, [C.c_void_p, C.c_int32, _D]),
+            "orc_sim_set_particle_k": (None, [C.c_void_p, C.c_int32, _D]),
+            "orc_sim_get_bonds_k": (None, [C.c_void_p, C.c_int32, _U8, _U8]),
+            "orc_sim_get_markers_k": (None, [C.c_void_p, C.c_int32, _D, _D]),
             "orc_num_threads": (C.c_int32, []),
             "orc_set_threads": (None, [C.c_int32]),
         }
@@ -282,17 +300,39 @@ def set_threads(n: int):
 # Whole simulation
 # ----------------------------------------------------------------------------------------
 
+def particle_entries(w: dict) -> list:
+    """(particle, ligand) descriptor pairs of a workload: the single form ("particle",
+    "ligand") or the list form ("particles": [{"particle": ..., "ligand": ...}, ...])."""
+    if "particles" in w:
+        return [(e["particle"], e["ligand"]) for e in w["particles"]]
+    if w.get("particle") is not None:
+        return [(w["particle"], w["ligand"])]
+    return []
+
+
+def particle_params(part: dict, lig: dict) -> ParticleParams:
+    q = ParticleParams()
+    q.shape, q.a, q.b = part["shape"], part["a_major"], part["b_minor"]
+    q.xc, q.yc, q.theta0, q.rho_p, q.nl = part["xc"], part["yc"], part["theta0"], part["rho_p"], part["n_markers"]
+    q.rho_l_num, q.rho_l_den = lig["rho_l_num"], lig["rho_l_den"]
+    q.sigma_hat, q.sigma_star_ratio = lig["sigma_hat"], lig["sigma_star_ratio"]
+    q.y_cr_hat, q.y_eq_ratio = lig["y_cr_hat"], lig["y_eq_ratio"]
+    q.k_f, q.k_r0, q.kbt_hat, q.hamaker_hat = lig["k_f"], lig["k_r0"], lig["kbt_hat"], lig["hamaker_hat"]
+    return q
+
+
 def params_from_workload(w: dict, *, walls=True, init_rest=False, extra_g=(0.0, 0.0)) -> Params:
-    """Map a workload descriptor (see paper_1808_01448_amd.workloads) onto oracle parameters."""
+    """Map a workload descriptor (see paper_1808_01448_amd.workloads) onto oracle parameters
+    (the first particle; Sim.from_workload adds the others)."""
     L = w["lattice"]
     P = Params()
     P.nx, P.ny, P.tau, P.re, P.seed = L["nx"], L["ny"], L["tau"], L["re"], L["seed"]
     P.walls = 1 if walls else 0
     P.init_rest = 1 if init_rest else 0
     P.extra_gx, P.extra_gy = extra_g
-    part = w.get("particle")
-    if part is not None:
-        lig = w["ligand"]
+    entries = particle_entries(w)
+    if entries:
+        part, lig = entries[0]
         P.has_particle = 1
         P.shape = part["shape"]
         P.a, P.b = part["a_major"], part["b_minor"]
@@ -306,7 +346,8 @@ def params_from_workload(w: dict, *, walls=True, init_rest=False, extra_g=(0.0, 
 
 
 class Sim:
-    """FP64 oracle simulation (one particle at most)."""
+    """FP64 oracle simulation (any number of particles up to 64; the single-particle calls
+    refer to particle 0)."""
 
     DERIVED = ("nu", "umax", "gx", "gy", "sigma", "sigma_star", "y_cr", "y_eq", "kBT", "hamaker",
                "mass", "inertia")
@@ -318,10 +359,48 @@ class Sim:
             raise ValueError("oracle rejected the parameters")
         self.nx, self.ny = params.nx, params.ny
         self.nl = params.nl if params.has_particle else 0
+        self.nls = [self.nl] if params.has_particle else []
 
     @classmethod
     def from_workload(cls, w: dict, **kw):
-        return cls(params_from_workload(w, **kw))
+        s = cls(params_from_workload(w, **kw))
+        for part, lig in particle_entries(w)[1:]:
+            s.add_particle(part, lig)
+        return s
+
+    def add_particle(self, part: dict, lig: dict) -> int:
+        k = lib().orc_sim_add_particle(self._h, C.byref(particle_params(part, lig)))
+        if k < 0:
+            raise ValueError("oracle rejected the particle")
+        self.nls.append(part["n_markers"])
+        return k
+
+    @property
+    def n_particles(self) -> int:
+        return int(lib().orc_sim_num_particles(self._h))
+
+    def step_all(self, n=1):
+        """n steps; returns (flags, records [n, particles, TRACE_W])."""
+        tr = np.zeros((n, self.n_particles, TRACE_W))
+        flags = lib().orc_sim_step_all(self._h, n, _p(tr))
+        return flags, tr
+
+    def particle_k(self, k: int):
+        out = np.zeros(12)
+        lib().orc_sim_get_particle_k(self._h, int(k), _p(out))
+        return out
+
+    def bonds_k(self, k: int):
+        nl = self.nls[k]
+        b = np.zeros(nl, np.uint8); lg = np.zeros(nl, np.uint8)
+        lib().orc_sim_get_bonds_k(self._h, int(k), _p(b, _U8), _p(lg, _U8))
+        return b, lg
+
+    def markers_k(self, k: int):
+        nl = self.nls[k]
+        X = np.zeros((nl, 2)); n = np.zeros((nl, 2))
+        lib().orc_sim_get_markers_k(self._h, int(k), _p(X), _p(n))
+        return X, n
 
     def close(self):
         if self._h:

@@ -542,7 +542,7 @@ typedef struct {
     int32_t walls;     /* 1: bounce-back walls (the product's only mode); 0: periodic y (test) */
     int32_t init_rest; /* 0: start from f_eq(1, u_poiseuille(y)); 1: start from f_eq(1, 0) */
     double extra_gx, extra_gy; /* body force added to the Poiseuille drive (test hooks) */
-    int32_t has_particle;
+    int32_t has_particle;      /* particle 0 from the fields below */
     int32_t shape;
     double a, b, xc, yc, theta0, rho_p;
     int32_t nl;
@@ -550,21 +550,53 @@ typedef struct {
     double sigma_hat, sigma_star_ratio, y_cr_hat, y_eq_ratio, k_f, k_r0, kbt_hat, hamaker_hat;
 } orc_params;
 
+/* One particle: shape and placement, ligands and bond constants (Table 1 groups). */
+typedef struct {
+    int32_t shape;
+    double a, b, xc, yc, theta0, rho_p;
+    int32_t nl;
+    int32_t rho_l_num, rho_l_den;
+    double sigma_hat, sigma_star_ratio, y_cr_hat, y_eq_ratio, k_f, k_r0, kbt_hat, hamaker_hat;
+} orc_particle_params;
+
 #define ORC_TRACE_W 20
+#define ORC_MAX_PARTICLES 64
+
+typedef struct {
+    orc_particle_params q;
+    double sigma, sigma_star, y_cr, y_eq, kBT, hamaker, mass, inertia;
+    double xc, yc, th, ux_p, uy_p, om;   /* time level n   */
+    double xc1, yc1, th1, ux1, uy1, om1; /* time level n-1 */
+    double *V, *xi, *nuv, *S, *X, *nrm, *Pp, *Ud, *Fl, *tl, *dd, *fb;
+    uint8_t *ligand, *bond, *bond_new;
+    double rec[ORC_TRACE_W]; /* record of the last step */
+} orc_particle;
 
 typedef struct {
     orc_params p;
     double nu, umax, gx, gy;
-    double sigma, sigma_star, y_cr, y_eq, kBT, hamaker, mass, inertia;
     int64_t step;
     int32_t flags;
     double *f, *fn, *fib, *rho, *ux, *uy;
-    /* particle */
-    double xc, yc, th, ux_p, uy_p, om;         /* time level n   */
-    double xc1, yc1, th1, ux1, uy1, om1;       /* time level n-1 */
-    double *V, *xi, *nuv, *S, *X, *nrm, *Pp, *Ud, *Fl, *tl, *dd, *fb;
-    uint8_t *ligand, *bond, *bond_new;
+    int32_t np;
+    orc_particle* P[ORC_MAX_PARTICLES];
 } orc_sim;
+
+/* Lattice-unit constants of a particle from the Table 1 groups (rho_ref = 1, H = ny). */
+static void derive_particle(const orc_sim* s, orc_particle* P)
+{
+    const orc_particle_params* q = &P->q;
+    double H = (double)s->p.ny;
+    double g = s->nu * s->nu / H; /* rho_ref nu^2 / H */
+    P->sigma = q->sigma_hat * g;
+    P->sigma_star = q->sigma_star_ratio * P->sigma;
+    P->y_cr = q->y_cr_hat * H;
+    P->y_eq = q->y_eq_ratio * P->y_cr;
+    P->kBT = q->kbt_hat * s->nu * s->nu * H;
+    P->hamaker = q->hamaker_hat * s->nu * s->nu * H;
+    P->mass = q->rho_p * M_PI * q->a * q->b;
+    P->inertia = P->mass * (q->a * q->a + q->b * q->b) / 4.0;
+}
 
 static void derive(orc_sim* s)
 {
@@ -574,29 +606,66 @@ static void derive(orc_sim* s)
     s->umax = p->re * s->nu / H;
     s->gx = 8.0 * s->nu * s->umax / (H * H) + p->extra_gx;
     s->gy = p->extra_gy;
-    double g = s->nu * s->nu / H; /* rho_ref nu^2 / H with rho_ref = 1 (Table 1 groups) */
-    s->sigma = p->sigma_hat * g;
-    s->sigma_star = p->sigma_star_ratio * s->sigma;
-    s->y_cr = p->y_cr_hat * H;
-    s->y_eq = p->y_eq_ratio * s->y_cr;
-    s->kBT = p->kbt_hat * s->nu * s->nu * H;
-    s->hamaker = p->hamaker_hat * s->nu * s->nu * H;
-    s->mass = p->rho_p * M_PI * p->a * p->b;
-    s->inertia = s->mass * (p->a * p->a + p->b * p->b) / 4.0;
 }
 
-static void place_markers(orc_sim* s)
+static void place_markers(orc_particle* P)
 {
-    int nl = s->p.nl;
-    double c = cos(s->th), sn = sin(s->th);
+    int nl = P->q.nl;
+    double c = cos(P->th), sn = sin(P->th);
     for (int l = 0; l < nl; ++l) {
-        double bx = s->xi[2 * l], by = s->xi[2 * l + 1];
-        s->X[2 * l] = s->xc + c * bx - sn * by;
-        s->X[2 * l + 1] = s->yc + sn * bx + c * by;
-        double mx = s->nuv[2 * l], my = s->nuv[2 * l + 1];
-        s->nrm[2 * l] = c * mx - sn * my;
-        s->nrm[2 * l + 1] = sn * mx + c * my;
+        double bx = P->xi[2 * l], by = P->xi[2 * l + 1];
+        P->X[2 * l] = P->xc + c * bx - sn * by;
+        P->X[2 * l + 1] = P->yc + sn * bx + c * by;
+        double mx = P->nuv[2 * l], my = P->nuv[2 * l + 1];
+        P->nrm[2 * l] = c * mx - sn * my;
+        P->nrm[2 * l + 1] = sn * mx + c * my;
     }
+}
+
+static void free_particle(orc_particle* P)
+{
+    if (!P) return;
+    free(P->V); free(P->xi); free(P->nuv); free(P->S); free(P->X); free(P->nrm); free(P->Pp);
+    free(P->Ud); free(P->Fl); free(P->tl); free(P->dd); free(P->fb);
+    free(P->ligand); free(P->bond); free(P->bond_new);
+    free(P);
+}
+
+/* Add a particle at rest at its placement, with no bonds; returns its index (the particle
+ * index of its bond draws) or -1. */
+int32_t orc_sim_add_particle(orc_sim* s, const orc_particle_params* q)
+{
+    if (s->np >= ORC_MAX_PARTICLES || s->step != 0 || q->nl < 3) return -1;
+    orc_particle* P = (orc_particle*)calloc(1, sizeof(orc_particle));
+    P->q = *q;
+    if (q->shape == 0) P->q.b = q->a;
+    int nl = q->nl;
+    P->V = (double*)calloc(2 * nl, sizeof(double));
+    P->xi = (double*)calloc(2 * nl, sizeof(double));
+    P->nuv = (double*)calloc(2 * nl, sizeof(double));
+    P->S = (double*)calloc(nl, sizeof(double));
+    P->X = (double*)calloc(2 * nl, sizeof(double));
+    P->nrm = (double*)calloc(2 * nl, sizeof(double));
+    P->Pp = (double*)calloc(2 * nl, sizeof(double));
+    P->Ud = (double*)calloc(2 * nl, sizeof(double));
+    P->Fl = (double*)calloc(2 * nl, sizeof(double));
+    P->tl = (double*)calloc(2 * nl, sizeof(double));
+    P->dd = (double*)calloc(nl, sizeof(double));
+    P->fb = (double*)calloc(2 * nl, sizeof(double));
+    P->ligand = (uint8_t*)calloc(nl, 1);
+    P->bond = (uint8_t*)calloc(nl, 1);
+    P->bond_new = (uint8_t*)calloc(nl, 1);
+    if (orc_geometry(P->q.shape, P->q.a, P->q.b, nl, P->V, P->xi, P->nuv, P->S) != 0) {
+        free_particle(P);
+        return -1;
+    }
+    orc_ligand_flags(nl, q->rho_l_num, q->rho_l_den, P->ligand);
+    P->xc = P->xc1 = q->xc;
+    P->yc = P->yc1 = q->yc;
+    P->th = P->th1 = q->theta0;
+    derive_particle(s, P);
+    s->P[s->np] = P;
+    return s->np++;
 }
 
 orc_sim* orc_sim_create(const orc_params* p)
@@ -621,33 +690,15 @@ orc_sim* orc_sim_create(const orc_params* p)
             for (int q = 0; q < 9; ++q) s->f[IDX(q, j, i, p->nx, p->ny)] = feq[q];
     }
     if (p->has_particle) {
-        int nl = p->nl;
-        s->V = (double*)calloc(2 * nl, sizeof(double));
-        s->xi = (double*)calloc(2 * nl, sizeof(double));
-        s->nuv = (double*)calloc(2 * nl, sizeof(double));
-        s->S = (double*)calloc(nl, sizeof(double));
-        s->X = (double*)calloc(2 * nl, sizeof(double));
-        s->nrm = (double*)calloc(2 * nl, sizeof(double));
-        s->Pp = (double*)calloc(2 * nl, sizeof(double));
-        s->Ud = (double*)calloc(2 * nl, sizeof(double));
-        s->Fl = (double*)calloc(2 * nl, sizeof(double));
-        s->tl = (double*)calloc(2 * nl, sizeof(double));
-        s->dd = (double*)calloc(nl, sizeof(double));
-        s->fb = (double*)calloc(2 * nl, sizeof(double));
-        s->ligand = (uint8_t*)calloc(nl, 1);
-        s->bond = (uint8_t*)calloc(nl, 1);
-        s->bond_new = (uint8_t*)calloc(nl, 1);
-        double b = p->shape == 0 ? p->a : p->b;
-        if (orc_geometry(p->shape, p->a, b, nl, s->V, s->xi, s->nuv, s->S) != 0) {
+        orc_particle_params q = {p->shape, p->a, p->b, p->xc, p->yc, p->theta0, p->rho_p, p->nl,
+                                 p->rho_l_num, p->rho_l_den, p->sigma_hat, p->sigma_star_ratio,
+                                 p->y_cr_hat, p->y_eq_ratio, p->k_f, p->k_r0, p->kbt_hat, p->hamaker_hat};
+        if (orc_sim_add_particle(s, &q) != 0) {
+            free(s->f); free(s->fn); free(s->fib); free(s->rho); free(s->ux); free(s->uy);
             free(s);
             return NULL;
         }
-        orc_ligand_flags(nl, p->rho_l_num, p->rho_l_den, s->ligand);
-        s->xc = s->xc1 = p->xc;
-        s->yc = s->yc1 = p->yc;
-        s->th = s->th1 = p->theta0;
         if (p->shape == 0) s->p.b = p->a;
-        derive(s);
     }
     return s;
 }
@@ -656,9 +707,7 @@ void orc_sim_destroy(orc_sim* s)
 {
     if (!s) return;
     free(s->f); free(s->fn); free(s->fib); free(s->rho); free(s->ux); free(s->uy);
-    free(s->V); free(s->xi); free(s->nuv); free(s->S); free(s->X); free(s->nrm); free(s->Pp);
-    free(s->Ud); free(s->Fl); free(s->tl); free(s->dd); free(s->fb);
-    free(s->ligand); free(s->bond); free(s->bond_new);
+    for (int k = 0; k < s->np; ++k) free_particle(s->P[k]);
     free(s);
 }
 
@@ -680,81 +729,97 @@ static void node_fields(orc_sim* s, int with_fib)
         }
 }
 
+/* Loads, bonds and the rigid-body update of particle k (steps 8-12 below), from the forced
+ * step-n node fields. */
+static void particle_update(orc_sim* s, int k)
+{
+    const orc_params* p = &s->p;
+    orc_particle* P = s->P[k];
+    const orc_particle_params* q = &P->q;
+    int nx = p->nx, ny = p->ny, nl = q->nl;
+    double Fh[3] = {0, 0, 0}, Fb[3] = {0, 0, 0}, Fw = 0.0, gap = 0.0;
+    int n_probing = 0;
+    for (int l = 0; l < nl; ++l) { /* probe 1.2 dx along the outward normal (below eq 8) */
+        P->Pp[2 * l] = P->X[2 * l] + 1.2 * P->nrm[2 * l];
+        P->Pp[2 * l + 1] = P->X[2 * l + 1] + 1.2 * P->nrm[2 * l + 1];
+    }
+    if (orc_tractions(nx, ny, s->nu, s->rho, s->ux, s->uy, nl, P->Pp, P->nrm, P->S, P->tl) != 0) s->flags |= 4;
+    for (int l = 0; l < nl; ++l) P->dd[l] = P->X[2 * l + 1] + 0.5;
+    int n_bonds = orc_bonds(nl, P->ligand, P->dd, P->bond, P->bond_new, P->y_cr, P->y_eq, P->sigma, P->sigma_star,
+                            q->k_f, q->k_r0, P->kBT, p->seed, s->step, (uint32_t)k, &n_probing);
+    for (int l = 0; l < nl; ++l) {
+        P->bond[l] = P->bond_new[l];
+        double mag = P->bond[l] ? P->sigma * (P->dd[l] - P->y_eq) : 0.0; /* eq 9 */
+        P->fb[2 * l] = mag * P->nrm[2 * l];
+        P->fb[2 * l + 1] = mag * P->nrm[2 * l + 1];
+    }
+    int32_t wflag = 0;
+    Fw = orc_wall_force(P->yc, P->th, q->a, q->b, P->hamaker, &gap, &wflag);
+    if (wflag) s->flags |= 2;
+    for (int l = 0; l < nl; ++l) {
+        double rx = P->X[2 * l] - P->xc, ry = P->X[2 * l + 1] - P->yc;
+        Fh[0] += P->tl[2 * l];
+        Fh[1] += P->tl[2 * l + 1];
+        Fh[2] += rx * P->tl[2 * l + 1] - ry * P->tl[2 * l];
+        Fb[0] += P->fb[2 * l];
+        Fb[1] += P->fb[2 * l + 1];
+        Fb[2] += rx * P->fb[2 * l + 1] - ry * P->fb[2 * l];
+    }
+    double Fx = Fh[0] + Fb[0], Fy = Fh[1] + Fb[1] + Fw, M = Fh[2] + Fb[2];
+    double ux_n = orc_bdf2(P->ux_p, P->ux1, Fx / P->mass);
+    double uy_n = orc_bdf2(P->uy_p, P->uy1, Fy / P->mass);
+    double om_n = orc_bdf2(P->om, P->om1, M / P->inertia);
+    double xc_n = orc_bdf2(P->xc, P->xc1, ux_n);
+    double yc_n = orc_bdf2(P->yc, P->yc1, uy_n);
+    double th_n = orc_bdf2(P->th, P->th1, om_n);
+    if (!isfinite(Fx) || !isfinite(Fy) || !isfinite(M) || !isfinite(ux_n) || !isfinite(uy_n) || !isfinite(om_n))
+        s->flags |= 1;
+    P->ux1 = P->ux_p; P->uy1 = P->uy_p; P->om1 = P->om;
+    P->xc1 = P->xc; P->yc1 = P->yc; P->th1 = P->th;
+    P->ux_p = ux_n; P->uy_p = uy_n; P->om = om_n;
+    P->xc = xc_n; P->yc = yc_n; P->th = th_n;
+    double rec[ORC_TRACE_W] = {(double)s->step, P->xc, P->yc, P->th, P->ux_p, P->uy_p, P->om,
+                               Fx, Fy, M, Fh[0], Fh[1], Fh[2], Fb[0], Fb[1], Fb[2], Fw, gap,
+                               (double)n_bonds, (double)n_probing};
+    memcpy(P->rec, rec, sizeof(rec));
+}
+
 /* One time step n -> n+1 in the order:
- *  1 markers at (X_c^n, theta^n);  2 node moments without the IB force;
- *  3-4 MLS interpolation and direct-forcing marker forces;  5 spread to the lattice;
+ *  1 markers of every particle at (X_c^n, theta^n);  2 node moments without the IB force;
+ *  3-4 MLS interpolation and direct-forcing marker forces;  5 spread to the lattice,
+ *  particles in index order (particles meet only through the fluid);
  *  6-7 collide (eq 1, 4) and stream with the total body force g + fib;
- *  8 probe loads (eq 7-8) from the forced step-n fields;  9 bonds (eq 9-11);
- *  10 wall force (eq 12);  11 totals F, M;  12 rigid-body update (eq 13-16).
- * trace (ORC_TRACE_W doubles) receives the record of this step when not NULL. */
+ *  then for each particle: 8 probe loads (eq 7-8) from the forced step-n fields (the spread
+ *  force of every particle included);  9 bonds (eq 9-11; the particle's index keys its
+ *  draws);  10 wall force (eq 12);  11 totals F, M;  12 rigid-body update (eq 13-16).
+ * trace (np x ORC_TRACE_W doubles) receives the records of this step when not NULL. */
 static int step_once(orc_sim* s, double* trace)
 {
     const orc_params* p = &s->p;
-    int nx = p->nx, ny = p->ny, nl = p->nl;
+    int nx = p->nx, ny = p->ny;
     size_t N = (size_t)nx * ny;
     memset(s->fib, 0, 2 * N * sizeof(double));
-    double Fh[3] = {0, 0, 0}, Fb[3] = {0, 0, 0}, Fw = 0.0, gap = 0.0;
-    int n_bonds = 0, n_probing = 0;
-    if (p->has_particle) {
-        place_markers(s);
+    if (s->np > 0) {
+        for (int k = 0; k < s->np; ++k) place_markers(s->P[k]);
         node_fields(s, 0);
-        for (int l = 0; l < nl; ++l) {
-            double rx = s->X[2 * l] - s->xc, ry = s->X[2 * l + 1] - s->yc;
-            s->Ud[2 * l] = s->ux_p - s->om * ry;
-            s->Ud[2 * l + 1] = s->uy_p + s->om * rx;
+        for (int k = 0; k < s->np; ++k) {
+            orc_particle* P = s->P[k];
+            int nl = P->q.nl;
+            for (int l = 0; l < nl; ++l) {
+                double rx = P->X[2 * l] - P->xc, ry = P->X[2 * l + 1] - P->yc;
+                P->Ud[2 * l] = P->ux_p - P->om * ry;
+                P->Ud[2 * l + 1] = P->uy_p + P->om * rx;
+            }
+            if (orc_ib_forces(nx, ny, s->rho, s->ux, s->uy, nl, P->X, P->Ud, P->Fl) != 0) s->flags |= 4;
+            if (orc_spread(nx, ny, nl, P->X, P->S, P->Fl, s->fib) != 0) s->flags |= 4;
         }
-        if (orc_ib_forces(nx, ny, s->rho, s->ux, s->uy, nl, s->X, s->Ud, s->Fl) != 0) s->flags |= 4;
-        if (orc_spread(nx, ny, nl, s->X, s->S, s->Fl, s->fib) != 0) s->flags |= 4;
     }
-    orc_collide_stream(nx, ny, p->walls, p->tau, s->gx, s->gy, p->has_particle ? s->fib : NULL, s->f, s->fn);
-    if (p->has_particle) {
+    orc_collide_stream(nx, ny, p->walls, p->tau, s->gx, s->gy, s->np > 0 ? s->fib : NULL, s->f, s->fn);
+    if (s->np > 0) {
         node_fields(s, 1);
-        for (int l = 0; l < nl; ++l) { /* probe 1.2 dx along the outward normal (below eq 8) */
-            s->Pp[2 * l] = s->X[2 * l] + 1.2 * s->nrm[2 * l];
-            s->Pp[2 * l + 1] = s->X[2 * l + 1] + 1.2 * s->nrm[2 * l + 1];
-        }
-        if (orc_tractions(nx, ny, s->nu, s->rho, s->ux, s->uy, nl, s->Pp, s->nrm, s->S, s->tl) != 0)
-            s->flags |= 4;
-        for (int l = 0; l < nl; ++l) s->dd[l] = s->X[2 * l + 1] + 0.5;
-        n_bonds = orc_bonds(nl, s->ligand, s->dd, s->bond, s->bond_new, s->y_cr, s->y_eq, s->sigma,
-                            s->sigma_star, p->k_f, p->k_r0, s->kBT, p->seed, s->step, 0u, &n_probing);
-        for (int l = 0; l < nl; ++l) {
-            s->bond[l] = s->bond_new[l];
-            double mag = s->bond[l] ? s->sigma * (s->dd[l] - s->y_eq) : 0.0; /* eq 9 */
-            s->fb[2 * l] = mag * s->nrm[2 * l];
-            s->fb[2 * l + 1] = mag * s->nrm[2 * l + 1];
-        }
-        int32_t wflag = 0;
-        Fw = orc_wall_force(s->yc, s->th, p->a, p->b, s->hamaker, &gap, &wflag);
-        if (wflag) s->flags |= 2;
-        for (int l = 0; l < nl; ++l) {
-            double rx = s->X[2 * l] - s->xc, ry = s->X[2 * l + 1] - s->yc;
-            Fh[0] += s->tl[2 * l];
-            Fh[1] += s->tl[2 * l + 1];
-            Fh[2] += rx * s->tl[2 * l + 1] - ry * s->tl[2 * l];
-            Fb[0] += s->fb[2 * l];
-            Fb[1] += s->fb[2 * l + 1];
-            Fb[2] += rx * s->fb[2 * l + 1] - ry * s->fb[2 * l];
-        }
-        double Fx = Fh[0] + Fb[0], Fy = Fh[1] + Fb[1] + Fw, M = Fh[2] + Fb[2];
-        double ux_n = orc_bdf2(s->ux_p, s->ux1, Fx / s->mass);
-        double uy_n = orc_bdf2(s->uy_p, s->uy1, Fy / s->mass);
-        double om_n = orc_bdf2(s->om, s->om1, M / s->inertia);
-        double xc_n = orc_bdf2(s->xc, s->xc1, ux_n);
-        double yc_n = orc_bdf2(s->yc, s->yc1, uy_n);
-        double th_n = orc_bdf2(s->th, s->th1, om_n);
-        if (!isfinite(Fx) || !isfinite(Fy) || !isfinite(M) || !isfinite(ux_n) || !isfinite(uy_n) ||
-            !isfinite(om_n))
-            s->flags |= 1;
-        s->ux1 = s->ux_p; s->uy1 = s->uy_p; s->om1 = s->om;
-        s->xc1 = s->xc; s->yc1 = s->yc; s->th1 = s->th;
-        s->ux_p = ux_n; s->uy_p = uy_n; s->om = om_n;
-        s->xc = xc_n; s->yc = yc_n; s->th = th_n;
-        if (trace) {
-            double rec[ORC_TRACE_W] = {(double)s->step, s->xc, s->yc, s->th, s->ux_p, s->uy_p, s->om,
-                                       Fx, Fy, M, Fh[0], Fh[1], Fh[2], Fb[0], Fb[1], Fb[2], Fw, gap,
-                                       (double)n_bonds, (double)n_probing};
-            memcpy(trace, rec, sizeof(rec));
+        for (int k = 0; k < s->np; ++k) {
+            particle_update(s, k);
+            if (trace) memcpy(trace + (size_t)k * ORC_TRACE_W, s->P[k]->rec, sizeof(s->P[k]->rec));
         }
     }
     double* t = s->f;
@@ -764,11 +829,28 @@ static int step_once(orc_sim* s, double* trace)
     return s->flags;
 }
 
+/* nsteps steps; trace (when not NULL) receives particle 0's record of each step. */
 int32_t orc_sim_step(orc_sim* s, int64_t nsteps, double* trace)
 {
-    for (int64_t n = 0; n < nsteps; ++n) step_once(s, trace ? trace + n * ORC_TRACE_W : NULL);
+    double* all = s->np > 1 && trace ? (double*)malloc((size_t)s->np * ORC_TRACE_W * sizeof(double)) : NULL;
+    for (int64_t n = 0; n < nsteps; ++n) {
+        double* t = trace ? (all ? all : trace + n * ORC_TRACE_W) : NULL;
+        step_once(s, t);
+        if (all) memcpy(trace + n * ORC_TRACE_W, all, ORC_TRACE_W * sizeof(double));
+    }
+    free(all);
     return s->flags;
 }
+
+/* nsteps steps; trace (when not NULL) receives every particle's record: [n][k][ORC_TRACE_W]. */
+int32_t orc_sim_step_all(orc_sim* s, int64_t nsteps, double* trace)
+{
+    for (int64_t n = 0; n < nsteps; ++n)
+        step_once(s, trace ? trace + (size_t)n * s->np * ORC_TRACE_W : NULL);
+    return s->flags;
+}
+
+int32_t orc_sim_num_particles(const orc_sim* s) { return s->np; }
 
 void orc_sim_get_f(const orc_sim* s, double* out) { memcpy(out, s->f, 9 * (size_t)s->p.nx * s->p.ny * sizeof(double)); }
 void orc_sim_set_f(orc_sim* s, const double* in) { memcpy(s->f, in, 9 * (size_t)s->p.nx * s->p.ny * sizeof(double)); }
@@ -776,51 +858,63 @@ void orc_sim_get_fib(const orc_sim* s, double* out) { memcpy(out, s->fib, 2 * (s
 int64_t orc_sim_get_step(const orc_sim* s) { return s->step; }
 int32_t orc_sim_get_flags(const orc_sim* s) { return s->flags; }
 
-/* Derived lattice-unit parameters: nu, umax, gx, gy, sigma, sigma*, y_cr, y_eq, kBT, H_k,
- * mass, inertia. */
+/* Derived lattice-unit parameters: nu, umax, gx, gy, then particle 0's sigma, sigma*, y_cr,
+ * y_eq, kBT, H_k, mass, inertia (zeros without a particle). */
 void orc_sim_get_derived(const orc_sim* s, double* out)
 {
-    double v[12] = {s->nu, s->umax, s->gx, s->gy, s->sigma, s->sigma_star, s->y_cr, s->y_eq,
-                    s->kBT, s->hamaker, s->mass, s->inertia};
+    const orc_particle* P = s->np > 0 ? s->P[0] : NULL;
+    double v[12] = {s->nu, s->umax, s->gx, s->gy,
+                    P ? P->sigma : 0.0, P ? P->sigma_star : 0.0, P ? P->y_cr : 0.0, P ? P->y_eq : 0.0,
+                    P ? P->kBT : 0.0, P ? P->hamaker : 0.0, P ? P->mass : 0.0, P ? P->inertia : 0.0};
     memcpy(out, v, sizeof(v));
 }
 
-/* Particle state: xc, yc, theta, ux, uy, omega and the same at the previous level. */
-void orc_sim_get_particle(const orc_sim* s, double* out)
+/* Particle k's state: xc, yc, theta, ux, uy, omega and the same at the previous level. */
+void orc_sim_get_particle_k(const orc_sim* s, int32_t k, double* out)
 {
-    double v[12] = {s->xc, s->yc, s->th, s->ux_p, s->uy_p, s->om,
-                    s->xc1, s->yc1, s->th1, s->ux1, s->uy1, s->om1};
+    const orc_particle* P = s->P[k];
+    double v[12] = {P->xc, P->yc, P->th, P->ux_p, P->uy_p, P->om, P->xc1, P->yc1, P->th1, P->ux1, P->uy1, P->om1};
     memcpy(out, v, sizeof(v));
 }
 
-void orc_sim_set_particle(orc_sim* s, const double* in)
+void orc_sim_set_particle_k(orc_sim* s, int32_t k, const double* in)
 {
-    s->xc = in[0]; s->yc = in[1]; s->th = in[2]; s->ux_p = in[3]; s->uy_p = in[4]; s->om = in[5];
-    s->xc1 = in[6]; s->yc1 = in[7]; s->th1 = in[8]; s->ux1 = in[9]; s->uy1 = in[10]; s->om1 = in[11];
+    orc_particle* P = s->P[k];
+    P->xc = in[0]; P->yc = in[1]; P->th = in[2]; P->ux_p = in[3]; P->uy_p = in[4]; P->om = in[5];
+    P->xc1 = in[6]; P->yc1 = in[7]; P->th1 = in[8]; P->ux1 = in[9]; P->uy1 = in[10]; P->om1 = in[11];
 }
 
-void orc_sim_get_bonds(const orc_sim* s, uint8_t* bonded, uint8_t* ligand)
+void orc_sim_get_bonds_k(const orc_sim* s, int32_t k, uint8_t* bonded, uint8_t* ligand)
 {
-    memcpy(bonded, s->bond, s->p.nl);
-    memcpy(ligand, s->ligand, s->p.nl);
+    memcpy(bonded, s->P[k]->bond, s->P[k]->q.nl);
+    memcpy(ligand, s->P[k]->ligand, s->P[k]->q.nl);
 }
 
-void orc_sim_set_bonds(orc_sim* s, const uint8_t* bonded) { memcpy(s->bond, bonded, s->p.nl); }
+void orc_sim_set_bonds_k(orc_sim* s, int32_t k, const uint8_t* bonded) { memcpy(s->P[k]->bond, bonded, s->P[k]->q.nl); }
 
-/* Body-frame geometry (xi, nu, S) and the lab-frame markers / normals of the last placement. */
+void orc_sim_get_particle(const orc_sim* s, double* out) { orc_sim_get_particle_k(s, 0, out); }
+void orc_sim_set_particle(orc_sim* s, const double* in) { orc_sim_set_particle_k(s, 0, in); }
+void orc_sim_get_bonds(const orc_sim* s, uint8_t* bonded, uint8_t* ligand) { orc_sim_get_bonds_k(s, 0, bonded, ligand); }
+void orc_sim_set_bonds(orc_sim* s, const uint8_t* bonded) { orc_sim_set_bonds_k(s, 0, bonded); }
+
+/* Body-frame geometry (xi, nu, S) and the lab-frame markers / normals of particle 0. */
 void orc_sim_get_geometry(const orc_sim* s, double* xi, double* nu, double* S)
 {
-    memcpy(xi, s->xi, 2 * s->p.nl * sizeof(double));
-    memcpy(nu, s->nuv, 2 * s->p.nl * sizeof(double));
-    memcpy(S, s->S, s->p.nl * sizeof(double));
+    const orc_particle* P = s->P[0];
+    memcpy(xi, P->xi, 2 * P->q.nl * sizeof(double));
+    memcpy(nu, P->nuv, 2 * P->q.nl * sizeof(double));
+    memcpy(S, P->S, P->q.nl * sizeof(double));
 }
 
-void orc_sim_get_markers(orc_sim* s, double* X, double* n)
+void orc_sim_get_markers_k(orc_sim* s, int32_t k, double* X, double* n)
 {
-    place_markers(s);
-    memcpy(X, s->X, 2 * s->p.nl * sizeof(double));
-    memcpy(n, s->nrm, 2 * s->p.nl * sizeof(double));
+    orc_particle* P = s->P[k];
+    place_markers(P);
+    memcpy(X, P->X, 2 * P->q.nl * sizeof(double));
+    memcpy(n, P->nrm, 2 * P->q.nl * sizeof(double));
 }
+
+void orc_sim_get_markers(orc_sim* s, double* X, double* n) { orc_sim_get_markers_k(s, 0, X, n); }
 
 int32_t orc_num_threads(void)
 {
