@@ -147,7 +147,10 @@ int lbib_abi_version(void);
  * handle creates and owns.  On success *out receives the handle. */
 lbib_status lbib_create(const lbib_lattice_desc* desc, void* hip_stream, lbib_handle* out);
 
-/* Add the particle (at most one per simulation in this build).  *particle_id receives 0. */
+/* Add a particle (up to 64 per simulation); *particle_id receives its index, which also keys
+ * its bond draws.  Particles interact only through the fluid (the paper's particles do not
+ * collide; placements must not overlap).  With several particles each step runs the split
+ * particle phase (see lbib_set_overlap, mode 3). */
 lbib_status lbib_particle_add(lbib_handle h, const lbib_particle_desc* desc, int32_t* particle_id);
 
 /* Decorate particle particle_id with ligands; required before lbib_init when a particle
@@ -223,6 +226,13 @@ lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size);
  * run one after the other on the handle's stream.  Mode 2 (the default) overlaps when one
  * sweep moves at least 64 MiB; below that the two cross-stream waits of a step cost more
  * than they hide.  Both schedules give bit-identical results. */
+/* Mode 3 (used whenever a simulation has several particles): the particle phase runs as two
+ * launches over all particles -- first every particle stages its box and spreads its marker
+ * forces, then every particle evaluates its probe loads (with the spread force of every
+ * particle that reaches a probe node, summed in particle order), bonds and rigid-body update
+ * -- and the sweep adds at each node the force of every particle whose box reaches it, in
+ * particle order.  For a single particle it gives the same results as modes 0-2.  Kernel
+ * timing then reports the first launch as kernel 1 and the second as kernel 2. */
 lbib_status lbib_set_overlap(lbib_handle h, int32_t mode);
 
 /* Storage layout of the population buffers, chosen before lbib_init: mode 0 push (the

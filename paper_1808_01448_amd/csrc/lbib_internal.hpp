@@ -83,6 +83,12 @@ struct SweepArgs {
     double scale, inv_scale;  // stored value = (f - w) scale (a power of two; 1 but for FP16)
 };
 
+// Where the sweep and the probes of a multi-particle step find particle p's spread force.
+struct PartRef {
+    const TileDesc* desc;
+    const int64_t* tile;
+};
+
 // Everything the particle phase needs; passed by value.
 template <typename T>
 struct ParticleArgs {
@@ -117,6 +123,11 @@ struct ParticleArgs {
     lbib_particle_state* trace;
     int64_t trace_cap, trace_start;
     int32_t* flags;
+    // several particles: the step's mask (one 64-bit word of particle bits per 64 x 4 tile,
+    // mtx tiles along x) and every particle's box and force tile
+    unsigned long long* pmask;
+    const PartRef* refs;
+    int32_t mtx;
 };
 
 // Launchers (lbib_sweep.hip, lbib_particle.hip).  All enqueue on `stream` and return the launch status.
@@ -127,6 +138,13 @@ hipError_t launch_init(T* f, int32_t nx, int32_t ny, int32_t pitch, int64_t plan
 // the box in `desc` (which carry no spread force); only the nodes of the box in `desc`
 // (box_cap bounds the launch).
 enum SweepMode { SWEEP_ALL = 0, SWEEP_OUTSIDE = 1, SWEEP_BOX = 2 };
+// Sweep of a step with several particles: node forces from every particle whose box reaches
+// the node (listed by the tile mask mcur, summed in particle order); each block also clears
+// its tile's word of mnext, the mask of the next step.
+template <typename T>
+hipError_t launch_sweep_multi(const T* fin, T* fout, const SweepArgs& a, const unsigned long long* mcur,
+                              unsigned long long* mnext, const PartRef* refs, bool pull, hipStream_t stream,
+                              hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 // t0 / t1 (optional) receive the kernel's own start and end times.
 // pull selects the layout of the population buffers (pop_index in lbib_device.hpp).
 template <typename T>
@@ -141,6 +159,12 @@ size_t particle_lds_aux_bytes(int32_t box_cap);
 template <typename T>
 hipError_t launch_particle(const ParticleArgs<T>& a, hipStream_t stream, hipEvent_t t0 = nullptr,
                            hipEvent_t t1 = nullptr);
+// The two launches of the split particle phase (mode 1: spread and mark; mode 2: loads,
+// bonds, update), one workgroup per particle of args[0..n).
+template <typename T>
+hipError_t launch_particle_split(const ParticleArgs<T>* args, int32_t n, const T* f, unsigned long long* pmask,
+                                 int32_t mode, int32_t max_nl, int32_t lds_cap, size_t lds, hipStream_t stream,
+                                 hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
 // A pool of independent simulations stepped together (one launch per kernel per step).
 // The particle launch runs member active[b] in workgroup b and copies the member's box

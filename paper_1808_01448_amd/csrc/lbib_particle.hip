@@ -306,6 +306,46 @@ __device__ __forceinline__ void fill_marked(const ParticleArgs<T>& a, const BoxV
     }
 }
 
+__device__ __forceinline__ bool box_has(const TileDesc& d, int i, int j, int nx)
+{
+    int di = i - d.i0w;
+    if (di < 0) di += nx;
+    const int dj = j - d.j0;
+    return di < d.w && dj >= 0 && dj < d.h;
+}
+
+// The spread force of every particle at node (i, j) (i wrapped), summed in particle order:
+// the step's mask of the node's 64 x 4 tile lists the particles whose boxes reach it.
+template <typename T>
+__device__ __forceinline__ void multi_force(const ParticleArgs<T>& a, int i, int j, double& fx, double& fy)
+{
+    fx = fy = 0.0;
+    for (unsigned long long m = a.pmask[(j >> 2) * a.mtx + (i >> 6)]; m; m &= m - 1) {
+        const PartRef r = a.refs[__builtin_ctzll(m)];
+        const TileDesc d = *r.desc;
+        if (d.active && box_has(d, i, j, a.nx)) {
+            int di = i - d.i0w;
+            if (di < 0) di += a.nx;
+            const int64_t* t = r.tile + 2 * ((size_t)(j - d.j0) * d.w + di);
+            fx += ldexp((double)t[0], -d.scale);
+            fy += ldexp((double)t[1], -d.scale);
+        }
+    }
+}
+
+// Set this particle's bit in the step's mask of every 64 x 4 tile its box reaches.
+template <typename T>
+__device__ __forceinline__ void mark_tiles(const ParticleArgs<T>& a, int x0, int y0, int w, int h)
+{
+    const unsigned long long bit = 1ull << a.pid;
+    const int ty0 = y0 >> 2, ty1 = (y0 + h - 1) >> 2;
+    for (int c = threadIdx.x; c < w; c += PB) {
+        const int i = wrap(x0 + c, a.nx);
+        if (c != 0 && (i & 63) != 0) continue;  // one thread per tile column of the box
+        for (int ty = ty0; ty <= ty1; ++ty) atomicOr(a.pmask + (size_t)ty * a.mtx + (i >> 6), bit);
+    }
+}
+
 template <bool LDS>
 __device__ __forceinline__ void force_add(unsigned long long* p, int64_t v)
 {
@@ -318,7 +358,13 @@ __device__ __forceinline__ void force_add(unsigned long long* p, int64_t v)
 // One particle's phase, run by one workgroup.  MPT markers per thread (nl <= MPT * PB).
 // LDS: the box lives in dynamic LDS (`base`), else in the global scratch a.box_global (plain
 // loads and stores ordered by the workgroup barriers, device-scope atomics for the force).
-template <typename T, int MPT, bool LDS>
+// MODE 0: the whole phase of a simulation's only particle.  With several particles the
+// phase is split in two launches so that every probe sees the spread force of every
+// particle: MODE 1 stages the box, spreads the marker forces into the particle's tile and
+// marks the step's tile mask; MODE 2 stages the box again and evaluates the probe loads
+// (the spread force at a probe node summed over the particles that reach it), the bonds,
+// the wall force and the rigid-body update.
+template <typename T, int MPT, bool LDS, int MODE = 0>
 __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, double* lds_box)
 {
     __shared__ double shd[8][NW];
@@ -388,7 +434,7 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, double*
             LIG[k] = a.ligand[l] != 0;
             BND[k] = a.bond[l] != 0;
             Mls m;
-            const bool ok = box_ok && mls_shape(g.X, fluid_row(g.Y, a.ny), a.ny, m, false);
+            const bool ok = MODE != 2 && box_ok && mls_shape(g.X, fluid_row(g.Y, a.ny), a.ny, m, false);
             if (ok) {
                 double rl = 0.0, usx = 0.0, usy = 0.0;
 #pragma unroll
@@ -414,78 +460,91 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, double*
                 NYS[k] = m.nys;
                 const double mag = fmax(fabs(SFx[k]), fabs(SFy[k]));
                 maxsf = (mag <= 1e300) ? fmax(maxsf, mag) : INFINITY;
-            } else if (box_ok) {
+            } else if (MODE != 2 && box_ok) {
                 flags |= FLAG_MLS;
             }
         }
     }
-    maxsf = wave_max(maxsf);
-    if ((tid & 63) == 0) shd[0][tid >> 6] = maxsf;
-    __syncthreads();
-    maxsf = shd[0][0];
+    bool spread_ok = false;
+    int scale = 0;
+    if (MODE != 2) {
+        maxsf = wave_max(maxsf);
+        if ((tid & 63) == 0) shd[0][tid >> 6] = maxsf;
+        __syncthreads();
+        maxsf = shd[0][0];
 #pragma unroll
-    for (int u = 1; u < NW; ++u) maxsf = fmax(maxsf, shd[0][u]);
-    __syncthreads();
+        for (int u = 1; u < NW; ++u) maxsf = fmax(maxsf, shd[0][u]);
+        __syncthreads();
 
-    // ---- spread: 64-bit fixed point, so the sum does not depend on the order --------
-    // |phi| < 2 and at most 64 markers reach a node, so |sum| < 2^7 maxsf; with
-    // maxsf < 2^e the scale 2^(55-e) keeps every node below 2^62.
-    const bool finite_sf = maxsf <= 1e300;
-    const bool spread_ok = box_ok && finite_sf;
-    if (box_ok && !finite_sf && tid == 0) flags |= FLAG_NONFINITE;
-    int e2 = 0;
-    frexp(finite_sf ? maxsf : 1.0, &e2);
-    const int scale = 55 - e2;
-    if (spread_ok) {
+        // ---- spread: 64-bit fixed point, so the sum does not depend on the order --------
+        // |phi| < 2 and at most 64 markers reach a node, so |sum| < 2^7 maxsf; with
+        // maxsf < 2^e the scale 2^(55-e) keeps every node below 2^62.
+        const bool finite_sf = maxsf <= 1e300;
+        spread_ok = box_ok && finite_sf;
+        if (box_ok && !finite_sf && tid == 0) flags |= FLAG_NONFINITE;
+        int e2 = 0;
+        frexp(finite_sf ? maxsf : 1.0, &e2);
+        scale = 55 - e2;
+        if (spread_ok) {
 #pragma unroll
-        for (int k = 0; k < MPT; ++k) {
-            if (!OK[k]) continue;
+            for (int k = 0; k < MPT; ++k) {
+                if (!OK[k]) continue;
 #pragma unroll
-            for (int bb = 0; bb < 3; ++bb)
+                for (int bb = 0; bb < 3; ++bb)
 #pragma unroll
-                for (int cc = 0; cc < 3; ++cc) {
-                    if (bb >= NYS[k] || cc >= NXS[k]) continue;
-                    const double p = PH[k][3 * bb + cc];
-                    const int n = (J0[k] + bb - y0) * w + (I0[k] + cc - x0);
-                    force_add<LDS>(B.fx + n, (int64_t)llrint(ldexp(p * SFx[k], scale)));
-                    force_add<LDS>(B.fy + n, (int64_t)llrint(ldexp(p * SFy[k], scale)));
-                }
-        }
-    }
-    __syncthreads();
-    if (spread_ok) {
-        for (int k = tid; k < nbox; k += PB) {
-            unsigned long long qx = 0, qy = 0;  // no support reaches an unmarked node
-            if ((mask[k >> 5] >> (k & 31)) & 1u) {
-                if (LDS) {
-                    qx = B.fx[k];
-                    qy = B.fy[k];
-                } else {
-                    qx = __hip_atomic_load(B.fx + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    qy = __hip_atomic_load(B.fy + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
+                    for (int cc = 0; cc < 3; ++cc) {
+                        if (bb >= NYS[k] || cc >= NXS[k]) continue;
+                        const double p = PH[k][3 * bb + cc];
+                        const int n = (J0[k] + bb - y0) * w + (I0[k] + cc - x0);
+                        force_add<LDS>(B.fx + n, (int64_t)llrint(ldexp(p * SFx[k], scale)));
+                        force_add<LDS>(B.fy + n, (int64_t)llrint(ldexp(p * SFy[k], scale)));
+                    }
             }
-            a.tile[2 * k] = (int64_t)qx;
-            a.tile[2 * k + 1] = (int64_t)qy;
+        }
+        __syncthreads();
+        if (spread_ok) {
+            for (int k = tid; k < nbox; k += PB) {
+                unsigned long long qx = 0, qy = 0;  // no support reaches an unmarked node
+                if ((mask[k >> 5] >> (k & 31)) & 1u) {
+                    if (LDS) {
+                        qx = B.fx[k];
+                        qy = B.fy[k];
+                    } else {
+                        qx = __hip_atomic_load(B.fx + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        qy = __hip_atomic_load(B.fy + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+                a.tile[2 * k] = (int64_t)qx;
+                a.tile[2 * k + 1] = (int64_t)qy;
+            }
+        }
+        if (tid == 0) {
+            TileDesc d;
+            d.i0w = wrap(box_ok ? x0 : 0, a.nx);
+            d.j0 = box_ok ? y0 : 0;
+            d.w = box_ok ? w : 0;
+            d.h = box_ok ? h : 0;
+            d.scale = scale;
+            d.active = spread_ok ? 1 : 0;
+            d.i0u = box_ok ? x0 : 0;
+            d.pad = 0;
+            *a.desc = d;
+            if (a.check_zone) {
+                const TileDesc z = a.zone[a.parity_in];
+                // the concurrent sweep of the nodes outside the predicted box is only valid when
+                // the prediction equals this box
+                if (!z.active || z.i0w != d.i0w || z.j0 != d.j0 || z.w != d.w || z.h != d.h) flags |= FLAG_TILE;
+            }
         }
     }
-    if (tid == 0) {
-        TileDesc d;
-        d.i0w = wrap(box_ok ? x0 : 0, a.nx);
-        d.j0 = box_ok ? y0 : 0;
-        d.w = box_ok ? w : 0;
-        d.h = box_ok ? h : 0;
-        d.scale = scale;
-        d.active = spread_ok ? 1 : 0;
-        d.i0u = box_ok ? x0 : 0;
-        d.pad = 0;
-        *a.desc = d;
-        if (a.check_zone) {
-            const TileDesc z = a.zone[a.parity_in];
-            // the concurrent sweep of the nodes outside the predicted box is only valid when
-            // the prediction equals this box
-            if (!z.active || z.i0w != d.i0w || z.j0 != d.j0 || z.w != d.w || z.h != d.h) flags |= FLAG_TILE;
-        }
+    if (MODE == 1) {
+        __syncthreads();
+        if (box_ok) mark_tiles(a, x0, y0, w, h);
+        int v[1] = {flags};
+        const int op[1] = {1};
+        block_int<1>(v, op, shi);
+        if (tid == 0 && v[0]) atomicOr(a.flags, v[0]);
+        return;
     }
 
     // ---- probe loads (eq 7-8) and wall distances ---------------------------------------
@@ -511,7 +570,13 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, double*
                             const int e = 3 * bb + cc;
                             const int n = (m.j0 + bb - y0) * w + (m.i0 + cc - x0);
                             double vx = B.ux[n], vy = B.uy[n];
-                            if (spread_ok) {
+                            if (MODE == 2) {
+                                double fx, fy;
+                                multi_force(a, wrap(m.i0 + cc, a.nx), m.j0 + bb, fx, fy);
+                                const double hinv = 0.5 * B.inv[n];
+                                vx += fx * hinv;
+                                vy += fy * hinv;
+                            } else if (spread_ok) {
                                 unsigned long long qx, qy;
                                 if (LDS) {
                                     qx = B.fx[n];
@@ -649,7 +714,7 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, double*
 
     // ---- the box of the next step (the sweep of the nodes outside it may then run while
     // the next particle phase does) -------------------------------------------------------
-    {
+    if (MODE == 0) {
         const double nxc = shd[0][0], nyc = shd[1][0], nth = shd[2][0];
         int rn[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
         accumulate_bounds<T, MPT>(a, nxc, nyc, cos(nth), sin(nth), rn);
@@ -677,6 +742,57 @@ __global__ __launch_bounds__(PB) void particle_kernel(ParticleArgs<T> a)
 {
     extern __shared__ double lds_box[];
     particle_phase<T, MPT, LDS>(a, lds_box);
+}
+
+// Split particle phase of a simulation with several particles: workgroup b runs particle b
+// in MODE 1 (spread) or MODE 2 (loads, bonds, update) on the populations f of this step and
+// the step's tile mask.
+template <typename T, int MPT, int MODE>
+__global__ __launch_bounds__(PB) void split_particle_kernel(const ParticleArgs<T>* __restrict__ args,
+                                                            const T* __restrict__ f,
+                                                            unsigned long long* __restrict__ pmask, int32_t lds_cap)
+{
+    extern __shared__ double lds_box[];
+    ParticleArgs<T> a = args[blockIdx.x];
+    a.f = f;
+    a.pmask = pmask;
+    if (a.box_cap <= lds_cap)
+        particle_phase<T, MPT, true, MODE>(a, lds_box);
+    else
+        particle_phase<T, MPT, false, MODE>(a, lds_box);
+}
+
+template <typename T, int MPT, int MODE>
+hipError_t launch_split_mode(const ParticleArgs<T>* args, int32_t n, const T* f, unsigned long long* pmask,
+                             int32_t lds_cap, size_t lds, hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
+{
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)split_particle_kernel<T, MPT, MODE>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 158 * 1024);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipExtLaunchKernelGGL(split_particle_kernel<T, MPT, MODE>, dim3(n), dim3(PB), (uint32_t)lds, stream, t0, t1, 0u,
+                          args, f, pmask, lds_cap);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_particle_split(const ParticleArgs<T>* args, int32_t n, const T* f, unsigned long long* pmask,
+                                 int32_t mode, int32_t max_nl, int32_t lds_cap, size_t lds, hipStream_t stream,
+                                 hipEvent_t t0, hipEvent_t t1)
+{
+    if (n <= 0) return hipSuccess;
+    if (lds > 158 * 1024 || (mode != 1 && mode != 2)) return hipErrorInvalidValue;
+#define LBIB_SPLIT(M)                                                                                    \
+    return mode == 1 ? launch_split_mode<T, M, 1>(args, n, f, pmask, lds_cap, lds, stream, t0, t1)      \
+                     : launch_split_mode<T, M, 2>(args, n, f, pmask, lds_cap, lds, stream, t0, t1)
+    if (max_nl <= PB) LBIB_SPLIT(1);
+    if (max_nl <= 2 * PB) LBIB_SPLIT(2);
+    if (max_nl <= 4 * PB) LBIB_SPLIT(4);
+#undef LBIB_SPLIT
+    return hipErrorInvalidValue;
 }
 
 // Particle phases of a pool of independent simulations: workgroup b runs member
@@ -906,7 +1022,10 @@ hipError_t launch_copy(const float4* src, float4* dst, int64_t n, hipStream_t st
 #define LBIB_PARTICLE_INSTANTIATE(T)                                                                        \
     template hipError_t launch_pool_particle<T>(const ParticleArgs<T>*, const int32_t*, TileDesc*, int32_t,      \
                                                 int32_t, int32_t, size_t, hipStream_t, hipEvent_t, hipEvent_t); \
-    template hipError_t launch_particle<T>(const ParticleArgs<T>&, hipStream_t, hipEvent_t, hipEvent_t);
+    template hipError_t launch_particle<T>(const ParticleArgs<T>&, hipStream_t, hipEvent_t, hipEvent_t);        \
+    template hipError_t launch_particle_split<T>(const ParticleArgs<T>*, int32_t, const T*, unsigned long long*, \
+                                                 int32_t, int32_t, int32_t, size_t, hipStream_t, hipEvent_t,     \
+                                                 hipEvent_t);
 LBIB_PARTICLE_INSTANTIATE(double)
 LBIB_PARTICLE_INSTANTIATE(float)
 LBIB_PARTICLE_INSTANTIATE(half_t)

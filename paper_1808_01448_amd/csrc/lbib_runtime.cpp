@@ -39,7 +39,7 @@ struct lbib_sim {
     bool own_stream = false;
     hipStream_t stream2 = nullptr;  // particle chain of the overlapped schedule
     hipEvent_t evA = nullptr, evB = nullptr;
-    int overlap = 2;  // 0 serial, 1 overlapped, 2 chosen by lattice size
+    int overlap = 2;  // 0 serial, 1 overlapped, 2 chosen by lattice size, 3 split particle phase
     int layout = 2;   // 0 push, 1 pull, 2 chosen by lattice size (at lbib_init)
     bool zone_valid = false;  // the zone slot of the next step holds its box
     int state = 0;  // 0 created, 1 running, 2 failed
@@ -51,6 +51,17 @@ struct lbib_sim {
     int32_t* d_flags = nullptr;
     int64_t steps = 0;
     Timing timing;
+    // split particle phase (several particles, or overlap mode 3): the two tile masks (by
+    // step parity), every particle's box and tile, the particle arguments on the device
+    unsigned long long* d_masks = nullptr;
+    int32_t mtx = 0;
+    int64_t ntiles = 0;
+    PartRef* d_refs = nullptr;
+    void* d_args = nullptr;
+    std::vector<unsigned char> h_args;  // host copy of the arguments (kept for the async upload)
+    bool args_dirty = true;
+    int32_t max_nl = 0, lds_cap = 0;
+    size_t lds_bytes = 0;
 };
 
 namespace {
@@ -84,6 +95,10 @@ void free_all(lbib_sim* h)
     if (h->fB) (void)hipFree(h->fB);
     h->fA = h->fB = nullptr;
     dfree(h->d_flags);
+    dfree(h->d_masks);
+    dfree(h->d_refs);
+    if (h->d_args) (void)hipFree(h->d_args);
+    h->d_args = nullptr;
     for (int k = 0; k < kKinds; ++k) {
         for (auto e : h->timing.ev[k]) (void)hipEventDestroy(e);
         h->timing.ev[k].clear();
@@ -101,7 +116,25 @@ ParticleArgs<T> particle_args(lbib_sim* h, Particle& p)
     ParticleArgs<T> a;
     fill_particle_args<T>(a, h->g, h->desc.seed, p, h->d_flags);
     a.f = (const T*)h->fA;
+    a.pid = (uint32_t)(&p - h->parts.data());  // the particle's index keys its bond draws
+    a.refs = h->d_refs;
+    a.mtx = h->mtx;
     return a;
+}
+
+// Upload the arguments of the split particle phase (stream-ordered, from a host copy that
+// stays alive until the next upload, which waits for the stream).
+template <typename T>
+lbib_status upload_split_args(lbib_sim* h)
+{
+    const size_t n = h->parts.size();
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->h_args.assign(n * sizeof(ParticleArgs<T>), 0);
+    ParticleArgs<T>* a = (ParticleArgs<T>*)h->h_args.data();
+    for (size_t k = 0; k < n; ++k) a[k] = particle_args<T>(h, h->parts[k]);
+    HIPCHK(h, hipMemcpyAsync(h->d_args, a, h->h_args.size(), hipMemcpyHostToDevice, h->stream));
+    h->args_dirty = false;
+    return LBIB_OK;
 }
 
 SweepArgs sweep_args(lbib_sim* h)
@@ -148,10 +181,32 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
 {
     const SweepArgs sa = sweep_args(h);
     bool joined = true;
+    const bool split = h->parts.size() > 1 || (h->overlap == 3 && !h->parts.empty());
+    if (split && h->args_dirty) {
+        lbib_status st = upload_split_args<T>(h);
+        if (st != LBIB_OK) return st;
+    }
     for (int64_t s = 0; s < n; ++s) {
         const T* fin = (const T*)h->fA;
         T* fout = (T*)h->fB;
-        if (h->parts.empty()) {
+        if (split) {
+            // every particle spreads and marks the tile mask, then every particle evaluates its
+            // loads (seeing all spread forces) and moves, then the lattice is swept
+            const int par = (int)(h->steps & 1);
+            unsigned long long* mcur = h->d_masks + par * h->ntiles;
+            unsigned long long* mnext = h->d_masks + (par ^ 1) * h->ntiles;
+            const int32_t np = (int32_t)h->parts.size();
+            const ParticleArgs<T>* args = (const ParticleArgs<T>*)h->d_args;
+            const EvPair e1 = timing_events(h, 1);
+            HIPCHK(h, launch_particle_split<T>(args, np, fin, mcur, 1, h->max_nl, h->lds_cap, h->lds_bytes, h->stream,
+                                               e1.t0, e1.t1));
+            const EvPair e2 = timing_events(h, 2);
+            HIPCHK(h, launch_particle_split<T>(args, np, fin, mcur, 2, h->max_nl, h->lds_cap, h->lds_bytes, h->stream,
+                                               e2.t0, e2.t1));
+            const EvPair e0 = timing_events(h, 0);
+            HIPCHK(h, launch_sweep_multi<T>(fin, fout, sa, mcur, mnext, h->d_refs, h->g.pull, h->stream, e0.t0, e0.t1));
+            h->zone_valid = false;
+        } else if (h->parts.empty()) {
             const EvPair e0 = timing_events(h, 0);
             HIPCHK(h, launch_sweep<T>(fin, fout, sa, SWEEP_ALL, nullptr, nullptr, 0, h->g.pull, h->stream, e0.t0, e0.t1));
         } else {
@@ -296,7 +351,7 @@ lbib_status lbib_particle_add(lbib_handle h, const lbib_particle_desc* d, int32_
     try {
         if (!d || !pid) return fail(h, LBIB_E_INVALID, "lbib_particle_add: NULL argument");
         if (h->state != 0) return fail(h, LBIB_E_STATE, "lbib_particle_add: must precede lbib_init");
-        if (!h->parts.empty()) return fail(h, LBIB_E_UNSUPPORTED, "lbib_particle_add: one particle per simulation");
+        if (h->parts.size() >= 64) return fail(h, LBIB_E_UNSUPPORTED, "lbib_particle_add: at most 64 particles");
         Particle p;
         std::string msg;
         const lbib_status v = prepare_particle(h->desc, *d, p, msg);
@@ -371,6 +426,32 @@ lbib_status lbib_init(lbib_handle h)
     if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return bail(e, "lbib_init: sync");
     for (auto& p : h->parts)
         if ((e = upload_particle(p, h->stream)) != hipSuccess) return bail(e, "lbib_init: upload");
+    if (!h->parts.empty()) {
+        // tile masks, particle references and arguments of the split particle phase
+        h->mtx = (h->desc.nx + 63) / 64;
+        h->ntiles = (int64_t)h->mtx * ((h->desc.ny + 3) / 4);
+        const size_t np = h->parts.size();
+        std::vector<PartRef> refs(np);
+        for (size_t k = 0; k < np; ++k) {
+            refs[k] = PartRef{h->parts[k].d_desc, h->parts[k].d_tile};
+            const Particle& p = h->parts[k];
+            h->max_nl = std::max(h->max_nl, p.nl);
+            if (particle_lds_bytes(p.box_cap)) {
+                h->lds_cap = std::max(h->lds_cap, p.box_cap);
+                h->lds_bytes = std::max(h->lds_bytes, particle_lds_bytes(p.box_cap));
+            } else {
+                h->lds_bytes = std::max(h->lds_bytes, particle_lds_aux_bytes(p.box_cap));
+            }
+        }
+        const size_t args_bytes = np * std::max(sizeof(ParticleArgs<double>), sizeof(ParticleArgs<float>));
+        if ((e = dalloc(&h->d_masks, (size_t)(2 * h->ntiles))) != hipSuccess ||
+            (e = dalloc(&h->d_refs, np)) != hipSuccess || (e = hipMalloc(&h->d_args, args_bytes)) != hipSuccess)
+            return bail(e, "lbib_init: device allocation");
+        if ((e = hipMemsetAsync(h->d_masks, 0, (size_t)(2 * h->ntiles) * 8, h->stream)) != hipSuccess ||
+            (e = hipMemcpy(h->d_refs, refs.data(), np * sizeof(PartRef), hipMemcpyHostToDevice)) != hipSuccess)
+            return bail(e, "lbib_init: upload");
+        h->args_dirty = true;
+    }
     if ((e = hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking)) != hipSuccess)
         return bail(e, "lbib_init: second stream");
     if ((e = hipEventCreateWithFlags(&h->evA, hipEventDisableTiming)) != hipSuccess ||
@@ -561,6 +642,7 @@ lbib_status lbib_trace_enable(lbib_handle h, int32_t pid, int64_t capacity)
         p->trace_cap = capacity;
     }
     p->trace_start = h->steps;
+    h->args_dirty = true;
     return LBIB_OK;
 }
 
@@ -639,6 +721,7 @@ lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size)
         HIPCHK(h, hipMemcpy(p.d_bond, r, p.nl, hipMemcpyHostToDevice));
         r += p.nl;
         p.trace_start = hd.steps;  // a trace restarts at the restored step
+        h->args_dirty = true;
     }
     const int32_t zero = 0;
     HIPCHK(h, hipMemcpy(h->d_flags, &zero, sizeof(zero), hipMemcpyHostToDevice));
@@ -689,7 +772,7 @@ lbib_status lbib_kernel_time(lbib_handle h, int32_t kernel, double* total_ms, in
 lbib_status lbib_set_overlap(lbib_handle h, int32_t mode)
 {
     if (!h) return fail(nullptr, LBIB_E_INVALID, "lbib_set_overlap: NULL handle");
-    if (mode < 0 || mode > 2) return fail(h, LBIB_E_INVALID, "lbib_set_overlap: mode must be 0, 1 or 2");
+    if (mode < 0 || mode > 3) return fail(h, LBIB_E_INVALID, "lbib_set_overlap: mode must be 0, 1, 2 or 3");
     h->overlap = mode;
     return LBIB_OK;
 }

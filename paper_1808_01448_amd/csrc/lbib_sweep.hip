@@ -120,6 +120,53 @@ __global__ __launch_bounds__(256) void sweep_box_kernel(const T* __restrict__ fi
                             a.gy + ldexp((double)t[1], -d.scale));
 }
 
+// Sweep of a step with several particles (64 x 4 tiles, as sweep_kernel).
+template <typename T, bool PULL>
+__global__ __launch_bounds__(256) void sweep_multi_kernel(const T* __restrict__ fin, T* __restrict__ fout, SweepArgs a,
+                                                          const unsigned long long* __restrict__ mcur,
+                                                          unsigned long long* __restrict__ mnext,
+                                                          const PartRef* __restrict__ refs, int gx, int nblocks)
+{
+    int b = blockIdx.x;
+    {
+        const int q = nblocks >> 3, r = nblocks & 7, x = b & 7, k = b >> 3;
+        b = (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+    }
+    const unsigned long long m = mcur[b];
+    if (threadIdx.x == 0) mnext[b] = 0ull;
+    const int i = (b % gx) * 64 + (int)(threadIdx.x & 63);
+    const int j = (b / gx) * 4 + (int)(threadIdx.x >> 6);
+    if (i >= a.nx || j >= a.ny) return;
+    double Fx = a.gx, Fy = a.gy;
+    for (unsigned long long r = m; r; r &= r - 1) {
+        const PartRef pr = refs[__builtin_ctzll(r)];
+        const TileDesc d = *pr.desc;
+        if (d.active && in_box(d, i, j, a.nx)) {
+            int di = i - d.i0w;
+            if (di < 0) di += a.nx;
+            const int64_t* t = pr.tile + 2 * ((size_t)(j - d.j0) * d.w + di);
+            Fx += ldexp((double)t[0], -d.scale);
+            Fy += ldexp((double)t[1], -d.scale);
+        }
+    }
+    collide_stream<T, PULL>(fin, fout, a, i, j, Fx, Fy);
+}
+
+template <typename T>
+hipError_t launch_sweep_multi(const T* fin, T* fout, const SweepArgs& a, const unsigned long long* mcur,
+                              unsigned long long* mnext, const PartRef* refs, bool pull, hipStream_t stream,
+                              hipEvent_t t0, hipEvent_t t1)
+{
+    const int gx = (a.nx + 63) / 64, gy = (a.ny + 3) / 4, nb = gx * gy;
+    if (pull)
+        hipExtLaunchKernelGGL(sweep_multi_kernel<T, true>, dim3(nb), dim3(256), 0u, stream, t0, t1, 0u, fin, fout, a,
+                              mcur, mnext, refs, gx, nb);
+    else
+        hipExtLaunchKernelGGL(sweep_multi_kernel<T, false>, dim3(nb), dim3(256), 0u, stream, t0, t1, 0u, fin, fout,
+                              a, mcur, mnext, refs, gx, nb);
+    return hipGetLastError();
+}
+
 template <typename T, bool PULL>
 hipError_t launch_sweep_layout(const T* fin, T* fout, const SweepArgs& a, int mode, const TileDesc* desc,
                                const int64_t* tile, int32_t box_cap, hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
@@ -151,7 +198,10 @@ hipError_t launch_sweep(const T* fin, T* fout, const SweepArgs& a, int mode, con
 #define LBIB_SWEEP_INSTANTIATE(T)                                                                               \
     template hipError_t launch_init<T>(T*, int32_t, int32_t, int32_t, int64_t, double, double, bool, hipStream_t); \
     template hipError_t launch_sweep<T>(const T*, T*, const SweepArgs&, int, const TileDesc*, const int64_t*,      \
-                                        int32_t, bool, hipStream_t, hipEvent_t, hipEvent_t);
+                                        int32_t, bool, hipStream_t, hipEvent_t, hipEvent_t);                      \
+    template hipError_t launch_sweep_multi<T>(const T*, T*, const SweepArgs&, const unsigned long long*,           \
+                                              unsigned long long*, const PartRef*, bool, hipStream_t, hipEvent_t,  \
+                                              hipEvent_t);
 LBIB_SWEEP_INSTANTIATE(double)
 LBIB_SWEEP_INSTANTIATE(float)
 LBIB_SWEEP_INSTANTIATE(half_t)

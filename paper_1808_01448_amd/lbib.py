@@ -178,6 +178,16 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def particle_entries(w: dict) -> list:
+    """(particle, ligand) descriptor pairs of a workload: the single form ("particle",
+    "ligand") or the list form ("particles": [{"particle": ..., "ligand": ...}, ...])."""
+    if "particles" in w:
+        return [(e["particle"], e["ligand"]) for e in w["particles"]]
+    if w.get("particle") is not None:
+        return [(w["particle"], w["ligand"])]
+    return []
+
+
 def _lattice_desc(lat: dict) -> LatticeDesc:
     return LatticeDesc(int(lat["nx"]), int(lat["ny"]), float(lat["tau"]), float(lat["re"]), int(lat.get("drive", 0)),
                        int(lat.get("precision", FP64)), int(lat.get("seed", 0)))
@@ -217,15 +227,17 @@ class Sim:
         self.stream = stream
         _check(L.lbib_create(C.byref(d), _stream_ptr(stream), C.byref(self._h)))
         self.nl = 0
+        self.nls = []
         try:
-            part = workload.get("particle")
-            if part is not None:
+            for part, lig in particle_entries(workload):
                 pd = _particle_desc(part)
                 pid = C.c_int32()
                 self._call(L.lbib_particle_add, C.byref(pd), C.byref(pid))
-                self.nl = int(part["n_markers"])
-                ld = _ligand_desc(workload["ligand"])
-                self._call(L.lbib_ligands_set, 0, C.byref(ld))
+                self.nls.append(int(part["n_markers"]))
+                ld = _ligand_desc(lig)
+                self._call(L.lbib_ligands_set, pid.value, C.byref(ld))
+            if self.nls:
+                self.nl = self.nls[0]
                 r = workload.get("receptor", {"wall": 0, "density": 1.0})
                 rd = ReceptorDesc(int(r["wall"]), float(r["density"]))
                 self._call(L.lbib_receptors_set, C.byref(rd))
@@ -285,15 +297,17 @@ class Sim:
         return {n: getattr(s, n) for n in STATE_FIELDS}
 
     def bonds(self, pid: int = 0):
-        b = np.zeros(self.nl, np.uint8)
-        lg = np.zeros(self.nl, np.uint8)
-        self._call(lib().lbib_read_bonds, pid, b.ctypes.data_as(_U8), lg.ctypes.data_as(_U8), self.nl)
+        nl = self.nls[pid]
+        b = np.zeros(nl, np.uint8)
+        lg = np.zeros(nl, np.uint8)
+        self._call(lib().lbib_read_bonds, pid, b.ctypes.data_as(_U8), lg.ctypes.data_as(_U8), nl)
         return b, lg
 
     def markers(self, pid: int = 0):
-        X = np.zeros((self.nl, 2))
-        n = np.zeros((self.nl, 2))
-        self._call(lib().lbib_read_markers, pid, X.ctypes.data_as(_D), n.ctypes.data_as(_D), self.nl)
+        nl = self.nls[pid]
+        X = np.zeros((nl, 2))
+        n = np.zeros((nl, 2))
+        self._call(lib().lbib_read_markers, pid, X.ctypes.data_as(_D), n.ctypes.data_as(_D), nl)
         return X, n
 
     def field(self, which: int) -> np.ndarray:
@@ -355,7 +369,8 @@ class Sim:
         return bool(v.value)
 
     def set_overlap(self, mode):
-        """0 / False: serial; 1 / True: overlapped; 2: chosen by lattice size (default)."""
+        """0 / False: serial; 1 / True: overlapped; 2: chosen by lattice size (default); 3: the
+        split particle phase (always used with several particles)."""
         self._call(lib().lbib_set_overlap, int(mode))
 
     # -- timing --------------------------------------------------------------------------

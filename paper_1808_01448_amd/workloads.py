@@ -109,6 +109,7 @@ def without_particle(w: dict) -> dict:
     w = copy.deepcopy(w)
     w.pop("particle", None)
     w.pop("ligand", None)
+    w.pop("particles", None)
     w["name"] = w["name"] + "_no_particle"
     return w
 
@@ -202,6 +203,66 @@ def serving_requests(n: int, seed: int = 0, *, steps_range=(5_000, 50_000), nx_r
         w["name"] = f"request{k}_" + w["name"]
         out.append(w)
     return out
+
+
+def _ellipse_points(a: float, b: float, xc: float, yc: float, th: float, n: int = 96) -> np.ndarray:
+    """n points of the boundary of the ellipse (semi-axis a along the body y axis)."""
+    t = np.linspace(0.0, 2.0 * np.pi, n, endpoint=False)
+    bx, by = b * np.sin(t), -a * np.cos(t)
+    c, s = np.cos(th), np.sin(th)
+    return np.stack([xc + c * bx - s * by, yc + s * bx + c * by], axis=1)
+
+
+def multi_particle_channel(nx: int = 2048, ny: int = 512, n: int = 32, seed: int = 0, *, precision: str = "fp32",
+                           re: float = 0.1, area_frac: float = 0.025, gap: float = 4.0, steps: int = 5_000,
+                           max_tries: int = 200_000) -> dict:
+    """n particles in one channel: aspect ratio ~ U[1, 3] (1 is a circle), area area_frac H^2
+    each, angle ~ U[0, pi), placed by rejection sampling so that every boundary keeps at least
+    `gap` lattice units from the walls (y = -1/2, ny - 1/2) and from every other boundary
+    (periodic in x); ligand density and bond strength per particle drawn from the sweep's
+    sets; tau 0.8, seed `seed`."""
+    g = rng(seed)
+    H = float(ny)
+    parts, boundaries = [], []
+    tries = 0
+    while len(parts) < n:
+        tries += 1
+        if tries > max_tries:
+            raise ValueError("placement failed: too dense for the requested gap")
+        ar = float(g.uniform(1.0, 3.0))
+        a = math.sqrt(ar * area_frac * H * H / math.pi)
+        b = a / ar
+        th = float(g.uniform(0.0, math.pi))
+        hs = math.sqrt(b * b * math.sin(th) ** 2 + a * a * math.cos(th) ** 2)
+        xc = float(g.uniform(0.0, nx))
+        yc = float(g.uniform(-0.5 + gap + hs, ny - 0.5 - gap - hs))
+        pts = _ellipse_points(a, b, xc, yc, th)
+        ok = True
+        for q in boundaries:
+            for shift in (-nx, 0.0, nx):
+                d = np.min(np.hypot(pts[:, None, 0] - q[None, :, 0] - shift, pts[:, None, 1] - q[None, :, 1]))
+                if d < gap + 1.0:  # the sampled boundaries are within ~1 lu of the curves
+                    ok = False
+                    break
+            if not ok:
+                break
+        if not ok:
+            continue
+        boundaries.append(pts)
+        shape = 0 if ar < 1.0 + 1e-9 else 1
+        rl = SWEEP_RHO_L[int(g.integers(len(SWEEP_RHO_L)))]
+        strength = SWEEP_STRENGTH[int(g.integers(len(SWEEP_STRENGTH)))]
+        parts.append(dict(
+            particle=dict(shape=shape, a_major=a, b_minor=b, xc=xc, yc=yc, theta0=th, rho_p=1.0,
+                          n_markers=_n_markers("circle" if shape == 0 else "ar3", a, b)),
+            ligand=_ligand(rl, strength)))
+    return dict(
+        name=f"multi_{nx}x{ny}_{n}particles_{precision}_seed{seed}",
+        lattice=dict(nx=nx, ny=ny, tau=0.8, re=re, drive=0, precision=PRECISION[precision], seed=seed),
+        particles=parts,
+        receptor=dict(wall=0, density=1.0),
+        steps=steps,
+    )
 
 
 def poisson_arrivals(n: int, rate: float, seed: int = 0) -> np.ndarray:

@@ -117,8 +117,8 @@ def test_call_order_and_ligand_validation(L):
     try:
         pid = C.c_int32()
         assert L.lbib_step(h, 1) == lbib.E_STATE
-        assert L.lbib_particle_add(h, C.byref(_pdesc()), C.byref(pid)) == lbib.OK
-        assert L.lbib_particle_add(h, C.byref(_pdesc(xc=40.0)), C.byref(pid)) == lbib.E_UNSUPPORTED
+        assert L.lbib_particle_add(h, C.byref(_pdesc()), C.byref(pid)) == lbib.OK and pid.value == 0
+        assert L.lbib_particle_add(h, C.byref(_pdesc(xc=40.0)), C.byref(pid)) == lbib.OK and pid.value == 1
         # a particle without ligands cannot be initialised
         assert L.lbib_init(h) == lbib.E_STATE
         bad = lbib.LigandDesc(3, 2, 27.8, 0.5, 6.8e-3, 0.5, 1.0, 1e-4, 1e-5, 1e-8)
@@ -128,6 +128,8 @@ def test_call_order_and_ligand_validation(L):
         assert L.lbib_ligands_set(h, 5, C.byref(bad)) == lbib.E_INVALID
         good = lbib.LigandDesc(1, 2, 27.8, 0.5, 6.8e-3, 0.5, 1.0, 1e-4, 1e-5, 1e-8)
         assert L.lbib_ligands_set(h, 0, C.byref(good)) == lbib.OK
+        assert L.lbib_init(h) == lbib.E_STATE  # particle 1 still has no ligands
+        assert L.lbib_ligands_set(h, 1, C.byref(good)) == lbib.OK
         assert L.lbib_receptors_set(h, C.byref(lbib.ReceptorDesc(0, 0.5))) == lbib.E_UNSUPPORTED
         assert L.lbib_receptors_set(h, C.byref(lbib.ReceptorDesc(1, 1.0))) == lbib.E_UNSUPPORTED
         assert L.lbib_receptors_set(h, C.byref(lbib.ReceptorDesc(0, 1.0))) == lbib.OK
@@ -194,3 +196,14 @@ def test_server_host_validation(L):
     assert L.lbib_server_last_error(None)
     assert L.lbib_server_progress(None, None) == lbib.E_INVALID
     L.lbib_server_destroy(None)
+
+
+def test_particle_count_limit(L):
+    st, h = _create(L, nx=256)
+    try:
+        pid = C.c_int32()
+        for k in range(64):
+            assert L.lbib_particle_add(h, C.byref(_pdesc(xc=4.0 * k)), C.byref(pid)) == lbib.OK and pid.value == k
+        assert L.lbib_particle_add(h, C.byref(_pdesc()), C.byref(pid)) == lbib.E_UNSUPPORTED
+    finally:
+        L.lbib_destroy(h)
