@@ -105,6 +105,72 @@ def batched_leg(steps: int, stream) -> dict:
     }
 
 
+def multi_leg(steps: int, err_steps: int, stream) -> dict:
+    """2048 x 512 channel with 32 particles (aspect ratio 1-3, area 0.025 H^2 each), Re 0.1:
+    throughput with FP32, FP16 and BF16 population storage, and each storage's error against
+    the FP64 oracle over the first err_steps steps."""
+    import numpy as np
+
+    import oracle
+    from paper_1808_01448_amd import lbib
+    from paper_1808_01448_amd import workloads as W
+
+    w = W.multi_particle_channel(2048, 512, 32, 0)
+    n = len(w["particles"])
+    cells = w["lattice"]["nx"] * w["lattice"]["ny"]
+    log(f"bench: 32-particle leg, FP64 oracle over {err_steps} steps")
+    o = oracle.Sim.from_workload(W.with_precision(w, "fp64"))
+    t0 = time.perf_counter()
+    _, to = o.step_all(err_steps)
+    t_orc = time.perf_counter() - t0
+    _, uxo, uyo = o.fields()
+    x0 = np.array([[e["particle"]["xc"], e["particle"]["yc"]] for e in w["particles"]])
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    out = {"workload": "2048 x 512 channel, 32 particles (aspect ratio U[1,3], area 0.025 H^2, random angle, "
+                       "boundary gaps >= 4 lu), Re 0.1, tau 0.8, ligand density and bond strength per particle",
+           "unit": "MLUPS", "steps_timed": steps, "error_steps": err_steps,
+           "oracle_seconds": round(t_orc, 2), "storages": {}}
+    for prec in ("fp32", "fp16", "bf16"):
+        wp = W.with_precision(w, prec)
+        s = lbib.Sim(wp, stream=stream)
+        for k in range(n):
+            s.trace_enable(err_steps, k)
+        s.step(err_steps)
+        s.sync()
+        tg = np.stack([s.trace(err_steps, k) for k in range(n)], axis=1)
+        _, ux, uy = s.fields()
+        err = {"velocity": rel(tg[..., 4:6], to[..., 4:6]),
+               "displacement": rel(tg[..., 1:3] - x0, to[..., 1:3] - x0),
+               "force": rel(tg[..., 7:9], to[..., 7:9]),
+               "field": rel(np.stack([ux, uy]), np.stack([uxo, uyo])),
+               "bond_count_steps_differing": int((tg[..., -2] != to[..., -2]).sum())}
+        s.step(20)
+        s.sync()
+        t0 = time.perf_counter()
+        s.step(steps)
+        s.sync()
+        dt = time.perf_counter() - t0
+        s.kernel_timing(7)
+        s.step(50)
+        k_ms = [s.kernel_time(k)[0] / max(s.kernel_time(k)[1], 1) for k in range(3)]
+        s.kernel_timing(0)
+        bpu = s.bytes_per_update
+        s.close()
+        sweep_gbs = bpu * cells / (k_ms[0] * 1e-3) / 1e9
+        out["storages"][prec] = {
+            "mlups": round(cells * steps / dt / 1e6, 1), "ms_per_step": round(dt * 1e3 / steps, 4),
+            "bytes_per_update": bpu, "sweep_us": round(k_ms[0] * 1e3, 2),
+            "particle_spread_us": round(k_ms[1] * 1e3, 2), "particle_loads_us": round(k_ms[2] * 1e3, 2),
+            "sweep_gbs": round(sweep_gbs, 1), "sweep_frac_of_8tbs": round(sweep_gbs / HBM_PEAK_GBS, 4),
+            "error_vs_fp64_oracle": {k: (round(v, 8) if isinstance(v, float) else v) for k, v in err.items()},
+        }
+        log(f"bench: {prec}: {out['storages'][prec]['mlups']} MLUPS, velocity error {err['velocity']:.2e}")
+    return out
+
+
 def serving_leg(n: int, full: bool, stream) -> dict:
     """Poisson arrivals of single-particle solves at 0.7 x the server's measured capacity,
     served by continuous batching, against the plain one-simulation-at-a-time server on the
@@ -156,6 +222,10 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=200,
                     help="steps of the 216-simulation sweep, pooled and plain (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=64, help="requests of the serving leg (0: skip)")
+    ap.add_argument("--multi-steps", type=int, default=500,
+                    help="steps of the 32-particle 2048 x 512 leg per storage precision (0: skip)")
+    ap.add_argument("--multi-err-steps", type=int, default=200,
+                    help="steps of that leg compared with the FP64 oracle")
     ap.add_argument("--serve-full", action="store_true",
                     help="serving leg at the full request mix: 256 requests of 5k-50k steps (several minutes)")
     args = ap.parse_args()
@@ -240,6 +310,10 @@ def main():
     if args.batched_steps > 0:
         batched = batched_leg(args.batched_steps, stream)
 
+    multi = None
+    if args.multi_steps > 0:
+        multi = multi_leg(args.multi_steps, args.multi_err_steps, stream)
+
     served = None
     if args.serve_requests > 0 or args.serve_full:
         served = serving_leg(256 if args.serve_full else args.serve_requests, args.serve_full, stream)
@@ -273,6 +347,7 @@ def main():
         "cpu_baseline": cpu,
         "batched": batched,
         "served": served,
+        "multi_particle": multi,
         "final_particle": {k: p[k] for k in ("step", "xc", "yc", "theta", "n_bonds")},
     }
     print(json.dumps(out), flush=True)
