@@ -112,7 +112,7 @@ struct ParticleArgs {
     uint64_t seed;
     uint32_t pid;
     int64_t* tile;      // [box_cap][2] fixed-point spread force on the box (read by the sweep)
-    double* box_global;  // [6][box_cap] node fields when the box does not fit in LDS
+    double* box_global;  // room for the node fields of box_cap nodes when they may not fit in LDS
     int32_t box_cap;     // node capacity of the box
     TileDesc* desc;      // this step's box
     TileDesc* zone;      // zone[2]: boxes of future steps, slot = step parity
@@ -128,6 +128,7 @@ struct ParticleArgs {
     unsigned long long* pmask;
     const PartRef* refs;
     int32_t mtx;
+    int32_t nparts;  // entries of refs
 };
 
 // Launchers (lbib_sweep.hip, lbib_particle.hip).  All enqueue on `stream` and return the launch status.
@@ -151,19 +152,25 @@ template <typename T>
 hipError_t launch_sweep(const T* fin, T* fout, const SweepArgs& a, int mode, const TileDesc* desc,
                         const int64_t* tile, int32_t box_cap, bool pull, hipStream_t stream, hipEvent_t t0 = nullptr,
                         hipEvent_t t1 = nullptr);
-// Bytes of dynamic LDS the particle phase needs for a box of box_cap nodes kept in LDS, or
-// 0 when the box is kept in global memory instead; then it still needs
-// particle_lds_aux_bytes (the node mask and the fill queues), which must not exceed 158 KB.
+// LDS of the particle phase.  particle_lds_aux_bytes: the node mask, its prefix counts, the
+// fill queues and the overlap list, which must not exceed 158 KB.  particle_lds_bytes: that
+// plus the node fields of every node of a box of box_cap nodes, or 0 when this exceeds
+// 158 KB (the particle then needs global scratch for the fields of the nodes its supports
+// reach, used when they do not fit in the LDS of the launch).  particle_launch_lds: the
+// dynamic LDS a launch gives the particle (the most a workgroup may take when the whole
+// box may not fit).
 size_t particle_lds_bytes(int32_t box_cap);
 size_t particle_lds_aux_bytes(int32_t box_cap);
+size_t particle_launch_lds(int32_t box_cap);
 template <typename T>
 hipError_t launch_particle(const ParticleArgs<T>& a, hipStream_t stream, hipEvent_t t0 = nullptr,
                            hipEvent_t t1 = nullptr);
 // The two launches of the split particle phase (mode 1: spread and mark; mode 2: loads,
-// bonds, update), one workgroup per particle of args[0..n).
+// bonds, update), one workgroup per particle of args[0..n); lds: the dynamic LDS of the
+// launch (the most particle_launch_lds of the particles).
 template <typename T>
 hipError_t launch_particle_split(const ParticleArgs<T>* args, int32_t n, const T* f, unsigned long long* pmask,
-                                 int32_t mode, int32_t max_nl, int32_t lds_cap, size_t lds, hipStream_t stream,
+                                 int32_t mode, int32_t max_nl, size_t lds, hipStream_t stream,
                                  hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
 // A pool of independent simulations stepped together (one launch per kernel per step).
@@ -187,12 +194,11 @@ struct PoolSweep {
 struct PoolSweepConfig {
     int32_t bx, tpb;
 };
+// lds: the dynamic LDS of the launch (the most particle_launch_lds of the members).
 template <typename T>
-// lds_cap: the largest box kept in LDS; lds: the dynamic LDS of the launch (the most any
-// member needs).
 hipError_t launch_pool_particle(const ParticleArgs<T>* args, const int32_t* active, TileDesc* ctl, int32_t n_active,
-                                int32_t max_nl, int32_t lds_cap, size_t lds, hipStream_t stream,
-                                hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+                                int32_t max_nl, size_t lds, hipStream_t stream, hipEvent_t t0 = nullptr,
+                                hipEvent_t t1 = nullptr);
 template <typename T>
 hipError_t launch_pool_sweep(const PoolSweep<T>* sims, const TileDesc* ctl, const int2* table, int32_t n_blocks,
                              PoolSweepConfig cfg, hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);

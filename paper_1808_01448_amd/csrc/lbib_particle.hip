@@ -152,85 +152,214 @@ __device__ __forceinline__ MarkerGeo marker_geo(const double* xi, const double* 
     return g;
 }
 
-// Bounding box (unwrapped x) of every support a particle at (xc, yc, theta) reaches:
-// minima of (i_lo, -i_hi, j_lo, -j_hi) accumulated into r[4].
-template <typename T, int MPT>
-__device__ __forceinline__ void accumulate_bounds(const ParticleArgs<T>& a, double xc, double yc, double cth,
-                                                  double sth, int (&r)[4])
-{
-#pragma unroll
-    for (int k = 0; k < MPT; ++k) {
-        const int l = threadIdx.x + k * PB;
-        if (l < a.nl) {
-            const MarkerGeo g = marker_geo(a.xi, a.nuv, l, xc, yc, cth, sth, a.ny);
-            int ilo, ihi, jlo, jhi;
-            if (support_range(g.X, fluid_row(g.Y, a.ny), a.ny, ilo, ihi, jlo, jhi)) {
-                r[0] = min(r[0], ilo);
-                r[1] = min(r[1], -ihi);
-                r[2] = min(r[2], jlo);
-                r[3] = min(r[3], -jhi);
-            }
-            if (support_range(g.px, g.py, a.ny, ilo, ihi, jlo, jhi)) {
-                r[0] = min(r[0], ilo);
-                r[1] = min(r[1], -ihi);
-                r[2] = min(r[2], jlo);
-                r[3] = min(r[3], -jhi);
-            }
-        }
-    }
-}
-
-// Node fields of the box, structure of arrays over box_cap nodes: rho, u* (the velocity
-// with half the uniform drive, without the spread force), 1/rho, and the two fixed-point
-// spread-force accumulators.
-struct BoxView {
-    double *rho, *ux, *uy, *inv;
-    unsigned long long *fx, *fy;
+// LDS of the particle phase (dynamic, lds_bytes bytes), in this order: the probe launch's
+// list of the particles whose boxes overlap this one (kMaxParticles entries), the per-wave
+// queues of the fill, mask[wcap] (one bit per box node, set where a support of this launch
+// reaches), pre[wcap] (the marked nodes before each mask word) and, when they fit, the node
+// fields of the marked nodes; otherwise those live in the global scratch box_global.
+// wcap = ceil(box_cap / 32).  A marked node's slot is its rank among the marked nodes in
+// row-major box order, so the fields take 48 bytes per node of the ring that the supports
+// cover next to the surface, not per node of the box.
+struct NodeView {
+    double *rho, *ux, *uy, *inv;    // density, u* (velocity with half the uniform drive and without
+                                    // the spread force), 1/rho
+    unsigned long long *fx, *fy;    // this particle's fixed-point spread force; in the probe launch
+                                    // of several particles, the total spread force (FP64 bits)
 };
 
-constexpr int kBoxDoubles = 6;  // 4 doubles + 2 64-bit integers per node
-constexpr int kFillU = 4;       // marked nodes per lane in flight while filling the box
-constexpr int kQueue = 64 * kFillU + 64;  // per-wave queue of marked nodes (LDS ints)
+// A particle whose box of this step overlaps the box of the particle running the probe
+// launch, with where its spread force lies.
+struct OvEntry {
+    const int64_t* tile;
+    int32_t i0w, j0, w, h, scale, pad;
+};
 
-// LDS beside the box fields: one bit per box node (marked when some support reaches it) and
-// the per-wave queues of the fill.
+constexpr int kMaxParticles = 64;
+constexpr int kFields = 6;                // per marked node: 4 doubles + 2 64-bit integers
+constexpr int kFillU = 4;                 // marked nodes per lane in flight while filling
+constexpr int kQueue = 64 * kFillU + 64;  // per-wave queue of marked nodes (LDS ints)
+constexpr size_t kLdsMax = 158 * 1024;    // dynamic LDS a workgroup may take beside the static part
+constexpr size_t kLdsHead = sizeof(OvEntry) * kMaxParticles + (size_t)NW * kQueue * 4;
+
 size_t particle_lds_aux_bytes(int32_t box_cap)
 {
-    return (size_t)((box_cap + 31) / 32) * 4 + (size_t)NW * kQueue * 4;
+    return kLdsHead + (size_t)((box_cap + 31) / 32) * 8;
 }
 
 size_t particle_lds_bytes(int32_t box_cap)
 {
-    const size_t bytes = (size_t)box_cap * kBoxDoubles * 8 + particle_lds_aux_bytes(box_cap);
-    return bytes <= 158 * 1024 ? bytes : 0;  // gfx950: 160 KB of LDS per workgroup
+    const size_t bytes = particle_lds_aux_bytes(box_cap) + (size_t)box_cap * kFields * 8;
+    return bytes <= kLdsMax ? bytes : 0;
 }
 
-// Set the bit of every box node in the support window of a marker or probe of this step (the
-// full window of mls_shape: nodes of zero weight are read too, multiplied by zero).
+size_t particle_launch_lds(int32_t box_cap)
+{
+    const size_t bytes = particle_lds_bytes(box_cap);
+    return bytes ? bytes : kLdsMax;
+}
+
+// The markers of this thread (l = threadIdx.x + k PB) at one position of the particle.
+template <int MPT>
+struct MarkerSet {
+    double X[MPT], Y[MPT], NX[MPT], NY[MPT], PX[MPT], PY[MPT];
+    bool in[MPT];
+};
+
 template <typename T, int MPT>
-__device__ __forceinline__ void mark_supports(const ParticleArgs<T>& a, double xc, double yc, double cth, double sth,
-                                              int x0, int y0, int w, int h, uint32_t* mask)
+__device__ __forceinline__ void marker_set(const ParticleArgs<T>& a, double xc, double yc, double cth, double sth,
+                                           MarkerSet<MPT>& G)
 {
 #pragma unroll
     for (int k = 0; k < MPT; ++k) {
         const int l = threadIdx.x + k * PB;
-        if (l >= a.nl) continue;
-        const MarkerGeo g = marker_geo(a.xi, a.nuv, l, xc, yc, cth, sth, a.ny);
+        G.in[k] = l < a.nl;
+        G.X[k] = G.Y[k] = G.NX[k] = G.NY[k] = G.PX[k] = G.PY[k] = 0.0;
+        if (G.in[k]) {
+            const MarkerGeo g = marker_geo(a.xi, a.nuv, l, xc, yc, cth, sth, a.ny);
+            G.X[k] = g.X;
+            G.Y[k] = g.Y;
+            G.NX[k] = g.nx;
+            G.NY[k] = g.ny;
+            G.PX[k] = g.px;
+            G.PY[k] = g.py;
+        }
+    }
+}
+
+// Bounding box (unwrapped x) of every marker and probe support of the set: minima of
+// (i_lo, -i_hi, j_lo, -j_hi) accumulated into r[4].
+template <int MPT>
+__device__ __forceinline__ void set_bounds(const MarkerSet<MPT>& G, int ny, int (&r)[4])
+{
+#pragma unroll
+    for (int k = 0; k < MPT; ++k) {
+        if (!G.in[k]) continue;
 #pragma unroll
         for (int pt = 0; pt < 2; ++pt) {
             int ilo, ihi, jlo, jhi;
-            const bool ok = pt == 0 ? support_range(g.X, fluid_row(g.Y, a.ny), a.ny, ilo, ihi, jlo, jhi)
-                                    : support_range(g.px, g.py, a.ny, ilo, ihi, jlo, jhi);
-            if (!ok) continue;
-            for (int j = jlo; j <= jhi; ++j)
-                for (int i = ilo; i <= ihi; ++i) {
-                    const int di = i - x0, dj = j - y0;
-                    if (di < 0 || di >= w || dj < 0 || dj >= h) continue;
-                    const int n = dj * w + di;
-                    atomicOr(mask + (n >> 5), 1u << (n & 31));
-                }
+            const bool ok = pt == 0 ? support_range(G.X[k], fluid_row(G.Y[k], ny), ny, ilo, ihi, jlo, jhi)
+                                    : support_range(G.PX[k], G.PY[k], ny, ilo, ihi, jlo, jhi);
+            if (ok) {
+                r[0] = min(r[0], ilo);
+                r[1] = min(r[1], -ihi);
+                r[2] = min(r[2], jlo);
+                r[3] = min(r[3], -jhi);
+            }
         }
     }
+}
+
+// Set the mask bits of the support window at (X, Y) (the full window of mls_shape: nodes of
+// zero weight are read too, multiplied by zero); a window row is at most 3 nodes, so one
+// atomic per mask word it touches.
+__device__ __forceinline__ void mark_window(double X, double Y, int ny, int x0, int y0, int w, int h, uint32_t* mask)
+{
+    int ilo, ihi, jlo, jhi;
+    if (!support_range(X, Y, ny, ilo, ihi, jlo, jhi)) return;
+    ilo = max(ilo - x0, 0);
+    ihi = min(ihi - x0, w - 1);
+    jlo = max(jlo - y0, 0);
+    jhi = min(jhi - y0, h - 1);
+    if (ihi < ilo) return;
+    const uint64_t run = (1ull << (ihi - ilo + 1)) - 1ull;
+    for (int j = jlo; j <= jhi; ++j) {
+        const int n = j * w + ilo;
+        const uint64_t bits = run << (n & 31);
+        atomicOr(mask + (n >> 5), (uint32_t)bits);
+        if (bits >> 32) atomicOr(mask + (n >> 5) + 1, (uint32_t)(bits >> 32));
+    }
+}
+
+// which: bit 0 the marker windows, bit 1 the probe windows.
+template <int MPT>
+__device__ __forceinline__ void mark_windows(const MarkerSet<MPT>& G, int ny, int which, int x0, int y0, int w, int h,
+                                             uint32_t* mask)
+{
+#pragma unroll
+    for (int k = 0; k < MPT; ++k) {
+        if (!G.in[k]) continue;
+        if (which & 1) mark_window(G.X[k], fluid_row(G.Y[k], ny), ny, x0, y0, w, h, mask);
+        if (which & 2) mark_window(G.PX[k], G.PY[k], ny, x0, y0, w, h, mask);
+    }
+}
+
+// Exclusive prefix of the popcounts of mask[0..nw) into pre; returns the total to every
+// thread.  Thread t takes a run of consecutive words, so the runs are in word order.
+__device__ __forceinline__ int mask_prefix(const uint32_t* mask, int* pre, int nw, int (*sh)[NW])
+{
+    const int per = (nw + PB - 1) / PB;
+    const int w0 = min((int)threadIdx.x * per, nw), w1 = min(w0 + per, nw);
+    int s = 0;
+    for (int k = w0; k < w1; ++k) s += __popc(mask[k]);
+    const int lane = threadIdx.x & 63;
+    int incl = s;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int v = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += v;
+    }
+    if (lane == 63) sh[0][threadIdx.x >> 6] = incl;
+    __syncthreads();
+    int run = incl - s, total = 0;
+#pragma unroll
+    for (int u = 0; u < NW; ++u) {
+        const int v = sh[0][u];
+        if (u < (int)(threadIdx.x >> 6)) run += v;
+        total += v;
+    }
+    for (int k = w0; k < w1; ++k) {
+        pre[k] = run;
+        run += __popc(mask[k]);
+    }
+    __syncthreads();
+    return total;
+}
+
+// Slot of marked box node n.
+__device__ __forceinline__ int node_slot(const uint32_t* mask, const int* pre, int n)
+{
+    const int wd = n >> 5;
+    return pre[wd] + __popc(mask[wd] & ((1u << (n & 31)) - 1u));
+}
+
+// The particles (this one included) whose boxes of this step overlap this particle's box,
+// in particle order (the boxes are arcs along the periodic x axis); only they can put a
+// spread force on its probe nodes.
+template <typename T>
+__device__ __forceinline__ int overlap_list(const ParticleArgs<T>& a, int x0, int y0, int w, int h, OvEntry* ov,
+                                            int (*sh)[NW])
+{
+    if (threadIdx.x < 64) {
+        const int q = threadIdx.x;
+        bool take = false;
+        OvEntry e{};
+        if (q < a.nparts && w > 0 && h > 0) {
+            const TileDesc d = *a.refs[q].desc;
+            if (d.active && d.w > 0 && d.h > 0) {
+                const int xw = wrap(x0, a.nx);
+                int dq = d.i0w - xw;
+                if (dq < 0) dq += a.nx;
+                int dm = xw - d.i0w;
+                if (dm < 0) dm += a.nx;
+                take = (dq < w || dm < d.w) && d.j0 < y0 + h && y0 < d.j0 + d.h;
+                e.tile = a.refs[q].tile;
+                e.i0w = d.i0w;
+                e.j0 = d.j0;
+                e.w = d.w;
+                e.h = d.h;
+                e.scale = d.scale;
+            }
+        }
+        const unsigned long long bal = __ballot(take);
+        const int below =
+            (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        if (take) ov[below] = e;
+        if (q == 0) sh[0][0] = __popcll(bal);
+    }
+    __syncthreads();
+    const int n = sh[0][0];
+    __syncthreads();
+    return n;
 }
 
 __device__ __forceinline__ void wave_sync_lds()
@@ -242,11 +371,14 @@ __device__ __forceinline__ void wave_sync_lds()
 
 // Node fields at the marked nodes of the box.  Each wave walks its share of the box (64
 // consecutive nodes per round), appends the marked ones to its LDS queue (ballot + prefix
-// count) and, whenever 64 U are queued, loads and reduces them U per lane; so the loads in
-// flight stay full while only the ring of nodes next to the surface is read.
-template <typename T, bool LDS>
-__device__ __forceinline__ void fill_marked(const ParticleArgs<T>& a, const BoxView& B, const uint32_t* mask, int nbox,
-                                            int x0, int y0, int w, int* q)
+// count) and, whenever 64 U are queued, loads and reduces them U per lane, so the loads in
+// flight stay full while only the marked nodes are read.  TOTAL (the probe launch of
+// several particles): the total spread force at each node, summed over the overlapping
+// particles in particle order.
+template <typename T, bool TOTAL>
+__device__ __forceinline__ void fill_marked(const ParticleArgs<T>& a, const NodeView& B, const uint32_t* mask,
+                                            const int* pre, int nbox, int x0, int y0, int w, int* q,
+                                            const OvEntry* ov, int nov)
 {
     const int lane = threadIdx.x & 63;
     int qn = 0;  // wave-uniform
@@ -264,19 +396,50 @@ __device__ __forceinline__ void fill_marked(const ParticleArgs<T>& a, const BoxV
         if (qn >= 64 * kFillU || (!more && qn > 0)) {
             wave_sync_lds();
             const int take = min(qn, 64 * kFillU);
-            int kk[kFillU];
+            int kk[kFillU], ii[kFillU], jj[kFillU];
             double v[kFillU][9];
 #pragma unroll
             for (int u = 0; u < kFillU; ++u) {
                 const int e = lane + 64 * u;
                 kk[u] = e < take ? q[e] : -1;
+                ii[u] = jj[u] = 0;
                 if (kk[u] >= 0) {
-                    const int j = y0 + kk[u] / w;
-                    const int i = wrap(x0 + kk[u] % w, a.nx);
+                    jj[u] = y0 + kk[u] / w;
+                    ii[u] = wrap(x0 + kk[u] % w, a.nx);
 #pragma unroll
                     for (int c = 0; c < 9; ++c)
-                        v[u][c] = (double)st_load(a.f, pop_index(c, i, j, a.nx, a.ny, a.pitch, a.plane, a.pull != 0),
+                        v[u][c] = (double)st_load(a.f, pop_index(c, ii[u], jj[u], a.nx, a.ny, a.pitch, a.plane,
+                                                                 a.pull != 0),
                                                   a.inv_scale, false);
+                }
+            }
+            double fx[kFillU], fy[kFillU];
+#pragma unroll
+            for (int u = 0; u < kFillU; ++u) fx[u] = fy[u] = 0.0;
+            if (TOTAL) {
+                for (int e = 0; e < nov; ++e) {
+                    const OvEntry E = ov[e];
+                    int64_t tx[kFillU], ty[kFillU];
+                    bool in[kFillU];
+#pragma unroll
+                    for (int u = 0; u < kFillU; ++u) {
+                        int di = ii[u] - E.i0w;
+                        if (di < 0) di += a.nx;
+                        const int dj = jj[u] - E.j0;
+                        in[u] = kk[u] >= 0 && di < E.w && dj >= 0 && dj < E.h;
+                        tx[u] = ty[u] = 0;
+                        if (in[u]) {
+                            const int64_t* t = E.tile + 2 * ((size_t)dj * E.w + di);
+                            tx[u] = t[0];
+                            ty[u] = t[1];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < kFillU; ++u) {
+                        if (!in[u]) continue;
+                        fx[u] += ldexp((double)tx[u], -E.scale);
+                        fy[u] += ldexp((double)ty[u], -E.scale);
+                    }
                 }
             }
 #pragma unroll
@@ -286,13 +449,13 @@ __device__ __forceinline__ void fill_marked(const ParticleArgs<T>& a, const BoxV
                 shifted_moments<double, double>(v[u], dr, jx, jy);
                 const double rho = 1.0 + dr;
                 const double inv = 1.0 / rho;
-                const int k = kk[u];
-                B.rho[k] = rho;
-                B.inv[k] = inv;
-                B.ux[k] = (jx + 0.5 * a.gx) * inv;
-                B.uy[k] = (jy + 0.5 * a.gy) * inv;
-                B.fx[k] = 0ull;
-                B.fy[k] = 0ull;
+                const int s = node_slot(mask, pre, kk[u]);
+                B.rho[s] = rho;
+                B.inv[s] = inv;
+                B.ux[s] = (jx + 0.5 * a.gx) * inv;
+                B.uy[s] = (jy + 0.5 * a.gy) * inv;
+                B.fx[s] = TOTAL ? (unsigned long long)__double_as_longlong(fx[u]) : 0ull;
+                B.fy[s] = TOTAL ? (unsigned long long)__double_as_longlong(fy[u]) : 0ull;
             }
             const int rest = qn - take;  // < 64, moved to the front (no overlap: take >= 256)
             wave_sync_lds();
@@ -303,33 +466,6 @@ __device__ __forceinline__ void fill_marked(const ParticleArgs<T>& a, const BoxV
             qn = rest;
         }
         if (!more && qn == 0) break;
-    }
-}
-
-__device__ __forceinline__ bool box_has(const TileDesc& d, int i, int j, int nx)
-{
-    int di = i - d.i0w;
-    if (di < 0) di += nx;
-    const int dj = j - d.j0;
-    return di < d.w && dj >= 0 && dj < d.h;
-}
-
-// The spread force of every particle at node (i, j) (i wrapped), summed in particle order:
-// the step's mask of the node's 64 x 4 tile lists the particles whose boxes reach it.
-template <typename T>
-__device__ __forceinline__ void multi_force(const ParticleArgs<T>& a, int i, int j, double& fx, double& fy)
-{
-    fx = fy = 0.0;
-    for (unsigned long long m = a.pmask[(j >> 2) * a.mtx + (i >> 6)]; m; m &= m - 1) {
-        const PartRef r = a.refs[__builtin_ctzll(m)];
-        const TileDesc d = *r.desc;
-        if (d.active && box_has(d, i, j, a.nx)) {
-            int di = i - d.i0w;
-            if (di < 0) di += a.nx;
-            const int64_t* t = r.tile + 2 * ((size_t)(j - d.j0) * d.w + di);
-            fx += ldexp((double)t[0], -d.scale);
-            fy += ldexp((double)t[1], -d.scale);
-        }
     }
 }
 
@@ -355,102 +491,82 @@ __device__ __forceinline__ void force_add(unsigned long long* p, int64_t v)
         __hip_atomic_fetch_add(p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One particle's phase, run by one workgroup.  MPT markers per thread (nl <= MPT * PB).
-// LDS: the box lives in dynamic LDS (`base`), else in the global scratch a.box_global (plain
-// loads and stores ordered by the workgroup barriers, device-scope atomics for the force).
-// MODE 0: the whole phase of a simulation's only particle.  With several particles the
-// phase is split in two launches so that every probe sees the spread force of every
-// particle: MODE 1 stages the box, spreads the marker forces into the particle's tile and
-// marks the step's tile mask; MODE 2 stages the box again and evaluates the probe loads
-// (the spread force at a probe node summed over the particles that reach it), the bonds,
-// the wall force and the rigid-body update.
-template <typename T, int MPT, bool LDS, int MODE = 0>
-__device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, double* lds_box)
+template <bool LDS>
+__device__ __forceinline__ unsigned long long force_load(const unsigned long long* p)
 {
-    __shared__ double shd[8][NW];
-    __shared__ int shi[8][NW];
+    if (LDS) return *p;
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// What the first part of the particle phase hands to the rest.
+template <int MPT>
+struct PhaseCtx {
+    double xc, yc, th, ux, uy, om, cth, sth;
+    int64_t step;
+    int x0, y0, w, h, nbox, nmarked, flags;
+    bool box_ok;
+    const uint32_t* mask;
+    const int* pre;
+    MarkerSet<MPT> G;
+};
+
+// The particle phase after the box and its marked nodes are known; LDS: the node fields are
+// in LDS, else in the global scratch (plain loads and stores ordered by the workgroup
+// barriers, device-scope atomics for the force).
+template <typename T, int MPT, bool LDS, int MODE>
+__device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const PhaseCtx<MPT>& c, const NodeView& B,
+                                           int* queue, const OvEntry* ov, int nov, double (*shd)[NW], int (*shi)[NW])
+{
     const int tid = threadIdx.x;
     const int nl = a.nl;
-    const int cap = a.box_cap;
-    double* base = LDS ? lds_box : a.box_global;
-    uint32_t* mask = (uint32_t*)(LDS ? lds_box + (size_t)cap * kBoxDoubles : lds_box);
-    int* queue = (int*)(mask + (cap + 31) / 32) + (tid >> 6) * kQueue;
-    BoxView B;
-    B.rho = base;
-    B.ux = base + cap;
-    B.uy = base + 2 * cap;
-    B.inv = base + 3 * cap;
-    B.fx = (unsigned long long*)(base + 4 * cap);
-    B.fy = (unsigned long long*)(base + 5 * cap);
-
+    const int x0 = c.x0, y0 = c.y0, w = c.w, h = c.h, nbox = c.nbox;
+    const bool box_ok = c.box_ok;
+    const uint32_t* mask = c.mask;
+    const int* pre = c.pre;
+    const double xc = c.xc, yc = c.yc, th = c.th, ux = c.ux, uy = c.uy, om = c.om, cth = c.cth, sth = c.sth;
+    const int64_t step = c.step;
+    int flags = c.flags;
     DevParticle* st = a.st;
-    const double xc = st->xc, yc = st->yc, th = st->th, ux = st->ux, uy = st->uy, om = st->om;
-    const int64_t step = st->step;
-    const double cth = cos(th), sth = sin(th);
-    int flags = 0;
 
-    // ---- the box: every node a marker or probe support reaches this step --------------
-    int r[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
-    accumulate_bounds<T, MPT>(a, xc, yc, cth, sth, r);
-    {
-        const int op[4] = {2, 2, 2, 2};
-        block_int<4>(r, op, shi);
-    }
-    const int x0 = r[0], y0 = r[2];
-    const int w = (r[0] != 0x7fffffff) ? -r[1] - r[0] + 1 : 0;
-    const int h = (r[2] != 0x7fffffff) ? -r[3] - r[2] + 1 : 0;
-    const bool box_ok = w > 0 && h > 0 && w <= a.nx && (int64_t)w * h <= cap;
-    if (!box_ok && tid == 0) flags |= FLAG_TILE;
-
-    // ---- the box nodes some support reaches this step, then their node fields ----------
-    const int nbox = box_ok ? w * h : 0;
-    for (int k = tid; k < (nbox + 31) / 32; k += PB) mask[k] = 0u;
-    __syncthreads();
-    if (box_ok) mark_supports<T, MPT>(a, xc, yc, cth, sth, x0, y0, w, h, mask);
-    __syncthreads();
-    fill_marked<T, LDS>(a, B, mask, nbox, x0, y0, w, queue);
+    fill_marked<T, MODE == 2>(a, B, mask, pre, nbox, x0, y0, w, queue, ov, nov);
     __syncthreads();
 
     // ---- markers: MLS interpolation and direct forcing ----------------------------------
-    double X[MPT], Y[MPT], NX[MPT], NY[MPT], PX[MPT], PY[MPT], S[MPT], SFx[MPT], SFy[MPT], PH[MPT][9];
-    int I0[MPT], J0[MPT], NXS[MPT], NYS[MPT];
+    double S[MPT], SFx[MPT], SFy[MPT], PH[MPT][9];
+    int I0[MPT], J0[MPT], NXS[MPT], NYS[MPT], SR[MPT][3];
     bool OK[MPT], LIG[MPT], BND[MPT];
     double maxsf = 0.0;
 #pragma unroll
     for (int k = 0; k < MPT; ++k) {
         const int l = tid + k * PB;
-        OK[k] = false;
-        NXS[k] = NYS[k] = 0;
-        SFx[k] = SFy[k] = 0.0;
+        OK[k] = LIG[k] = BND[k] = false;
+        NXS[k] = NYS[k] = I0[k] = J0[k] = 0;
+        S[k] = SFx[k] = SFy[k] = 0.0;
         if (l < nl) {
-            const MarkerGeo g = marker_geo(a.xi, a.nuv, l, xc, yc, cth, sth, a.ny);
-            X[k] = g.X;
-            Y[k] = g.Y;
-            NX[k] = g.nx;
-            NY[k] = g.ny;
-            PX[k] = g.px;
-            PY[k] = g.py;
             S[k] = a.S[l];
             LIG[k] = a.ligand[l] != 0;
             BND[k] = a.bond[l] != 0;
             Mls m;
-            const bool ok = MODE != 2 && box_ok && mls_shape(g.X, fluid_row(g.Y, a.ny), a.ny, m, false);
+            const bool ok = MODE != 2 && box_ok && mls_shape(c.G.X[k], fluid_row(c.G.Y[k], a.ny), a.ny, m, false);
             if (ok) {
                 double rl = 0.0, usx = 0.0, usy = 0.0;
 #pragma unroll
-                for (int bb = 0; bb < 3; ++bb)
+                for (int bb = 0; bb < 3; ++bb) {
+                    // the window row is marked whole, so its nodes hold consecutive slots
+                    SR[k][bb] = bb < m.nys ? node_slot(mask, pre, (m.j0 + bb - y0) * w + (m.i0 - x0)) : 0;
 #pragma unroll
                     for (int cc = 0; cc < 3; ++cc) {
                         const double p = m.phi[3 * bb + cc];
                         PH[k][3 * bb + cc] = p;
                         if (bb < m.nys && cc < m.nxs) {
-                            const int n = (m.j0 + bb - y0) * w + (m.i0 + cc - x0);
-                            rl += p * B.rho[n];
-                            usx += p * B.ux[n];
-                            usy += p * B.uy[n];
+                            const int s = SR[k][bb] + cc;
+                            rl += p * B.rho[s];
+                            usx += p * B.ux[s];
+                            usy += p * B.uy[s];
                         }
                     }
-                const double rx = g.X - xc, ry = g.Y - yc;
+                }
+                const double rx = c.G.X[k] - xc, ry = c.G.Y[k] - yc;
                 OK[k] = true;
                 SFx[k] = S[k] * (2.0 * rl * (ux - om * ry - usx));
                 SFy[k] = S[k] * (2.0 * rl * (uy + om * rx - usy));
@@ -495,27 +611,28 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, double*
                     for (int cc = 0; cc < 3; ++cc) {
                         if (bb >= NYS[k] || cc >= NXS[k]) continue;
                         const double p = PH[k][3 * bb + cc];
-                        const int n = (J0[k] + bb - y0) * w + (I0[k] + cc - x0);
-                        force_add<LDS>(B.fx + n, (int64_t)llrint(ldexp(p * SFx[k], scale)));
-                        force_add<LDS>(B.fy + n, (int64_t)llrint(ldexp(p * SFy[k], scale)));
+                        const int s = SR[k][bb] + cc;
+                        force_add<LDS>(B.fx + s, (int64_t)llrint(ldexp(p * SFx[k], scale)));
+                        force_add<LDS>(B.fy + s, (int64_t)llrint(ldexp(p * SFy[k], scale)));
                     }
             }
         }
         __syncthreads();
         if (spread_ok) {
+            // the box's tile for the sweep (and the other particles' probes): zero where no
+            // marker support reaches
             for (int k = tid; k < nbox; k += PB) {
-                unsigned long long qx = 0, qy = 0;  // no support reaches an unmarked node
-                if ((mask[k >> 5] >> (k & 31)) & 1u) {
-                    if (LDS) {
-                        qx = B.fx[k];
-                        qy = B.fy[k];
-                    } else {
-                        qx = __hip_atomic_load(B.fx + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        qy = __hip_atomic_load(B.fy + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    }
+                const uint32_t mw = mask[k >> 5];
+                unsigned long long qx = 0, qy = 0;
+                if ((mw >> (k & 31)) & 1u) {
+                    const int s = pre[k >> 5] + __popc(mw & ((1u << (k & 31)) - 1u));
+                    qx = force_load<LDS>(B.fx + s);
+                    qy = force_load<LDS>(B.fy + s);
                 }
-                a.tile[2 * k] = (int64_t)qx;
-                a.tile[2 * k + 1] = (int64_t)qy;
+                longlong2 t;
+                t.x = (long long)qx;
+                t.y = (long long)qy;
+                *(longlong2*)(a.tile + 2 * (size_t)k) = t;
             }
         }
         if (tid == 0) {
@@ -559,52 +676,48 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, double*
         PRB[k] = false;
         if (l < nl) {
             Mls m;
-            const bool ok = box_ok && mls_shape(PX[k], PY[k], a.ny, m, true);
+            const bool ok = box_ok && mls_shape(c.G.PX[k], c.G.PY[k], a.ny, m, true);
             if (ok) {
                 double rp = 0.0, gxx = 0.0, gxy = 0.0, gyx = 0.0, gyy = 0.0;
 #pragma unroll
-                for (int bb = 0; bb < 3; ++bb)
+                for (int bb = 0; bb < 3; ++bb) {
+                    const int sr = bb < m.nys ? node_slot(mask, pre, (m.j0 + bb - y0) * w + (m.i0 - x0)) : 0;
 #pragma unroll
                     for (int cc = 0; cc < 3; ++cc) {
                         if (bb < m.nys && cc < m.nxs) {
                             const int e = 3 * bb + cc;
-                            const int n = (m.j0 + bb - y0) * w + (m.i0 + cc - x0);
-                            double vx = B.ux[n], vy = B.uy[n];
+                            const int s = sr + cc;
+                            double vx = B.ux[s], vy = B.uy[s];
                             if (MODE == 2) {
-                                double fx, fy;
-                                multi_force(a, wrap(m.i0 + cc, a.nx), m.j0 + bb, fx, fy);
-                                const double hinv = 0.5 * B.inv[n];
+                                const double fx = __longlong_as_double((long long)B.fx[s]);
+                                const double fy = __longlong_as_double((long long)B.fy[s]);
+                                const double hinv = 0.5 * B.inv[s];
                                 vx += fx * hinv;
                                 vy += fy * hinv;
                             } else if (spread_ok) {
-                                unsigned long long qx, qy;
-                                if (LDS) {
-                                    qx = B.fx[n];
-                                    qy = B.fy[n];
-                                } else {
-                                    qx = __hip_atomic_load(B.fx + n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                                    qy = __hip_atomic_load(B.fy + n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                                }
-                                const double hinv = 0.5 * B.inv[n];
+                                const unsigned long long qx = force_load<LDS>(B.fx + s);
+                                const unsigned long long qy = force_load<LDS>(B.fy + s);
+                                const double hinv = 0.5 * B.inv[s];
                                 vx += ldexp((double)(int64_t)qx, -scale) * hinv;
                                 vy += ldexp((double)(int64_t)qy, -scale) * hinv;
                             }
-                            rp += m.phi[e] * B.rho[n];
+                            rp += m.phi[e] * B.rho[s];
                             gxx += m.psx[e] * vx;
                             gxy += m.psy[e] * vx;
                             gyx += m.psx[e] * vy;
                             gyy += m.psy[e] * vy;
                         }
                     }
+                }
                 const double p = (rp - 1.0) * (1.0 / 3.0);
                 const double sxx = rp * a.nu * (2.0 * gxx), syy = rp * a.nu * (2.0 * gyy);
                 const double sxy = rp * a.nu * (gxy + gyx);
-                TX[k] = (-p * NX[k] + sxx * NX[k] + sxy * NY[k]) * S[k];
-                TY[k] = (-p * NY[k] + sxy * NX[k] + syy * NY[k]) * S[k];
+                TX[k] = (-p * c.G.NX[k] + sxx * c.G.NX[k] + sxy * c.G.NY[k]) * S[k];
+                TY[k] = (-p * c.G.NY[k] + sxy * c.G.NX[k] + syy * c.G.NY[k]) * S[k];
             } else if (box_ok) {
                 flags |= FLAG_MLS;
             }
-            D[k] = Y[k] + 0.5;
+            D[k] = c.G.Y[k] + 0.5;
             PRB[k] = LIG[k] && D[k] < a.y_cr;
             nprobe += PRB[k] ? 1 : 0;
         }
@@ -626,7 +739,7 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, double*
     for (int k = 0; k < MPT; ++k) {
         const int l = tid + k * PB;
         if (l < nl) {
-            const double rx = X[k] - xc, ry = Y[k] - yc;
+            const double rx = c.G.X[k] - xc, ry = c.G.Y[k] - yc;
             const uint8_t b = bond_update(LIG[k], BND[k], D[k], Tf, bp, a.seed, step, (uint32_t)l, a.pid);
             a.bond[l] = b;
             acc[0] += TX[k];
@@ -634,7 +747,7 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, double*
             acc[2] += rx * TY[k] - ry * TX[k];
             if (b) {
                 const double mag = a.sigma * (D[k] - a.y_eq);
-                const double fx = mag * NX[k], fy = mag * NY[k];
+                const double fx = mag * c.G.NX[k], fy = mag * c.G.NY[k];
                 acc[3] += fx;
                 acc[4] += fy;
                 acc[5] += rx * fy - ry * fx;
@@ -650,7 +763,6 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, double*
         nb = v[0];
         flags = v[1];
     }
-
     // ---- wall force (eq 12), totals and the rigid-body update (eq 13-16) --------------
     if (tid == 0) {
         const double hx = acc[0], hy = acc[1], hm = acc[2], bx_ = acc[3], by_ = acc[4], bm = acc[5];
@@ -716,8 +828,10 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, double*
     // the next particle phase does) -------------------------------------------------------
     if (MODE == 0) {
         const double nxc = shd[0][0], nyc = shd[1][0], nth = shd[2][0];
+        MarkerSet<MPT> Gn;
+        marker_set<T, MPT>(a, nxc, nyc, cos(nth), sin(nth), Gn);
         int rn[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
-        accumulate_bounds<T, MPT>(a, nxc, nyc, cos(nth), sin(nth), rn);
+        set_bounds<MPT>(Gn, a.ny, rn);
         const int op[4] = {2, 2, 2, 2};
         block_int<4>(rn, op, shi);
         if (tid == 0) {
@@ -729,7 +843,7 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, double*
             z.w = nw;
             z.h = nh;
             z.scale = 0;
-            z.active = (nw > 0 && nh > 0 && nw <= a.nx && (int64_t)nw * nh <= cap) ? 1 : 0;
+            z.active = (nw > 0 && nh > 0 && nw <= a.nx && (int64_t)nw * nh <= a.box_cap) ? 1 : 0;
             z.i0u = rn[0] != 0x7fffffff ? rn[0] : 0;
             z.pad = 0;
             a.zone[a.parity_out] = z;
@@ -737,11 +851,102 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, double*
     }
 }
 
-template <typename T, int MPT, bool LDS>
-__global__ __launch_bounds__(PB) void particle_kernel(ParticleArgs<T> a)
+// One particle's phase, run by one workgroup.  MPT markers per thread (nl <= MPT * PB);
+// lds: the dynamic LDS of lds_bytes bytes.
+// MODE 0: the whole phase of a simulation's only particle.  With several particles the
+// phase is split in two launches so that every probe sees the spread force of every
+// particle: MODE 1 stages the marker supports, spreads the marker forces into the
+// particle's tile and marks the step's tile mask; MODE 2 stages the probe supports with the
+// total spread force there and evaluates the probe loads, the bonds, the wall force and the
+// rigid-body update.
+template <typename T, int MPT, int MODE>
+__device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, char* lds, uint32_t lds_bytes)
 {
-    extern __shared__ double lds_box[];
-    particle_phase<T, MPT, LDS>(a, lds_box);
+    __shared__ double shd[8][NW];
+    __shared__ int shi[8][NW];
+    const int tid = threadIdx.x;
+    OvEntry* ov = (OvEntry*)lds;
+    int* queue = (int*)(lds + sizeof(OvEntry) * kMaxParticles) + (tid >> 6) * kQueue;
+    const int wcap = (a.box_cap + 31) / 32;
+    uint32_t* mask = (uint32_t*)(lds + kLdsHead);
+    int* pre = (int*)(mask + wcap);
+    double* fields = (double*)(pre + wcap);  // 8-byte aligned: kLdsHead and 8 wcap are multiples of 8
+    const size_t aux = kLdsHead + (size_t)wcap * 8;
+    const int lds_slots = lds_bytes > aux ? (int)((lds_bytes - aux) / (kFields * 8)) : 0;
+
+    PhaseCtx<MPT> c;
+    const DevParticle* st = a.st;
+    c.xc = st->xc;
+    c.yc = st->yc;
+    c.th = st->th;
+    c.ux = st->ux;
+    c.uy = st->uy;
+    c.om = st->om;
+    c.step = st->step;
+    c.cth = cos(c.th);
+    c.sth = sin(c.th);
+    c.flags = 0;
+    marker_set<T, MPT>(a, c.xc, c.yc, c.cth, c.sth, c.G);
+
+    // ---- the box: every node a marker or probe support reaches this step --------------
+    int r[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
+    set_bounds<MPT>(c.G, a.ny, r);
+    {
+        const int op[4] = {2, 2, 2, 2};
+        block_int<4>(r, op, shi);
+    }
+    c.x0 = r[0];
+    c.y0 = r[2];
+    c.w = (r[0] != 0x7fffffff) ? -r[1] - r[0] + 1 : 0;
+    c.h = (r[2] != 0x7fffffff) ? -r[3] - r[2] + 1 : 0;
+    c.box_ok = c.w > 0 && c.h > 0 && c.w <= a.nx && (int64_t)c.w * c.h <= a.box_cap;
+    if (!c.box_ok && tid == 0) c.flags |= FLAG_TILE;
+
+    // ---- the nodes this launch's supports reach, and their slots ------------------------
+    c.nbox = c.box_ok ? c.w * c.h : 0;
+    const int nw = (c.nbox + 31) / 32;
+    for (int k = tid; k < nw; k += PB) mask[k] = 0u;
+    __syncthreads();
+    if (c.box_ok) mark_windows<MPT>(c.G, a.ny, MODE == 0 ? 3 : MODE == 1 ? 1 : 2, c.x0, c.y0, c.w, c.h, mask);
+    __syncthreads();
+    c.nmarked = mask_prefix(mask, pre, nw, shi);
+    c.mask = mask;
+    c.pre = pre;
+    const int nov = MODE == 2 ? overlap_list(a, c.x0, c.y0, c.w, c.h, ov, shi) : 0;
+
+    NodeView B;
+    if (c.nmarked <= lds_slots || !a.box_global) {
+        if (c.nmarked > lds_slots) {  // no scratch to hold the fields (a launch with too little LDS)
+            c.box_ok = false;
+            c.nbox = 0;
+            if (tid == 0) c.flags |= FLAG_TILE;
+        }
+        const int m = c.box_ok ? c.nmarked : 0;
+        B.rho = fields;
+        B.ux = fields + m;
+        B.uy = fields + 2 * m;
+        B.inv = fields + 3 * m;
+        B.fx = (unsigned long long*)(fields + 4 * m);
+        B.fy = (unsigned long long*)(fields + 5 * m);
+        phase_body<T, MPT, true, MODE>(a, c, B, queue, ov, nov, shd, shi);
+    } else {
+        double* g = a.box_global;
+        const int m = c.nmarked;
+        B.rho = g;
+        B.ux = g + m;
+        B.uy = g + 2 * m;
+        B.inv = g + 3 * m;
+        B.fx = (unsigned long long*)(g + 4 * m);
+        B.fy = (unsigned long long*)(g + 5 * m);
+        phase_body<T, MPT, false, MODE>(a, c, B, queue, ov, nov, shd, shi);
+    }
+}
+
+template <typename T, int MPT>
+__global__ __launch_bounds__(PB) void particle_kernel(ParticleArgs<T> a, uint32_t lds_bytes)
+{
+    extern __shared__ double lds_dyn[];
+    particle_phase<T, MPT, 0>(a, (char*)lds_dyn, lds_bytes);
 }
 
 // Split particle phase of a simulation with several particles: workgroup b runs particle b
@@ -750,44 +955,46 @@ __global__ __launch_bounds__(PB) void particle_kernel(ParticleArgs<T> a)
 template <typename T, int MPT, int MODE>
 __global__ __launch_bounds__(PB) void split_particle_kernel(const ParticleArgs<T>* __restrict__ args,
                                                             const T* __restrict__ f,
-                                                            unsigned long long* __restrict__ pmask, int32_t lds_cap)
+                                                            unsigned long long* __restrict__ pmask, uint32_t lds_bytes)
 {
-    extern __shared__ double lds_box[];
+    extern __shared__ double lds_dyn[];
     ParticleArgs<T> a = args[blockIdx.x];
     a.f = f;
     a.pmask = pmask;
-    if (a.box_cap <= lds_cap)
-        particle_phase<T, MPT, true, MODE>(a, lds_box);
-    else
-        particle_phase<T, MPT, false, MODE>(a, lds_box);
+    particle_phase<T, MPT, MODE>(a, (char*)lds_dyn, lds_bytes);
+}
+
+template <typename K>
+hipError_t allow_max_lds(K kernel, bool& done)
+{
+    if (done) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+    if (e == hipSuccess) done = true;
+    return e;
 }
 
 template <typename T, int MPT, int MODE>
-hipError_t launch_split_mode(const ParticleArgs<T>* args, int32_t n, const T* f, unsigned long long* pmask,
-                             int32_t lds_cap, size_t lds, hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
+hipError_t launch_split_mode(const ParticleArgs<T>* args, int32_t n, const T* f, unsigned long long* pmask, size_t lds,
+                             hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
 {
     static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)split_particle_kernel<T, MPT, MODE>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 158 * 1024);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    hipError_t e = allow_max_lds(split_particle_kernel<T, MPT, MODE>, attr);
+    if (e != hipSuccess) return e;
     hipExtLaunchKernelGGL(split_particle_kernel<T, MPT, MODE>, dim3(n), dim3(PB), (uint32_t)lds, stream, t0, t1, 0u,
-                          args, f, pmask, lds_cap);
+                          args, f, pmask, (uint32_t)lds);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_particle_split(const ParticleArgs<T>* args, int32_t n, const T* f, unsigned long long* pmask,
-                                 int32_t mode, int32_t max_nl, int32_t lds_cap, size_t lds, hipStream_t stream,
-                                 hipEvent_t t0, hipEvent_t t1)
+                                 int32_t mode, int32_t max_nl, size_t lds, hipStream_t stream, hipEvent_t t0,
+                                 hipEvent_t t1)
 {
     if (n <= 0) return hipSuccess;
-    if (lds > 158 * 1024 || (mode != 1 && mode != 2)) return hipErrorInvalidValue;
-#define LBIB_SPLIT(M)                                                                                    \
-    return mode == 1 ? launch_split_mode<T, M, 1>(args, n, f, pmask, lds_cap, lds, stream, t0, t1)      \
-                     : launch_split_mode<T, M, 2>(args, n, f, pmask, lds_cap, lds, stream, t0, t1)
+    if (n > kMaxParticles || lds > kLdsMax || lds < kLdsHead || (mode != 1 && mode != 2)) return hipErrorInvalidValue;
+#define LBIB_SPLIT(M)                                                                                \
+    return mode == 1 ? launch_split_mode<T, M, 1>(args, n, f, pmask, lds, stream, t0, t1)           \
+                     : launch_split_mode<T, M, 2>(args, n, f, pmask, lds, stream, t0, t1)
     if (max_nl <= PB) LBIB_SPLIT(1);
     if (max_nl <= 2 * PB) LBIB_SPLIT(2);
     if (max_nl <= 4 * PB) LBIB_SPLIT(4);
@@ -800,14 +1007,13 @@ hipError_t launch_particle_split(const ParticleArgs<T>* args, int32_t n, const T
 // has raised a flag, does nothing (ctl[k].pad = -1: its sweep does nothing either), so a
 // failed member stays frozen at the step that failed.  Otherwise ctl[k] receives the box
 // descriptor of step n with pad = the parity of n: the populations of step n are in f for
-// even n and in fB for odd n.  Boxes up to lds_cap nodes are staged in LDS, larger ones in
-// their global scratch.
+// even n and in fB for odd n.
 template <typename T, int MPT>
 __global__ __launch_bounds__(PB) void pool_particle_kernel(const ParticleArgs<T>* __restrict__ args,
                                                            const int32_t* __restrict__ active,
-                                                           TileDesc* __restrict__ ctl, int32_t lds_cap)
+                                                           TileDesc* __restrict__ ctl, uint32_t lds_bytes)
 {
-    extern __shared__ double lds_box[];
+    extern __shared__ double lds_dyn[];
     const int k = active[blockIdx.x];
     ParticleArgs<T> a = args[k];
     const int64_t n = a.st->step;
@@ -816,10 +1022,7 @@ __global__ __launch_bounds__(PB) void pool_particle_kernel(const ParticleArgs<T>
         return;
     }
     a.f = (n & 1) ? a.fB : a.f;
-    if (a.box_cap <= lds_cap)
-        particle_phase<T, MPT, true>(a, lds_box);
-    else
-        particle_phase<T, MPT, false>(a, lds_box);
+    particle_phase<T, MPT, 0>(a, (char*)lds_dyn, lds_bytes);
     if (threadIdx.x == 0) {  // the thread that wrote *a.desc in the particle phase
         TileDesc d = *a.desc;
         d.pad = (int32_t)(n & 1);
@@ -827,63 +1030,44 @@ __global__ __launch_bounds__(PB) void pool_particle_kernel(const ParticleArgs<T>
     }
 }
 
+template <typename T, int MPT>
+hipError_t launch_pool_mpt(const ParticleArgs<T>* args, const int32_t* active, TileDesc* ctl, int32_t n_active,
+                           size_t lds, hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
+{
+    static bool attr = false;
+    hipError_t e = allow_max_lds(pool_particle_kernel<T, MPT>, attr);
+    if (e != hipSuccess) return e;
+    if (t0 || t1)
+        hipExtLaunchKernelGGL((pool_particle_kernel<T, MPT>), dim3(n_active), dim3(PB), (uint32_t)lds, stream, t0, t1,
+                              0u, args, active, ctl, (uint32_t)lds);
+    else
+        hipLaunchKernelGGL((pool_particle_kernel<T, MPT>), dim3(n_active), dim3(PB), lds, stream, args, active, ctl,
+                           (uint32_t)lds);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_pool_particle(const ParticleArgs<T>* args, const int32_t* active, TileDesc* ctl, int32_t n_active,
-                                int32_t max_nl, int32_t lds_cap, size_t lds, hipStream_t stream, hipEvent_t t0,
-                                hipEvent_t t1)
+                                int32_t max_nl, size_t lds, hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
 {
     if (n_active <= 0) return hipSuccess;
-    if (lds > 158 * 1024) return hipErrorInvalidValue;
-    static bool attr[3] = {false, false, false};
-#define LBIB_POOL_LAUNCH(M, IDX)                                                                                      \
-    do {                                                                                                               \
-        if (!attr[IDX]) {                                                                                              \
-            hipError_t e = hipFuncSetAttribute((const void*)pool_particle_kernel<T, M>,                                \
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, 158 * 1024);                \
-            if (e != hipSuccess) return e;                                                                             \
-            attr[IDX] = true;                                                                                          \
-        }                                                                                                              \
-        if (t0 || t1)                                                                                                  \
-            hipExtLaunchKernelGGL((pool_particle_kernel<T, M>), dim3(n_active), dim3(PB), (uint32_t)lds, stream, t0, t1, \
-                                  0u, args, active, ctl, lds_cap);                                                     \
-        else                                                                                                           \
-            hipLaunchKernelGGL((pool_particle_kernel<T, M>), dim3(n_active), dim3(PB), lds, stream, args, active, ctl,   \
-                               lds_cap);                                                                               \
-    } while (0)
-    if (max_nl <= PB)
-        LBIB_POOL_LAUNCH(1, 0);
-    else if (max_nl <= 2 * PB)
-        LBIB_POOL_LAUNCH(2, 1);
-    else if (max_nl <= 4 * PB)
-        LBIB_POOL_LAUNCH(4, 2);
-    else
-        return hipErrorInvalidValue;
-#undef LBIB_POOL_LAUNCH
-    return hipGetLastError();
+    if (lds > kLdsMax || lds < kLdsHead) return hipErrorInvalidValue;
+    if (max_nl <= PB) return launch_pool_mpt<T, 1>(args, active, ctl, n_active, lds, stream, t0, t1);
+    if (max_nl <= 2 * PB) return launch_pool_mpt<T, 2>(args, active, ctl, n_active, lds, stream, t0, t1);
+    if (max_nl <= 4 * PB) return launch_pool_mpt<T, 4>(args, active, ctl, n_active, lds, stream, t0, t1);
+    return hipErrorInvalidValue;
 }
 
 template <typename T, int MPT>
 hipError_t launch_particle_mpt(const ParticleArgs<T>& a, hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
 {
-    static bool attr_set = false;  // once per instantiation, for the largest LDS request allowed
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)particle_kernel<T, MPT, true>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 158 * 1024);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)particle_kernel<T, MPT, false>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, 158 * 1024);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
-    const size_t lds = particle_lds_bytes(a.box_cap);
-    if (lds) {
-        hipExtLaunchKernelGGL(particle_kernel<T, MPT, true>, dim3(1), dim3(PB), (uint32_t)lds, stream, t0, t1, 0u, a);
-    } else {
-        const size_t aux = particle_lds_aux_bytes(a.box_cap);
-        if (aux > 158 * 1024) return hipErrorInvalidValue;
-        hipExtLaunchKernelGGL(particle_kernel<T, MPT, false>, dim3(1), dim3(PB), (uint32_t)aux, stream, t0, t1, 0u,
-                              a);
-    }
+    static bool attr = false;
+    hipError_t e = allow_max_lds(particle_kernel<T, MPT>, attr);
+    if (e != hipSuccess) return e;
+    const size_t lds = particle_launch_lds(a.box_cap);
+    if (particle_lds_aux_bytes(a.box_cap) > lds) return hipErrorInvalidValue;
+    hipExtLaunchKernelGGL(particle_kernel<T, MPT>, dim3(1), dim3(PB), (uint32_t)lds, stream, t0, t1, 0u, a,
+                          (uint32_t)lds);
     return hipGetLastError();
 }
 
@@ -1021,11 +1205,10 @@ hipError_t launch_copy(const float4* src, float4* dst, int64_t n, hipStream_t st
 
 #define LBIB_PARTICLE_INSTANTIATE(T)                                                                        \
     template hipError_t launch_pool_particle<T>(const ParticleArgs<T>*, const int32_t*, TileDesc*, int32_t,      \
-                                                int32_t, int32_t, size_t, hipStream_t, hipEvent_t, hipEvent_t); \
+                                                int32_t, size_t, hipStream_t, hipEvent_t, hipEvent_t);          \
     template hipError_t launch_particle<T>(const ParticleArgs<T>&, hipStream_t, hipEvent_t, hipEvent_t);        \
     template hipError_t launch_particle_split<T>(const ParticleArgs<T>*, int32_t, const T*, unsigned long long*, \
-                                                 int32_t, int32_t, int32_t, size_t, hipStream_t, hipEvent_t,     \
-                                                 hipEvent_t);
+                                                 int32_t, int32_t, size_t, hipStream_t, hipEvent_t, hipEvent_t);
 LBIB_PARTICLE_INSTANTIATE(double)
 LBIB_PARTICLE_INSTANTIATE(float)
 LBIB_PARTICLE_INSTANTIATE(half_t)

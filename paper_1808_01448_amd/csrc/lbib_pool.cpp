@@ -139,7 +139,7 @@ struct lbib_pool {
     size_t table_cap = 0;
     TileDesc* d_ctl = nullptr;  // per running member: its box of the step and the step parity
     size_t ctl_cap = 0;
-    int32_t n_active = 0, n_blocks = 0, max_nl = 0, lds_cap = 0;
+    int32_t n_active = 0, n_blocks = 0, max_nl = 0;
     size_t lds_bytes = 0;
     PoolSweepConfig cfg{256, 4};
     // optional replay of graph_steps steps as one HIP graph (rebuilt with the tables)
@@ -211,7 +211,7 @@ lbib_status rebuild(lbib_pool* h)
     std::vector<int32_t> active(run.size());
     std::vector<PoolSweep<T>> sims(run.size());
     std::vector<int2> table;
-    int32_t max_nl = 0, lds_cap = 0;
+    int32_t max_nl = 0;
     size_t lds_bytes = 0;
     for (size_t k = 0; k < run.size(); ++k) {
         Member& m = *run[k];
@@ -225,12 +225,7 @@ lbib_status rebuild(lbib_pool* h)
         a.parity_out = 1;
         active[k] = (int32_t)k;
         max_nl = std::max(max_nl, m.p.nl);
-        if (particle_lds_bytes(m.p.box_cap)) {
-            lds_cap = std::max(lds_cap, m.p.box_cap);
-            lds_bytes = std::max(lds_bytes, particle_lds_bytes(m.p.box_cap));
-        } else {
-            lds_bytes = std::max(lds_bytes, particle_lds_aux_bytes(m.p.box_cap));
-        }
+        lds_bytes = std::max(lds_bytes, particle_launch_lds(m.p.box_cap));
         PoolSweep<T>& s = sims[k];
         s = PoolSweep<T>{};
         s.a.nx = m.g.nx;
@@ -273,7 +268,6 @@ lbib_status rebuild(lbib_pool* h)
     h->n_active = (int32_t)run.size();
     h->n_blocks = (int32_t)table.size();
     h->max_nl = max_nl;
-    h->lds_cap = lds_cap;
     h->lds_bytes = lds_bytes;
     h->dirty = false;
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
@@ -300,7 +294,7 @@ template <typename T>
 hipError_t launch_step(lbib_pool* h, EvPair e1, EvPair e0)
 {
     hipError_t e = launch_pool_particle<T>((const ParticleArgs<T>*)h->d_args, h->d_active, h->d_ctl, h->n_active,
-                                           h->max_nl, h->lds_cap, h->lds_bytes, h->stream, e1.t0, e1.t1);
+                                           h->max_nl, h->lds_bytes, h->stream, e1.t0, e1.t1);
     if (e != hipSuccess) return e;
     return launch_pool_sweep<T>((const PoolSweep<T>*)h->d_sims, h->d_ctl, h->d_table, h->n_blocks, h->cfg, h->stream,
                                 e0.t0, e0.t1);

@@ -60,7 +60,7 @@ struct lbib_sim {
     void* d_args = nullptr;
     std::vector<unsigned char> h_args;  // host copy of the arguments (kept for the async upload)
     bool args_dirty = true;
-    int32_t max_nl = 0, lds_cap = 0;
+    int32_t max_nl = 0;
     size_t lds_bytes = 0;
 };
 
@@ -119,6 +119,7 @@ ParticleArgs<T> particle_args(lbib_sim* h, Particle& p)
     a.pid = (uint32_t)(&p - h->parts.data());  // the particle's index keys its bond draws
     a.refs = h->d_refs;
     a.mtx = h->mtx;
+    a.nparts = (int32_t)h->parts.size();
     return a;
 }
 
@@ -198,10 +199,10 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
             const int32_t np = (int32_t)h->parts.size();
             const ParticleArgs<T>* args = (const ParticleArgs<T>*)h->d_args;
             const EvPair e1 = timing_events(h, 1);
-            HIPCHK(h, launch_particle_split<T>(args, np, fin, mcur, 1, h->max_nl, h->lds_cap, h->lds_bytes, h->stream,
+            HIPCHK(h, launch_particle_split<T>(args, np, fin, mcur, 1, h->max_nl, h->lds_bytes, h->stream,
                                                e1.t0, e1.t1));
             const EvPair e2 = timing_events(h, 2);
-            HIPCHK(h, launch_particle_split<T>(args, np, fin, mcur, 2, h->max_nl, h->lds_cap, h->lds_bytes, h->stream,
+            HIPCHK(h, launch_particle_split<T>(args, np, fin, mcur, 2, h->max_nl, h->lds_bytes, h->stream,
                                                e2.t0, e2.t1));
             const EvPair e0 = timing_events(h, 0);
             HIPCHK(h, launch_sweep_multi<T>(fin, fout, sa, mcur, mnext, h->d_refs, h->g.pull, h->stream, e0.t0, e0.t1));
@@ -436,12 +437,7 @@ lbib_status lbib_init(lbib_handle h)
             refs[k] = PartRef{h->parts[k].d_desc, h->parts[k].d_tile};
             const Particle& p = h->parts[k];
             h->max_nl = std::max(h->max_nl, p.nl);
-            if (particle_lds_bytes(p.box_cap)) {
-                h->lds_cap = std::max(h->lds_cap, p.box_cap);
-                h->lds_bytes = std::max(h->lds_bytes, particle_lds_bytes(p.box_cap));
-            } else {
-                h->lds_bytes = std::max(h->lds_bytes, particle_lds_aux_bytes(p.box_cap));
-            }
+            h->lds_bytes = std::max(h->lds_bytes, particle_launch_lds(p.box_cap));
         }
         const size_t args_bytes = np * std::max(sizeof(ParticleArgs<double>), sizeof(ParticleArgs<float>));
         if ((e = dalloc(&h->d_masks, (size_t)(2 * h->ntiles))) != hipSuccess ||
