@@ -232,7 +232,10 @@ lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size);
  * particle that reaches a probe node, summed in particle order), bonds and rigid-body update
  * -- and the sweep adds at each node the force of every particle whose box reaches it, in
  * particle order.  For a single particle it gives the same results as modes 0-2.  Kernel
- * timing then reports the first launch as kernel 1 and the second as kernel 2. */
+ * timing then reports the first launch as kernel 1 and the second as kernel 2.  A simulation
+ * with several particles runs the two launches and the sweep in that order on its stream,
+ * except in mode 1, where the second launch runs on a second stream beside the sweep (same
+ * results; two cross-stream waits per step). */
 lbib_status lbib_set_overlap(lbib_handle h, int32_t mode);
 
 /* Storage layout of the population buffers, chosen before lbib_init: mode 0 push (the

@@ -193,10 +193,10 @@ lbib_status prepare_particle(const lbib_lattice_desc& lat, const lbib_particle_d
 size_t particle_block_bytes(const Particle& p)
 {
     const size_t nl = (size_t)p.nl, cap = (size_t)p.box_cap;
-    const bool global_box = !particle_lds_bytes(p.box_cap);
+    const size_t scratch = particle_scratch_bytes(p.box_cap);
     return 2 * align_up(2 * nl * 8) + align_up(nl * 8) + 2 * align_up(nl) + align_up(2 * cap * 8) +
-           (global_box ? align_up(6 * cap * 8) : 0) + align_up(sizeof(TileDesc)) + align_up(2 * sizeof(TileDesc)) +
-           align_up(sizeof(DevParticle));
+           align_up((cap + 31) / 32 * 8) + (scratch ? align_up(scratch) : 0) + align_up(sizeof(TileDesc)) +
+           align_up(2 * sizeof(TileDesc)) + align_up(sizeof(DevParticle));
 }
 
 void carve_particle(Particle& p, char* block)
@@ -214,7 +214,9 @@ void carve_particle(Particle& p, char* block)
     p.d_lig = (uint8_t*)take(nl);
     p.d_bond = (uint8_t*)take(nl);
     p.d_tile = (int64_t*)take(2 * cap * 8);
-    p.d_box = particle_lds_bytes(p.box_cap) ? nullptr : (double*)take(6 * cap * 8);
+    p.d_ring = (uint2*)take((cap + 31) / 32 * 8);
+    const size_t scratch = particle_scratch_bytes(p.box_cap);
+    p.d_box = scratch ? (double*)take(scratch) : nullptr;
     p.d_desc = (TileDesc*)take(sizeof(TileDesc));
     p.d_zone = (TileDesc*)take(2 * sizeof(TileDesc));
     p.d_st = (DevParticle*)take(sizeof(DevParticle));
@@ -248,6 +250,7 @@ void free_particle(Particle& p)
     p.d_xi = p.d_nuv = p.d_S = nullptr;
     p.d_lig = p.d_bond = nullptr;
     p.d_tile = nullptr;
+    p.d_ring = nullptr;
     p.d_box = nullptr;
     p.d_desc = p.d_zone = nullptr;
     p.d_st = nullptr;
@@ -323,6 +326,7 @@ void fill_particle_args(ParticleArgs<T>& a, const LatticeGeom& g, uint64_t seed,
     a.seed = seed;
     a.pid = 0;
     a.tile = p.d_tile;
+    a.ring = p.d_ring;
     a.box_global = p.d_box;
     a.box_cap = p.box_cap;
     a.desc = p.d_desc;

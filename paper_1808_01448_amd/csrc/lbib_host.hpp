@@ -50,7 +50,8 @@ struct Particle {
     double *d_xi = nullptr, *d_nuv = nullptr, *d_S = nullptr;
     uint8_t *d_lig = nullptr, *d_bond = nullptr;
     int64_t* d_tile = nullptr;
-    double* d_box = nullptr;  // box node fields when they do not fit in LDS
+    uint2* d_ring = nullptr;  // split phase: per 32 box nodes, the mask word and the slots before it
+    double* d_box = nullptr;  // node fields and node map when they may not fit in LDS
     int box_cap = 0;
     TileDesc* d_desc = nullptr;
     TileDesc* d_zone = nullptr;  // two slots, by step parity

@@ -83,10 +83,14 @@ struct SweepArgs {
     double scale, inv_scale;  // stored value = (f - w) scale (a power of two; 1 but for FP16)
 };
 
-// Where the sweep and the probes of a multi-particle step find particle p's spread force.
+// Where the sweep and the probes of a multi-particle step find particle p's spread force:
+// the box node n = dj w + di carries a force when bit n % 32 of ring[n / 32].x is set; it is
+// then entry s = ring[n / 32].y + (set bits below n % 32) of the compact list tile[2 s],
+// tile[2 s + 1] (64-bit fixed point, value q 2^-scale).
 struct PartRef {
     const TileDesc* desc;
     const int64_t* tile;
+    const uint2* ring;
 };
 
 // Everything the particle phase needs; passed by value.
@@ -111,8 +115,10 @@ struct ParticleArgs {
     double sigma, sigma_star, y_cr, y_eq, k_f, k_r0, kBT, hamaker;
     uint64_t seed;
     uint32_t pid;
-    int64_t* tile;      // [box_cap][2] fixed-point spread force on the box (read by the sweep)
-    double* box_global;  // room for the node fields of box_cap nodes when they may not fit in LDS
+    int64_t* tile;      // [box_cap][2] fixed-point spread force on the box (read by the sweep); in
+                        // the split phase, the compact list of the nodes the marker supports reach
+    uint2* ring;        // split phase: the index of that list (PartRef)
+    double* box_global;  // node fields and node map of up to box_cap nodes when they may not fit in LDS
     int32_t box_cap;     // node capacity of the box
     TileDesc* desc;      // this step's box
     TileDesc* zone;      // zone[2]: boxes of future steps, slot = step parity
@@ -159,9 +165,11 @@ hipError_t launch_sweep(const T* fin, T* fout, const SweepArgs& a, int mode, con
 // reach, used when they do not fit in the LDS of the launch).  particle_launch_lds: the
 // dynamic LDS a launch gives the particle (the most a workgroup may take when the whole
 // box may not fit).
+// particle_scratch_bytes: the global scratch a particle needs (0 when its whole box fits).
 size_t particle_lds_bytes(int32_t box_cap);
 size_t particle_lds_aux_bytes(int32_t box_cap);
 size_t particle_launch_lds(int32_t box_cap);
+size_t particle_scratch_bytes(int32_t box_cap);
 template <typename T>
 hipError_t launch_particle(const ParticleArgs<T>& a, hipStream_t stream, hipEvent_t t0 = nullptr,
                            hipEvent_t t1 = nullptr);

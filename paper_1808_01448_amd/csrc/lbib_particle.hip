@@ -27,7 +27,7 @@ using namespace dev;
 // Workgroup reductions: butterfly within each 64-wide wavefront, then the per-wave partials
 // in wave order.  The order is fixed, so results are bit-reproducible.
 // ---------------------------------------------------------------------------------------
-constexpr int PB = 256;       // threads of the particle workgroup
+constexpr int PB = 512;       // threads of the particle workgroup
 constexpr int NW = PB / 64;   // wavefronts per workgroup
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -153,13 +153,13 @@ __device__ __forceinline__ MarkerGeo marker_geo(const double* xi, const double* 
 }
 
 // LDS of the particle phase (dynamic, lds_bytes bytes), in this order: the probe launch's
-// list of the particles whose boxes overlap this one (kMaxParticles entries), the per-wave
-// queues of the fill, mask[wcap] (one bit per box node, set where a support of this launch
-// reaches), pre[wcap] (the marked nodes before each mask word) and, when they fit, the node
-// fields of the marked nodes; otherwise those live in the global scratch box_global.
-// wcap = ceil(box_cap / 32).  A marked node's slot is its rank among the marked nodes in
-// row-major box order, so the fields take 48 bytes per node of the ring that the supports
-// cover next to the surface, not per node of the box.
+// list of the particles whose boxes overlap this one (kMaxParticles entries), mask[wcap]
+// (one bit per box node, set where a support of this launch reaches), pre[wcap] (the
+// marked nodes before each mask word) and, when they fit, the node fields and the node map
+// (slot -> box node) of the marked nodes; otherwise those live in the global scratch
+// box_global.  wcap = ceil(box_cap / 32).  A marked node's slot is its rank among the
+// marked nodes in row-major box order, so the fields take kSlotBytes per node of the ring
+// that the supports cover next to the surface, not per node of the box.
 struct NodeView {
     double *rho, *ux, *uy, *inv;    // density, u* (velocity with half the uniform drive and without
                                     // the spread force), 1/rho
@@ -168,18 +168,19 @@ struct NodeView {
 };
 
 // A particle whose box of this step overlaps the box of the particle running the probe
-// launch, with where its spread force lies.
+// launch, with where its spread force lies (PartRef).
 struct OvEntry {
     const int64_t* tile;
+    const uint2* ring;
     int32_t i0w, j0, w, h, scale, pad;
 };
 
 constexpr int kMaxParticles = 64;
-constexpr int kFields = 6;                // per marked node: 4 doubles + 2 64-bit integers
-constexpr int kFillU = 4;                 // marked nodes per lane in flight while filling
-constexpr int kQueue = 64 * kFillU + 64;  // per-wave queue of marked nodes (LDS ints)
-constexpr size_t kLdsMax = 158 * 1024;    // dynamic LDS a workgroup may take beside the static part
-constexpr size_t kLdsHead = sizeof(OvEntry) * kMaxParticles + (size_t)NW * kQueue * 4;
+constexpr int kFields = 6;                      // per marked node: 4 doubles + 2 64-bit integers
+constexpr size_t kSlotBytes = kFields * 8 + 4;  // the fields and the node map entry
+constexpr int kFillU = 4;                       // marked nodes per lane in flight while filling
+constexpr size_t kLdsMax = 158 * 1024;          // dynamic LDS a workgroup may take beside the static part
+constexpr size_t kLdsHead = sizeof(OvEntry) * kMaxParticles;
 
 size_t particle_lds_aux_bytes(int32_t box_cap)
 {
@@ -188,7 +189,7 @@ size_t particle_lds_aux_bytes(int32_t box_cap)
 
 size_t particle_lds_bytes(int32_t box_cap)
 {
-    const size_t bytes = particle_lds_aux_bytes(box_cap) + (size_t)box_cap * kFields * 8;
+    const size_t bytes = particle_lds_aux_bytes(box_cap) + (size_t)box_cap * kSlotBytes;
     return bytes <= kLdsMax ? bytes : 0;
 }
 
@@ -196,6 +197,11 @@ size_t particle_launch_lds(int32_t box_cap)
 {
     const size_t bytes = particle_lds_bytes(box_cap);
     return bytes ? bytes : kLdsMax;
+}
+
+size_t particle_scratch_bytes(int32_t box_cap)
+{
+    return particle_lds_bytes(box_cap) ? 0 : (size_t)box_cap * kSlotBytes;
 }
 
 // The markers of this thread (l = threadIdx.x + k PB) at one position of the particle.
@@ -315,6 +321,28 @@ __device__ __forceinline__ int mask_prefix(const uint32_t* mask, int* pre, int n
     return total;
 }
 
+// The node map: slot -> box node, for the marked nodes of mask[0..nw).  Each half-wave
+// takes one word per round, one bit per lane; four rounds' words are read at once.
+__device__ __forceinline__ void write_node_map(const uint32_t* mask, const int* pre, int nw, int* nodes)
+{
+    constexpr int kU = 4, kStep = PB / 32;
+    const int b = threadIdx.x & 31;
+    const uint32_t below = (1u << b) - 1u;
+    for (int k0 = (int)(threadIdx.x >> 5); k0 < nw; k0 += kU * kStep) {
+        uint32_t m[kU];
+        int p[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int k = k0 + u * kStep;
+            m[u] = k < nw ? mask[k] : 0u;
+            p[u] = k < nw ? pre[k] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            if ((m[u] >> b) & 1u) nodes[p[u] + __popc(m[u] & below)] = 32 * (k0 + u * kStep) + b;
+    }
+}
+
 // Slot of marked box node n.
 __device__ __forceinline__ int node_slot(const uint32_t* mask, const int* pre, int n)
 {
@@ -325,16 +353,18 @@ __device__ __forceinline__ int node_slot(const uint32_t* mask, const int* pre, i
 // The particles (this one included) whose boxes of this step overlap this particle's box,
 // in particle order (the boxes are arcs along the periodic x axis); only they can put a
 // spread force on its probe nodes.
+// Lane q of the first wave holds particle q's reference rq and box dq (read at the start of
+// the launch, so the loads overlap the work before).
 template <typename T>
-__device__ __forceinline__ int overlap_list(const ParticleArgs<T>& a, int x0, int y0, int w, int h, OvEntry* ov,
-                                            int (*sh)[NW])
+__device__ __forceinline__ int overlap_list(const ParticleArgs<T>& a, const PartRef& rq, const TileDesc& dq, int x0,
+                                            int y0, int w, int h, OvEntry* ov, int (*sh)[NW])
 {
     if (threadIdx.x < 64) {
         const int q = threadIdx.x;
         bool take = false;
         OvEntry e{};
         if (q < a.nparts && w > 0 && h > 0) {
-            const TileDesc d = *a.refs[q].desc;
+            const TileDesc d = dq;
             if (d.active && d.w > 0 && d.h > 0) {
                 const int xw = wrap(x0, a.nx);
                 int dq = d.i0w - xw;
@@ -342,7 +372,8 @@ __device__ __forceinline__ int overlap_list(const ParticleArgs<T>& a, int x0, in
                 int dm = xw - d.i0w;
                 if (dm < 0) dm += a.nx;
                 take = (dq < w || dm < d.w) && d.j0 < y0 + h && y0 < d.j0 + d.h;
-                e.tile = a.refs[q].tile;
+                e.tile = rq.tile;
+                e.ring = rq.ring;
                 e.i0w = d.i0w;
                 e.j0 = d.j0;
                 e.w = d.w;
@@ -362,110 +393,95 @@ __device__ __forceinline__ int overlap_list(const ParticleArgs<T>& a, int x0, in
     return n;
 }
 
-__device__ __forceinline__ void wave_sync_lds()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Node fields at the marked nodes of the box.  Each wave walks its share of the box (64
-// consecutive nodes per round), appends the marked ones to its LDS queue (ballot + prefix
-// count) and, whenever 64 U are queued, loads and reduces them U per lane, so the loads in
-// flight stay full while only the marked nodes are read.  TOTAL (the probe launch of
-// several particles): the total spread force at each node, summed over the overlapping
-// particles in particle order.
+// Node fields at the marked nodes: slots s0 + tid + u PB for u < kFillU per round, so the
+// loads of kFillU nodes per lane are in flight at once and neighbouring lanes read
+// neighbouring nodes of a row.  TOTAL (the probe launch of several particles): also the
+// total spread force at each node, summed over the overlapping particles in particle order.
 template <typename T, bool TOTAL>
-__device__ __forceinline__ void fill_marked(const ParticleArgs<T>& a, const NodeView& B, const uint32_t* mask,
-                                            const int* pre, int nbox, int x0, int y0, int w, int* q,
-                                            const OvEntry* ov, int nov)
+__device__ __forceinline__ void fill_nodes(const ParticleArgs<T>& a, const NodeView& B, const int* nodes, int nm,
+                                           int x0, int y0, int w, const OvEntry* ov, int nov)
 {
-    const int lane = threadIdx.x & 63;
-    int qn = 0;  // wave-uniform
-    for (int k0 = threadIdx.x & ~63;; k0 += PB) {
-        const bool more = k0 < nbox;
-        if (more) {
-            const int k = k0 + lane;
-            const bool m = k < nbox && ((mask[k >> 5] >> (k & 31)) & 1u);
-            const unsigned long long bal = __ballot(m);
-            const int below = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-            if (m) q[qn + below] = k;
-            qn += __popcll(bal);
-        }
-        if (qn >= 64 * kFillU || (!more && qn > 0)) {
-            wave_sync_lds();
-            const int take = min(qn, 64 * kFillU);
-            int kk[kFillU], ii[kFillU], jj[kFillU];
-            double v[kFillU][9];
+    for (int s0 = 0; s0 < nm; s0 += PB * kFillU) {
+        int kk[kFillU], ii[kFillU], jj[kFillU];
+        double v[kFillU][9];
 #pragma unroll
-            for (int u = 0; u < kFillU; ++u) {
-                const int e = lane + 64 * u;
-                kk[u] = e < take ? q[e] : -1;
-                ii[u] = jj[u] = 0;
-                if (kk[u] >= 0) {
-                    jj[u] = y0 + kk[u] / w;
-                    ii[u] = wrap(x0 + kk[u] % w, a.nx);
+        for (int u = 0; u < kFillU; ++u) {
+            const int sl = s0 + u * PB + (int)threadIdx.x;
+            kk[u] = sl < nm ? nodes[sl] : -1;
+            ii[u] = jj[u] = 0;
+            if (kk[u] >= 0) {
+                jj[u] = y0 + kk[u] / w;
+                ii[u] = wrap(x0 + kk[u] % w, a.nx);
 #pragma unroll
-                    for (int c = 0; c < 9; ++c)
-                        v[u][c] = (double)st_load(a.f, pop_index(c, ii[u], jj[u], a.nx, a.ny, a.pitch, a.plane,
-                                                                 a.pull != 0),
-                                                  a.inv_scale, false);
-                }
+                for (int c = 0; c < 9; ++c)
+                    v[u][c] = (double)st_load(a.f, pop_index(c, ii[u], jj[u], a.nx, a.ny, a.pitch, a.plane, a.pull != 0),
+                                              a.inv_scale, false);
             }
-            double fx[kFillU], fy[kFillU];
+        }
+        double fx[kFillU], fy[kFillU];
 #pragma unroll
-            for (int u = 0; u < kFillU; ++u) fx[u] = fy[u] = 0.0;
-            if (TOTAL) {
-                for (int e = 0; e < nov; ++e) {
-                    const OvEntry E = ov[e];
-                    int64_t tx[kFillU], ty[kFillU];
-                    bool in[kFillU];
+        for (int u = 0; u < kFillU; ++u) fx[u] = fy[u] = 0.0;
+        if (TOTAL) {
+            // two overlapping particles per round, so their index and force loads overlap;
+            // the sums still run in particle order
+            for (int e0 = 0; e0 < nov; e0 += 2) {
+                const int ne = min(2, nov - e0);
+                OvEntry E[2];
+                E[0] = ov[e0];
+                E[1] = ov[e0 + ne - 1];
+                int n[2][kFillU];
+                uint2 r[2][kFillU];
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
 #pragma unroll
                     for (int u = 0; u < kFillU; ++u) {
-                        int di = ii[u] - E.i0w;
+                        int di = ii[u] - E[q].i0w;
                         if (di < 0) di += a.nx;
-                        const int dj = jj[u] - E.j0;
-                        in[u] = kk[u] >= 0 && di < E.w && dj >= 0 && dj < E.h;
-                        tx[u] = ty[u] = 0;
-                        if (in[u]) {
-                            const int64_t* t = E.tile + 2 * ((size_t)dj * E.w + di);
-                            tx[u] = t[0];
-                            ty[u] = t[1];
+                        const int dj = jj[u] - E[q].j0;
+                        n[q][u] = (q < ne && kk[u] >= 0 && di < E[q].w && dj >= 0 && dj < E[q].h) ? dj * E[q].w + di
+                                                                                                   : -1;
+                        r[q][u] = n[q][u] >= 0 ? E[q].ring[n[q][u] >> 5] : make_uint2(0u, 0u);
+                    }
+                int64_t tx[2][kFillU], ty[2][kFillU];
+                bool in[2][kFillU];
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int u = 0; u < kFillU; ++u) {
+                        const int nn = n[q][u];
+                        in[q][u] = nn >= 0 && ((r[q][u].x >> (nn & 31)) & 1u);
+                        tx[q][u] = ty[q][u] = 0;
+                        if (in[q][u]) {
+                            const int sl = (int)r[q][u].y + __popc(r[q][u].x & ((1u << (nn & 31)) - 1u));
+                            tx[q][u] = E[q].tile[2 * sl];
+                            ty[q][u] = E[q].tile[2 * sl + 1];
                         }
                     }
 #pragma unroll
-                    for (int u = 0; u < kFillU; ++u) {
-                        if (!in[u]) continue;
-                        fx[u] += ldexp((double)tx[u], -E.scale);
-                        fy[u] += ldexp((double)ty[u], -E.scale);
-                    }
-                }
-            }
+                for (int q = 0; q < 2; ++q)
 #pragma unroll
-            for (int u = 0; u < kFillU; ++u) {
-                if (kk[u] < 0) continue;
-                double dr, jx, jy;
-                shifted_moments<double, double>(v[u], dr, jx, jy);
-                const double rho = 1.0 + dr;
-                const double inv = 1.0 / rho;
-                const int s = node_slot(mask, pre, kk[u]);
-                B.rho[s] = rho;
-                B.inv[s] = inv;
-                B.ux[s] = (jx + 0.5 * a.gx) * inv;
-                B.uy[s] = (jy + 0.5 * a.gy) * inv;
-                B.fx[s] = TOTAL ? (unsigned long long)__double_as_longlong(fx[u]) : 0ull;
-                B.fy[s] = TOTAL ? (unsigned long long)__double_as_longlong(fy[u]) : 0ull;
+                    for (int u = 0; u < kFillU; ++u) {
+                        if (!in[q][u]) continue;
+                        fx[u] += ldexp((double)tx[q][u], -E[q].scale);
+                        fy[u] += ldexp((double)ty[q][u], -E[q].scale);
+                    }
             }
-            const int rest = qn - take;  // < 64, moved to the front (no overlap: take >= 256)
-            wave_sync_lds();
-            const int mv = lane < rest ? q[take + lane] : 0;
-            wave_sync_lds();
-            if (lane < rest) q[lane] = mv;
-            wave_sync_lds();
-            qn = rest;
         }
-        if (!more && qn == 0) break;
+#pragma unroll
+        for (int u = 0; u < kFillU; ++u) {
+            if (kk[u] < 0) continue;
+            const int sl = s0 + u * PB + (int)threadIdx.x;
+            double dr, jx, jy;
+            shifted_moments<double, double>(v[u], dr, jx, jy);
+            const double rho = 1.0 + dr;
+            const double inv = 1.0 / rho;
+            B.rho[sl] = rho;
+            B.inv[sl] = inv;
+            B.ux[sl] = (jx + 0.5 * a.gx) * inv;
+            B.uy[sl] = (jy + 0.5 * a.gy) * inv;
+            B.fx[sl] = TOTAL ? (unsigned long long)__double_as_longlong(fx[u]) : 0ull;
+            B.fy[sl] = TOTAL ? (unsigned long long)__double_as_longlong(fy[u]) : 0ull;
+        }
     }
 }
 
@@ -502,11 +518,13 @@ __device__ __forceinline__ unsigned long long force_load(const unsigned long lon
 template <int MPT>
 struct PhaseCtx {
     double xc, yc, th, ux, uy, om, cth, sth;
+    double xc1, yc1, th1, ux1, uy1, om1;  // level n-1
     int64_t step;
     int x0, y0, w, h, nbox, nmarked, flags;
     bool box_ok;
     const uint32_t* mask;
     const int* pre;
+    const int* nodes;
     MarkerSet<MPT> G;
 };
 
@@ -515,7 +533,7 @@ struct PhaseCtx {
 // barriers, device-scope atomics for the force).
 template <typename T, int MPT, bool LDS, int MODE>
 __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const PhaseCtx<MPT>& c, const NodeView& B,
-                                           int* queue, const OvEntry* ov, int nov, double (*shd)[NW], int (*shi)[NW])
+                                           const OvEntry* ov, int nov, double (*shd)[NW], int (*shi)[NW])
 {
     const int tid = threadIdx.x;
     const int nl = a.nl;
@@ -528,7 +546,7 @@ __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const Phase
     int flags = c.flags;
     DevParticle* st = a.st;
 
-    fill_marked<T, MODE == 2>(a, B, mask, pre, nbox, x0, y0, w, queue, ov, nov);
+    fill_nodes<T, MODE == 2>(a, B, c.nodes, c.nmarked, x0, y0, w, ov, nov);
     __syncthreads();
 
     // ---- markers: MLS interpolation and direct forcing ----------------------------------
@@ -618,9 +636,17 @@ __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const Phase
             }
         }
         __syncthreads();
-        if (spread_ok) {
-            // the box's tile for the sweep (and the other particles' probes): zero where no
-            // marker support reaches
+        if (spread_ok && MODE == 1) {
+            // the compact list and its index for the sweep and the other particles' probes
+            for (int k = tid; k < c.nmarked; k += PB) {
+                longlong2 t;
+                t.x = (long long)force_load<LDS>(B.fx + k);
+                t.y = (long long)force_load<LDS>(B.fy + k);
+                *(longlong2*)(a.tile + 2 * (size_t)k) = t;
+            }
+            for (int k = tid; k < (nbox + 31) / 32; k += PB) a.ring[k] = make_uint2(mask[k], (uint32_t)pre[k]);
+        } else if (spread_ok) {
+            // the box's tile for the sweep: zero where no marker support reaches
             for (int k = tid; k < nbox; k += PB) {
                 const uint32_t mw = mask[k >> 5];
                 unsigned long long qx = 0, qy = 0;
@@ -755,13 +781,32 @@ __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const Phase
             }
         }
     }
-    block_sum<6>(acc, shd);
-    {
-        int v[2] = {nb, flags};
-        const int op[2] = {0, 1};
-        block_int<2>(v, op, shi);
-        nb = v[0];
-        flags = v[1];
+    // per-wave partials, then thread 0 (the only user) adds them in wave order
+#pragma unroll
+    for (int k = 0; k < 6; ++k) acc[k] = wave_sum(acc[k]);
+    nb = wave_isum(nb);
+    flags = wave_ior(flags);
+    if ((tid & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) shd[k][tid >> 6] = acc[k];
+        shi[0][tid >> 6] = nb;
+        shi[1][tid >> 6] = flags;
+    }
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            double sum = shd[k][0];
+#pragma unroll
+            for (int u = 1; u < NW; ++u) sum += shd[k][u];
+            acc[k] = sum;
+        }
+        nb = shi[0][0];
+        flags = shi[1][0];
+        for (int u = 1; u < NW; ++u) {
+            nb += shi[0][u];
+            flags |= shi[1][u];
+        }
     }
     // ---- wall force (eq 12), totals and the rigid-body update (eq 13-16) --------------
     if (tid == 0) {
@@ -772,12 +817,12 @@ __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const Phase
         const double eps = gap > 1e-3 ? gap : 1e-3;
         const double fw = a.hamaker / (8.0 * sqrt(2.0)) * sqrt(sqrt(a.a * a.b) / (eps * eps * eps * eps * eps));
         const double Fx = hx + bx_, Fy = hy + by_ + fw, M = hm + bm;
-        const double nux = (2.0 / 3.0) * (2.0 * ux - 0.5 * st->ux1 + Fx / a.mass);
-        const double nuy = (2.0 / 3.0) * (2.0 * uy - 0.5 * st->uy1 + Fy / a.mass);
-        const double nom = (2.0 / 3.0) * (2.0 * om - 0.5 * st->om1 + M / a.inertia);
-        const double nxc = (2.0 / 3.0) * (2.0 * xc - 0.5 * st->xc1 + nux);
-        const double nyc = (2.0 / 3.0) * (2.0 * yc - 0.5 * st->yc1 + nuy);
-        const double nth = (2.0 / 3.0) * (2.0 * th - 0.5 * st->th1 + nom);
+        const double nux = (2.0 / 3.0) * (2.0 * ux - 0.5 * c.ux1 + Fx / a.mass);
+        const double nuy = (2.0 / 3.0) * (2.0 * uy - 0.5 * c.uy1 + Fy / a.mass);
+        const double nom = (2.0 / 3.0) * (2.0 * om - 0.5 * c.om1 + M / a.inertia);
+        const double nxc = (2.0 / 3.0) * (2.0 * xc - 0.5 * c.xc1 + nux);
+        const double nyc = (2.0 / 3.0) * (2.0 * yc - 0.5 * c.yc1 + nuy);
+        const double nth = (2.0 / 3.0) * (2.0 * th - 0.5 * c.th1 + nom);
         if (!(isfinite(Fx) && isfinite(Fy) && isfinite(M) && isfinite(nux) && isfinite(nuy) && isfinite(nom)))
             fl |= FLAG_NONFINITE;
         st->xc1 = xc;
@@ -851,6 +896,27 @@ __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const Phase
     }
 }
 
+// Lays out the node fields and the node map of the marked nodes from base (LDS: dynamic LDS,
+// else the global scratch), writes the map and runs the rest of the phase.
+template <typename T, int MPT, bool LDS, int MODE>
+__device__ __forceinline__ void phase_rest(const ParticleArgs<T>& a, PhaseCtx<MPT>& c, double* base, const OvEntry* ov,
+                                           int nov, double (*shd)[NW], int (*shi)[NW])
+{
+    const int m = c.nmarked;
+    NodeView B;
+    B.rho = base;
+    B.ux = base + m;
+    B.uy = base + 2 * m;
+    B.inv = base + 3 * m;
+    B.fx = (unsigned long long*)(base + 4 * m);
+    B.fy = (unsigned long long*)(base + 5 * m);
+    int* nodes = (int*)(base + 6 * m);
+    c.nodes = nodes;
+    write_node_map(c.mask, c.pre, (c.nbox + 31) / 32, nodes);
+    __syncthreads();
+    phase_body<T, MPT, LDS, MODE>(a, c, B, ov, nov, shd, shi);
+}
+
 // One particle's phase, run by one workgroup.  MPT markers per thread (nl <= MPT * PB);
 // lds: the dynamic LDS of lds_bytes bytes.
 // MODE 0: the whole phase of a simulation's only particle.  With several particles the
@@ -866,14 +932,20 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, char* l
     __shared__ int shi[8][NW];
     const int tid = threadIdx.x;
     OvEntry* ov = (OvEntry*)lds;
-    int* queue = (int*)(lds + sizeof(OvEntry) * kMaxParticles) + (tid >> 6) * kQueue;
     const int wcap = (a.box_cap + 31) / 32;
     uint32_t* mask = (uint32_t*)(lds + kLdsHead);
     int* pre = (int*)(mask + wcap);
     double* fields = (double*)(pre + wcap);  // 8-byte aligned: kLdsHead and 8 wcap are multiples of 8
     const size_t aux = kLdsHead + (size_t)wcap * 8;
-    const int lds_slots = lds_bytes > aux ? (int)((lds_bytes - aux) / (kFields * 8)) : 0;
+    const int lds_slots = lds_bytes > aux ? (int)((lds_bytes - aux) / kSlotBytes) : 0;
 
+    // the probe launch's references to every particle's box and force list
+    PartRef rq{};
+    TileDesc dq{};
+    if (MODE == 2 && tid < a.nparts) {
+        rq = a.refs[tid];
+        dq = *rq.desc;
+    }
     PhaseCtx<MPT> c;
     const DevParticle* st = a.st;
     c.xc = st->xc;
@@ -883,6 +955,12 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, char* l
     c.uy = st->uy;
     c.om = st->om;
     c.step = st->step;
+    c.xc1 = st->xc1;
+    c.yc1 = st->yc1;
+    c.th1 = st->th1;
+    c.ux1 = st->ux1;
+    c.uy1 = st->uy1;
+    c.om1 = st->om1;
     c.cth = cos(c.th);
     c.sth = sin(c.th);
     c.flags = 0;
@@ -912,34 +990,20 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, char* l
     c.nmarked = mask_prefix(mask, pre, nw, shi);
     c.mask = mask;
     c.pre = pre;
-    const int nov = MODE == 2 ? overlap_list(a, c.x0, c.y0, c.w, c.h, ov, shi) : 0;
+    const int nov = MODE == 2 ? overlap_list(a, rq, dq, c.x0, c.y0, c.w, c.h, ov, shi) : 0;
 
-    NodeView B;
-    if (c.nmarked <= lds_slots || !a.box_global) {
-        if (c.nmarked > lds_slots) {  // no scratch to hold the fields (a launch with too little LDS)
-            c.box_ok = false;
-            c.nbox = 0;
-            if (tid == 0) c.flags |= FLAG_TILE;
-        }
-        const int m = c.box_ok ? c.nmarked : 0;
-        B.rho = fields;
-        B.ux = fields + m;
-        B.uy = fields + 2 * m;
-        B.inv = fields + 3 * m;
-        B.fx = (unsigned long long*)(fields + 4 * m);
-        B.fy = (unsigned long long*)(fields + 5 * m);
-        phase_body<T, MPT, true, MODE>(a, c, B, queue, ov, nov, shd, shi);
-    } else {
-        double* g = a.box_global;
-        const int m = c.nmarked;
-        B.rho = g;
-        B.ux = g + m;
-        B.uy = g + 2 * m;
-        B.inv = g + 3 * m;
-        B.fx = (unsigned long long*)(g + 4 * m);
-        B.fy = (unsigned long long*)(g + 5 * m);
-        phase_body<T, MPT, false, MODE>(a, c, B, queue, ov, nov, shd, shi);
+    // fields and node map in LDS when they fit, else in the global scratch
+    const bool fits = c.nmarked <= lds_slots;
+    if (!fits && !a.box_global) {  // no scratch to hold them (a launch with too little LDS)
+        c.box_ok = false;
+        c.nbox = 0;
+        c.nmarked = 0;
+        if (tid == 0) c.flags |= FLAG_TILE;
     }
+    if (fits || !a.box_global)
+        phase_rest<T, MPT, true, MODE>(a, c, fields, ov, nov, shd, shi);
+    else
+        phase_rest<T, MPT, false, MODE>(a, c, a.box_global, ov, nov, shd, shi);
 }
 
 template <typename T, int MPT>
@@ -997,7 +1061,6 @@ hipError_t launch_particle_split(const ParticleArgs<T>* args, int32_t n, const T
                      : launch_split_mode<T, M, 2>(args, n, f, pmask, lds, stream, t0, t1)
     if (max_nl <= PB) LBIB_SPLIT(1);
     if (max_nl <= 2 * PB) LBIB_SPLIT(2);
-    if (max_nl <= 4 * PB) LBIB_SPLIT(4);
 #undef LBIB_SPLIT
     return hipErrorInvalidValue;
 }
@@ -1054,7 +1117,6 @@ hipError_t launch_pool_particle(const ParticleArgs<T>* args, const int32_t* acti
     if (lds > kLdsMax || lds < kLdsHead) return hipErrorInvalidValue;
     if (max_nl <= PB) return launch_pool_mpt<T, 1>(args, active, ctl, n_active, lds, stream, t0, t1);
     if (max_nl <= 2 * PB) return launch_pool_mpt<T, 2>(args, active, ctl, n_active, lds, stream, t0, t1);
-    if (max_nl <= 4 * PB) return launch_pool_mpt<T, 4>(args, active, ctl, n_active, lds, stream, t0, t1);
     return hipErrorInvalidValue;
 }
 
@@ -1076,7 +1138,6 @@ hipError_t launch_particle(const ParticleArgs<T>& a, hipStream_t stream, hipEven
 {
     if (a.nl <= PB) return launch_particle_mpt<T, 1>(a, stream, t0, t1);
     if (a.nl <= 2 * PB) return launch_particle_mpt<T, 2>(a, stream, t0, t1);
-    if (a.nl <= 4 * PB) return launch_particle_mpt<T, 4>(a, stream, t0, t1);
     return hipErrorInvalidValue;
 }
 

@@ -172,6 +172,9 @@ EvPair timing_events(lbib_sim* h, int kind)
     return p;
 }
 
+// Bytes one lattice sweep moves (every population read and written once).
+double sweep_bytes(const lbib_sim* h) { return (double)h->desc.nx * h->desc.ny * 18.0 * h->g.elem; }
+
 // One time step is the particle phase then the lattice sweep.  Serial schedule: both on the
 // caller's stream.  Overlapped schedule (when the previous step has predicted this step's
 // box): the particle phase runs on the second stream while the caller's stream sweeps the
@@ -198,14 +201,28 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
             unsigned long long* mnext = h->d_masks + (par ^ 1) * h->ntiles;
             const int32_t np = (int32_t)h->parts.size();
             const ParticleArgs<T>* args = (const ParticleArgs<T>*)h->d_args;
+            // mode 1: the second particle launch (which reads the populations of the step and
+            // writes only particle state) runs on the second stream beside the sweep, and the
+            // next step's first launch waits for both.  The two cross-stream waits cost more
+            // than the overlap saves at the sizes measured (2048 x 512, 32 particles: 67.6
+            // against 55.2 us per step), so no other mode uses it.
+            const bool ovl = h->overlap == 1;
+            if (!joined) HIPCHK(h, hipStreamWaitEvent(h->stream, h->evB, 0));
             const EvPair e1 = timing_events(h, 1);
             HIPCHK(h, launch_particle_split<T>(args, np, fin, mcur, 1, h->max_nl, h->lds_bytes, h->stream,
                                                e1.t0, e1.t1));
+            hipStream_t s2 = h->stream;
+            if (ovl) {
+                HIPCHK(h, hipEventRecord(h->evA, h->stream));
+                HIPCHK(h, hipStreamWaitEvent(h->stream2, h->evA, 0));
+                s2 = h->stream2;
+            }
             const EvPair e2 = timing_events(h, 2);
-            HIPCHK(h, launch_particle_split<T>(args, np, fin, mcur, 2, h->max_nl, h->lds_bytes, h->stream,
-                                               e2.t0, e2.t1));
+            HIPCHK(h, launch_particle_split<T>(args, np, fin, mcur, 2, h->max_nl, h->lds_bytes, s2, e2.t0, e2.t1));
+            if (ovl) HIPCHK(h, hipEventRecord(h->evB, h->stream2));
             const EvPair e0 = timing_events(h, 0);
             HIPCHK(h, launch_sweep_multi<T>(fin, fout, sa, mcur, mnext, h->d_refs, h->g.pull, h->stream, e0.t0, e0.t1));
+            joined = !ovl;
             h->zone_valid = false;
         } else if (h->parts.empty()) {
             const EvPair e0 = timing_events(h, 0);
@@ -218,8 +235,7 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
             pa.parity_out = par ^ 1;
             // the overlapped schedule pays two cross-stream waits per step (~10 us); it wins
             // once a sweep moves more than ~64 MiB (the particle phase then hides behind it)
-            const bool overlap =
-                h->overlap == 1 || (h->overlap == 2 && (double)h->desc.nx * h->desc.ny * 18.0 * h->g.elem >= 64.0 * 1048576.0);
+            const bool overlap = h->overlap == 1 || (h->overlap == 2 && sweep_bytes(h) >= 64.0 * 1048576.0);
             if (!overlap || !h->zone_valid) {
                 pa.check_zone = 0;
                 const EvPair e1 = timing_events(h, 1);
@@ -434,7 +450,7 @@ lbib_status lbib_init(lbib_handle h)
         const size_t np = h->parts.size();
         std::vector<PartRef> refs(np);
         for (size_t k = 0; k < np; ++k) {
-            refs[k] = PartRef{h->parts[k].d_desc, h->parts[k].d_tile};
+            refs[k] = PartRef{h->parts[k].d_desc, h->parts[k].d_tile, h->parts[k].d_ring};
             const Particle& p = h->parts[k];
             h->max_nl = std::max(h->max_nl, p.nl);
             h->lds_bytes = std::max(h->lds_bytes, particle_launch_lds(p.box_cap));

@@ -144,9 +144,13 @@ __global__ __launch_bounds__(256) void sweep_multi_kernel(const T* __restrict__ 
         if (d.active && in_box(d, i, j, a.nx)) {
             int di = i - d.i0w;
             if (di < 0) di += a.nx;
-            const int64_t* t = pr.tile + 2 * ((size_t)(j - d.j0) * d.w + di);
-            Fx += ldexp((double)t[0], -d.scale);
-            Fy += ldexp((double)t[1], -d.scale);
+            const int n = (j - d.j0) * d.w + di;
+            const uint2 r = pr.ring[n >> 5];
+            if ((r.x >> (n & 31)) & 1u) {  // a marker support reaches the node
+                const int64_t* t = pr.tile + 2 * ((int)r.y + __popc(r.x & ((1u << (n & 31)) - 1u)));
+                Fx += ldexp((double)t[0], -d.scale);
+                Fy += ldexp((double)t[1], -d.scale);
+            }
         }
     }
     collide_stream<T, PULL>(fin, fout, a, i, j, Fx, Fy);

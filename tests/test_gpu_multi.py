@@ -150,3 +150,20 @@ def test_multi_layouts_and_checkpoint(L):
     np.testing.assert_array_equal(a.f, b.f)
     a.close()
     b.close()
+
+
+def test_multi_overlapped_schedule_identical(L):
+    """Mode 1 (the probe launch beside the sweep on a second stream) gives the results of the
+    serial schedule bit for bit."""
+    w = W.multi_particle_channel(256, 96, 6, seed=4, precision="fp32", area_frac=0.02)
+    outs = []
+    for mode in (0, 1):
+        s, tr = gpu_run(L, w, 150, overlap=mode)
+        s.step(7)  # a second call: the schedule joins its streams at the end of each call
+        s.sync()
+        outs.append(([s.particle(k) for k in range(6)], tr, s.f))
+        s.close()
+    assert outs[0][0] == outs[1][0]
+    for k in range(6):
+        np.testing.assert_array_equal(outs[0][1][k], outs[1][1][k])
+    np.testing.assert_array_equal(outs[0][2], outs[1][2])
