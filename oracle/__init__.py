@@ -52,7 +52,7 @@ class Params(C.Structure):
         ("rho_l_num", C.c_int32), ("rho_l_den", C.c_int32),
         ("sigma_hat", C.c_double), ("sigma_star_ratio", C.c_double), ("y_cr_hat", C.c_double),
         ("y_eq_ratio", C.c_double), ("k_f", C.c_double), ("k_r0", C.c_double),
-        ("kbt_hat", C.c_double), ("hamaker_hat", C.c_double),
+        ("kbt_hat", C.c_double), ("hamaker_hat", C.c_double), ("drive", C.c_int32),
     ]
 
 
@@ -88,6 +88,8 @@ def lib():
             "orc_moments": (None, [_D, C.c_double, C.c_double, _D, _D, _D]),
             "orc_collide_stream": (None, [C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                           C.c_double, _D, _D, _D]),
+            "orc_collide_stream_uw": (None, [C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                             C.c_double, C.c_double, _D, _D, _D]),
             "orc_spline_w": (C.c_double, [C.c_double]),
             "orc_mls": (C.c_int32, [C.c_int32, C.c_int32, C.c_double, C.c_double, _I32, _I32, _D, _D, _D]),
             "orc_ellipse_arc": (C.c_double, [C.c_double, C.c_double, C.c_double]),
@@ -173,13 +175,14 @@ def moments(f9, fx=0.0, fy=0.0):
     return r.value, ux.value, uy.value
 
 
-def collide_stream(f, tau, gx, gy, fib=None, walls=True):
-    """One sweep on plain populations f[9, ny, nx]; fib[2, ny, nx] optional."""
+def collide_stream(f, tau, gx, gy, fib=None, walls=True, uw=0.0):
+    """One sweep on plain populations f[9, ny, nx]; fib[2, ny, nx] optional; uw: speed of the
+    top wall along x."""
     f = np.ascontiguousarray(f, np.float64)
     _, ny, nx = f.shape
     out = np.empty_like(f)
     fibp = None if fib is None else _p(np.ascontiguousarray(fib, np.float64))
-    lib().orc_collide_stream(nx, ny, 1 if walls else 0, tau, gx, gy, fibp, _p(f), _p(out))
+    lib().orc_collide_stream_uw(nx, ny, 1 if walls else 0, uw, tau, gx, gy, fibp, _p(f), _p(out))
     return out
 
 
@@ -330,6 +333,7 @@ def params_from_workload(w: dict, *, walls=True, init_rest=False, extra_g=(0.0, 
     P.walls = 1 if walls else 0
     P.init_rest = 1 if init_rest else 0
     P.extra_gx, P.extra_gy = extra_g
+    P.drive = L.get("drive", 0)
     entries = particle_entries(w)
     if entries:
         part, lig = entries[0]

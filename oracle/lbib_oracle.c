@@ -94,11 +94,15 @@ void orc_moments(const double* f9, double Fx, double Fy, double* rho, double* ux
  * side (dt = 1):  f*_i = f_i - (f_i - f_i^eq)/tau + F_i,  then f_i(x + e_i) = f*_i(x).
  * x is periodic.  With walls != 0 a link leaving the channel through y = -1/2 or
  * y = ny - 1/2 is reflected back into the opposite direction at the same node (half-way
- * bounce-back on resting walls); with walls == 0 y is periodic too (test mode).
- * The body force on node (i, j) is (gx, gy) plus fib (two planes [c][j][i]) when given.
- * Rows are independent, so the OpenMP split cannot change any result bit. */
-void orc_collide_stream(int32_t nx, int32_t ny, int32_t walls, double tau, double gx, double gy,
-                        const double* fib, const double* fin, double* fout)
+ * bounce-back); the top wall moves along x at speed uw, which the reflection carries as
+ * f_opp(i)(x) = f*_i(x) - 2 w_i rho_w (e_i . u_wall) / cs^2 with rho_w = 1 (the reading of
+ * the moving wall of the shear setup, "Modeling the adhesion dynamics" section, for
+ * half-way walls; the paper's own walls are Zou-He known-velocity nodes).  With
+ * walls == 0 y is periodic too (test mode).  The body force on node (i, j) is (gx, gy)
+ * plus fib (two planes [c][j][i]) when given.  Rows are independent, so the OpenMP split
+ * cannot change any result bit. */
+void orc_collide_stream_uw(int32_t nx, int32_t ny, int32_t walls, double uw, double tau, double gx, double gy,
+                           const double* fib, const double* fin, double* fout)
 {
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < ny; ++j) {
@@ -119,8 +123,10 @@ void orc_collide_stream(int32_t nx, int32_t ny, int32_t walls, double tau, doubl
                 int id = ((i + EX[q]) % nx + nx) % nx;
                 int jd = j + EY[q];
                 if (walls) {
-                    if (jd < 0 || jd >= ny)
+                    if (jd < 0)
                         fout[IDX(OPP[q], j, i, nx, ny)] = post;
+                    else if (jd >= ny)
+                        fout[IDX(OPP[q], j, i, nx, ny)] = post - 2.0 * WQ[q] * (EX[q] * uw) / CS2;
                     else
                         fout[IDX(q, jd, id, nx, ny)] = post;
                 } else {
@@ -130,6 +136,13 @@ void orc_collide_stream(int32_t nx, int32_t ny, int32_t walls, double tau, doubl
             }
         }
     }
+}
+
+/* The same sweep with resting walls. */
+void orc_collide_stream(int32_t nx, int32_t ny, int32_t walls, double tau, double gx, double gy,
+                        const double* fib, const double* fin, double* fout)
+{
+    orc_collide_stream_uw(nx, ny, walls, 0.0, tau, gx, gy, fib, fin, fout);
 }
 
 /* ------------------------------------------------------------------------------------- */
@@ -548,6 +561,8 @@ typedef struct {
     int32_t nl;
     int32_t rho_l_num, rho_l_den;
     double sigma_hat, sigma_star_ratio, y_cr_hat, y_eq_ratio, k_f, k_r0, kbt_hat, hamaker_hat;
+    int32_t drive; /* 0: body-force Poiseuille, resting walls; 1: resting bottom wall, top wall
+                      moving at u_max, no body force (linear shear) */
 } orc_params;
 
 /* One particle: shape and placement, ligands and bond constants (Table 1 groups). */
@@ -598,15 +613,21 @@ static void derive_particle(const orc_sim* s, orc_particle* P)
     P->inertia = P->mass * (q->a * q->a + q->b * q->b) / 4.0;
 }
 
+/* Lattice-unit constants: nu from tau (below eq 1); Re = H u_max / nu ("Modeling the
+ * adhesion dynamics" section) gives u_max, the centre-line speed of the Poiseuille drive
+ * (body force 8 nu u_max / H^2) or the speed of the moving top wall of the shear drive. */
 static void derive(orc_sim* s)
 {
     const orc_params* p = &s->p;
     double H = (double)p->ny;
     s->nu = CS2 * (p->tau - 0.5);
     s->umax = p->re * s->nu / H;
-    s->gx = 8.0 * s->nu * s->umax / (H * H) + p->extra_gx;
+    s->gx = (p->drive == 1 ? 0.0 : 8.0 * s->nu * s->umax / (H * H)) + p->extra_gx;
     s->gy = p->extra_gy;
 }
+
+/* Speed of the moving top wall (0 for the resting walls of the Poiseuille drive). */
+static double wall_speed(const orc_sim* s) { return s->p.drive == 1 ? s->umax : 0.0; }
 
 static void place_markers(orc_particle* P)
 {
@@ -670,7 +691,7 @@ int32_t orc_sim_add_particle(orc_sim* s, const orc_particle_params* q)
 
 orc_sim* orc_sim_create(const orc_params* p)
 {
-    if (p->nx < 4 || p->ny < 4 || !(p->tau > 0.5)) return NULL;
+    if (p->nx < 4 || p->ny < 4 || !(p->tau > 0.5) || p->drive < 0 || p->drive > 1) return NULL;
     orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
     s->p = *p;
     derive(s);
@@ -683,7 +704,9 @@ orc_sim* orc_sim_create(const orc_params* p)
     s->uy = (double*)calloc(N, sizeof(double));
     double H = (double)p->ny;
     for (int j = 0; j < p->ny; ++j) {
-        double u0 = p->init_rest ? 0.0 : 4.0 * s->umax * (j + 0.5) * (H - 0.5 - j) / (H * H);
+        /* the developed profile: parabolic (Poiseuille) or linear (shear), walls at -1/2, H - 1/2 */
+        double u0 = p->drive == 1 ? s->umax * (j + 0.5) / H : 4.0 * s->umax * (j + 0.5) * (H - 0.5 - j) / (H * H);
+        if (p->init_rest) u0 = 0.0;
         double feq[9];
         orc_feq(1.0, u0, 0.0, feq);
         for (int i = 0; i < p->nx; ++i)
@@ -814,7 +837,8 @@ static int step_once(orc_sim* s, double* trace)
             if (orc_spread(nx, ny, nl, P->X, P->S, P->Fl, s->fib) != 0) s->flags |= 4;
         }
     }
-    orc_collide_stream(nx, ny, p->walls, p->tau, s->gx, s->gy, s->np > 0 ? s->fib : NULL, s->f, s->fn);
+    orc_collide_stream_uw(nx, ny, p->walls, wall_speed(s), p->tau, s->gx, s->gy, s->np > 0 ? s->fib : NULL, s->f,
+                          s->fn);
     if (s->np > 0) {
         node_fields(s, 1);
         for (int k = 0; k < s->np; ++k) {
