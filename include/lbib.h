@@ -12,10 +12,14 @@
  *
  * Conventions shared by every call
  *  - Lattice units: dx = dt = 1, rho_ref = 1, cs^2 = 1/3, nu = (tau - 1/2)/3.
- *  - Node (i, j) sits at (x, y) = (i, j), 0 <= i < nx, 0 <= j < ny.  x is periodic.  Resting
- *    half-way bounce-back walls lie at y = -1/2 (the receptor wall) and y = ny - 1/2, so the
- *    channel height is H = ny.  The flow is driven by the body force g = (8 nu u_max / H^2, 0)
- *    with u_max = Re nu / H (the centre-line velocity of the Poiseuille profile).
+ *  - Node (i, j) sits at (x, y) = (i, j), 0 <= i < nx, 0 <= j < ny.  x is periodic.
+ *    Half-way bounce-back walls lie at y = -1/2 (the receptor wall, at rest) and y = ny - 1/2,
+ *    so the channel height is H = ny, and u_max = Re nu / H.  Drive 0: both walls rest and the
+ *    body force g = (8 nu u_max / H^2, 0) drives a Poiseuille flow of centre-line velocity
+ *    u_max.  Drive 1 (the shear setup of the section "Modeling the adhesion dynamics ..."):
+ *    no body force; the top wall moves along x at u_max (moving-wall bounce-back: a
+ *    population reflected there gains -2 w_q rho_ref (e_q . u_wall) / cs^2), giving the
+ *    linear shear u_x = u_max (y + 1/2) / H.
  *  - Populations are D2Q9 in the order e_0 = (0,0), e_1 = (1,0), e_2 = (0,1), e_3 = (-1,0),
  *    e_4 = (0,-1), e_5 = (1,1), e_6 = (-1,1), e_7 = (-1,-1), e_8 = (1,-1) (eq 3).  Host arrays
  *    of populations are plain f (not shifted), FP64, laid out [q][j][i] with i fastest.
@@ -74,9 +78,10 @@ typedef enum {
  * body) is FP64 for every storage.  Bytes per lattice update: 144, 72, 36, 36. */
 enum { LBIB_FP64 = 0, LBIB_FP32 = 1, LBIB_FP16 = 2, LBIB_BF16 = 3 };
 
-/* Lattice (section "Modeling the adhesion dynamics ..."; Table 1).  drive must be 0
- * (body-force Poiseuille with resting bounce-back walls).  Requirements: nx >= 4, ny >= 4,
- * tau > 1/2, Re >= 0. */
+/* Lattice (section "Modeling the adhesion dynamics ..."; Table 1).  drive: 0 body-force
+ * Poiseuille with resting walls, 1 moving top wall (linear shear); the initial state is the
+ * developed profile of the drive at rho = 1.  Requirements: nx >= 4, ny >= 4, tau > 1/2,
+ * Re >= 0, drive 0 or 1. */
 typedef struct {
     int32_t nx, ny;
     double tau;

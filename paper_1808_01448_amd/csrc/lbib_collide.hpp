@@ -1,7 +1,7 @@
 // lbib_collide.hpp -- the per-node update of the lattice sweep, shared by the sweep of one
 // simulation and the sweep of a pool: BGK collision with Guo forcing (eq 1-6) evaluated in
-// FP64, and streaming with half-way bounce-back at the two walls and periodic x, in the
-// push or the pull layout of the population buffers.
+// FP64, and streaming with half-way bounce-back at the two walls (the top one possibly
+// moving along x) and periodic x, in the push or the pull layout of the population buffers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -63,6 +63,7 @@ __device__ __forceinline__ void collide_push(const T* __restrict__ fin, T* __res
     C g[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) g[q] = st_load(fin, q * P + c, a.inv_scale, true);
+    wall_reflect<C>(g, j, a.ny, a.uw6);
     C post[9];
     collide_node<C>(g, a, (C)Fx, (C)Fy, post);
 
@@ -109,6 +110,7 @@ __device__ __forceinline__ void collide_pull(const T* __restrict__ fin, T* __res
     C g[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) g[q] = st_load(fin, pop_index(q, i, j, a.nx, a.ny, a.pitch, P, true), a.inv_scale, true);
+    wall_reflect<C>(g, j, a.ny, a.uw6);
     C post[9];
     collide_node<C>(g, a, (C)Fx, (C)Fy, post);
 #pragma unroll

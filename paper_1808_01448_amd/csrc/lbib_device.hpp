@@ -230,6 +230,19 @@ __device__ inline bool mls_shape(double X, double Y, int ny, Mls& m, bool want_g
     return true;
 }
 
+// Moving top wall: a population that reaches the top row through the wall (directions 7
+// and 8, reflected from 5 and 6 at the same node) carries -2 w e.u_wall / cs^2, i.e.
+// -u_w/6 and +u_w/6.  Buffers hold the reflected values without it and every load of level
+// n adds it, in either layout, so both layouts store the same values.
+template <typename C>
+__device__ __forceinline__ void wall_reflect(C (&g)[9], int j, int ny, double uw6)
+{
+    if (j == ny - 1 && uw6 != 0.0) {
+        g[7] -= (C)uw6;
+        g[8] += (C)uw6;
+    }
+}
+
 __device__ __forceinline__ int wrap(int i, int n)
 {
     i %= n;

@@ -104,7 +104,7 @@ lbib_status check_lattice(const lbib_lattice_desc& d, std::string& msg)
     if ((int64_t)d.nx * d.ny > (int64_t)1 << 31) return msg = "more than 2^31 nodes", LBIB_E_INVALID;
     if (!is_finite(d.tau) || !(d.tau > 0.5)) return msg = "tau must be > 1/2", LBIB_E_INVALID;
     if (!is_finite(d.re) || d.re < 0) return msg = "Re must be >= 0", LBIB_E_INVALID;
-    if (d.drive != 0) return msg = "only drive 0 (body-force Poiseuille) is built", LBIB_E_UNSUPPORTED;
+    if (d.drive != 0 && d.drive != 1) return msg = "drive must be 0 (Poiseuille) or 1 (moving top wall)", LBIB_E_INVALID;
     if (d.precision != LBIB_FP64 && d.precision != LBIB_FP32 && d.precision != LBIB_FP16 && d.precision != LBIB_BF16)
         return msg = "precision must be LBIB_FP64, LBIB_FP32, LBIB_FP16 or LBIB_BF16", LBIB_E_UNSUPPORTED;
     return LBIB_OK;
@@ -124,8 +124,10 @@ LatticeGeom lattice_geom(const lbib_lattice_desc& d)
     g.tau = d.tau;
     g.nu = (d.tau - 0.5) / 3.0;
     g.umax = d.re * g.nu / H;
-    g.gx = 8.0 * g.nu * g.umax / (H * H);
+    g.drive = d.drive;
+    g.gx = d.drive == 1 ? 0.0 : 8.0 * g.nu * g.umax / (H * H);
     g.gy = 0.0;
+    g.uw = d.drive == 1 ? g.umax : 0.0;
     if (d.precision == LBIB_FP16) {
         // the largest deviation f - w to expect is that of the rest population at a few times
         // u_max; a power of two maps it to ~2^13, far below the binary16 maximum (65504) and
@@ -299,6 +301,7 @@ void fill_particle_args(ParticleArgs<T>& a, const LatticeGeom& g, uint64_t seed,
     a.pull = g.pull ? 1 : 0;
     a.plane = g.plane;
     a.inv_scale = 1.0 / g.scale;
+    a.uw6 = g.uw / 6.0;
     a.gx = g.gx;
     a.gy = g.gy;
     a.nu = g.nu;
@@ -352,11 +355,18 @@ hipError_t init_populations(void* f, const LatticeGeom& g, hipStream_t s)
     hipError_t e = hipMemsetAsync(f, 0, bytes, s);
     if (e != hipSuccess) return e;
     switch (g.precision) {
-        case LBIB_FP64: return launch_init<double>((double*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, g.scale, g.pull, s);
-        case LBIB_FP32: return launch_init<float>((float*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, g.scale, g.pull, s);
-        case LBIB_FP16: return launch_init<half_t>((half_t*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, g.scale, g.pull, s);
-        default: return launch_init<bf16_t>((bf16_t*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, g.scale, g.pull, s);
+        case LBIB_FP64: return launch_init<double>((double*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, g.scale, g.pull, g.drive, s);
+        case LBIB_FP32: return launch_init<float>((float*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, g.scale, g.pull, g.drive, s);
+        case LBIB_FP16: return launch_init<half_t>((half_t*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, g.scale, g.pull, g.drive, s);
+        default: return launch_init<bf16_t>((bf16_t*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, g.scale, g.pull, g.drive, s);
     }
+}
+
+// What a top-row population that arrives through the moving wall carries beyond the stored
+// value (wall_reflect on the device): -u_w/6 for direction 7, +u_w/6 for 8.
+static double wall_term(const LatticeGeom& g, int q)
+{
+    return q == 7 ? -g.uw / 6.0 : q == 8 ? g.uw / 6.0 : 0.0;
 }
 
 hipError_t download_populations(const void* fdev, const LatticeGeom& g, std::vector<double>& f)
@@ -372,12 +382,12 @@ hipError_t download_populations(const void* fdev, const LatticeGeom& g, std::vec
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 const int64_t k = host_pop_index(g, q, i, j);
-                double v;
+                double v = j == ny - 1 ? wall_term(g, q) : 0.0;
                 switch (g.precision) {
-                    case LBIB_FP64: v = ((const double*)raw.data())[k]; break;
-                    case LBIB_FP32: v = (double)((const float*)raw.data())[k]; break;
-                    case LBIB_FP16: v = (double)f16_to_f32(((const uint16_t*)raw.data())[k]) * inv; break;
-                    default: v = (double)bf16_to_f32(((const uint16_t*)raw.data())[k]); break;
+                    case LBIB_FP64: v += ((const double*)raw.data())[k]; break;
+                    case LBIB_FP32: v += (double)((const float*)raw.data())[k]; break;
+                    case LBIB_FP16: v += (double)f16_to_f32(((const uint16_t*)raw.data())[k]) * inv; break;
+                    default: v += (double)bf16_to_f32(((const uint16_t*)raw.data())[k]); break;
                 }
                 f[((size_t)q * ny + j) * nx + i] = kWq[q] + v;
             }
@@ -393,7 +403,7 @@ hipError_t upload_populations(void* fdev, const LatticeGeom& g, const double* f)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 const int64_t k = host_pop_index(g, q, i, j);
-                const double v = f[((size_t)q * ny + j) * nx + i] - kWq[q];
+                const double v = f[((size_t)q * ny + j) * nx + i] - kWq[q] - (j == ny - 1 ? wall_term(g, q) : 0.0);
                 switch (g.precision) {
                     case LBIB_FP64: ((double*)raw.data())[k] = v; break;
                     case LBIB_FP32: ((float*)raw.data())[k] = (float)v; break;

@@ -26,6 +26,8 @@ struct LatticeGeom {
     int precision = LBIB_FP64;
     double scale = 1.0;  // stored value = (f - w) scale (a power of two; 1 but for FP16)
     double tau = 0, nu = 0, umax = 0, gx = 0, gy = 0;
+    int drive = 0;    // 0 body-force Poiseuille, 1 moving top wall (linear shear)
+    double uw = 0;    // speed of the top wall (umax for drive 1, else 0)
 };
 
 // Host conversions of the 16-bit storages (round to nearest even).

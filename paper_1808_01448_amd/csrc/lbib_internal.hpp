@@ -81,6 +81,7 @@ struct SweepArgs {
     double guo;     // 1 - 1 / (2 tau)
     double gx, gy;  // uniform body force
     double scale, inv_scale;  // stored value = (f - w) scale (a power of two; 1 but for FP16)
+    double uw6;     // speed of the moving top wall / 6 (0: resting walls); see wall_reflect
 };
 
 // Where the sweep and the probes of a multi-particle step find particle p's spread force:
@@ -103,6 +104,7 @@ struct ParticleArgs {
     int32_t pull;  // layout of f: 0 push, 1 pull
     int64_t plane;
     double inv_scale;  // f - w = stored value * inv_scale
+    double uw6;        // speed of the moving top wall / 6 (wall_reflect)
     double gx, gy, nu;
     // body-frame surface: centroids xi[2l], outward normals nuv[2l], lengths S[l]
     const double* xi;
@@ -138,9 +140,11 @@ struct ParticleArgs {
 };
 
 // Launchers (lbib_sweep.hip, lbib_particle.hip).  All enqueue on `stream` and return the launch status.
+// drive 0: the Poiseuille profile of centre-line speed umax; 1: the linear shear profile of
+// a top wall moving at umax.
 template <typename T>
 hipError_t launch_init(T* f, int32_t nx, int32_t ny, int32_t pitch, int64_t plane, double umax, double scale,
-                       bool pull, hipStream_t stream);
+                       bool pull, int32_t drive, hipStream_t stream);
 // Sweep modes: every node (forces from desc/tile when desc != NULL); only nodes outside
 // the box in `desc` (which carry no spread force); only the nodes of the box in `desc`
 // (box_cap bounds the launch).

@@ -416,6 +416,7 @@ __device__ __forceinline__ void fill_nodes(const ParticleArgs<T>& a, const NodeV
                 for (int c = 0; c < 9; ++c)
                     v[u][c] = (double)st_load(a.f, pop_index(c, ii[u], jj[u], a.nx, a.ny, a.pitch, a.plane, a.pull != 0),
                                               a.inv_scale, false);
+                wall_reflect<double>(v[u], jj[u], a.ny, a.uw6);
             }
         }
         double fx[kFillU], fy[kFillU];

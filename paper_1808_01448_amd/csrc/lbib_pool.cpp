@@ -238,6 +238,7 @@ lbib_status rebuild(lbib_pool* h)
         s.a.gy = m.g.gy;
         s.a.scale = m.g.scale;
         s.a.inv_scale = 1.0 / m.g.scale;
+        s.a.uw6 = m.g.uw / 6.0;
         s.fA = (T*)m.fA;
         s.fB = (T*)m.fB;
         s.tile = m.p.d_tile;

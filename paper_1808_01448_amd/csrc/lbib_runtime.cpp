@@ -151,6 +151,7 @@ SweepArgs sweep_args(lbib_sim* h)
     a.gy = h->g.gy;
     a.scale = h->g.scale;
     a.inv_scale = 1.0 / h->g.scale;
+    a.uw6 = h->g.uw / 6.0;
     return a;
 }
 

@@ -25,23 +25,26 @@ namespace lbib {
 using namespace dev;
 
 // ---------------------------------------------------------------------------------------
-// Initial state: f = f_eq(1, (u(y), 0)) with the Poiseuille profile of a channel with walls
-// at y = -1/2 and y = ny - 1/2.  Stored shifted: g_q = w_q (3 e.u + 9/2 (e.u)^2 - 3/2 u^2).
+// Initial state: f = f_eq(1, (u(y), 0)) with the developed profile of a channel with walls
+// at y = -1/2 and y = ny - 1/2: Poiseuille (drive 0) or the linear shear of a top wall
+// moving at umax (drive 1).  Stored shifted: g_q = w_q (3 e.u + 9/2 (e.u)^2 - 3/2 u^2).
 // In the pull layout each stored value is the one that streams into the node and direction
-// where the initial state prescribes it.
+// where the initial state prescribes it.  A value that reaches the top row through a moving
+// wall is stored without the wall term, which every load adds (wall_reflect).
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ double init_value(int q, int j, int ny, double umax)
+__device__ __forceinline__ double init_value(int q, int j, int ny, double umax, int drive)
 {
     const double H = (double)ny;
-    const double u = 4.0 * umax * (j + 0.5) * (H - 0.5 - j) / (H * H);
+    const double u = drive == 1 ? umax * (j + 0.5) / H : 4.0 * umax * (j + 0.5) * (H - 0.5 - j) / (H * H);
     const double eu = kEx[q] * u;
     return kW[q] * (3.0 * eu + 4.5 * eu * eu - 1.5 * u * u);
 }
 
 template <typename T, bool PULL>
 __global__ __launch_bounds__(256) void init_kernel(T* f, int nx, int ny, int pitch, int64_t plane, double umax,
-                                                   double scale)
+                                                   double scale, int drive)
 {
+    const double uw6 = drive == 1 ? umax / 6.0 : 0.0;
     const int i = blockIdx.x * 64 + threadIdx.x;
     const int j = blockIdx.y * 4 + threadIdx.y;
     if (i >= nx || j >= ny) return;
@@ -51,21 +54,28 @@ __global__ __launch_bounds__(256) void init_kernel(T* f, int nx, int ny, int pit
         // push: population q of (i, j); pull: the value (i, j) emits along e_q, which arrives
         // as population q at (i + e_x, j + e_y), or reflects into population opp(q) at (i, j)
         const int dj = j + kEy[q];
-        const double v = !PULL ? init_value(q, j, ny, umax)
-                               : (dj >= 0 && dj < ny ? init_value(q, dj, ny, umax) : init_value(kOpp[q], j, ny, umax));
+        double v = !PULL ? init_value(q, j, ny, umax, drive)
+                         : (dj >= 0 && dj < ny ? init_value(q, dj, ny, umax, drive)
+                                               : init_value(kOpp[q], j, ny, umax, drive));
+        // the slot the top row's loads of populations 7 and 8 read
+        const int p = !PULL ? q : (dj >= ny ? kOpp[q] : -1);
+        if (j == ny - 1 && p == 7) v += uw6;
+        if (j == ny - 1 && p == 8) v -= uw6;
         st_store(f, q * plane + c, (typename St<T>::C)v, scale, false);
     }
 }
 
 template <typename T>
 hipError_t launch_init(T* f, int32_t nx, int32_t ny, int32_t pitch, int64_t plane, double umax, double scale,
-                       bool pull, hipStream_t stream)
+                       bool pull, int32_t drive, hipStream_t stream)
 {
     dim3 block(64, 4), grid((nx + 63) / 64, (ny + 3) / 4);
     if (pull)
-        hipLaunchKernelGGL((init_kernel<T, true>), grid, block, 0, stream, f, nx, ny, pitch, plane, umax, scale);
+        hipLaunchKernelGGL((init_kernel<T, true>), grid, block, 0, stream, f, nx, ny, pitch, plane, umax, scale,
+                           (int)drive);
     else
-        hipLaunchKernelGGL((init_kernel<T, false>), grid, block, 0, stream, f, nx, ny, pitch, plane, umax, scale);
+        hipLaunchKernelGGL((init_kernel<T, false>), grid, block, 0, stream, f, nx, ny, pitch, plane, umax, scale,
+                           (int)drive);
     return hipGetLastError();
 }
 
@@ -200,7 +210,8 @@ hipError_t launch_sweep(const T* fin, T* fout, const SweepArgs& a, int mode, con
 }
 
 #define LBIB_SWEEP_INSTANTIATE(T)                                                                               \
-    template hipError_t launch_init<T>(T*, int32_t, int32_t, int32_t, int64_t, double, double, bool, hipStream_t); \
+    template hipError_t launch_init<T>(T*, int32_t, int32_t, int32_t, int64_t, double, double, bool, int32_t,     \
+                                       hipStream_t);                                                             \
     template hipError_t launch_sweep<T>(const T*, T*, const SweepArgs&, int, const TileDesc*, const int64_t*,      \
                                         int32_t, bool, hipStream_t, hipEvent_t, hipEvent_t);                      \
     template hipError_t launch_sweep_multi<T>(const T*, T*, const SweepArgs&, const unsigned long long*,           \

@@ -204,9 +204,20 @@ def _ligand_desc(g: dict) -> LigandDesc:
                       float(g["kbt_hat"]), float(g["hamaker_hat"]))
 
 
+def _state_dtype() -> np.dtype:
+    kinds = {C.c_int64: np.int64, C.c_int32: np.int32, C.c_double: np.float64}
+    dt = np.dtype([(n, kinds[t]) for n, t in ParticleState._fields_], align=True)
+    assert dt.itemsize == C.sizeof(ParticleState)
+    return dt
+
+
 def _trace_array(buf, count: int) -> np.ndarray:
-    return np.array([[float(getattr(buf[k], n)) for n in STATE_FIELDS] for k in range(count)]).reshape(
-        count, len(STATE_FIELDS))
+    """Records as float64 [count, 20] in the field order of STATE_FIELDS."""
+    a = np.frombuffer(buf, dtype=_state_dtype(), count=count)
+    out = np.empty((count, len(STATE_FIELDS)))
+    for c, n in enumerate(STATE_FIELDS):
+        out[:, c] = a[n]
+    return out
 
 
 # ----------------------------------------------------------------------------------------

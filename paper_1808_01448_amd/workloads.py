@@ -165,6 +165,30 @@ def sweep_member(nx: int, ny: int, shape: str, rho_l: tuple[int, int], strength:
     )
 
 
+def shear_setup(shape: str = "circle", rho_l: tuple[int, int] = (1, 2), re: float = 0.1, *, strength: int = 1,
+                H: int = 200, precision: str = "fp64", seed: int = 0, steps: int = 100_000,
+                theta0: float = 0.0) -> dict:
+    """The computational domain of the paper's adhesion study ("Modeling the adhesion
+    dynamics" section): [0, 10 H] x [0, H] with H = 200 nodes, tau = 1 (nu = 1/6), a resting
+    receptor wall at the bottom and a top wall moving at u_max = Re nu / H (drive 1, linear
+    shear); the particle (area 0.025 H^2) at rest a gap y0 = 3e-3 H above the bottom wall,
+    at x = 10 H / 4.  theta0 = 0 puts the major axis normal to the wall (the paper does not
+    state the initial orientation of its ellipses)."""
+    a, b = _semi_axes(shape, float(H))
+    half_normal = a if abs(math.cos(theta0)) > 0.5 else b  # semi-axis along y at theta0 = 0 or pi/2
+    nx = 10 * H
+    return dict(
+        name=f"shear_{nx}x{H}_{shape}_rl{rho_l[0]}-{rho_l[1]}_s{strength}_re{re}_seed{seed}",
+        lattice=dict(nx=nx, ny=H, tau=1.0, re=re, drive=1, precision=PRECISION[precision], seed=seed),
+        particle=dict(shape=0 if shape == "circle" else 1, a_major=a, b_minor=b, xc=nx / 4.0,
+                      yc=-0.5 + 3e-3 * H + half_normal, theta0=theta0, rho_p=1.0,
+                      n_markers=_n_markers(shape, a, b)),
+        ligand=_ligand(rho_l, strength),
+        receptor=dict(wall=0, density=1.0),
+        steps=steps,
+    )
+
+
 def batched_sweep(seed: int = 0, *, precision: str = "fp32", steps: int = 10_000) -> list[dict]:
     """The 216-simulation sweep: shape {circle, AR2, AR3} x ligand density {0.3, 0.5, 0.7, 0.9}
     x bond strength {1, 2} x Re {0.01, 0.1, 1} x seed {0, 1, 2}; each grid drawn (in this
