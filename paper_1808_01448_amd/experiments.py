@@ -32,10 +32,17 @@ RHO_L = ((3, 10), (1, 2), (7, 10), (9, 10))
 
 def adhesion_study(shapes=("circle",), rho_ls=RHO_L, re: float = 0.1, *, steps: int = 200_000, strength: int = 1,
                    precision: str = "fp64", seed: int = 0, H: int = 200, theta0: float = 0.0, chunk: int = 20_000,
-                   log=None) -> list[dict]:
+                   k_f: float | None = None, log=None) -> list[dict]:
+    """k_f: the bond formation rate per step (the paper gives only k_f / k_r0 = 8.5e3, which
+    is kept; None takes the workloads reading)."""
     cases = [W.shear_setup(shape, rl, re, strength=strength, H=H, precision=precision, seed=seed, steps=steps,
                            theta0=theta0)
              for shape in shapes for rl in rho_ls]
+    if k_f is not None:
+        for w in cases:
+            aff = w["ligand"]["k_f"] / w["ligand"]["k_r0"]
+            w["ligand"]["k_f"], w["ligand"]["k_r0"] = k_f, k_f / aff
+            w["name"] += f"_kf{k_f:g}"
     budget = sum(lbib.Pool.footprint(w) for w in cases) + (256 << 20)
     out = []
     with lbib.Pool(W.PRECISION[precision], budget_bytes=budget) as P:
@@ -76,7 +83,7 @@ def summarize(w: dict, tr: np.ndarray, state: int) -> dict:
     return dict(
         case=w["name"], shape={0: "circle"}.get(part["shape"], "ellipse"),
         aspect=round(part["a_major"] / part["b_minor"], 3), rho_l=lig["rho_l_num"] / lig["rho_l_den"],
-        re=lat["re"], steps_run=int(len(tr)), finished=state == lbib.POOL_FINISHED,
+        re=lat["re"], k_f=lig["k_f"], steps_run=int(len(tr)), finished=state == lbib.POOL_FINISHED,
         n_markers=nl, n_ligands=n_lig, bonds=bonds, active_ligand_fraction=bonds / n_lig if n_lig else 0.0,
         bonds_per_marker=bonds / nl, max_bonds=int(tr[:, col["n_bonds"]].max()) if len(tr) else 0,
         y_min_over_H=float(half[:, col["gap"]].min() / H) if len(half) else float("nan"),
@@ -95,9 +102,10 @@ def main(argv=None) -> int:
     ap.add_argument("--precision", default="fp64", choices=list(W.PRECISION))
     ap.add_argument("--theta0", type=float, default=0.0)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--k-f", type=float, default=None, help="bond formation rate per step (affinity kept)")
     args = ap.parse_args(argv)
     res = adhesion_study(tuple(args.shapes), re=args.re, steps=args.steps, strength=args.strength,
-                         precision=args.precision, seed=args.seed, theta0=args.theta0,
+                         precision=args.precision, seed=args.seed, theta0=args.theta0, k_f=args.k_f,
                          log=lambda m: print(m, file=sys.stderr, flush=True))
     for r in res:
         print(json.dumps(r), flush=True)

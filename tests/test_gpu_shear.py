@@ -175,3 +175,25 @@ def test_shear_two_particles_against_oracle(L, orc):
         assert eU < 1e-10
         np.testing.assert_array_equal(tg[:, -2], to[:, k, -2])
     s.close()
+
+
+def test_adhesion_study_trends(L):
+    """The paper's domain (H = 200, [0, 10 H], tau = 1, Re 0.1, y0 = 3e-3 H), 30k steps in one
+    pool: the mean bond count grows with the ligand density (the trend of Tables 2-4), a flat
+    AR3 ellipse binds more ligands than the circle of the same area, and the bound circle rolls
+    clockwise with the shear (Omega < 0 here, counter-clockwise positive)."""
+    from paper_1808_01448_amd import experiments as E
+
+    res = E.adhesion_study(("circle", "ar3"), re=0.1, steps=30_000, precision="fp32", theta0=np.pi / 2,
+                           chunk=10_000)
+    for r in res:
+        say(r["case"], f"bonds {r['bonds']:.2f} y_min/H {r['y_min_over_H']:.2e} Omega H/u {r['omega_H_over_umax']:.3f}")
+        assert r["finished"]
+    circ = [r for r in res if r["shape"] == "circle"]
+    ell = [r for r in res if r["shape"] == "ellipse"]
+    for group in (circ, ell):
+        b = [r["bonds"] for r in sorted(group, key=lambda r: r["rho_l"])]
+        assert all(x < y for x, y in zip(b, b[1:])), b
+    for c, e in zip(sorted(circ, key=lambda r: r["rho_l"]), sorted(ell, key=lambda r: r["rho_l"])):
+        assert e["bonds"] > c["bonds"]
+    assert all(-0.5 < r["omega_H_over_umax"] < -0.05 for r in circ)
