@@ -225,8 +225,10 @@ lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size);
 
 /* Schedule of a step.  Overlapped (mode 1): the particle phase of step n runs on a second
  * stream the handle owns, concurrently with the sweep of every node outside the particle's
- * box (the nodes the step's MLS supports reach, predicted exactly by step n-1); the box is
- * swept after the particle phase.  Serial (mode 0), and always on the first step after
+ * box (the nodes the step's MLS supports reach, predicted exactly by step n-1) on a third
+ * stream the handle owns, restricted to every compute unit but one where the device allows
+ * CU masks; the particle's workgroup sweeps the box itself after the particle update.
+ * Serial (mode 0), and always on the first step after
  * lbib_init / lbib_load / lbib_write_particle: the particle phase and a sweep of all nodes
  * run one after the other on the handle's stream.  Mode 2 (the default) overlaps when one
  * sweep moves at least 64 MiB; below that the two cross-stream waits of a step cost more
@@ -259,8 +261,9 @@ lbib_status lbib_get_layout(lbib_handle h, int32_t* pull);
 
 /* Kernel timing: HIP events bracket every launch of the kernels selected by the bit mask
  * `enable` (0 switches timing off): bit 0 the lattice sweep of all nodes or of the nodes
- * outside the particle's box (kernel 0), bit 1 the particle phase (kernel 1), bit 2 the
- * sweep of the box (kernel 2).  lbib_kernel_time synchronises and returns the summed
+ * outside the particle's box (kernel 0), bit 1 the particle phase (kernel 1; in the
+ * overlapped schedule it includes the sweep of the box), bit 2 the second particle launch of
+ * the split phase (kernel 2).  lbib_kernel_time synchronises and returns the summed
  * milliseconds and launch counts since the last enable.  The events delay the hand-over
  * between the two streams of the overlapped schedule: time whole steps without them. */
 lbib_status lbib_kernel_timing(lbib_handle h, int32_t enable);

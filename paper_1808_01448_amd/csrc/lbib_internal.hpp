@@ -137,6 +137,11 @@ struct ParticleArgs {
     const PartRef* refs;
     int32_t mtx;
     int32_t nparts;  // entries of refs
+    // a single particle's phase may also sweep the nodes of its box (the overlapped
+    // schedule): when fout is set, the workgroup collides and streams every box node into
+    // fout with the lattice constants sw, after the particle update
+    T* fout;
+    SweepArgs sw;
 };
 
 // Launchers (lbib_sweep.hip, lbib_particle.hip).  All enqueue on `stream` and return the launch status.

@@ -16,6 +16,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "lbib_collide.hpp"
 #include "lbib_device.hpp"
 #include "lbib_internal.hpp"
 
@@ -137,12 +138,11 @@ struct MarkerGeo {
     double X, Y, nx, ny, px, py;
 };
 
-__device__ __forceinline__ MarkerGeo marker_geo(const double* xi, const double* nuv, int l, double xc, double yc,
+// (bx, by): body-frame centroid of the element, (mx, my): its body-frame outward normal.
+__device__ __forceinline__ MarkerGeo marker_geo(double bx, double by, double mx, double my, double xc, double yc,
                                                 double cth, double sth, int ny)
 {
     MarkerGeo g;
-    const double bx = xi[2 * l], by = xi[2 * l + 1];
-    const double mx = nuv[2 * l], my = nuv[2 * l + 1];
     g.X = xc + cth * bx - sth * by;
     g.Y = yc + sth * bx + cth * by;
     g.nx = cth * mx - sth * my;
@@ -211,17 +211,26 @@ struct MarkerSet {
     bool in[MPT];
 };
 
-template <typename T, int MPT>
-__device__ __forceinline__ void marker_set(const ParticleArgs<T>& a, double xc, double yc, double cth, double sth,
-                                           MarkerSet<MPT>& G)
+// Per-marker surface data of this thread's markers, read once at the start of the launch
+// (so the loads overlap): body-frame centroid and normal, element length, ligand and bond
+// flags at the start of the step.
+template <int MPT>
+struct MarkerData {
+    double bx[MPT], by[MPT], mx[MPT], my[MPT], S[MPT];
+    bool lig[MPT], bnd[MPT];
+};
+
+template <int MPT>
+__device__ __forceinline__ void marker_set(const MarkerData<MPT>& D, int nl, int ny, double xc, double yc, double cth,
+                                           double sth, MarkerSet<MPT>& G)
 {
 #pragma unroll
     for (int k = 0; k < MPT; ++k) {
         const int l = threadIdx.x + k * PB;
-        G.in[k] = l < a.nl;
+        G.in[k] = l < nl;
         G.X[k] = G.Y[k] = G.NX[k] = G.NY[k] = G.PX[k] = G.PY[k] = 0.0;
         if (G.in[k]) {
-            const MarkerGeo g = marker_geo(a.xi, a.nuv, l, xc, yc, cth, sth, a.ny);
+            const MarkerGeo g = marker_geo(D.bx[k], D.by[k], D.mx[k], D.my[k], xc, yc, cth, sth, ny);
             G.X[k] = g.X;
             G.Y[k] = g.Y;
             G.NX[k] = g.nx;
@@ -527,6 +536,8 @@ struct PhaseCtx {
     const int* pre;
     const int* nodes;
     MarkerSet<MPT> G;
+    MarkerData<MPT> D;
+    TileDesc zin;
 };
 
 // The particle phase after the box and its marked nodes are known; LDS: the node fields are
@@ -562,9 +573,9 @@ __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const Phase
         NXS[k] = NYS[k] = I0[k] = J0[k] = 0;
         S[k] = SFx[k] = SFy[k] = 0.0;
         if (l < nl) {
-            S[k] = a.S[l];
-            LIG[k] = a.ligand[l] != 0;
-            BND[k] = a.bond[l] != 0;
+            S[k] = c.D.S[k];
+            LIG[k] = c.D.lig[k];
+            BND[k] = c.D.bnd[k];
             Mls m;
             const bool ok = MODE != 2 && box_ok && mls_shape(c.G.X[k], fluid_row(c.G.Y[k], a.ny), a.ny, m, false);
             if (ok) {
@@ -674,7 +685,7 @@ __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const Phase
             d.pad = 0;
             *a.desc = d;
             if (a.check_zone) {
-                const TileDesc z = a.zone[a.parity_in];
+                const TileDesc z = c.zin;
                 // the concurrent sweep of the nodes outside the predicted box is only valid when
                 // the prediction equals this box
                 if (!z.active || z.i0w != d.i0w || z.j0 != d.j0 || z.w != d.w || z.h != d.h) flags |= FLAG_TILE;
@@ -875,7 +886,7 @@ __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const Phase
     if (MODE == 0) {
         const double nxc = shd[0][0], nyc = shd[1][0], nth = shd[2][0];
         MarkerSet<MPT> Gn;
-        marker_set<T, MPT>(a, nxc, nyc, cos(nth), sin(nth), Gn);
+        marker_set<MPT>(c.D, a.nl, a.ny, nxc, nyc, cos(nth), sin(nth), Gn);
         int rn[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
         set_bounds<MPT>(Gn, a.ny, rn);
         const int op[4] = {2, 2, 2, 2};
@@ -893,6 +904,26 @@ __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const Phase
             z.i0u = rn[0] != 0x7fffffff ? rn[0] : 0;
             z.pad = 0;
             a.zone[a.parity_out] = z;
+        }
+        // ---- the sweep of the box nodes (the rest of the lattice is swept beside this
+        // launch): the force at a node is the body force plus this particle's spread there,
+        // as the box sweep kernel forms it from the tile -----------------------------------
+        if (a.fout && spread_ok) {
+            for (int k = tid; k < nbox; k += PB) {
+                const uint32_t mw = mask[k >> 5];
+                int64_t qx = 0, qy = 0;
+                if ((mw >> (k & 31)) & 1u) {
+                    const int s = pre[k >> 5] + __popc(mw & ((1u << (k & 31)) - 1u));
+                    qx = (int64_t)force_load<LDS>(B.fx + s);
+                    qy = (int64_t)force_load<LDS>(B.fy + s);
+                }
+                const int i = wrap(x0 + k % w, a.nx), j = y0 + k / w;
+                const double Fx = a.sw.gx + ldexp((double)qx, -scale), Fy = a.sw.gy + ldexp((double)qy, -scale);
+                if (a.pull)
+                    collide_stream<T, true>(a.f, a.fout, a.sw, i, j, Fx, Fy);
+                else
+                    collide_stream<T, false>(a.f, a.fout, a.sw, i, j, Fx, Fy);
+            }
         }
     }
 }
@@ -948,6 +979,24 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, char* l
         dq = *rq.desc;
     }
     PhaseCtx<MPT> c;
+#pragma unroll
+    for (int k = 0; k < MPT; ++k) {
+        const int l = tid + k * PB;
+        c.D.bx[k] = c.D.by[k] = c.D.mx[k] = c.D.my[k] = c.D.S[k] = 0.0;
+        c.D.lig[k] = c.D.bnd[k] = false;
+        if (l < a.nl) {
+            c.D.bx[k] = a.xi[2 * l];
+            c.D.by[k] = a.xi[2 * l + 1];
+            c.D.mx[k] = a.nuv[2 * l];
+            c.D.my[k] = a.nuv[2 * l + 1];
+            c.D.S[k] = a.S[l];
+            c.D.lig[k] = a.ligand[l] != 0;
+            c.D.bnd[k] = a.bond[l] != 0;
+        }
+    }
+    TileDesc zin{};  // the box the previous step predicted for this one (thread 0)
+    if (MODE == 0 && a.check_zone && tid == 0) zin = a.zone[a.parity_in];
+    c.zin = zin;
     const DevParticle* st = a.st;
     c.xc = st->xc;
     c.yc = st->yc;
@@ -965,7 +1014,7 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, char* l
     c.cth = cos(c.th);
     c.sth = sin(c.th);
     c.flags = 0;
-    marker_set<T, MPT>(a, c.xc, c.yc, c.cth, c.sth, c.G);
+    marker_set<MPT>(c.D, a.nl, a.ny, c.xc, c.yc, c.cth, c.sth, c.G);
 
     // ---- the box: every node a marker or probe support reaches this step --------------
     int r[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};

@@ -167,3 +167,17 @@ def test_multi_overlapped_schedule_identical(L):
     for k in range(6):
         np.testing.assert_array_equal(outs[0][1][k], outs[1][1][k])
     np.testing.assert_array_equal(outs[0][2], outs[1][2])
+
+
+def test_sixty_four_particles_against_oracle(L, orc):
+    """The most particles a lattice takes: 64 small ellipses on 2048 x 512 (every bit of the
+    64-bit tile-mask words in use), FP32, 120 steps."""
+    w = W.multi_particle_channel(2048, 512, 64, seed=5, precision="fp32", area_frac=0.004, steps=120)
+    assert len(w["particles"]) == 64
+    steps = 120
+    s, tg = gpu_run(L, w, steps)
+    o = orc.Sim.from_workload(W.with_precision(w, "fp64"))
+    _, to = o.step_all(steps)
+    for k in (0, 31, 62, 63):
+        compare(tg[k], to[:, k, :], w, k, TOL["fp32"], "64 particles")
+    s.close()
