@@ -239,10 +239,14 @@ lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size);
  * particle that reaches a probe node, summed in particle order), bonds and rigid-body update
  * -- and the sweep adds at each node the force of every particle whose box reaches it, in
  * particle order.  For a single particle it gives the same results as modes 0-2.  Kernel
- * timing then reports the first launch as kernel 1 and the second as kernel 2.  A simulation
- * with several particles runs the two launches and the sweep in that order on its stream,
- * except in mode 1, where the second launch runs on a second stream beside the sweep (same
- * results; two cross-stream waits per step). */
+ * timing then reports the first launch as kernel 1 and the second as kernel 2.  With several
+ * particles, modes 0 and 2 run both halves as one launch whose workgroups (one per particle,
+ * each taking a CU) wait for each other between the spread and the loads; it starts after
+ * the stream's previous work, and a wait that exceeds a few seconds (other streams keeping
+ * every CU busy) fails the simulation with LBIB_E_NUMERIC rather than hang: use mode 3 beside
+ * such work.  Mode 3 runs the two launches and the sweep in order on the handle's stream;
+ * mode 1 runs the second launch on a second stream beside the sweep.  All give the same
+ * results bit for bit. */
 lbib_status lbib_set_overlap(lbib_handle h, int32_t mode);
 
 /* Storage layout of the population buffers, chosen before lbib_init: mode 0 push (the

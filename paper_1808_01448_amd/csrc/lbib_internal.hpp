@@ -15,6 +15,7 @@ enum : int32_t {
     FLAG_CONTACT = 2,    // analytic gap to the receptor wall <= 0
     FLAG_MLS = 4,        // singular MLS moment matrix
     FLAG_TILE = 8,       // spread footprint larger than the allocated tile
+    FLAG_SYNC = 16,      // a grid barrier of the one-launch particle phase timed out
 };
 
 // Rigid-body state of one particle, resident in device memory.  Levels n and n-1 feed the
@@ -142,6 +143,9 @@ struct ParticleArgs {
     // fout with the lattice constants sw, after the particle update
     T* fout;
     SweepArgs sw;
+    // the one-launch split phase: grid-barrier counter and the value this launch waits for
+    unsigned long long* bar;
+    unsigned long long bar_target;
 };
 
 // Launchers (lbib_sweep.hip, lbib_particle.hip).  All enqueue on `stream` and return the launch status.
@@ -189,6 +193,15 @@ template <typename T>
 hipError_t launch_particle_split(const ParticleArgs<T>* args, int32_t n, const T* f, unsigned long long* pmask,
                                  int32_t mode, int32_t max_nl, size_t lds, hipStream_t stream,
                                  hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+// The same phase as one launch: every workgroup spreads, then all meet at a grid barrier
+// (bar: a counter that only grows; this launch waits for it to reach target = its previous
+// value + n), then each evaluates its loads, bonds and update.  The n <= 64 workgroups
+// (one CU each) must be resident together: the caller launches it only on a stream whose
+// previous work has finished and the barrier's wait is bounded.
+template <typename T>
+hipError_t launch_particle_fused(const ParticleArgs<T>* args, int32_t n, const T* f, unsigned long long* pmask,
+                                 int32_t max_nl, size_t lds, unsigned long long* bar, unsigned long long target,
+                                 hipStream_t stream);
 
 // A pool of independent simulations stepped together (one launch per kernel per step).
 // The particle launch runs member active[b] in workgroup b and copies the member's box

@@ -168,11 +168,11 @@ struct NodeView {
 };
 
 // A particle whose box of this step overlaps the box of the particle running the probe
-// launch, with where its spread force lies (PartRef).
+// launch, with where its spread force lies (PartRef); pid: its index.
 struct OvEntry {
     const int64_t* tile;
     const uint2* ring;
-    int32_t i0w, j0, w, h, scale, pad;
+    int32_t i0w, j0, w, h, scale, pid;
 };
 
 constexpr int kMaxParticles = 64;
@@ -383,6 +383,7 @@ __device__ __forceinline__ int overlap_list(const ParticleArgs<T>& a, const Part
                 take = (dq < w || dm < d.w) && d.j0 < y0 + h && y0 < d.j0 + d.h;
                 e.tile = rq.tile;
                 e.ring = rq.ring;
+                e.pid = q;
                 e.i0w = d.i0w;
                 e.j0 = d.j0;
                 e.w = d.w;
@@ -495,19 +496,6 @@ __device__ __forceinline__ void fill_nodes(const ParticleArgs<T>& a, const NodeV
     }
 }
 
-// Set this particle's bit in the step's mask of every 64 x 4 tile its box reaches.
-template <typename T>
-__device__ __forceinline__ void mark_tiles(const ParticleArgs<T>& a, int x0, int y0, int w, int h)
-{
-    const unsigned long long bit = 1ull << a.pid;
-    const int ty0 = y0 >> 2, ty1 = (y0 + h - 1) >> 2;
-    for (int c = threadIdx.x; c < w; c += PB) {
-        const int i = wrap(x0 + c, a.nx);
-        if (c != 0 && (i & 63) != 0) continue;  // one thread per tile column of the box
-        for (int ty = ty0; ty <= ty1; ++ty) atomicOr(a.pmask + (size_t)ty * a.mtx + (i >> 6), bit);
-    }
-}
-
 template <bool LDS>
 __device__ __forceinline__ void force_add(unsigned long long* p, int64_t v)
 {
@@ -522,6 +510,113 @@ __device__ __forceinline__ unsigned long long force_load(const unsigned long lon
 {
     if (LDS) return *p;
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The total spread force at every marked node, summed over the overlapping particles in
+// particle order, written over this particle's own fixed-point value (FP64 bits): its own
+// share comes from LDS, the others' from their compact lists (the one-launch split phase,
+// after its grid barrier).
+template <typename T, bool LDS>
+__device__ __forceinline__ void total_forces(const ParticleArgs<T>& a, const NodeView& B, const int* nodes, int nm,
+                                             int x0, int y0, int w, const OvEntry* ov, int nov)
+{
+    for (int s0 = 0; s0 < nm; s0 += PB * kFillU) {
+        int sl[kFillU], ii[kFillU], jj[kFillU];
+        double fx[kFillU], fy[kFillU];
+#pragma unroll
+        for (int u = 0; u < kFillU; ++u) {
+            sl[u] = s0 + u * PB + (int)threadIdx.x;
+            fx[u] = fy[u] = 0.0;
+            ii[u] = jj[u] = 0;
+            if (sl[u] < nm) {
+                const int k = nodes[sl[u]];
+                jj[u] = y0 + k / w;
+                ii[u] = wrap(x0 + k % w, a.nx);
+            }
+        }
+        for (int e = 0; e < nov; ++e) {
+            const OvEntry E = ov[e];
+            const bool self = E.pid == (int)a.pid;
+            int64_t tx[kFillU], ty[kFillU];
+            bool in[kFillU];
+#pragma unroll
+            for (int u = 0; u < kFillU; ++u) {
+                in[u] = false;
+                tx[u] = ty[u] = 0;
+                if (sl[u] >= nm) continue;
+                if (self) {
+                    in[u] = true;
+                    tx[u] = (int64_t)force_load<LDS>(B.fx + sl[u]);
+                    ty[u] = (int64_t)force_load<LDS>(B.fy + sl[u]);
+                    continue;
+                }
+                int di = ii[u] - E.i0w;
+                if (di < 0) di += a.nx;
+                const int dj = jj[u] - E.j0;
+                if (di >= E.w || dj < 0 || dj >= E.h) continue;
+                const int n = dj * E.w + di;
+                const uint2 r = E.ring[n >> 5];
+                if (!((r.x >> (n & 31)) & 1u)) continue;
+                const int q = (int)r.y + __popc(r.x & ((1u << (n & 31)) - 1u));
+                in[u] = true;
+                tx[u] = E.tile[2 * q];
+                ty[u] = E.tile[2 * q + 1];
+            }
+#pragma unroll
+            for (int u = 0; u < kFillU; ++u) {
+                if (!in[u]) continue;
+                fx[u] += ldexp((double)tx[u], -E.scale);
+                fy[u] += ldexp((double)ty[u], -E.scale);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kFillU; ++u) {
+            if (sl[u] >= nm) continue;
+            B.fx[sl[u]] = (unsigned long long)__double_as_longlong(fx[u]);
+            B.fy[sl[u]] = (unsigned long long)__double_as_longlong(fy[u]);
+        }
+    }
+}
+
+// Barrier of every workgroup of the one-launch split phase.  The workgroup barrier completes
+// every wave's stores into the L2 of its XCD; one thread then releases them at device scope
+// (writing back the L2), counts in, and polls (sleeping between polls) until the count
+// reaches the launch's target; its device-scope acquire invalidates the CU's caches, which
+// every wave of the workgroup shares, before the second workgroup barrier lets them read.
+// The workgroups are co-resident by size: at most 64 of them, one per CU (their LDS), and
+// the previous launch on the stream has finished.  The wait gives up after kSpinLimit polls
+// and raises FLAG_SYNC, so every workgroup always finishes.
+constexpr unsigned kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ void grid_barrier(unsigned long long* ctr, unsigned long long target, int& flags)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned polls = 0;
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++polls > kSpinLimit) {
+                flags |= FLAG_SYNC;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+// Set this particle's bit in the step's mask of every 64 x 4 tile its box reaches.
+template <typename T>
+__device__ __forceinline__ void mark_tiles(const ParticleArgs<T>& a, int x0, int y0, int w, int h)
+{
+    const unsigned long long bit = 1ull << a.pid;
+    const int ty0 = y0 >> 2, ty1 = (y0 + h - 1) >> 2;
+    for (int c = threadIdx.x; c < w; c += PB) {
+        const int i = wrap(x0 + c, a.nx);
+        if (c != 0 && (i & 63) != 0) continue;  // one thread per tile column of the box
+        for (int ty = ty0; ty <= ty1; ++ty) atomicOr(a.pmask + (size_t)ty * a.mtx + (i >> 6), bit);
+    }
 }
 
 // What the first part of the particle phase hands to the rest.
@@ -545,7 +640,7 @@ struct PhaseCtx {
 // barriers, device-scope atomics for the force).
 template <typename T, int MPT, bool LDS, int MODE>
 __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const PhaseCtx<MPT>& c, const NodeView& B,
-                                           const OvEntry* ov, int nov, double (*shd)[NW], int (*shi)[NW])
+                                           OvEntry* ov, int nov, double (*shd)[NW], int (*shi)[NW])
 {
     const int tid = threadIdx.x;
     const int nl = a.nl;
@@ -648,7 +743,7 @@ __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const Phase
             }
         }
         __syncthreads();
-        if (spread_ok && MODE == 1) {
+        if (spread_ok && (MODE == 1 || MODE == 4)) {
             // the compact list and its index for the sweep and the other particles' probes
             for (int k = tid; k < c.nmarked; k += PB) {
                 longlong2 t;
@@ -692,14 +787,30 @@ __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const Phase
             }
         }
     }
-    if (MODE == 1) {
+    if (MODE == 1 || MODE == 4) {
         __syncthreads();
         if (box_ok) mark_tiles(a, x0, y0, w, h);
+    }
+    if (MODE == 1) {
         int v[1] = {flags};
         const int op[1] = {1};
         block_int<1>(v, op, shi);
         if (tid == 0 && v[0]) atomicOr(a.flags, v[0]);
         return;
+    }
+    if (MODE == 4) {
+        // every particle's list, index, box and tile bits of this step are written: meet,
+        // then read the other boxes and sum the total spread force at the marked nodes
+        grid_barrier(a.bar, a.bar_target, flags);
+        PartRef rq{};
+        TileDesc dq{};
+        if (tid < a.nparts) {
+            rq = a.refs[tid];
+            dq = *rq.desc;
+        }
+        const int nov4 = overlap_list(a, rq, dq, x0, y0, w, h, ov, shi);
+        total_forces<T, LDS>(a, B, c.nodes, c.nmarked, x0, y0, w, ov, nov4);
+        __syncthreads();
     }
 
     // ---- probe loads (eq 7-8) and wall distances ---------------------------------------
@@ -726,7 +837,7 @@ __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const Phase
                             const int e = 3 * bb + cc;
                             const int s = sr + cc;
                             double vx = B.ux[s], vy = B.uy[s];
-                            if (MODE == 2) {
+                            if (MODE == 2 || MODE == 4) {
                                 const double fx = __longlong_as_double((long long)B.fx[s]);
                                 const double fy = __longlong_as_double((long long)B.fy[s]);
                                 const double hinv = 0.5 * B.inv[s];
@@ -931,7 +1042,7 @@ __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const Phase
 // Lays out the node fields and the node map of the marked nodes from base (LDS: dynamic LDS,
 // else the global scratch), writes the map and runs the rest of the phase.
 template <typename T, int MPT, bool LDS, int MODE>
-__device__ __forceinline__ void phase_rest(const ParticleArgs<T>& a, PhaseCtx<MPT>& c, double* base, const OvEntry* ov,
+__device__ __forceinline__ void phase_rest(const ParticleArgs<T>& a, PhaseCtx<MPT>& c, double* base, OvEntry* ov,
                                            int nov, double (*shd)[NW], int (*shi)[NW])
 {
     const int m = c.nmarked;
@@ -1035,7 +1146,8 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, char* l
     const int nw = (c.nbox + 31) / 32;
     for (int k = tid; k < nw; k += PB) mask[k] = 0u;
     __syncthreads();
-    if (c.box_ok) mark_windows<MPT>(c.G, a.ny, MODE == 0 ? 3 : MODE == 1 ? 1 : 2, c.x0, c.y0, c.w, c.h, mask);
+    if (c.box_ok)
+        mark_windows<MPT>(c.G, a.ny, (MODE == 0 || MODE == 4) ? 3 : MODE == 1 ? 1 : 2, c.x0, c.y0, c.w, c.h, mask);
     __syncthreads();
     c.nmarked = mask_prefix(mask, pre, nw, shi);
     c.mask = mask;
@@ -1112,6 +1224,47 @@ hipError_t launch_particle_split(const ParticleArgs<T>* args, int32_t n, const T
     if (max_nl <= PB) LBIB_SPLIT(1);
     if (max_nl <= 2 * PB) LBIB_SPLIT(2);
 #undef LBIB_SPLIT
+    return hipErrorInvalidValue;
+}
+
+// The split phase as one launch (MODE 4): workgroup b runs particle b; the workgroups meet
+// at a grid barrier between the spread and the loads.
+template <typename T, int MPT>
+__global__ __launch_bounds__(PB) void fused_particle_kernel(const ParticleArgs<T>* __restrict__ args,
+                                                            const T* __restrict__ f,
+                                                            unsigned long long* __restrict__ pmask, uint32_t lds_bytes,
+                                                            unsigned long long* bar, unsigned long long target)
+{
+    extern __shared__ double lds_dyn[];
+    ParticleArgs<T> a = args[blockIdx.x];
+    a.f = f;
+    a.pmask = pmask;
+    a.bar = bar;
+    a.bar_target = target;
+    particle_phase<T, MPT, 4>(a, (char*)lds_dyn, lds_bytes);
+}
+
+template <typename T, int MPT>
+hipError_t launch_fused_mpt(const ParticleArgs<T>* args, int32_t n, const T* f, unsigned long long* pmask, size_t lds,
+                            unsigned long long* bar, unsigned long long target, hipStream_t stream)
+{
+    static bool attr = false;
+    hipError_t e = allow_max_lds(fused_particle_kernel<T, MPT>, attr);
+    if (e != hipSuccess) return e;
+    hipExtLaunchKernelGGL(fused_particle_kernel<T, MPT>, dim3(n), dim3(PB), (uint32_t)lds, stream, nullptr, nullptr, 0u,
+                          args, f, pmask, (uint32_t)lds, bar, target);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_particle_fused(const ParticleArgs<T>* args, int32_t n, const T* f, unsigned long long* pmask,
+                                 int32_t max_nl, size_t lds, unsigned long long* bar, unsigned long long target,
+                                 hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    if (n > kMaxParticles || lds > kLdsMax || lds < kLdsHead || !bar) return hipErrorInvalidValue;
+    if (max_nl <= PB) return launch_fused_mpt<T, 1>(args, n, f, pmask, lds, bar, target, stream);
+    if (max_nl <= 2 * PB) return launch_fused_mpt<T, 2>(args, n, f, pmask, lds, bar, target, stream);
     return hipErrorInvalidValue;
 }
 
@@ -1319,7 +1472,10 @@ hipError_t launch_copy(const float4* src, float4* dst, int64_t n, hipStream_t st
                                                 int32_t, size_t, hipStream_t, hipEvent_t, hipEvent_t);          \
     template hipError_t launch_particle<T>(const ParticleArgs<T>&, hipStream_t, hipEvent_t, hipEvent_t);        \
     template hipError_t launch_particle_split<T>(const ParticleArgs<T>*, int32_t, const T*, unsigned long long*, \
-                                                 int32_t, int32_t, size_t, hipStream_t, hipEvent_t, hipEvent_t);
+                                                 int32_t, int32_t, size_t, hipStream_t, hipEvent_t, hipEvent_t); \
+    template hipError_t launch_particle_fused<T>(const ParticleArgs<T>*, int32_t, const T*, unsigned long long*, \
+                                                 int32_t, size_t, unsigned long long*, unsigned long long,        \
+                                                 hipStream_t);
 LBIB_PARTICLE_INSTANTIATE(double)
 LBIB_PARTICLE_INSTANTIATE(float)
 LBIB_PARTICLE_INSTANTIATE(half_t)

@@ -398,6 +398,7 @@ std::string flag_text(int32_t fl)
     if (fl & FLAG_CONTACT) m += " particle touches the receptor wall (gap <= 0);";
     if (fl & FLAG_MLS) m += " singular MLS moment matrix;";
     if (fl & FLAG_TILE) m += " spread footprint exceeds the tile;";
+    if (fl & FLAG_SYNC) m += " grid barrier timed out;";
     return m;
 }
 

@@ -55,6 +55,11 @@ struct lbib_sim {
     // split particle phase (several particles, or overlap mode 3): the two tile masks (by
     // step parity), every particle's box and tile, the particle arguments on the device
     unsigned long long* d_masks = nullptr;
+    // one-launch split phase: grid-barrier counter (grows by the particle count per launch),
+    // launches made, and whether the device has a CU for every particle's workgroup
+    unsigned long long* d_bar = nullptr;
+    uint64_t bar_launches = 0;
+    bool one_launch = false;
     int32_t mtx = 0;
     int64_t ntiles = 0;
     PartRef* d_refs = nullptr;
@@ -97,6 +102,7 @@ void free_all(lbib_sim* h)
     h->fA = h->fB = nullptr;
     dfree(h->d_flags);
     dfree(h->d_masks);
+    dfree(h->d_bar);
     dfree(h->d_refs);
     if (h->d_args) (void)hipFree(h->d_args);
     h->d_args = nullptr;
@@ -233,18 +239,34 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
             // against 55.2 us per step), so no other mode uses it.
             const bool ovl = h->overlap == 1;
             if (!joined) HIPCHK(h, hipStreamWaitEvent(h->stream, h->evB, 0));
-            const EvPair e1 = timing_events(h, 1);
-            HIPCHK(h, launch_particle_split<T>(args, np, fin, mcur, 1, h->max_nl, h->lds_bytes, h->stream,
-                                               e1.t0, e1.t1));
-            hipStream_t s2 = h->stream;
-            if (ovl) {
-                HIPCHK(h, hipEventRecord(h->evA, h->stream));
-                HIPCHK(h, hipStreamWaitEvent(h->stream2, h->evA, 0));
-                s2 = h->stream2;
+            // modes 0 and 2 with several particles: both halves in one launch, met at a grid
+            // barrier (same results; no second launch, no second staging of the supports).
+            // Its workgroups (one CU each) start together: the stream's previous work is done.
+            bool done = false;
+            if (h->one_launch && np > 1 && (h->overlap == 0 || h->overlap == 2)) {
+                const EvPair e1 = timing_events(h, 1);
+                if (e1.t0) HIPCHK(h, hipEventRecord(e1.t0, h->stream));
+                const unsigned long long target = (unsigned long long)(h->bar_launches + 1) * (unsigned long long)np;
+                HIPCHK(h, launch_particle_fused<T>(args, np, fin, mcur, h->max_nl, h->lds_bytes, h->d_bar, target,
+                                                   h->stream));
+                h->bar_launches += 1;
+                done = true;
+                if (e1.t1) HIPCHK(h, hipEventRecord(e1.t1, h->stream));
             }
-            const EvPair e2 = timing_events(h, 2);
-            HIPCHK(h, launch_particle_split<T>(args, np, fin, mcur, 2, h->max_nl, h->lds_bytes, s2, e2.t0, e2.t1));
-            if (ovl) HIPCHK(h, hipEventRecord(h->evB, h->stream2));
+            hipStream_t s2 = h->stream;
+            if (!done) {
+                const EvPair e1 = timing_events(h, 1);
+                HIPCHK(h, launch_particle_split<T>(args, np, fin, mcur, 1, h->max_nl, h->lds_bytes, h->stream,
+                                                   e1.t0, e1.t1));
+                if (ovl) {
+                    HIPCHK(h, hipEventRecord(h->evA, h->stream));
+                    HIPCHK(h, hipStreamWaitEvent(h->stream2, h->evA, 0));
+                    s2 = h->stream2;
+                }
+                const EvPair e2 = timing_events(h, 2);
+                HIPCHK(h, launch_particle_split<T>(args, np, fin, mcur, 2, h->max_nl, h->lds_bytes, s2, e2.t0, e2.t1));
+                if (ovl) HIPCHK(h, hipEventRecord(h->evB, h->stream2));
+            }
             const EvPair e0 = timing_events(h, 0);
             HIPCHK(h, launch_sweep_multi<T>(fin, fout, sa, mcur, mnext, h->d_refs, h->g.pull, h->stream, e0.t0, e0.t1));
             joined = !ovl;
@@ -324,6 +346,7 @@ lbib_status check_flags(lbib_sim* h)
         if (fl & FLAG_CONTACT) m += " particle touches the receptor wall (gap <= 0);";
         if (fl & FLAG_MLS) m += " singular MLS moment matrix;";
         if (fl & FLAG_TILE) m += " spread footprint exceeds the tile;";
+        if (fl & FLAG_SYNC) m += " grid barrier timed out;";
         return fail(h, LBIB_E_NUMERIC, m);
     }
     return LBIB_OK;
@@ -496,6 +519,14 @@ lbib_status lbib_init(lbib_handle h)
             h->lds_bytes = std::max(h->lds_bytes, particle_launch_lds(p.box_cap));
         }
         const size_t args_bytes = np * std::max(sizeof(ParticleArgs<double>), sizeof(ParticleArgs<float>));
+        int cus = 0, dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+            h->one_launch = cus >= (int)np;
+        h->bar_launches = 0;
+        if ((e = dalloc(&h->d_bar, 1)) != hipSuccess ||
+            (e = hipMemsetAsync(h->d_bar, 0, sizeof(unsigned long long), h->stream)) != hipSuccess)
+            return bail(e, "lbib_init: barrier counter");
         if ((e = dalloc(&h->d_masks, (size_t)(2 * h->ntiles))) != hipSuccess ||
             (e = dalloc(&h->d_refs, np)) != hipSuccess || (e = hipMalloc(&h->d_args, args_bytes)) != hipSuccess)
             return bail(e, "lbib_init: device allocation");

@@ -181,3 +181,21 @@ def test_sixty_four_particles_against_oracle(L, orc):
     for k in (0, 31, 62, 63):
         compare(tg[k], to[:, k, :], w, k, TOL["fp32"], "64 particles")
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp16"])
+def test_one_launch_equals_two_launches(L, prec):
+    """Several particles: the one cooperative launch (spread, grid barrier, loads; the default)
+    and the two launches of mode 3 give the same particles, bonds and populations bit for
+    bit, including neighbours whose probe supports reach each other's spread."""
+    w = W.multi_particle_channel(256, 96, 8, seed=6, precision=prec, area_frac=0.03)
+    outs = []
+    for mode in (2, 3):
+        s, tr = gpu_run(L, w, 200, overlap=mode)
+        outs.append(([s.particle(k) for k in range(8)], tr, s.f, [s.bonds(k)[0] for k in range(8)]))
+        s.close()
+    assert outs[0][0] == outs[1][0]
+    for k in range(8):
+        np.testing.assert_array_equal(outs[0][1][k], outs[1][1][k])
+        np.testing.assert_array_equal(outs[0][3][k], outs[1][3][k])
+    np.testing.assert_array_equal(outs[0][2], outs[1][2])
