@@ -107,8 +107,9 @@ def batched_leg(steps: int, stream) -> dict:
 
 def multi_leg(steps: int, err_steps: int, stream) -> dict:
     """2048 x 512 channel with 32 particles (aspect ratio 1-3, area 0.025 H^2 each), Re 0.1:
-    throughput with FP32, FP16 and BF16 population storage, and each storage's error against
-    the FP64 oracle over the first err_steps steps."""
+    throughput with FP32, FP16 and BF16 storage of f - w_q and FP16 and BF16 storage of
+    f - f_eq (the "_neq" storages), and each storage's error against the FP64 oracle over the
+    first err_steps steps."""
     import numpy as np
 
     import oracle
@@ -135,7 +136,7 @@ def multi_leg(steps: int, err_steps: int, stream) -> dict:
                        "then the sweep",
            "unit": "MLUPS", "steps_timed": steps, "error_steps": err_steps,
            "oracle_seconds": round(t_orc, 2), "storages": {}}
-    for prec in ("fp32", "fp16", "bf16"):
+    for prec in ("fp32", "fp16", "bf16", "fp16_neq", "bf16_neq"):
         wp = W.with_precision(w, prec)
         s = lbib.Sim(wp, stream=stream)
         for k in range(n):

@@ -75,8 +75,12 @@ typedef enum {
  * momentum balance at a level that accumulates over thousands of steps at the small
  * velocities of capillary flow) and in FP32 for the 16-bit storages, whose rounding is far
  * coarser.  The particle phase (MLS solves, interpolation, loads, bonds, reductions, rigid
- * body) is FP64 for every storage.  Bytes per lattice update: 144, 72, 36, 36. */
-enum { LBIB_FP64 = 0, LBIB_FP32 = 1, LBIB_FP16 = 2, LBIB_BF16 = 3 };
+ * body) is FP64 for every storage.  Bytes per lattice update: 144, 72, 36, 36. *
+ * LBIB_FP16_NEQ and LBIB_BF16_NEQ store instead f - f_eq(rho, u) of the node that emitted
+ * each population (its non-equilibrium part, typically 10^-2 of f - w_q), in the same two
+ * formats (FP16 with the same scale rule), with that node's rho - 1, u_x and u_y kept beside
+ * in FP32; the collision runs in FP64.  Bytes per lattice update: 60. */
+enum { LBIB_FP64 = 0, LBIB_FP32 = 1, LBIB_FP16 = 2, LBIB_BF16 = 3, LBIB_FP16_NEQ = 4, LBIB_BF16_NEQ = 5 };
 
 /* Lattice (section "Modeling the adhesion dynamics ..."; Table 1).  drive: 0 body-force
  * Poiseuille with resting walls, 1 moving top wall (linear shear); the initial state is the

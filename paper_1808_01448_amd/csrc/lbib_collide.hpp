@@ -26,8 +26,9 @@ using namespace dev;
 // bit-identical results.  The compute type C is FP64 for the FP64 and FP32 storages and
 // FP32 for the 16-bit ones, whose storage rounding is far coarser than FP32 arithmetic.
 // ---------------------------------------------------------------------------------------
+// m (optional): the (rho - 1, u_x, u_y) the equilibrium was formed with.
 template <typename C>
-__device__ __forceinline__ void collide_node(const C g[9], const SweepArgs& a, C Fx, C Fy, C post[9])
+__device__ __forceinline__ void collide_node(const C g[9], const SweepArgs& a, C Fx, C Fy, C post[9], C* m = nullptr)
 {
     C drho, jx, jy;
     shifted_moments<C, C>(g, drho, jx, jy);
@@ -48,6 +49,34 @@ __device__ __forceinline__ void collide_node(const C g[9], const SweepArgs& a, C
         const C src = guo * w * fma(c9 * eu, eF, c3 * (eF - uF));
         post[q] = fma(-omega, g[q] - geq, g[q]) + src;
     }
+    if (m) {
+        m[0] = drho;
+        m[1] = ux;
+        m[2] = uy;
+    }
+}
+
+// Non-equilibrium storages: the post-collision values leave relative to the equilibrium of
+// the moments stored for this node (rounded to FP32 first, so that every reader forms the same
+// equilibrium from them), and the moments are stored at the node.
+template <typename T, typename C>
+__device__ __forceinline__ void neq_encode(T* fout, const SweepArgs& a, size_t c, const C m[3], C post[9], bool nt)
+{
+    if constexpr (St<T>::neq) {
+        float* mo = neq_moments(fout, a.plane);
+        const float m0 = (float)m[0], m1 = (float)m[1], m2 = (float)m[2];
+        if (nt) {
+            __builtin_nontemporal_store(m0, mo + c);
+            __builtin_nontemporal_store(m1, mo + a.plane + c);
+            __builtin_nontemporal_store(m2, mo + 2 * a.plane + c);
+        } else {
+            mo[c] = m0;
+            mo[a.plane + c] = m1;
+            mo[2 * a.plane + c] = m2;
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) post[q] -= feq_shift<C>(q, (C)m0, (C)m1, (C)m2);
+    }
 }
 
 // Push layout: collide node (i, j) and scatter its populations to the neighbours, with
@@ -61,11 +90,10 @@ __device__ __forceinline__ void collide_push(const T* __restrict__ fin, T* __res
     const size_t c = (size_t)j * a.pitch + i;
     // populations are read exactly once per step: stream them past the caches
     C g[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) g[q] = st_load(fin, q * P + c, a.inv_scale, true);
-    wall_reflect<C>(g, j, a.ny, a.uw6);
-    C post[9];
-    collide_node<C>(g, a, (C)Fx, (C)Fy, post);
+    load_node<T, C>(fin, i, j, a.nx, a.ny, a.pitch, P, false, a.inv_scale, a.uw6, true, g);
+    C post[9], m[3];
+    collide_node<C>(g, a, (C)Fx, (C)Fy, post, m);
+    neq_encode<T, C>(fout, a, c, m, post, false);
 
     const int ip = (i + 1 == a.nx) ? 0 : i + 1;
     const int im = (i == 0) ? a.nx - 1 : i - 1;
@@ -108,11 +136,10 @@ __device__ __forceinline__ void collide_pull(const T* __restrict__ fin, T* __res
     const int64_t P = a.plane;
     const size_t c = (size_t)j * a.pitch + i;
     C g[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) g[q] = st_load(fin, pop_index(q, i, j, a.nx, a.ny, a.pitch, P, true), a.inv_scale, true);
-    wall_reflect<C>(g, j, a.ny, a.uw6);
-    C post[9];
-    collide_node<C>(g, a, (C)Fx, (C)Fy, post);
+    load_node<T, C>(fin, i, j, a.nx, a.ny, a.pitch, P, true, a.inv_scale, a.uw6, true, g);
+    C post[9], m[3];
+    collide_node<C>(g, a, (C)Fx, (C)Fy, post, m);
+    neq_encode<T, C>(fout, a, c, m, post, true);
 #pragma unroll
     for (int q = 0; q < 9; ++q) st_store(fout, q * P + c, post[q], a.scale, true);
 }

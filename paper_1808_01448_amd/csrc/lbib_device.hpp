@@ -66,6 +66,15 @@ __device__ __forceinline__ float st_load(const bf16_t* p, int64_t i, double, boo
     return __builtin_bit_cast(float, (uint32_t)b << 16);
 }
 
+__device__ __forceinline__ float st_load(const half_neq_t* p, int64_t i, double inv_scale, bool nt)
+{
+    return st_load((const half_t*)p, i, inv_scale, nt);
+}
+__device__ __forceinline__ float st_load(const bf16_neq_t* p, int64_t i, double inv_scale, bool nt)
+{
+    return st_load((const bf16_t*)p, i, inv_scale, nt);
+}
+
 __device__ __forceinline__ void st_store(double* p, int64_t i, double v, double, bool nt)
 {
     if (nt)
@@ -100,6 +109,59 @@ __device__ __forceinline__ void st_store(bf16_t* p, int64_t i, float v, double, 
         __builtin_nontemporal_store(b, r + i);
     else
         r[i] = b;
+}
+
+__device__ __forceinline__ void st_store(half_neq_t* p, int64_t i, double v, double scale, bool nt)
+{
+    st_store((half_t*)p, i, (float)v, scale, nt);
+}
+__device__ __forceinline__ void st_store(bf16_neq_t* p, int64_t i, double v, double scale, bool nt)
+{
+    st_store((bf16_t*)p, i, (float)v, scale, nt);
+}
+
+// The three FP32 moment planes (rho - 1, u_x, u_y per node, same pitch) that follow the nine
+// population planes of a non-equilibrium buffer.
+template <typename T>
+__device__ __forceinline__ const float* neq_moments(const T* f, int64_t plane)
+{
+    return (const float*)((const uint16_t*)f + 9 * plane);
+}
+template <typename T>
+__device__ __forceinline__ float* neq_moments(T* f, int64_t plane)
+{
+    return (float*)((uint16_t*)f + 9 * plane);
+}
+
+// Shifted equilibrium f_eq,q(rho, u) - w_q = w_q (drho + A + drho A) with
+// A = 3 e.u + 9/2 (e.u)^2 - 3/2 u^2 (eq 2), in the operation order of the collision.
+template <typename C>
+__device__ __forceinline__ C feq_shift(int q, C drho, C ux, C uy)
+{
+    const C c3 = 3.0, c45 = 4.5, c15 = 1.5;
+    const C uu = fma(ux, ux, uy * uy);
+    const C eu = (C)kEx[q] * ux + (C)kEy[q] * uy;
+    const C A = fma(c45 * eu, eu, fma(-c15, uu, c3 * eu));
+    return (C)kW[q] * fma(drho, A, drho + A);
+}
+
+// The node that emitted population q of node (i, j) and the direction it emitted it in:
+// (i - e_x, j - e_y) along q, or (i, j) itself along the opposite direction when that link
+// crosses a wall.
+__device__ __forceinline__ void pop_source(int q, int i, int j, int nx, int ny, int& si, int& sj, int& dir)
+{
+    const int jj = j - kEy[q];
+    if (jj < 0 || jj >= ny) {
+        si = i;
+        sj = j;
+        dir = kOpp[q];
+        return;
+    }
+    int ii = i - kEx[q];
+    ii = ii < 0 ? ii + nx : (ii >= nx ? ii - nx : ii);
+    si = ii;
+    sj = jj;
+    dir = q;
 }
 
 // Density and momentum of shifted populations g_q = f_q - w_q: rho = 1 + sum g (the weights
@@ -241,6 +303,29 @@ __device__ __forceinline__ void wall_reflect(C (&g)[9], int j, int ny, double uw
         g[7] -= (C)uw6;
         g[8] += (C)uw6;
     }
+}
+
+// The nine shifted populations g_q = f_q - w_q of node (i, j) at the start of a step, read
+// from a buffer in either layout as type R: the stored value, plus, for the non-equilibrium
+// storages, the shifted equilibrium of the node that emitted it (from the stored moments),
+// plus the moving wall's term.
+template <typename T, typename R>
+__device__ __forceinline__ void load_node(const T* f, int i, int j, int nx, int ny, int pitch, int64_t plane, bool pull,
+                                          double inv_scale, double uw6, bool nt, R (&g)[9])
+{
+#pragma unroll
+    for (int q = 0; q < 9; ++q) g[q] = (R)st_load(f, pop_index(q, i, j, nx, ny, pitch, plane, pull), inv_scale, nt);
+    if constexpr (St<T>::neq) {
+        const float* m = neq_moments(f, plane);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            int si, sj, dir;
+            pop_source(q, i, j, nx, ny, si, sj, dir);
+            const int64_t c = (int64_t)sj * pitch + si;
+            g[q] += feq_shift<R>(dir, (R)m[c], (R)m[plane + c], (R)m[2 * plane + c]);
+        }
+    }
+    wall_reflect<R>(g, j, ny, uw6);
 }
 
 __device__ __forceinline__ int wrap(int i, int n)

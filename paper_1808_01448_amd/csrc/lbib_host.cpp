@@ -105,8 +105,9 @@ lbib_status check_lattice(const lbib_lattice_desc& d, std::string& msg)
     if (!is_finite(d.tau) || !(d.tau > 0.5)) return msg = "tau must be > 1/2", LBIB_E_INVALID;
     if (!is_finite(d.re) || d.re < 0) return msg = "Re must be >= 0", LBIB_E_INVALID;
     if (d.drive != 0 && d.drive != 1) return msg = "drive must be 0 (Poiseuille) or 1 (moving top wall)", LBIB_E_INVALID;
-    if (d.precision != LBIB_FP64 && d.precision != LBIB_FP32 && d.precision != LBIB_FP16 && d.precision != LBIB_BF16)
-        return msg = "precision must be LBIB_FP64, LBIB_FP32, LBIB_FP16 or LBIB_BF16", LBIB_E_UNSUPPORTED;
+    if (d.precision < LBIB_FP64 || d.precision > LBIB_BF16_NEQ)
+        return msg = "precision must be one of LBIB_FP64, LBIB_FP32, LBIB_FP16, LBIB_BF16, LBIB_FP16_NEQ, LBIB_BF16_NEQ",
+               LBIB_E_UNSUPPORTED;
     return LBIB_OK;
 }
 
@@ -117,6 +118,7 @@ LatticeGeom lattice_geom(const lbib_lattice_desc& d)
     g.ny = d.ny;
     g.precision = d.precision;
     g.elem = d.precision == LBIB_FP64 ? 8 : d.precision == LBIB_FP32 ? 4 : 2;
+    g.neq = d.precision == LBIB_FP16_NEQ || d.precision == LBIB_BF16_NEQ;
     const int align = (int)(256 / g.elem);  // rows start on 256-byte boundaries
     g.pitch = (d.nx + align - 1) / align * align;
     g.plane = (int64_t)g.pitch * d.ny;
@@ -128,7 +130,9 @@ LatticeGeom lattice_geom(const lbib_lattice_desc& d)
     g.gx = d.drive == 1 ? 0.0 : 8.0 * g.nu * g.umax / (H * H);
     g.gy = 0.0;
     g.uw = d.drive == 1 ? g.umax : 0.0;
-    if (d.precision == LBIB_FP16) {
+    g.buf_bytes = (size_t)9 * g.plane * g.elem + (g.neq ? (size_t)3 * g.plane * 4 : 0);
+    g.upd_bytes = (int)(18 * g.elem) + (g.neq ? 24 : 0);
+    if (d.precision == LBIB_FP16 || d.precision == LBIB_FP16_NEQ) {
         // the largest deviation f - w to expect is that of the rest population at a few times
         // u_max; a power of two maps it to ~2^13, far below the binary16 maximum (65504) and
         // far above its subnormal range (< 2^-14)
@@ -229,7 +233,7 @@ void carve_particle(Particle& p, char* block)
 int64_t footprint_bytes(const lbib_lattice_desc& lat, const Particle* p)
 {
     const LatticeGeom g = lattice_geom(lat);
-    int64_t bytes = 2 * (int64_t)align_up((size_t)9 * g.plane * g.elem);
+    int64_t bytes = 2 * (int64_t)align_up(g.buf_bytes);
     if (p) bytes += (int64_t)particle_block_bytes(*p);
     return bytes;
 }
@@ -348,17 +352,25 @@ template void fill_particle_args<half_t>(ParticleArgs<half_t>&, const LatticeGeo
                                          int32_t*);
 template void fill_particle_args<bf16_t>(ParticleArgs<bf16_t>&, const LatticeGeom&, uint64_t, const Particle&,
                                          int32_t*);
+template void fill_particle_args<half_neq_t>(ParticleArgs<half_neq_t>&, const LatticeGeom&, uint64_t, const Particle&,
+                                             int32_t*);
+template void fill_particle_args<bf16_neq_t>(ParticleArgs<bf16_neq_t>&, const LatticeGeom&, uint64_t, const Particle&,
+                                             int32_t*);
 
 hipError_t init_populations(void* f, const LatticeGeom& g, hipStream_t s)
 {
-    const size_t bytes = (size_t)9 * g.plane * g.elem;
+    const size_t bytes = g.buf_bytes;
     hipError_t e = hipMemsetAsync(f, 0, bytes, s);
     if (e != hipSuccess) return e;
     switch (g.precision) {
         case LBIB_FP64: return launch_init<double>((double*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, g.scale, g.pull, g.drive, s);
         case LBIB_FP32: return launch_init<float>((float*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, g.scale, g.pull, g.drive, s);
         case LBIB_FP16: return launch_init<half_t>((half_t*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, g.scale, g.pull, g.drive, s);
-        default: return launch_init<bf16_t>((bf16_t*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, g.scale, g.pull, g.drive, s);
+        case LBIB_BF16: return launch_init<bf16_t>((bf16_t*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, g.scale, g.pull, g.drive, s);
+        case LBIB_FP16_NEQ:
+            return launch_init<half_neq_t>((half_neq_t*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, g.scale, g.pull, g.drive, s);
+        default:
+            return launch_init<bf16_neq_t>((bf16_neq_t*)f, g.nx, g.ny, g.pitch, g.plane, g.umax, g.scale, g.pull, g.drive, s);
     }
 }
 
@@ -369,26 +381,55 @@ static double wall_term(const LatticeGeom& g, int q)
     return q == 7 ? -g.uw / 6.0 : q == 8 ? g.uw / 6.0 : 0.0;
 }
 
+// Shifted equilibrium f_eq,q - w_q of moments (drho, u), in the device's operation order.
+static double feq_shift_host(int q, double drho, double ux, double uy)
+{
+    const double uu = std::fma(ux, ux, uy * uy);
+    const double eu = (double)kExq[q] * ux + (double)kEyq[q] * uy;
+    const double A = std::fma(4.5 * eu, eu, std::fma(-1.5, uu, 3.0 * eu));
+    return kWq[q] * std::fma(drho, A, drho + A);
+}
+
+// Non-equilibrium storages: the shifted equilibrium the reader of population q at (i, j)
+// adds, from the stored moments m (3 planes) of the node that emitted it.
+static double neq_term(const LatticeGeom& g, const float* m, int q, int i, int j)
+{
+    int si = i, sj = j, dir = q;
+    const int jj = j - kEyq[q];
+    if (jj < 0 || jj >= g.ny) {
+        dir = kOppq[q];
+    } else {
+        si = i - kExq[q];
+        si = si < 0 ? si + g.nx : (si >= g.nx ? si - g.nx : si);
+        sj = jj;
+    }
+    const int64_t c = (int64_t)sj * g.pitch + si;
+    return feq_shift_host(dir, (double)m[c], (double)m[g.plane + c], (double)m[2 * g.plane + c]);
+}
+
 hipError_t download_populations(const void* fdev, const LatticeGeom& g, std::vector<double>& f)
 {
     const int nx = g.nx, ny = g.ny;
-    const size_t n = (size_t)9 * g.plane;
     f.assign((size_t)9 * nx * ny, 0.0);
-    std::vector<unsigned char> raw(n * g.elem);
+    std::vector<unsigned char> raw(g.buf_bytes);
     hipError_t e = hipMemcpy(raw.data(), fdev, raw.size(), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return e;
+    const float* mom = (const float*)(raw.data() + (size_t)9 * g.plane * g.elem);
     const double inv = 1.0 / g.scale;
     for (int q = 0; q < 9; ++q)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 const int64_t k = host_pop_index(g, q, i, j);
-                double v = j == ny - 1 ? wall_term(g, q) : 0.0;
+                double v = 0.0;
                 switch (g.precision) {
-                    case LBIB_FP64: v += ((const double*)raw.data())[k]; break;
-                    case LBIB_FP32: v += (double)((const float*)raw.data())[k]; break;
-                    case LBIB_FP16: v += (double)f16_to_f32(((const uint16_t*)raw.data())[k]) * inv; break;
-                    default: v += (double)bf16_to_f32(((const uint16_t*)raw.data())[k]); break;
+                    case LBIB_FP64: v = ((const double*)raw.data())[k]; break;
+                    case LBIB_FP32: v = (double)((const float*)raw.data())[k]; break;
+                    case LBIB_FP16:
+                    case LBIB_FP16_NEQ: v = (double)f16_to_f32(((const uint16_t*)raw.data())[k]) * inv; break;
+                    default: v = (double)bf16_to_f32(((const uint16_t*)raw.data())[k]); break;
                 }
+                if (g.neq) v += neq_term(g, mom, q, i, j);
+                if (j == ny - 1) v += wall_term(g, q);
                 f[((size_t)q * ny + j) * nx + i] = kWq[q] + v;
             }
     return hipSuccess;
@@ -397,17 +438,38 @@ hipError_t download_populations(const void* fdev, const LatticeGeom& g, std::vec
 hipError_t upload_populations(void* fdev, const LatticeGeom& g, const double* f)
 {
     const int nx = g.nx, ny = g.ny;
-    const size_t n = (size_t)9 * g.plane;
-    std::vector<unsigned char> raw(n * g.elem, 0);
+    const size_t N = (size_t)nx * ny;
+    std::vector<unsigned char> raw(g.buf_bytes, 0);
+    float* mom = (float*)(raw.data() + (size_t)9 * g.plane * g.elem);
+    if (g.neq) {
+        // each node's moments (rho - 1, u) from the written populations: the equilibrium the
+        // values it emits are stored against
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                double r = 0.0, jx = 0.0, jy = 0.0;
+                for (int q = 0; q < 9; ++q) {
+                    const double v = f[(size_t)q * N + (size_t)j * nx + i];
+                    r += v;
+                    jx += v * kExq[q];
+                    jy += v * kEyq[q];
+                }
+                const int64_t c = (int64_t)j * g.pitch + i;
+                mom[c] = (float)(r - 1.0);
+                mom[g.plane + c] = (float)(jx / r);
+                mom[2 * g.plane + c] = (float)(jy / r);
+            }
+    }
     for (int q = 0; q < 9; ++q)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 const int64_t k = host_pop_index(g, q, i, j);
-                const double v = f[((size_t)q * ny + j) * nx + i] - kWq[q] - (j == ny - 1 ? wall_term(g, q) : 0.0);
+                double v = f[((size_t)q * ny + j) * nx + i] - kWq[q] - (j == ny - 1 ? wall_term(g, q) : 0.0);
+                if (g.neq) v -= neq_term(g, mom, q, i, j);
                 switch (g.precision) {
                     case LBIB_FP64: ((double*)raw.data())[k] = v; break;
                     case LBIB_FP32: ((float*)raw.data())[k] = (float)v; break;
-                    case LBIB_FP16: ((uint16_t*)raw.data())[k] = f32_to_f16((float)v * (float)g.scale); break;
+                    case LBIB_FP16:
+                    case LBIB_FP16_NEQ: ((uint16_t*)raw.data())[k] = f32_to_f16((float)v * (float)g.scale); break;
                     default: ((uint16_t*)raw.data())[k] = f32_to_bf16((float)v); break;
                 }
             }

@@ -28,6 +28,9 @@ struct LatticeGeom {
     double tau = 0, nu = 0, umax = 0, gx = 0, gy = 0;
     int drive = 0;    // 0 body-force Poiseuille, 1 moving top wall (linear shear)
     double uw = 0;    // speed of the top wall (umax for drive 1, else 0)
+    bool neq = false;       // values relative to the emitting node's equilibrium, moments beside
+    size_t buf_bytes = 0;   // one population buffer: 9 planes (+ 3 FP32 moment planes)
+    int upd_bytes = 0;      // HBM bytes of one lattice update
 };
 
 // Host conversions of the 16-bit storages (round to nearest even).

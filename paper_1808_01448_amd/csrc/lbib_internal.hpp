@@ -48,30 +48,56 @@ struct half_t {
 struct bf16_t {
     uint16_t b;
 };
+// The same two formats holding f - f_eq(rho, u) of the node that emitted the population (its
+// non-equilibrium part, far smaller than f - w), with that node's (rho - 1, u_x, u_y) kept
+// beside in FP32: three planes after the nine population planes of the buffer.
+struct half_neq_t {
+    uint16_t b;
+};
+struct bf16_neq_t {
+    uint16_t b;
+};
 
-// Storage traits: the bits in memory and the type the collision computes in (FP64 for the
-// FP64 and FP32 storages, FP32 for the 16-bit ones).
+// Storage traits: the bits in memory, the type the collision computes in (FP64 for the FP64,
+// FP32 and non-equilibrium storages, FP32 for the 16-bit f - w ones) and whether the stored
+// values are relative to the emitting node's equilibrium.
 template <typename T>
 struct St;
 template <>
 struct St<double> {
     using raw = double;
     using C = double;
+    static constexpr bool neq = false;
 };
 template <>
 struct St<float> {
     using raw = float;
     using C = double;
+    static constexpr bool neq = false;
 };
 template <>
 struct St<half_t> {
     using raw = uint16_t;
     using C = float;
+    static constexpr bool neq = false;
 };
 template <>
 struct St<bf16_t> {
     using raw = uint16_t;
     using C = float;
+    static constexpr bool neq = false;
+};
+template <>
+struct St<half_neq_t> {
+    using raw = uint16_t;
+    using C = double;
+    static constexpr bool neq = true;
+};
+template <>
+struct St<bf16_neq_t> {
+    using raw = uint16_t;
+    using C = double;
+    static constexpr bool neq = true;
 };
 
 // Lattice constants of one sweep.

@@ -422,11 +422,8 @@ __device__ __forceinline__ void fill_nodes(const ParticleArgs<T>& a, const NodeV
             if (kk[u] >= 0) {
                 jj[u] = y0 + kk[u] / w;
                 ii[u] = wrap(x0 + kk[u] % w, a.nx);
-#pragma unroll
-                for (int c = 0; c < 9; ++c)
-                    v[u][c] = (double)st_load(a.f, pop_index(c, ii[u], jj[u], a.nx, a.ny, a.pitch, a.plane, a.pull != 0),
-                                              a.inv_scale, false);
-                wall_reflect<double>(v[u], jj[u], a.ny, a.uw6);
+                load_node<T, double>(a.f, ii[u], jj[u], a.nx, a.ny, a.pitch, a.plane, a.pull != 0, a.inv_scale, a.uw6,
+                                     false, v[u]);
             }
         }
         double fx[kFillU], fy[kFillU];
@@ -1480,6 +1477,8 @@ LBIB_PARTICLE_INSTANTIATE(double)
 LBIB_PARTICLE_INSTANTIATE(float)
 LBIB_PARTICLE_INSTANTIATE(half_t)
 LBIB_PARTICLE_INSTANTIATE(bf16_t)
+LBIB_PARTICLE_INSTANTIATE(half_neq_t)
+LBIB_PARTICLE_INSTANTIATE(bf16_neq_t)
 #undef LBIB_PARTICLE_INSTANTIATE
 
 }  // namespace lbib

@@ -410,9 +410,10 @@ lbib_status lbib_pool_create(int32_t precision, int64_t hbm_budget_bytes, int32_
                              lbib_pool_handle* out)
 {
     if (!out) return fail(nullptr, LBIB_E_INVALID, "lbib_pool_create: NULL output");
-    if (precision != LBIB_FP64 && precision != LBIB_FP32 && precision != LBIB_FP16 && precision != LBIB_BF16)
+    if (precision < LBIB_FP64 || precision > LBIB_BF16_NEQ)
         return fail(nullptr, LBIB_E_UNSUPPORTED,
-                    "lbib_pool_create: precision must be LBIB_FP64, LBIB_FP32, LBIB_FP16 or LBIB_BF16");
+                    "lbib_pool_create: precision must be LBIB_FP64, LBIB_FP32, LBIB_FP16, LBIB_BF16, LBIB_FP16_NEQ or "
+                    "LBIB_BF16_NEQ");
     if (hbm_budget_bytes <= 0) return fail(nullptr, LBIB_E_INVALID, "lbib_pool_create: budget must be positive");
     if (max_members < 1 || max_members > 65536)
         return fail(nullptr, LBIB_E_INVALID, "lbib_pool_create: max_members must be in [1, 65536]");
@@ -507,7 +508,7 @@ lbib_status lbib_pool_add(lbib_pool_handle h, const lbib_lattice_desc* lat, cons
                         std::to_string(h->budget - h->in_use) + " left in the budget");
     m->block = h->arena.alloc((size_t)m->bytes);
     if (!m->block) return fail(h, LBIB_E_FULL, "lbib_pool_add: no contiguous free block of the budget is large enough");
-    const size_t pop = align_up((size_t)9 * m->g.plane * m->g.elem);
+    const size_t pop = align_up(m->g.buf_bytes);
     m->fA = m->block;
     m->fB = m->block + pop;
     carve_particle(m->p, m->block + 2 * pop);
@@ -544,7 +545,9 @@ lbib_status lbib_pool_step(lbib_pool_handle h, int64_t n)
         case LBIB_FP64: return enqueue<double>(h, n);
         case LBIB_FP32: return enqueue<float>(h, n);
         case LBIB_FP16: return enqueue<half_t>(h, n);
-        default: return enqueue<bf16_t>(h, n);
+        case LBIB_BF16: return enqueue<bf16_t>(h, n);
+        case LBIB_FP16_NEQ: return enqueue<half_neq_t>(h, n);
+        default: return enqueue<bf16_neq_t>(h, n);
     }
 }
 

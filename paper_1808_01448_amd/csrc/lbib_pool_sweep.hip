@@ -95,6 +95,8 @@ LBIB_POOL_SWEEP_INSTANTIATE(double)
 LBIB_POOL_SWEEP_INSTANTIATE(float)
 LBIB_POOL_SWEEP_INSTANTIATE(half_t)
 LBIB_POOL_SWEEP_INSTANTIATE(bf16_t)
+LBIB_POOL_SWEEP_INSTANTIATE(half_neq_t)
+LBIB_POOL_SWEEP_INSTANTIATE(bf16_neq_t)
 #undef LBIB_POOL_SWEEP_INSTANTIATE
 
 }  // namespace lbib

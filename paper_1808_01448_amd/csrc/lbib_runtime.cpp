@@ -203,7 +203,7 @@ hipError_t create_sweep_stream(hipStream_t* s)
 }
 
 // Bytes one lattice sweep moves (every population read and written once).
-double sweep_bytes(const lbib_sim* h) { return (double)h->desc.nx * h->desc.ny * 18.0 * h->g.elem; }
+double sweep_bytes(const lbib_sim* h) { return (double)h->desc.nx * h->desc.ny * h->g.upd_bytes; }
 
 // One time step is the particle phase then the lattice sweep.  Serial schedule: both on the
 // caller's stream.  Overlapped schedule (when the previous step has predicted this step's
@@ -379,7 +379,7 @@ struct BlobHeader {
 
 size_t blob_size(lbib_sim* h)
 {
-    size_t s = sizeof(BlobHeader) + (size_t)9 * h->g.plane * h->g.elem;
+    size_t s = sizeof(BlobHeader) + h->g.buf_bytes;
     for (auto& p : h->parts) s += sizeof(DevParticle) + (size_t)p.nl;
     return s;
 }
@@ -478,7 +478,7 @@ lbib_status lbib_init(lbib_handle h)
     if (h->state != 0) return fail(h, LBIB_E_STATE, "lbib_init: already initialised");
     for (auto& p : h->parts)
         if (!p.has_ligands) return fail(h, LBIB_E_STATE, "lbib_init: lbib_ligands_set missing for a particle");
-    const size_t bytes = (size_t)9 * h->g.plane * h->g.elem;
+    const size_t bytes = h->g.buf_bytes;
     // the push update's shifted stores are cheap while both buffers fit the 256 MB MALL
     // beside the rest of the working set; far above it the pull update's aligned stores win
     h->g.pull = h->layout == 1 || (h->layout == 2 && 2.0 * bytes > 512.0 * 1048576.0);
@@ -559,7 +559,9 @@ lbib_status lbib_step(lbib_handle h, int64_t n)
         case LBIB_FP64: return enqueue_steps<double>(h, n);
         case LBIB_FP32: return enqueue_steps<float>(h, n);
         case LBIB_FP16: return enqueue_steps<half_t>(h, n);
-        default: return enqueue_steps<bf16_t>(h, n);
+        case LBIB_BF16: return enqueue_steps<bf16_t>(h, n);
+        case LBIB_FP16_NEQ: return enqueue_steps<half_neq_t>(h, n);
+        default: return enqueue_steps<bf16_neq_t>(h, n);
     }
 }
 
@@ -768,7 +770,7 @@ lbib_status lbib_save(lbib_handle h, void* blob, int64_t* size)
     hd.nl = h->parts.empty() ? 0 : h->parts[0].nl;
     hd.layout = h->g.pull ? 1 : 0;
     hd.steps = h->steps;
-    hd.pop_bytes = (int64_t)9 * h->g.plane * (int64_t)h->g.elem;
+    hd.pop_bytes = (int64_t)h->g.buf_bytes;
     std::memcpy(w, &hd, sizeof(hd));
     w += sizeof(hd);
     HIPCHK(h, hipMemcpy(w, h->fA, (size_t)hd.pop_bytes, hipMemcpyDeviceToHost));
@@ -794,7 +796,7 @@ lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size)
     if (std::memcmp(hd.magic, "LBIBCKP2", 8) != 0 || hd.version != LBIB_ABI_VERSION || hd.nx != h->desc.nx ||
         hd.layout != (h->g.pull ? 1 : 0) ||
         hd.ny != h->desc.ny || hd.precision != h->desc.precision || hd.n_particles != (int32_t)h->parts.size() ||
-        (hd.n_particles && hd.nl != h->parts[0].nl) || hd.pop_bytes != (int64_t)9 * h->g.plane * (int64_t)h->g.elem)
+        (hd.n_particles && hd.nl != h->parts[0].nl) || hd.pop_bytes != (int64_t)h->g.buf_bytes)
         return fail(h, LBIB_E_INVALID, "lbib_load: checkpoint was made with different descriptors");
     const char* r = (const char*)blob + sizeof(hd);
     HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -882,7 +884,7 @@ lbib_status lbib_get_layout(lbib_handle h, int32_t* pull)
 lbib_status lbib_bytes_per_update(lbib_handle h, int64_t* bytes)
 {
     if (!h || !bytes) return fail(h, LBIB_E_INVALID, "lbib_bytes_per_update: NULL argument");
-    *bytes = (int64_t)(18 * h->g.elem);
+    *bytes = (int64_t)h->g.upd_bytes;
     return LBIB_OK;
 }
 

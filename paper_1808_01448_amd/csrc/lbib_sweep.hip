@@ -32,10 +32,15 @@ using namespace dev;
 // where the initial state prescribes it.  A value that reaches the top row through a moving
 // wall is stored without the wall term, which every load adds (wall_reflect).
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ double init_value(int q, int j, int ny, double umax, int drive)
+__device__ __forceinline__ double init_u(int j, int ny, double umax, int drive)
 {
     const double H = (double)ny;
-    const double u = drive == 1 ? umax * (j + 0.5) / H : 4.0 * umax * (j + 0.5) * (H - 0.5 - j) / (H * H);
+    return drive == 1 ? umax * (j + 0.5) / H : 4.0 * umax * (j + 0.5) * (H - 0.5 - j) / (H * H);
+}
+
+__device__ __forceinline__ double init_value(int q, int j, int ny, double umax, int drive)
+{
+    const double u = init_u(j, ny, umax, drive);
     const double eu = kEx[q] * u;
     return kW[q] * (3.0 * eu + 4.5 * eu * eu - 1.5 * u * u);
 }
@@ -61,7 +66,19 @@ __global__ __launch_bounds__(256) void init_kernel(T* f, int nx, int ny, int pit
         const int p = !PULL ? q : (dj >= ny ? kOpp[q] : -1);
         if (j == ny - 1 && p == 7) v += uw6;
         if (j == ny - 1 && p == 8) v -= uw6;
+        if constexpr (St<T>::neq) {
+            // relative to the equilibrium its reader forms from the emitting node's moments
+            int si = i, sj = j, dir = q;
+            if (!PULL) pop_source(q, i, j, nx, ny, si, sj, dir);
+            v -= feq_shift<double>(dir, 0.0, (double)(float)init_u(sj, ny, umax, drive), 0.0);
+        }
         st_store(f, q * plane + c, (typename St<T>::C)v, scale, false);
+    }
+    if constexpr (St<T>::neq) {
+        float* m = neq_moments(f, plane);
+        m[c] = 0.0f;
+        m[plane + c] = (float)init_u(j, ny, umax, drive);
+        m[2 * plane + c] = 0.0f;
     }
 }
 
@@ -221,6 +238,8 @@ LBIB_SWEEP_INSTANTIATE(double)
 LBIB_SWEEP_INSTANTIATE(float)
 LBIB_SWEEP_INSTANTIATE(half_t)
 LBIB_SWEEP_INSTANTIATE(bf16_t)
+LBIB_SWEEP_INSTANTIATE(half_neq_t)
+LBIB_SWEEP_INSTANTIATE(bf16_neq_t)
 #undef LBIB_SWEEP_INSTANTIATE
 
 }  // namespace lbib

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "_lib", "liblbib.so")
 OK, E_INVALID, E_STATE, E_NOMEM, E_DEVICE, E_NUMERIC, E_UNSUPPORTED, E_FULL = 0, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_STATE", -3: "E_NOMEM", -4: "E_DEVICE", -5: "E_NUMERIC",
                 -6: "E_UNSUPPORTED", -7: "E_FULL"}
-FP64, FP32, FP16, BF16 = 0, 1, 2, 3
+FP64, FP32, FP16, BF16, FP16_NEQ, BF16_NEQ = 0, 1, 2, 3, 4, 5
 POOL_RUNNING, POOL_FINISHED, POOL_FAILED = 0, 1, 2
 
 

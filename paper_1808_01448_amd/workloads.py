@@ -34,7 +34,7 @@ K_R0 = 1.0 / 8.5e3
 #   (sigma - sigma*) y_eq^2 / (2 kBT) = ln(k_f / k_r0)  with sigma* = sigma / 2.
 KBT_HAT = SIGMA_HAT[1] * (Y_EQ_RATIO * Y_CR_HAT) ** 2 / (4.0 * math.log(K_F / K_R0))
 
-PRECISION = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
+PRECISION = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "fp16_neq": 4, "bf16_neq": 5}
 
 
 def _ligand(rho_l: tuple[int, int], strength: int) -> dict:

@@ -81,7 +81,7 @@ def _create(L, **kw):
 @pytest.mark.parametrize("kw,status", [
     (dict(nx=3), lbib.E_INVALID), (dict(ny=2), lbib.E_INVALID), (dict(tau=0.5), lbib.E_INVALID),
     (dict(tau=float("nan")), lbib.E_INVALID), (dict(re=-1.0), lbib.E_INVALID),
-    (dict(drive=2), lbib.E_INVALID), (dict(drive=-1), lbib.E_INVALID), (dict(precision=4), lbib.E_UNSUPPORTED), (dict(precision=-1), lbib.E_UNSUPPORTED),
+    (dict(drive=2), lbib.E_INVALID), (dict(drive=-1), lbib.E_INVALID), (dict(precision=6), lbib.E_UNSUPPORTED), (dict(precision=-1), lbib.E_UNSUPPORTED),
 ])
 def test_create_rejects(L, kw, status):
     st, h = _create(L, **kw)
