@@ -302,7 +302,7 @@ def main():
             "frac_of_measured_copy": round(achieved / copy_gbs, 4) if copy_gbs > 0 else None,
             "particle_phase_avg_us": round(part_ms * 1e3, 2),
             "schedule": "particle phase (which then sweeps its box) on a second stream, concurrent with the "
-                        "sweep of the nodes outside the box on every CU but one",
+                        "sweep of the nodes outside the box",
         }
     p = sim.particle()
     sim.close()

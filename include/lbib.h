@@ -229,9 +229,8 @@ lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size);
 
 /* Schedule of a step.  Overlapped (mode 1): the particle phase of step n runs on a second
  * stream the handle owns, concurrently with the sweep of every node outside the particle's
- * box (the nodes the step's MLS supports reach, predicted exactly by step n-1) on a third
- * stream the handle owns, restricted to every compute unit but one where the device allows
- * CU masks; the particle's workgroup sweeps the box itself after the particle update.
+ * box (the nodes the step's MLS supports reach, predicted exactly by step n-1) on the
+ * handle's stream; the particle's workgroup sweeps the box itself after the particle update.
  * Serial (mode 0), and always on the first step after
  * lbib_init / lbib_load / lbib_write_particle: the particle phase and a sweep of all nodes
  * run one after the other on the handle's stream.  Mode 2 (the default) overlaps when one

@@ -38,8 +38,7 @@ struct lbib_sim {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipStream_t stream2 = nullptr;  // particle chain of the overlapped schedule
-    hipStream_t stream3 = nullptr;  // its sweep of the nodes outside the box: every CU but one
-    hipEvent_t evA = nullptr, evB = nullptr, evC = nullptr;
+    hipEvent_t evA = nullptr, evB = nullptr;
     int overlap = 2;  // 0 serial, 1 overlapped, 2 chosen by lattice size, 3 split particle phase
     int layout = 2;   // 0 push, 1 pull, 2 chosen by lattice size (at lbib_init)
     bool zone_valid = false;  // the zone slot of the next step holds its box
@@ -112,11 +111,9 @@ void free_all(lbib_sim* h)
     }
     if (h->evA) (void)hipEventDestroy(h->evA);
     if (h->evB) (void)hipEventDestroy(h->evB);
-    if (h->evC) (void)hipEventDestroy(h->evC);
-    h->evA = h->evB = h->evC = nullptr;
+    h->evA = h->evB = nullptr;
     if (h->stream2) (void)hipStreamDestroy(h->stream2);
-    if (h->stream3) (void)hipStreamDestroy(h->stream3);
-    h->stream2 = h->stream3 = nullptr;
+    h->stream2 = nullptr;
 }
 
 template <typename T>
@@ -182,32 +179,12 @@ EvPair timing_events(lbib_sim* h, int kind)
     return p;
 }
 
-// The stream of the overlapped schedule's big sweep: a CU mask that leaves one CU out, so the
-// particle phase (one workgroup of 512 threads) always finds a free CU at once instead of
-// waiting for the sweep's waves to drain from one (measured at ~18 us of its ~46 us beside the
-// sweep).  Without CU masking, an ordinary stream.
-hipError_t create_sweep_stream(hipStream_t* s)
-{
-    int dev = 0;
-    hipDeviceProp_t prop;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
-    if (e == hipSuccess && prop.multiProcessorCount > 1) {
-        const int n = prop.multiProcessorCount;
-        std::vector<uint32_t> mask((size_t)(n + 31) / 32, 0u);
-        for (int cu = 1; cu < n; ++cu) mask[cu / 32] |= 1u << (cu % 32);
-        if (hipExtStreamCreateWithCUMask(s, (uint32_t)mask.size(), mask.data()) == hipSuccess) return hipSuccess;
-        (void)hipGetLastError();
-    }
-    return hipStreamCreateWithFlags(s, hipStreamNonBlocking);
-}
-
 // Bytes one lattice sweep moves (every population read and written once).
 double sweep_bytes(const lbib_sim* h) { return (double)h->desc.nx * h->desc.ny * h->g.upd_bytes; }
 
 // One time step is the particle phase then the lattice sweep.  Serial schedule: both on the
 // caller's stream.  Overlapped schedule (when the previous step has predicted this step's
-// box): the particle phase runs on the second stream while the sweep stream sweeps the
+// box): the particle phase runs on the second stream while the caller's stream sweeps the
 // nodes outside the box (they carry no spread force); the particle's workgroup sweeps the
 // box itself after the update.  Both schedules compute every node with the same arithmetic.
 template <typename T>
@@ -215,7 +192,6 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
 {
     const SweepArgs sa = sweep_args(h);
     bool joined = true;
-    bool s3_ready = false;  // the sweep stream has waited for the caller's stream in this call
     const bool split = h->parts.size() > 1 || (h->overlap == 3 && !h->parts.empty());
     if (split && h->args_dirty) {
         lbib_status st = upload_split_args<T>(h);
@@ -285,10 +261,8 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
             const bool overlap = h->overlap == 1 || (h->overlap == 2 && sweep_bytes(h) >= 64.0 * 1048576.0);
             if (!overlap || !h->zone_valid) {
                 if (!joined) {  // the previous step ran overlapped
-                    HIPCHK(h, hipStreamWaitEvent(h->stream, h->evA, 0));
                     HIPCHK(h, hipStreamWaitEvent(h->stream, h->evB, 0));
                     joined = true;
-                    s3_ready = false;
                 }
                 pa.check_zone = 0;
                 const EvPair e1 = timing_events(h, 1);
@@ -299,11 +273,6 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
                 HIPCHK(h, hipEventRecord(h->evA, h->stream));
                 h->zone_valid = true;
             } else {
-                if (!s3_ready) {  // the sweep stream starts after the caller's work
-                    HIPCHK(h, hipEventRecord(h->evC, h->stream));
-                    HIPCHK(h, hipStreamWaitEvent(h->stream3, h->evC, 0));
-                    s3_ready = true;
-                }
                 // the particle's workgroup also sweeps its box after the update (no third
                 // launch on the particle chain)
                 pa.check_zone = 1;
@@ -314,11 +283,11 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
                 HIPCHK(h, launch_particle<T>(pa, h->stream2, e1.t0, e1.t1));
                 // the previous step's particle launch (with its box) before this sweep; the
                 // events are re-recorded only after both waits are enqueued
-                HIPCHK(h, hipStreamWaitEvent(h->stream3, h->evB, 0));
+                HIPCHK(h, hipStreamWaitEvent(h->stream, h->evB, 0));
                 const EvPair e0 = timing_events(h, 0);
-                HIPCHK(h, launch_sweep<T>(fin, fout, sa, SWEEP_OUTSIDE, p.d_zone + par, nullptr, 0, h->g.pull, h->stream3,
+                HIPCHK(h, launch_sweep<T>(fin, fout, sa, SWEEP_OUTSIDE, p.d_zone + par, nullptr, 0, h->g.pull, h->stream,
                                           e0.t0, e0.t1));
-                HIPCHK(h, hipEventRecord(h->evA, h->stream3));
+                HIPCHK(h, hipEventRecord(h->evA, h->stream));
                 HIPCHK(h, hipEventRecord(h->evB, h->stream2));
                 joined = false;
             }
@@ -328,7 +297,6 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
     }
     if (!joined) {
         // everything enqueued is ordered before later work on the caller's stream
-        HIPCHK(h, hipStreamWaitEvent(h->stream, h->evA, 0));
         HIPCHK(h, hipStreamWaitEvent(h->stream, h->evB, 0));
         HIPCHK(h, hipEventRecord(h->evA, h->stream));
     }
@@ -537,10 +505,8 @@ lbib_status lbib_init(lbib_handle h)
     }
     if ((e = hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking)) != hipSuccess)
         return bail(e, "lbib_init: second stream");
-    if ((e = create_sweep_stream(&h->stream3)) != hipSuccess) return bail(e, "lbib_init: sweep stream");
     if ((e = hipEventCreateWithFlags(&h->evA, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&h->evB, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&h->evC, hipEventDisableTiming)) != hipSuccess)
+        (e = hipEventCreateWithFlags(&h->evB, hipEventDisableTiming)) != hipSuccess)
         return bail(e, "lbib_init: events");
     if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return bail(e, "lbib_init: sync");
     h->state = 1;
