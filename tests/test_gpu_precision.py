@@ -169,3 +169,21 @@ def test_neq_population_roundtrip(L, prec):
         t.close()
     np.testing.assert_array_equal(outs[0], outs[1])
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp16", "fp16_neq", "bf16_neq"])
+def test_16bit_checkpoint_resume(L, prec):
+    """A checkpoint carries the stored values (and the moment planes of the f - f_eq
+    storages): resuming from it reproduces the uninterrupted run bit for bit."""
+    w = W.channel_small_binding(prec)
+    a = L.Sim(w)
+    a.step(60)
+    blob = a.save()
+    a.step(90)
+    b = L.Sim(w)
+    b.load(blob)
+    b.step(90)
+    assert a.particle() == b.particle()
+    np.testing.assert_array_equal(a.f, b.f)
+    a.close()
+    b.close()

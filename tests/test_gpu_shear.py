@@ -96,7 +96,7 @@ def test_shear_layouts_and_schedules_agree(L):
         np.testing.assert_array_equal(f, out[0][1])
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "fp16_neq"])
 def test_shear_storage_precisions_against_oracle(L, orc, prec):
     w0 = shear_small("fp64")
     steps = 800
@@ -110,7 +110,7 @@ def test_shear_storage_precisions_against_oracle(L, orc, prec):
     x0 = np.array([w0["particle"]["xc"], w0["particle"]["yc"]])
     eU, eX = rel(tg[:, 4:6], to[:, 4:6]), rel(tg[:, 1:3] - x0, to[:, 1:3] - x0)
     say(prec, f"velocity {eU:.2e} displacement {eX:.2e}")
-    tol = {"fp32": 1e-5, "fp16": 5e-3}[prec]  # the storage bars of the Poiseuille drive
+    tol = {"fp32": 1e-5, "fp16": 5e-3, "fp16_neq": 8e-5}[prec]  # the storage bars of the Poiseuille drive
     assert eU <= tol and eX <= tol
     s.close()
 
