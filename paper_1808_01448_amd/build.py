@@ -26,8 +26,9 @@ FLAGS = [
 # Device code is compiled without FMA contraction: the arithmetic of every kernel is then
 # exactly the written sequence (with the fused operations written out where they pay), so a
 # simulation gives bit-identical results whichever kernel variant runs it (one simulation
-# or a pool, push or pull layout, any number of markers per thread).
-PER_SOURCE = {src: ["-ffp-contract=off"] for src in ("lbib_sweep.hip", "lbib_pool_sweep.hip", "lbib_particle.hip")}
+# or a pool, push or pull layout, any number of markers per thread).  The host file is built
+# the same way: its equilibrium, used by read-outs of the f - f_eq storages, matches the device's.
+PER_SOURCE = {src: ["-ffp-contract=off"] for src in ("lbib_sweep.hip", "lbib_pool_sweep.hip", "lbib_particle.hip", "lbib_host.cpp")}
 
 
 def hipcc() -> str:

@@ -17,14 +17,22 @@ using namespace dev;
 
 // ---------------------------------------------------------------------------------------
 // Lattice sweep: collide (eq 1, 2, 4 with the moments of eq 5-6) and stream.
-// In the shifted variables (rho = 1 + drho) the equilibrium is
-//   f_eq - w = w (drho + A + drho A),  A = 3 e.u + 9/2 (e.u)^2 - 3/2 u^2,
-// and u = j' - j' drho / (1 + drho) with j' = sum g e + F/2; neither form ever adds the
-// O(1) density to the O(1e-5) deviations.  Device code is compiled without FMA
-// contraction and the fused operations below are explicit, so every kernel that runs this
-// update (either layout, one simulation or a pool) computes the same sequence and gives
-// bit-identical results.  The compute type C is FP64 for the FP64 and FP32 storages and
-// FP32 for the 16-bit ones, whose storage rounding is far coarser than FP32 arithmetic.
+// In the shifted variables (rho = 1 + drho) the BGK update with Guo's source is
+//   post_q = (1 - omega) g_q + omega (f_eq,q - w_q) + S_q,
+//   f_eq,q - w_q = w_q (drho + rho A),  A = 3 e.u + 9/2 (e.u)^2 - 3/2 u^2,
+//   S_q = (1 - omega/2) w_q (3 (e.F - u.F) + 9 (e.u)(e.F)),
+// with u = j' - j' drho / (1 + drho), j' = sum g e + F/2; no term ever adds the O(1) density
+// to the O(1e-5) deviations.  Split by parity in e_q,
+//   post_q = (1 - omega) g_q + w_q (I + E_q + O_q),  post_opp(q) = (1 - omega) g_opp(q) + w_q (I + E_q - O_q),
+//   I = omega drho - 3/2 omega rho u^2 - 3 (1 - omega/2) u.F,
+//   E_q = (e.u) (9/2 omega rho e.u + 9 (1 - omega/2) e.F),  O_q = 3 omega rho e.u + 3 (1 - omega/2) e.F,
+// so each pair of opposite directions shares its terms: about half the arithmetic of the
+// direction-by-direction form, which sets the time of the FP64 update on FP32 storage.
+// Device code is compiled without FMA contraction and the fused operations below are
+// explicit, so every kernel that runs this update (either layout, one simulation or a pool)
+// computes the same sequence and gives bit-identical results.  The compute type C is FP64
+// for the FP64 and FP32 storages and FP32 for the 16-bit ones, whose storage rounding is far
+// coarser than FP32 arithmetic.
 // ---------------------------------------------------------------------------------------
 // m (optional): the (rho - 1, u_x, u_y) the equilibrium was formed with.
 template <typename C>
@@ -32,23 +40,26 @@ __device__ __forceinline__ void collide_node(const C g[9], const SweepArgs& a, C
 {
     C drho, jx, jy;
     shifted_moments<C, C>(g, drho, jx, jy);
-    const C half = 0.5, c3 = 3.0, c45 = 4.5, c15 = 1.5, c9 = 9.0;
-    const C omega = (C)a.omega, guo = (C)a.guo;
+    const C omega = (C)a.omega, guo = (C)a.guo, keep = (C)1 - omega;
     const C r = drho / ((C)1 + drho);
-    const C jxF = fma(half, Fx, jx), jyF = fma(half, Fy, jy);
+    const C jxF = fma((C)0.5, Fx, jx), jyF = fma((C)0.5, Fy, jy);
     const C ux = fma(-jxF, r, jxF), uy = fma(-jyF, r, jyF);
     const C uu = fma(ux, ux, uy * uy);
     const C uF = fma(ux, Fx, uy * Fy);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        const C eu = (C)kEx[q] * ux + (C)kEy[q] * uy;
-        const C eF = (C)kEx[q] * Fx + (C)kEy[q] * Fy;
-        const C w = (C)kW[q];
-        const C A = fma(c45 * eu, eu, fma(-c15, uu, c3 * eu));
-        const C geq = w * fma(drho, A, drho + A);
-        const C src = guo * w * fma(c9 * eu, eF, c3 * (eF - uF));
-        post[q] = fma(-omega, g[q] - geq, g[q]) + src;
-    }
+    const C orho = fma(omega, drho, omega);  // omega rho
+    const C a3 = (C)3 * orho, a45 = (C)4.5 * orho, b3 = (C)3 * guo, b9 = (C)9 * guo;
+    const C iso = fma(-b3, uF, fma((C)-1.5 * orho, uu, omega * drho));
+    post[0] = fma(keep, g[0], (C)kW[0] * iso);
+    auto pair = [&](int q, int o, C eu, C eF) {
+        const C odd = fma(a3, eu, b3 * eF);
+        const C even = fma(eu, fma(a45, eu, b9 * eF), iso);
+        post[q] = fma(keep, g[q], (C)kW[q] * (even + odd));
+        post[o] = fma(keep, g[o], (C)kW[q] * (even - odd));
+    };
+    pair(1, 3, ux, Fx);
+    pair(2, 4, uy, Fy);
+    pair(5, 7, ux + uy, Fx + Fy);
+    pair(6, 8, uy - ux, Fy - Fx);
     if (m) {
         m[0] = drho;
         m[1] = ux;
@@ -74,8 +85,10 @@ __device__ __forceinline__ void neq_encode(T* fout, const SweepArgs& a, size_t c
             mo[a.plane + c] = m1;
             mo[2 * a.plane + c] = m2;
         }
+        C feq[9];
+        feq_shift_all<C>((C)m0, (C)m1, (C)m2, feq);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) post[q] -= feq_shift<C>(q, (C)m0, (C)m1, (C)m2);
+        for (int q = 0; q < 9; ++q) post[q] -= feq[q];
     }
 }
 

@@ -133,16 +133,59 @@ __device__ __forceinline__ float* neq_moments(T* f, int64_t plane)
     return (float*)((uint16_t*)f + 9 * plane);
 }
 
-// Shifted equilibrium f_eq,q(rho, u) - w_q = w_q (drho + A + drho A) with
-// A = 3 e.u + 9/2 (e.u)^2 - 3/2 u^2 (eq 2), in the operation order of the collision.
+// e_q . (x, y) for the D2Q9 directions, formed so that the value for the opposite direction
+// is the exact negative.
+template <typename C>
+__device__ __forceinline__ C e_dot(int q, C x, C y)
+{
+    switch (q) {
+        case 1: return x;
+        case 2: return y;
+        case 3: return -x;
+        case 4: return -y;
+        case 5: return x + y;
+        case 6: return y - x;
+        case 7: return -(x + y);
+        case 8: return x - y;
+        default: return (C)0;
+    }
+}
+
+// Shifted equilibrium (eq 2) f_eq,q(rho, u) - w_q = w_q (drho + rho A),
+// A = 3 e.u + 9/2 (e.u)^2 - 3/2 u^2, split by parity in e_q: w_q (E + O) with
+// E = (drho - 3/2 rho u^2) + 9/2 rho (e.u)^2 and O = 3 rho e.u.  Opposite directions differ
+// only in the sign of e.u, which flips O and leaves E bit for bit, so feq_shift_all (pairs
+// sharing E) and feq_shift (one direction) give identical values.
+template <typename C>
+__device__ __forceinline__ C feq_even_base(C drho, C ux, C uy)
+{
+    return fma((C)-1.5 * ((C)1 + drho), fma(ux, ux, uy * uy), drho);
+}
+template <typename C>
+__device__ __forceinline__ C feq_from_eu(C w, C rho, C base, C eu)
+{
+    return w * (fma((C)4.5 * rho * eu, eu, base) + (C)3 * rho * eu);
+}
 template <typename C>
 __device__ __forceinline__ C feq_shift(int q, C drho, C ux, C uy)
 {
-    const C c3 = 3.0, c45 = 4.5, c15 = 1.5;
-    const C uu = fma(ux, ux, uy * uy);
-    const C eu = (C)kEx[q] * ux + (C)kEy[q] * uy;
-    const C A = fma(c45 * eu, eu, fma(-c15, uu, c3 * eu));
-    return (C)kW[q] * fma(drho, A, drho + A);
+    return feq_from_eu<C>((C)kW[q], (C)1 + drho, feq_even_base<C>(drho, ux, uy), e_dot<C>(q, ux, uy));
+}
+template <typename C>
+__device__ __forceinline__ void feq_shift_all(C drho, C ux, C uy, C out[9])
+{
+    const C rho = (C)1 + drho, base = feq_even_base<C>(drho, ux, uy);
+    const C r45 = (C)4.5 * rho, r3 = (C)3 * rho;
+    out[0] = feq_from_eu<C>((C)kW[0], rho, base, (C)0);
+    auto pair = [&](int q, int o, C eu) {
+        const C even = fma(r45 * eu, eu, base), odd = r3 * eu;
+        out[q] = (C)kW[q] * (even + odd);
+        out[o] = (C)kW[q] * (even - odd);
+    };
+    pair(1, 3, ux);
+    pair(2, 4, uy);
+    pair(5, 7, ux + uy);
+    pair(6, 8, uy - ux);
 }
 
 // The node that emitted population q of node (i, j) and the direction it emitted it in:
@@ -322,7 +365,9 @@ __device__ __forceinline__ void load_node(const T* f, int i, int j, int nx, int 
             int si, sj, dir;
             pop_source(q, i, j, nx, ny, si, sj, dir);
             const int64_t c = (int64_t)sj * pitch + si;
-            g[q] += feq_shift<R>(dir, (R)m[c], (R)m[plane + c], (R)m[2 * plane + c]);
+            const R d = (R)m[c], x = (R)m[plane + c], y = (R)m[2 * plane + c];
+            const R eu = e_dot<R>(q, x, y);  // e_dir.u = -e_q.u for a reflected population
+            g[q] += feq_from_eu<R>((R)kW[q], (R)1 + d, feq_even_base<R>(d, x, y), dir == q ? eu : -eu);
         }
     }
     wall_reflect<R>(g, j, ny, uw6);

@@ -381,13 +381,26 @@ static double wall_term(const LatticeGeom& g, int q)
     return q == 7 ? -g.uw / 6.0 : q == 8 ? g.uw / 6.0 : 0.0;
 }
 
-// Shifted equilibrium f_eq,q - w_q of moments (drho, u), in the device's operation order.
+// Shifted equilibrium f_eq,q - w_q of moments (drho, u), in the device's operation order:
+// w_q (E + O) with the even part E = (drho - 3/2 rho u^2) + 9/2 rho (e.u)^2 and the odd part
+// O = 3 rho e.u, e.u formed so that opposite directions give exact negatives.
 static double feq_shift_host(int q, double drho, double ux, double uy)
 {
-    const double uu = std::fma(ux, ux, uy * uy);
-    const double eu = (double)kExq[q] * ux + (double)kEyq[q] * uy;
-    const double A = std::fma(4.5 * eu, eu, std::fma(-1.5, uu, 3.0 * eu));
-    return kWq[q] * std::fma(drho, A, drho + A);
+    double eu = 0.0;
+    switch (q) {
+        case 1: eu = ux; break;
+        case 2: eu = uy; break;
+        case 3: eu = -ux; break;
+        case 4: eu = -uy; break;
+        case 5: eu = ux + uy; break;
+        case 6: eu = uy - ux; break;
+        case 7: eu = -(ux + uy); break;
+        case 8: eu = ux - uy; break;
+        default: break;
+    }
+    const double rho = 1.0 + drho;
+    const double base = std::fma(-1.5 * rho, std::fma(ux, ux, uy * uy), drho);
+    return kWq[q] * (std::fma(4.5 * rho * eu, eu, base) + 3.0 * rho * eu);
 }
 
 // Non-equilibrium storages: the shifted equilibrium the reader of population q at (i, j)
