@@ -295,14 +295,15 @@ def main():
         roofline = {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "sweep_kernel<float, SWEEP_OUTSIDE, push>", "algorithmic_bytes_per_launch": bpu * cells,
+            "kernel": "sweep_overlap_kernel<float, push>", "algorithmic_bytes_per_launch": bpu * cells,
             "avg_launch_us": round(sweep_ms * 1e3, 2), "launches_timed": n0,
             "timing": f"HIP events (hipExtLaunchKernelGGL) on the sweep's stream over {kr} steps after the "
                       f"throughput region",
             "frac_of_measured_copy": round(achieved / copy_gbs, 4) if copy_gbs > 0 else None,
-            "particle_phase_avg_us": round(part_ms * 1e3, 2),
-            "schedule": "particle phase (which then sweeps its box) on a second stream, concurrent with the "
-                        "sweep of the nodes outside the box",
+            "particle_launch_avg_us": round(part_ms * 1e3, 2),
+            "schedule": "particle phases and sweeps on two streams with no event between them, handing "
+                        "over through device memory; the sweep's box tiles are taken by workgroups at the "
+                        "head of its grid once the particle has published its spread force",
         }
     p = sim.particle()
     sim.close()

@@ -227,15 +227,19 @@ lbib_status lbib_read_trace(lbib_handle h, int32_t pid, lbib_particle_state* out
 lbib_status lbib_save(lbib_handle h, void* blob, int64_t* size);
 lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size);
 
-/* Schedule of a step.  Overlapped (mode 1): the particle phase of step n runs on a second
- * stream the handle owns, concurrently with the sweep of every node outside the particle's
- * box (the nodes the step's MLS supports reach, predicted exactly by step n-1) on the
- * handle's stream; the particle's workgroup sweeps the box itself after the particle update.
- * Serial (mode 0), and always on the first step after
- * lbib_init / lbib_load / lbib_write_particle: the particle phase and a sweep of all nodes
- * run one after the other on the handle's stream.  Mode 2 (the default) overlaps when one
- * sweep moves at least 64 MiB; below that the two cross-stream waits of a step cost more
- * than they hide.  Both schedules give bit-identical results. */
+/* Schedule of a step.  Overlapped (mode 1): the particle phases run one after the other on a
+ * second stream the handle owns and the lattice sweeps on a third (CU-masked: one CU is left
+ * to the particle), with no event between the two chains; they hand over through device
+ * memory.  The sweep of step n reads the box step n-1 predicted (exactly) for step n and
+ * leaves the 64 x 4 tiles of that box, widened by 3 nodes, to workgroups at the head of its
+ * grid, which take them once particle phase n has published its spread force; particle phase
+ * n+1 starts once those workgroups have stored step n+1's populations around its box.  Every
+ * device-side wait is bounded: one that exceeds about a second fails the simulation with
+ * LBIB_E_NUMERIC.  Serial (mode 0), always on the first step after lbib_init / lbib_load /
+ * lbib_write_particle, and where CU masking is unavailable or ny >= 65536: the particle phase
+ * and a sweep of all nodes run one after the other on the handle's stream.  Mode 2 (the
+ * default) overlaps when one sweep moves at least 64 MiB.  Both schedules give bit-identical
+ * results. */
 /* Mode 3 (used whenever a simulation has several particles): the particle phase runs as two
  * launches over all particles -- first every particle stages its box and spreads its marker
  * forces, then every particle evaluates its probe loads (with the spread force of every
@@ -267,12 +271,11 @@ lbib_status lbib_set_layout(lbib_handle h, int32_t mode);
 lbib_status lbib_get_layout(lbib_handle h, int32_t* pull);
 
 /* Kernel timing: HIP events bracket every launch of the kernels selected by the bit mask
- * `enable` (0 switches timing off): bit 0 the lattice sweep of all nodes or of the nodes
- * outside the particle's box (kernel 0), bit 1 the particle phase (kernel 1; in the
- * overlapped schedule it includes the sweep of the box), bit 2 the second particle launch of
- * the split phase (kernel 2).  lbib_kernel_time synchronises and returns the summed
- * milliseconds and launch counts since the last enable.  The events delay the hand-over
- * between the two streams of the overlapped schedule: time whole steps without them. */
+ * `enable` (0 switches timing off): bit 0 the lattice sweep (kernel 0), bit 1 the particle
+ * phase (kernel 1; in the overlapped schedule the launch includes its wait for the previous
+ * sweep), bit 2 the second particle launch of the split phase (kernel 2).  lbib_kernel_time
+ * synchronises and returns the summed milliseconds and launch counts since the last enable.
+ * The events add work between the launches they time: time whole steps without them. */
 lbib_status lbib_kernel_timing(lbib_handle h, int32_t enable);
 lbib_status lbib_kernel_time(lbib_handle h, int32_t kernel, double* total_ms, int64_t* launches);
 

@@ -71,20 +71,14 @@ __device__ __forceinline__ void collide_node(const C g[9], const SweepArgs& a, C
 // the moments stored for this node (rounded to FP32 first, so that every reader forms the same
 // equilibrium from them), and the moments are stored at the node.
 template <typename T, typename C>
-__device__ __forceinline__ void neq_encode(T* fout, const SweepArgs& a, size_t c, const C m[3], C post[9], bool nt)
+__device__ __forceinline__ void neq_encode(T* fout, const SweepArgs& a, size_t c, const C m[3], C post[9], int pol)
 {
     if constexpr (St<T>::neq) {
         float* mo = neq_moments(fout, a.plane);
         const float m0 = (float)m[0], m1 = (float)m[1], m2 = (float)m[2];
-        if (nt) {
-            __builtin_nontemporal_store(m0, mo + c);
-            __builtin_nontemporal_store(m1, mo + a.plane + c);
-            __builtin_nontemporal_store(m2, mo + 2 * a.plane + c);
-        } else {
-            mo[c] = m0;
-            mo[a.plane + c] = m1;
-            mo[2 * a.plane + c] = m2;
-        }
+        put(mo + c, m0, pol);
+        put(mo + a.plane + c, m1, pol);
+        put(mo + 2 * a.plane + c, m2, pol);
         C feq[9];
         feq_shift_all<C>((C)m0, (C)m1, (C)m2, feq);
 #pragma unroll
@@ -92,21 +86,20 @@ __device__ __forceinline__ void neq_encode(T* fout, const SweepArgs& a, size_t c
     }
 }
 
-// Push layout: collide node (i, j) and scatter its populations to the neighbours, with
-// half-way bounce-back at the two walls and periodic x.
-template <typename T>
-__device__ __forceinline__ void collide_push(const T* __restrict__ fin, T* __restrict__ fout, const SweepArgs& a,
-                                             int i, int j, double Fx, double Fy)
+// Push layout: collide node (i, j), whose populations g load_node presented, and scatter
+// its results to the neighbours, with half-way bounce-back at the two walls and periodic x.
+// COH: coherent stores (a concurrently running launch reads the results).
+template <typename T, bool COH = false>
+__device__ __forceinline__ void push_update(T* __restrict__ fout, const SweepArgs& a, int i, int j,
+                                            const typename St<T>::C (&g)[9], double Fx, double Fy)
 {
     using C = typename St<T>::C;
     const int64_t P = a.plane;
     const size_t c = (size_t)j * a.pitch + i;
-    // populations are read exactly once per step: stream them past the caches
-    C g[9];
-    load_node<T, C>(fin, i, j, a.nx, a.ny, a.pitch, P, false, a.inv_scale, a.uw6, true, g);
+    const int pol = COH ? ST_COH : ST_PLAIN;
     C post[9], m[3];
     collide_node<C>(g, a, (C)Fx, (C)Fy, post, m);
-    neq_encode<T, C>(fout, a, c, m, post, false);
+    neq_encode<T, C>(fout, a, c, m, post, pol);
 
     const int ip = (i + 1 == a.nx) ? 0 : i + 1;
     const int im = (i == 0) ? a.nx - 1 : i - 1;
@@ -114,47 +107,65 @@ __device__ __forceinline__ void collide_push(const T* __restrict__ fin, T* __res
     const bool top = (j + 1 == a.ny), bot = (j == 0);
     const double sc = a.scale;
     // shifted values reflect unchanged: w_q = w_opp(q)
-    st_store(fout, 0 * P + c, post[0], sc, false);
-    st_store(fout, 1 * P + row + ip, post[1], sc, false);
-    st_store(fout, 3 * P + row + im, post[3], sc, false);
+    st_store(fout, 0 * P + c, post[0], sc, pol);
+    st_store(fout, 1 * P + row + ip, post[1], sc, pol);
+    st_store(fout, 3 * P + row + im, post[3], sc, pol);
     if (!top) {
-        st_store(fout, 2 * P + up + i, post[2], sc, false);
-        st_store(fout, 5 * P + up + ip, post[5], sc, false);
-        st_store(fout, 6 * P + up + im, post[6], sc, false);
+        st_store(fout, 2 * P + up + i, post[2], sc, pol);
+        st_store(fout, 5 * P + up + ip, post[5], sc, pol);
+        st_store(fout, 6 * P + up + im, post[6], sc, pol);
     } else {
-        st_store(fout, 4 * P + c, post[2], sc, false);
-        st_store(fout, 7 * P + c, post[5], sc, false);
-        st_store(fout, 8 * P + c, post[6], sc, false);
+        st_store(fout, 4 * P + c, post[2], sc, pol);
+        st_store(fout, 7 * P + c, post[5], sc, pol);
+        st_store(fout, 8 * P + c, post[6], sc, pol);
     }
     if (!bot) {
-        st_store(fout, 4 * P + dn + i, post[4], sc, false);
-        st_store(fout, 7 * P + dn + im, post[7], sc, false);
-        st_store(fout, 8 * P + dn + ip, post[8], sc, false);
+        st_store(fout, 4 * P + dn + i, post[4], sc, pol);
+        st_store(fout, 7 * P + dn + im, post[7], sc, pol);
+        st_store(fout, 8 * P + dn + ip, post[8], sc, pol);
     } else {
-        st_store(fout, 2 * P + c, post[4], sc, false);
-        st_store(fout, 5 * P + c, post[7], sc, false);
-        st_store(fout, 6 * P + c, post[8], sc, false);
+        st_store(fout, 2 * P + c, post[4], sc, pol);
+        st_store(fout, 5 * P + c, post[7], sc, pol);
+        st_store(fout, 6 * P + c, post[8], sc, pol);
     }
 }
 
-// Pull layout: gather the streamed populations of (i, j) from the previous step's
-// post-collision values (bounce-back across the walls), collide, and store the
-// post-collision values at (i, j) itself.  Every store is aligned and each value is written
-// once, so both go past the caches; the gathers hit lines neighbouring waves also read.
-template <typename T>
-__device__ __forceinline__ void collide_pull(const T* __restrict__ fin, T* __restrict__ fout, const SweepArgs& a,
-                                             int i, int j, double Fx, double Fy)
+// Pull layout: collide node (i, j), whose inflow g load_node gathered from the previous
+// step's post-collision values (bounce-back across the walls), and store the post-collision
+// values at (i, j) itself.  Every store is aligned and each value is written once, so both
+// go past the caches; the gathers hit lines neighbouring waves also read.
+template <typename T, bool COH = false>
+__device__ __forceinline__ void pull_update(T* __restrict__ fout, const SweepArgs& a, int i, int j,
+                                            const typename St<T>::C (&g)[9], double Fx, double Fy)
 {
     using C = typename St<T>::C;
     const int64_t P = a.plane;
     const size_t c = (size_t)j * a.pitch + i;
-    C g[9];
-    load_node<T, C>(fin, i, j, a.nx, a.ny, a.pitch, P, true, a.inv_scale, a.uw6, true, g);
+    const int pol = COH ? ST_COH : ST_NT;
     C post[9], m[3];
     collide_node<C>(g, a, (C)Fx, (C)Fy, post, m);
-    neq_encode<T, C>(fout, a, c, m, post, true);
+    neq_encode<T, C>(fout, a, c, m, post, pol);
 #pragma unroll
-    for (int q = 0; q < 9; ++q) st_store(fout, q * P + c, post[q], a.scale, true);
+    for (int q = 0; q < 9; ++q) st_store(fout, q * P + c, post[q], a.scale, pol);
+}
+
+// The populations of node (i, j) at the start of a step in the compute type, read past the
+// caches (they are read once per step).
+template <typename T, bool PULL>
+__device__ __forceinline__ void update_load(const T* __restrict__ fin, const SweepArgs& a, int i, int j,
+                                            typename St<T>::C (&g)[9])
+{
+    load_node<T, typename St<T>::C>(fin, i, j, a.nx, a.ny, a.pitch, a.plane, PULL, a.inv_scale, a.uw6, true, g);
+}
+
+template <typename T, bool PULL, bool COH = false>
+__device__ __forceinline__ void update_store(T* __restrict__ fout, const SweepArgs& a, int i, int j,
+                                             const typename St<T>::C (&g)[9], double Fx, double Fy)
+{
+    if (PULL)
+        pull_update<T, COH>(fout, a, i, j, g, Fx, Fy);
+    else
+        push_update<T, COH>(fout, a, i, j, g, Fx, Fy);
 }
 
 // Node update in either layout.
@@ -162,10 +173,137 @@ template <typename T, bool PULL>
 __device__ __forceinline__ void collide_stream(const T* __restrict__ fin, T* __restrict__ fout, const SweepArgs& a,
                                                int i, int j, double Fx, double Fy)
 {
-    if (PULL)
-        collide_pull<T>(fin, fout, a, i, j, Fx, Fy);
-    else
-        collide_push<T>(fin, fout, a, i, j, Fx, Fy);
+    typename St<T>::C g[9];
+    update_load<T, PULL>(fin, a, i, j, g);
+    update_store<T, PULL>(fout, a, i, j, g, Fx, Fy);
+}
+
+// Hand-over of the particle's force tile to the concurrent sweep (ClaimArgs) without cache
+// maintenance: loads and stores at agent scope are coherent across the XCDs' L2 caches, so
+// the writer only has to wait for its stores to complete before it sets the ready bit.  (A
+// release or acquire fence at agent scope writes back or invalidates a whole L2, which
+// beside the sweep's store stream costs tens of microseconds.)
+__device__ __forceinline__ void coherent_store(int64_t* p, int64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int64_t coherent_load(const int64_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void coherent_store(TileDesc* p, const TileDesc& d)
+{
+    const int64_t* s = (const int64_t*)&d;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) coherent_store((int64_t*)p + k, s[k]);
+}
+__device__ __forceinline__ TileDesc coherent_load(const TileDesc* p)
+{
+    TileDesc d;
+    int64_t* s = (int64_t*)&d;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s[k] = coherent_load((const int64_t*)p + k);
+    return d;
+}
+// Waits until every store this lane has issued has completed (s_waitcnt vmcnt(0)).
+__device__ __forceinline__ void stores_done() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Polls a monotonic hand-over counter (one lane) until it reaches target, sleeping between
+// polls.  Gives up after 2^20 polls (about a second) and raises FLAG_SYNC, and returns at
+// once while FLAG_SYNC is raised, so a simulation whose hand-over failed drains quickly.
+__device__ __forceinline__ void wait_counter(const unsigned long long* p, unsigned long long target, int32_t* flags)
+{
+    for (unsigned polls = 0; __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target; ++polls) {
+        if ((polls & 255u) == 0 && (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_SYNC))
+            return;
+        if (polls > (1u << 20)) {
+            atomicOr(flags, FLAG_SYNC);
+            return;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+__device__ __forceinline__ void publish_counter(unsigned long long* p, unsigned long long v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A predicted box in two 64-bit words, each carrying a 16-bit tag, so that one coherent
+// load of each gives a consistent box (both tags current) without a separate flag: word 0
+// i0w (32 bits), j0 (16); word 1 w (16), h (16), active (1); tag in the top 16 bits of
+// both.  Needs j0, w, h < 2^16.
+__device__ __forceinline__ void zone_pack(const TileDesc& z, uint32_t tag, unsigned long long* p)
+{
+    const unsigned long long t = (unsigned long long)(tag & 0xffffu) << 48;
+    const bool ok = z.active && z.j0 < 65536 && z.w < 65536 && z.h < 65536;
+    coherent_store((int64_t*)p, (int64_t)(t | ((unsigned long long)(uint32_t)z.j0 << 32) | (uint32_t)z.i0w));
+    coherent_store((int64_t*)p + 1, (int64_t)(t | ((unsigned long long)ok << 32) | ((unsigned long long)(uint32_t)z.h << 16) |
+                                             (uint32_t)z.w));
+}
+// Waits (one lane) until both words of the box carry tag, then unpacks it (inactive when the
+// wait times out, which raises FLAG_SYNC).  The first attempt uses plain loads: the tags
+// validate whatever they return (a stale copy only carries an older tag), and once the box is
+// written they mostly hit in the L2 that the first workgroup of the XCD filled.
+__device__ __forceinline__ TileDesc zone_wait(const unsigned long long* p, uint32_t tag, int32_t* flags)
+{
+    TileDesc z{};
+    const unsigned long long t = tag & 0xffffu;
+    unsigned long long w0 = p[0], w1 = p[1];
+    for (unsigned polls = 0;; ++polls) {
+        if ((w0 >> 48) == t && (w1 >> 48) == t) {
+            z.i0w = (int32_t)(uint32_t)w0;
+            z.j0 = (int32_t)((w0 >> 32) & 0xffffu);
+            z.w = (int32_t)(w1 & 0xffffu);
+            z.h = (int32_t)((w1 >> 16) & 0xffffu);
+            z.active = (int32_t)((w1 >> 32) & 1u);
+            return z;
+        }
+        if ((polls & 255u) == 0 && (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_SYNC))
+            return z;
+        if (polls > (1u << 20)) {
+            atomicOr(flags, FLAG_SYNC);
+            return z;
+        }
+        if (polls) __builtin_amdgcn_s_sleep(1);
+        w0 = (unsigned long long)coherent_load((const int64_t*)p);
+        w1 = (unsigned long long)coherent_load((const int64_t*)p + 1);
+    }
+}
+
+// The 64 x 4 node tiles of the sweep that a box, widened by m nodes on every side, reaches:
+// columns tx0, tx0 + 1, ... (ntx of them, periodic over the gx columns; the last column may be
+// narrower than 64 nodes), rows ty0 .. ty0 + nty - 1.  Zone tile e is column
+// (tx0 + e % ntx) mod gx of row ty0 + e / ntx.  The box is inactive, or has i0w in [0, nx),
+// w <= nx and rows j0 .. j0 + h - 1 in [0, ny).
+struct ZoneTiles {
+    int tx0, ntx, ty0, nty;
+};
+__device__ __forceinline__ ZoneTiles zone_tiles(const TileDesc& z, int nx, int ny, int gx, int m)
+{
+    ZoneTiles t{0, 0, 0, 0};
+    if (!z.active || z.w <= 0 || z.h <= 0) return t;
+    const int w = min(z.w + 2 * m, nx);
+    int i0 = z.i0w - m;
+    if (i0 < 0) i0 += nx;
+    t.tx0 = i0 >> 6;
+    int covered = min(64 * t.tx0 + 64, nx) - i0;
+    int tx = t.tx0;
+    t.ntx = 1;
+    while (covered < w && t.ntx < gx) {
+        tx = tx + 1 == gx ? 0 : tx + 1;
+        covered += min(64 * tx + 64, nx) - 64 * tx;
+        ++t.ntx;
+    }
+    t.ty0 = max(z.j0 - m, 0) >> 2;
+    t.nty = (min(z.j0 + z.h - 1 + m, ny - 1) >> 2) - t.ty0 + 1;
+    return t;
+}
+__device__ __forceinline__ bool zone_has_tile(const ZoneTiles& t, int tx, int ty, int gx)
+{
+    if (ty < t.ty0 || ty >= t.ty0 + t.nty) return false;
+    int k = tx - t.tx0;
+    if (k < 0) k += gx;
+    return k < t.ntx;
 }
 
 __device__ __forceinline__ bool in_box(const TileDesc& d, int i, int j, int nx)

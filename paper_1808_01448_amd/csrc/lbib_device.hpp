@@ -75,49 +75,47 @@ __device__ __forceinline__ float st_load(const bf16_neq_t* p, int64_t i, double 
     return st_load((const bf16_t*)p, i, inv_scale, nt);
 }
 
-__device__ __forceinline__ void st_store(double* p, int64_t i, double v, double, bool nt)
+// Store policies: plain; non-temporal (past the caches); coherent (an agent-scope store,
+// visible to other XCDs without cache maintenance, for data a concurrently running launch
+// reads).  A bool argument selects plain or non-temporal.
+enum : int { ST_PLAIN = 0, ST_NT = 1, ST_COH = 2 };
+template <typename S>
+__device__ __forceinline__ void put(S* p, S v, int pol)
 {
-    if (nt)
-        __builtin_nontemporal_store(v, p + i);
+    if (pol == ST_COH)
+        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else if (pol == ST_NT)
+        __builtin_nontemporal_store(v, p);
     else
-        p[i] = v;
+        *p = v;
 }
-__device__ __forceinline__ void st_store(float* p, int64_t i, double v, double, bool nt)
+__device__ __forceinline__ void st_store(double* p, int64_t i, double v, double, int pol)
 {
-    if (nt)
-        __builtin_nontemporal_store((float)v, p + i);
-    else
-        p[i] = (float)v;
+    put(p + i, v, pol);
 }
-__device__ __forceinline__ void st_store(half_t* p, int64_t i, float v, double scale, bool nt)
+__device__ __forceinline__ void st_store(float* p, int64_t i, double v, double, int pol)
 {
-    const uint16_t b = __builtin_bit_cast(uint16_t, (_Float16)(v * (float)scale));
-    uint16_t* r = (uint16_t*)p;
-    if (nt)
-        __builtin_nontemporal_store(b, r + i);
-    else
-        r[i] = b;
+    put(p + i, (float)v, pol);
 }
-__device__ __forceinline__ void st_store(bf16_t* p, int64_t i, float v, double, bool nt)
+__device__ __forceinline__ void st_store(half_t* p, int64_t i, float v, double scale, int pol)
+{
+    put((uint16_t*)p + i, __builtin_bit_cast(uint16_t, (_Float16)(v * (float)scale)), pol);
+}
+__device__ __forceinline__ void st_store(bf16_t* p, int64_t i, float v, double, int pol)
 {
     uint32_t x = __builtin_bit_cast(uint32_t, v);
     // round to nearest even on the 16 dropped bits; NaN stays a quiet NaN
     x = (x & 0x7fffffffu) > 0x7f800000u ? 0x7fc00000u : x + 0x7fffu + ((x >> 16) & 1u);
-    const uint16_t b = (uint16_t)(x >> 16);
-    uint16_t* r = (uint16_t*)p;
-    if (nt)
-        __builtin_nontemporal_store(b, r + i);
-    else
-        r[i] = b;
+    put((uint16_t*)p + i, (uint16_t)(x >> 16), pol);
 }
 
-__device__ __forceinline__ void st_store(half_neq_t* p, int64_t i, double v, double scale, bool nt)
+__device__ __forceinline__ void st_store(half_neq_t* p, int64_t i, double v, double scale, int pol)
 {
-    st_store((half_t*)p, i, (float)v, scale, nt);
+    st_store((half_t*)p, i, (float)v, scale, pol);
 }
-__device__ __forceinline__ void st_store(bf16_neq_t* p, int64_t i, double v, double scale, bool nt)
+__device__ __forceinline__ void st_store(bf16_neq_t* p, int64_t i, double v, double scale, int pol)
 {
-    st_store((bf16_t*)p, i, (float)v, scale, nt);
+    st_store((bf16_t*)p, i, (float)v, scale, pol);
 }
 
 // The three FP32 moment planes (rho - 1, u_x, u_y per node, same pitch) that follow the nine

@@ -191,6 +191,11 @@ lbib_status prepare_particle(const lbib_lattice_desc& lat, const lbib_particle_d
     const int side = (int)std::ceil(2.0 * amax + 2.4) + 5;
     if ((double)side * side > 1.0e6) return msg = "particle too large (box of more than 10^6 nodes)", LBIB_E_INVALID;
     p.box_cap = side * side;
+    // 64 x 4 sweep tiles a box of at most side x side nodes, widened by kZoneMargin, reaches
+    const int zs = side + 2 * kZoneMargin;
+    // one sweep workgroup per tile, a multiple of 8, at most 64 (each then takes several): those
+    // that wait for the particle's force never hold so many CUs that its workgroup finds none
+    p.zone_tiles = std::min(64, (((zs + 63) / 64 + 1) * ((zs + 3) / 4 + 1) + 7) / 8 * 8);
     if (!particle_lds_bytes(p.box_cap) && particle_lds_aux_bytes(p.box_cap) > 158 * 1024)
         return msg = "particle too large for the node mask in LDS", LBIB_E_INVALID;
     return LBIB_OK;
@@ -202,7 +207,7 @@ size_t particle_block_bytes(const Particle& p)
     const size_t scratch = particle_scratch_bytes(p.box_cap);
     return 2 * align_up(2 * nl * 8) + align_up(nl * 8) + 2 * align_up(nl) + align_up(2 * cap * 8) +
            align_up((cap + 31) / 32 * 8) + (scratch ? align_up(scratch) : 0) + align_up(sizeof(TileDesc)) +
-           align_up(2 * sizeof(TileDesc)) + align_up(sizeof(DevParticle));
+           align_up(2 * sizeof(TileDesc)) + align_up(16 * 8) + align_up(sizeof(DevParticle));
 }
 
 void carve_particle(Particle& p, char* block)
@@ -225,6 +230,7 @@ void carve_particle(Particle& p, char* block)
     p.d_box = scratch ? (double*)take(scratch) : nullptr;
     p.d_desc = (TileDesc*)take(sizeof(TileDesc));
     p.d_zone = (TileDesc*)take(2 * sizeof(TileDesc));
+    p.d_count = (unsigned long long*)take(16 * 8);
     p.d_st = (DevParticle*)take(sizeof(DevParticle));
     p.block = block;
     p.own_block = false;
@@ -259,6 +265,7 @@ void free_particle(Particle& p)
     p.d_ring = nullptr;
     p.d_box = nullptr;
     p.d_desc = p.d_zone = nullptr;
+    p.d_count = nullptr;
     p.d_st = nullptr;
     dfree(p.d_trace);
     p.trace_cap = 0;
@@ -289,7 +296,8 @@ hipError_t upload_particle(Particle& p, hipStream_t s)
         (e = hipMemcpyAsync(p.d_lig, p.ligand.data(), nl, hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(p.d_bond, p.zeros.data(), nl, hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(p.d_st, &p.st0, sizeof(DevParticle), hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(p.d_desc, p.td0, sizeof(TileDesc), hipMemcpyHostToDevice, s)) != hipSuccess)
+        (e = hipMemcpyAsync(p.d_desc, p.td0, sizeof(TileDesc), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemsetAsync(p.d_count, 0, 16 * 8, s)) != hipSuccess)
         return e;
     return hipSuccess;
 }

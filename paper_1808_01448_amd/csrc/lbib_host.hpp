@@ -60,6 +60,11 @@ struct Particle {
     int box_cap = 0;
     TileDesc* d_desc = nullptr;
     TileDesc* d_zone = nullptr;  // two slots, by step parity
+    // the overlapped schedule's hand-over words (0: force-ready count, 1: zone workgroups'
+    // count, from 2: four slots of the packed box; ParticleArgs, HandoverArgs) and the number of
+    // sweep workgroups that take the tiles of its widened box
+    unsigned long long* d_count = nullptr;
+    int zone_tiles = 0;
     DevParticle* d_st = nullptr;
     lbib_particle_state* d_trace = nullptr;
     int64_t trace_cap = 0, trace_start = 0;

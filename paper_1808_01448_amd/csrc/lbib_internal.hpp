@@ -15,7 +15,8 @@ enum : int32_t {
     FLAG_CONTACT = 2,    // analytic gap to the receptor wall <= 0
     FLAG_MLS = 4,        // singular MLS moment matrix
     FLAG_TILE = 8,       // spread footprint larger than the allocated tile
-    FLAG_SYNC = 16,      // a grid barrier of the one-launch particle phase timed out
+    FLAG_SYNC = 16,      // a device-side wait timed out (the grid barrier of the one-launch particle
+                         // phase, or a hand-over of the overlapped schedule)
 };
 
 // Rigid-body state of one particle, resident in device memory.  Levels n and n-1 feed the
@@ -164,11 +165,21 @@ struct ParticleArgs {
     const PartRef* refs;
     int32_t mtx;
     int32_t nparts;  // entries of refs
-    // a single particle's phase may also sweep the nodes of its box (the overlapped
-    // schedule): when fout is set, the workgroup collides and streams every box node into
-    // fout with the lattice constants sw, after the particle update
-    T* fout;
-    SweepArgs sw;
+    // hand-over of the overlapped schedule (NULL: none): once its tile and desc have completed
+    // the particle stores ready_value into the monotonic counter *ready; its prediction of the
+    // next box goes to the two words at zone_words, packed with zone_tag (zone_pack), after
+    // its last read of f
+    unsigned long long* ready;
+    unsigned long long ready_value;
+    unsigned long long* zone_words;
+    uint32_t zone_tag;
+    // the particle launch of the overlapped schedule starts once *zdone reaches zdone_target
+    // (the previous sweep's zone workgroups have stored their results; NULL: no wait), and
+    // with check_prev checks that its box lies inside the box zone[parity_out] (the previous
+    // step's), widened by kZoneMargin - 1
+    unsigned long long* zdone;
+    unsigned long long zdone_target;
+    int32_t check_prev;
     // the one-launch split phase: grid-barrier counter and the value this launch waits for
     unsigned long long* bar;
     unsigned long long bar_target;
@@ -180,10 +191,37 @@ struct ParticleArgs {
 template <typename T>
 hipError_t launch_init(T* f, int32_t nx, int32_t ny, int32_t pitch, int64_t plane, double umax, double scale,
                        bool pull, int32_t drive, hipStream_t stream);
-// Sweep modes: every node (forces from desc/tile when desc != NULL); only nodes outside
-// the box in `desc` (which carry no spread force); only the nodes of the box in `desc`
-// (box_cap bounds the launch).
-enum SweepMode { SWEEP_ALL = 0, SWEEP_OUTSIDE = 1, SWEEP_BOX = 2 };
+// The sweep beside the particle phase of one particle (the overlapped schedule), on its own
+// stream with no event between it and the particle's launches.  Every workgroup reads this
+// step's box as the previous particle launch predicted it (zone_words, two words that carry
+// zone_tag when that launch wrote them; it wrote them after its last read of the buffer this
+// sweep overwrites), waiting until the tags match.  The workgroups of the lattice skip every
+// 64 x 4 tile the box reaches; nzone more workgroups (a multiple of 8, at most 64), before them
+// in the grid, sweep those tiles once the concurrent particle launch has published this step's
+// force (desc and tile; *ready reaches ready_target).  No cycle of waits: a sweep waits for
+// particle launches already running when it starts; its waiting workgroups (at most 64) leave
+// whole CUs for the particle's once the others drain, and the sweep stream leaves one CU out.  The hand-over data use coherent accesses (lbib_collide.hpp);
+// a wait that exceeds about a second raises FLAG_SYNC in *flags and goes on, so every
+// workgroup finishes.
+// The zone workgroups cover the box widened by kZoneMargin nodes and store coherently, then
+// count in at *zdone; the next particle launch waits for their count instead of the end of
+// the sweep, and reads the populations of its box, which lie in that widened box as long as
+// the box moves at most one node per step (the particle checks it).
+constexpr int kZoneMargin = 3;
+struct HandoverArgs {
+    const unsigned long long* zone_words;
+    uint32_t zone_tag;
+    const TileDesc* desc;
+    const int64_t* tile;
+    const unsigned long long* ready;
+    unsigned long long ready_target;
+    unsigned long long* zdone;
+    int32_t* flags;
+    int32_t nzone;
+};
+template <typename T>
+hipError_t launch_sweep_overlap(const T* fin, T* fout, const SweepArgs& a, const HandoverArgs& c, bool pull,
+                                hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 // Sweep of a step with several particles: node forces from every particle whose box reaches
 // the node (listed by the tile mask mcur, summed in particle order); each block also clears
 // its tile's word of mnext, the mask of the next step.
@@ -191,12 +229,12 @@ template <typename T>
 hipError_t launch_sweep_multi(const T* fin, T* fout, const SweepArgs& a, const unsigned long long* mcur,
                               unsigned long long* mnext, const PartRef* refs, bool pull, hipStream_t stream,
                               hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
-// t0 / t1 (optional) receive the kernel's own start and end times.
-// pull selects the layout of the population buffers (pop_index in lbib_device.hpp).
+// Sweep of every node, with the spread force of desc / tile when desc != NULL.  t0 / t1
+// (optional) receive the kernel's own start and end times.  pull selects the layout of the
+// population buffers (pop_index in lbib_device.hpp).
 template <typename T>
-hipError_t launch_sweep(const T* fin, T* fout, const SweepArgs& a, int mode, const TileDesc* desc,
-                        const int64_t* tile, int32_t box_cap, bool pull, hipStream_t stream, hipEvent_t t0 = nullptr,
-                        hipEvent_t t1 = nullptr);
+hipError_t launch_sweep(const T* fin, T* fout, const SweepArgs& a, const TileDesc* desc, const int64_t* tile, bool pull,
+                        hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 // LDS of the particle phase.  particle_lds_aux_bytes: the node mask, its prefix counts, the
 // fill queues and the overlap list, which must not exceed 158 KB.  particle_lds_bytes: that
 // plus the node fields of every node of a box of box_cap nodes, or 0 when this exceeds

@@ -759,10 +759,9 @@ __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const Phase
                     qx = force_load<LDS>(B.fx + s);
                     qy = force_load<LDS>(B.fy + s);
                 }
-                longlong2 t;
-                t.x = (long long)qx;
-                t.y = (long long)qy;
-                *(longlong2*)(a.tile + 2 * (size_t)k) = t;
+                // coherent stores: the concurrent sweep may read them (HandoverArgs)
+                coherent_store(a.tile + 2 * (size_t)k, (int64_t)qx);
+                coherent_store(a.tile + 2 * (size_t)k + 1, (int64_t)qy);
             }
         }
         if (tid == 0) {
@@ -775,13 +774,20 @@ __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const Phase
             d.active = spread_ok ? 1 : 0;
             d.i0u = box_ok ? x0 : 0;
             d.pad = 0;
-            *a.desc = d;
+            coherent_store(a.desc, d);
             if (a.check_zone) {
                 const TileDesc z = c.zin;
-                // the concurrent sweep of the nodes outside the predicted box is only valid when
-                // the prediction equals this box
+                // the concurrent sweep sweeps the tiles of the predicted box with this force:
+                // only valid when the prediction equals this box
                 if (!z.active || z.i0w != d.i0w || z.j0 != d.j0 || z.w != d.w || z.h != d.h) flags |= FLAG_TILE;
             }
+        }
+        if (MODE == 0 && a.ready) {
+            // the concurrent sweep's zone workgroups read the tile and desc once this count
+            // is published; every lane's stores have completed before it
+            stores_done();
+            __syncthreads();
+            if (tid == 0) publish_counter(a.ready, a.ready_value);
         }
     }
     if (MODE == 1 || MODE == 4) {
@@ -1012,26 +1018,9 @@ __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const Phase
             z.i0u = rn[0] != 0x7fffffff ? rn[0] : 0;
             z.pad = 0;
             a.zone[a.parity_out] = z;
-        }
-        // ---- the sweep of the box nodes (the rest of the lattice is swept beside this
-        // launch): the force at a node is the body force plus this particle's spread there,
-        // as the box sweep kernel forms it from the tile -----------------------------------
-        if (a.fout && spread_ok) {
-            for (int k = tid; k < nbox; k += PB) {
-                const uint32_t mw = mask[k >> 5];
-                int64_t qx = 0, qy = 0;
-                if ((mw >> (k & 31)) & 1u) {
-                    const int s = pre[k >> 5] + __popc(mw & ((1u << (k & 31)) - 1u));
-                    qx = (int64_t)force_load<LDS>(B.fx + s);
-                    qy = (int64_t)force_load<LDS>(B.fy + s);
-                }
-                const int i = wrap(x0 + k % w, a.nx), j = y0 + k / w;
-                const double Fx = a.sw.gx + ldexp((double)qx, -scale), Fy = a.sw.gy + ldexp((double)qy, -scale);
-                if (a.pull)
-                    collide_stream<T, true>(a.f, a.fout, a.sw, i, j, Fx, Fy);
-                else
-                    collide_stream<T, false>(a.f, a.fout, a.sw, i, j, Fx, Fy);
-            }
+            // the next sweep reads the box from these words, and overwrites f once it has
+            // them: f was last read by the probes, whose results the update above used
+            if (a.zone_words) zone_pack(z, a.zone_tag, a.zone_words);
         }
     }
 }
@@ -1137,6 +1126,27 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, char* l
     c.h = (r[2] != 0x7fffffff) ? -r[3] - r[2] + 1 : 0;
     c.box_ok = c.w > 0 && c.h > 0 && c.w <= a.nx && (int64_t)c.w * c.h <= a.box_cap;
     if (!c.box_ok && tid == 0) c.flags |= FLAG_TILE;
+    if (MODE == 0 && a.zdone) {
+        // the overlapped schedule: the previous sweep's zone workgroups have stored this
+        // step's populations around the box (coherently) once they have all counted in; the
+        // acquire drops stale copies from this CU's caches before any of them is read
+        if (tid == 0) {
+            wait_counter(a.zdone, a.zdone_target, a.flags);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (a.check_prev && c.box_ok) {
+                // those workgroups covered the previous box widened by kZoneMargin: this box
+                // must lie in it widened by kZoneMargin - 1 (its readers' sources one further)
+                const TileDesc zp = a.zone[a.parity_out];
+                const int m = kZoneMargin - 1;
+                int dx = ((c.x0 - zp.i0w) % a.nx + a.nx) % a.nx;
+                if (dx >= a.nx / 2) dx -= a.nx;
+                const bool okx = zp.w + 2 * m >= a.nx || (dx >= -m && dx + c.w <= zp.w + m);
+                const bool oky = c.y0 >= zp.j0 - m && c.y0 + c.h <= zp.j0 + zp.h + m;
+                if (!zp.active || !okx || !oky) c.flags |= FLAG_TILE;
+            }
+        }
+        __syncthreads();
+    }
 
     // ---- the nodes this launch's supports reach, and their slots ------------------------
     c.nbox = c.box_ok ? c.w * c.h : 0;
@@ -1287,7 +1297,7 @@ __global__ __launch_bounds__(PB) void pool_particle_kernel(const ParticleArgs<T>
     a.f = (n & 1) ? a.fB : a.f;
     particle_phase<T, MPT, 0>(a, (char*)lds_dyn, lds_bytes);
     if (threadIdx.x == 0) {  // the thread that wrote *a.desc in the particle phase
-        TileDesc d = *a.desc;
+        TileDesc d = coherent_load(a.desc);
         d.pad = (int32_t)(n & 1);
         ctl[k] = d;
     }

@@ -53,7 +53,7 @@ __global__ __launch_bounds__(256) void pool_sweep_kernel(const PoolSweep<T>* __r
             Fx += ldexp((double)tl[0], -d.scale);
             Fy += ldexp((double)tl[1], -d.scale);
         }
-        collide_pull<T>(fin, fout, a, i, j, Fx, Fy);
+        collide_stream<T, true>(fin, fout, a, i, j, Fx, Fy);
     }
 }
 

@@ -22,7 +22,7 @@ namespace {
 
 constexpr int kTimingPool = 8192;  // event pairs per kernel kind
 
-constexpr int kKinds = 3;  // 0 lattice sweep (all or outside the box), 1 particle phase, 2 box sweep
+constexpr int kKinds = 3;  // 0 lattice sweep, 1 particle phase, 2 second launch of the split phase
 
 struct Timing {
     int32_t mask = 0;  // bit k: time kernel kind k
@@ -38,7 +38,12 @@ struct lbib_sim {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipStream_t stream2 = nullptr;  // particle chain of the overlapped schedule
-    hipEvent_t evA = nullptr, evB = nullptr;
+    hipStream_t stream3 = nullptr;  // its sweep: every CU but one (created at first use)
+    bool masked = false;            // stream3 is CU-masked (the overlapped schedule needs it)
+    unsigned long long plaunches = 0;  // single-particle launches since lbib_init (hand-over counts)
+    unsigned long long zdone_expected = 0;  // zone workgroups of the overlapped sweeps enqueued
+    bool prev_overlapped = false;           // the last step enqueued ran overlapped
+    hipEvent_t evA = nullptr, evB = nullptr, evC = nullptr;
     int overlap = 2;  // 0 serial, 1 overlapped, 2 chosen by lattice size, 3 split particle phase
     int layout = 2;   // 0 push, 1 pull, 2 chosen by lattice size (at lbib_init)
     bool zone_valid = false;  // the zone slot of the next step holds its box
@@ -111,9 +116,11 @@ void free_all(lbib_sim* h)
     }
     if (h->evA) (void)hipEventDestroy(h->evA);
     if (h->evB) (void)hipEventDestroy(h->evB);
-    h->evA = h->evB = nullptr;
+    if (h->evC) (void)hipEventDestroy(h->evC);
+    h->evA = h->evB = h->evC = nullptr;
     if (h->stream2) (void)hipStreamDestroy(h->stream2);
-    h->stream2 = nullptr;
+    if (h->stream3) (void)hipStreamDestroy(h->stream3);
+    h->stream2 = h->stream3 = nullptr;
 }
 
 template <typename T>
@@ -179,14 +186,47 @@ EvPair timing_events(lbib_sim* h, int kind)
     return p;
 }
 
+// The overlapped schedule's sweep stream: a CU mask that leaves one CU out of the sweep, a
+// CU its workgroups can never hold while they wait on the device for the particle's.  (A
+// one-workgroup launch goes to an XCD its queue chooses, so the particle may still queue
+// behind the sweep's dispatch; it parks on its CU a step ahead, so this costs no time, and
+// leaving one CU of every XCD out measured 3 % slower.)  Created at the first overlapped step
+// (each masked stream holds a hardware queue); without CU masking the overlapped schedule
+// stays off.
+hipError_t ensure_sweep_stream(lbib_sim* h)
+{
+    if (h->stream3) return hipSuccess;
+    hipError_t e = hipEventCreateWithFlags(&h->evC, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+    if (e == hipSuccess && prop.multiProcessorCount > 64) {
+        const int n = prop.multiProcessorCount;
+        std::vector<uint32_t> mask((size_t)(n + 31) / 32, 0u);
+        for (int cu = 1; cu < n; ++cu) mask[cu / 32] |= 1u << (cu % 32);
+        if (hipExtStreamCreateWithCUMask(&h->stream3, (uint32_t)mask.size(), mask.data()) == hipSuccess) {
+            h->masked = true;
+            return hipSuccess;
+        }
+        (void)hipGetLastError();
+    }
+    // no CU masking: the overlapped schedule stays off (the stream marks the attempt)
+    return hipStreamCreateWithFlags(&h->stream3, hipStreamNonBlocking);
+}
+
 // Bytes one lattice sweep moves (every population read and written once).
 double sweep_bytes(const lbib_sim* h) { return (double)h->desc.nx * h->desc.ny * h->g.upd_bytes; }
 
 // One time step is the particle phase then the lattice sweep.  Serial schedule: both on the
 // caller's stream.  Overlapped schedule (when the previous step has predicted this step's
 // box): the particle phase runs on the second stream while the caller's stream sweeps the
-// nodes outside the box (they carry no spread force); the particle's workgroup sweeps the
-// box itself after the update.  Both schedules compute every node with the same arithmetic.
+// lattice on a third, with no event between the two chains but the particle's wait for the
+// previous sweep: the sweep waits on the device for the previous particle launch, and the
+// tiles of the predicted box, which need the spread force, go to workgroups at the end of
+// its grid, which wait for the force to be published (HandoverArgs).  Both schedules compute
+// every node with the same arithmetic.
 template <typename T>
 lbib_status enqueue_steps(lbib_sim* h, int64_t n)
 {
@@ -249,18 +289,35 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
             h->zone_valid = false;
         } else if (h->parts.empty()) {
             const EvPair e0 = timing_events(h, 0);
-            HIPCHK(h, launch_sweep<T>(fin, fout, sa, SWEEP_ALL, nullptr, nullptr, 0, h->g.pull, h->stream, e0.t0, e0.t1));
+            HIPCHK(h, launch_sweep<T>(fin, fout, sa, nullptr, nullptr, h->g.pull, h->stream, e0.t0, e0.t1));
         } else {
             Particle& p = h->parts[0];
             ParticleArgs<T> pa = particle_args<T>(h, p);
             const int par = (int)(h->steps & 1);
             pa.parity_in = par;
             pa.parity_out = par ^ 1;
-            // the overlapped schedule pays two cross-stream waits per step (~10 us); it wins
-            // once a sweep moves more than ~64 MiB (the particle phase then hides behind it)
-            const bool overlap = h->overlap == 1 || (h->overlap == 2 && sweep_bytes(h) >= 64.0 * 1048576.0);
+            // hand-over (HandoverArgs): this launch publishes its force as count launches + 1
+            // and its box prediction with that tag in slot (step + 1) mod 4; the previous
+            // launch's carries launches, in slot step mod 4
+            const unsigned long long prev = h->plaunches;
+            pa.ready = p.d_count;
+            pa.ready_value = prev + 1;
+            pa.zone_words = p.d_count + 2 + 2 * ((h->steps + 1) & 3);
+            pa.zone_tag = (uint32_t)((prev + 1) & 0xffffu);
+            h->plaunches = prev + 1;
+            // the overlapped schedule wins once a sweep moves more than ~64 MiB (the particle
+            // phase then hides behind it).  It needs the CU-masked sweep stream: workgroups of
+            // the sweep and the particle's wait for each other on the device, and the particle
+            // must always find a CU.
+            bool overlap = h->overlap == 1 || (h->overlap == 2 && sweep_bytes(h) >= 64.0 * 1048576.0);
+            if (h->desc.ny >= 65536) overlap = false;  // the packed box (zone_pack)
+            if (overlap && h->zone_valid) HIPCHK(h, ensure_sweep_stream(h));
+            if (!h->masked) overlap = false;
             if (!overlap || !h->zone_valid) {
                 if (!joined) {  // the previous step ran overlapped
+                    HIPCHK(h, hipEventRecord(h->evA, h->stream3));
+                    HIPCHK(h, hipEventRecord(h->evB, h->stream2));
+                    HIPCHK(h, hipStreamWaitEvent(h->stream, h->evA, 0));
                     HIPCHK(h, hipStreamWaitEvent(h->stream, h->evB, 0));
                     joined = true;
                 }
@@ -268,27 +325,30 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
                 const EvPair e1 = timing_events(h, 1);
                 HIPCHK(h, launch_particle<T>(pa, h->stream, e1.t0, e1.t1));
                 const EvPair e0 = timing_events(h, 0);
-                HIPCHK(h, launch_sweep<T>(fin, fout, sa, SWEEP_ALL, p.d_desc, p.d_tile, p.box_cap, h->g.pull, h->stream, e0.t0,
-                                          e0.t1));
-                HIPCHK(h, hipEventRecord(h->evA, h->stream));
+                HIPCHK(h, launch_sweep<T>(fin, fout, sa, p.d_desc, p.d_tile, h->g.pull, h->stream, e0.t0, e0.t1));
                 h->zone_valid = true;
+                h->prev_overlapped = false;
             } else {
-                // the particle's workgroup also sweeps its box after the update (no third
-                // launch on the particle chain)
+                if (joined) {  // both chains start after the caller's work
+                    HIPCHK(h, hipEventRecord(h->evC, h->stream));
+                    HIPCHK(h, hipStreamWaitEvent(h->stream2, h->evC, 0));
+                    HIPCHK(h, hipStreamWaitEvent(h->stream3, h->evC, 0));
+                }
+                // the particle launch waits on the device for the previous sweep's zone
+                // workgroups; the sweep, for the previous particle launch's box and, in its
+                // zone workgroups, for this one's force: no event between the two chains
                 pa.check_zone = 1;
-                pa.fout = fout;
-                pa.sw = sa;
-                HIPCHK(h, hipStreamWaitEvent(h->stream2, h->evA, 0));
+                pa.zdone = p.d_count + 1;
+                pa.zdone_target = h->zdone_expected;
+                pa.check_prev = h->prev_overlapped ? 1 : 0;
                 const EvPair e1 = timing_events(h, 1);
                 HIPCHK(h, launch_particle<T>(pa, h->stream2, e1.t0, e1.t1));
-                // the previous step's particle launch (with its box) before this sweep; the
-                // events are re-recorded only after both waits are enqueued
-                HIPCHK(h, hipStreamWaitEvent(h->stream, h->evB, 0));
+                const HandoverArgs ha{p.d_count + 2 + 2 * (h->steps & 3), (uint32_t)(prev & 0xffffu), p.d_desc, p.d_tile,
+                                      p.d_count, prev + 1, p.d_count + 1, h->d_flags, p.zone_tiles};
                 const EvPair e0 = timing_events(h, 0);
-                HIPCHK(h, launch_sweep<T>(fin, fout, sa, SWEEP_OUTSIDE, p.d_zone + par, nullptr, 0, h->g.pull, h->stream,
-                                          e0.t0, e0.t1));
-                HIPCHK(h, hipEventRecord(h->evA, h->stream));
-                HIPCHK(h, hipEventRecord(h->evB, h->stream2));
+                HIPCHK(h, launch_sweep_overlap<T>(fin, fout, sa, ha, h->g.pull, h->stream3, e0.t0, e0.t1));
+                h->zdone_expected += (unsigned long long)p.zone_tiles;
+                h->prev_overlapped = true;
                 joined = false;
             }
         }
@@ -297,6 +357,11 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
     }
     if (!joined) {
         // everything enqueued is ordered before later work on the caller's stream
+        if (h->prev_overlapped) {  // the particle and sweep chains of one particle
+            HIPCHK(h, hipEventRecord(h->evA, h->stream3));
+            HIPCHK(h, hipEventRecord(h->evB, h->stream2));
+            HIPCHK(h, hipStreamWaitEvent(h->stream, h->evA, 0));
+        }
         HIPCHK(h, hipStreamWaitEvent(h->stream, h->evB, 0));
         HIPCHK(h, hipEventRecord(h->evA, h->stream));
     }
@@ -314,7 +379,7 @@ lbib_status check_flags(lbib_sim* h)
         if (fl & FLAG_CONTACT) m += " particle touches the receptor wall (gap <= 0);";
         if (fl & FLAG_MLS) m += " singular MLS moment matrix;";
         if (fl & FLAG_TILE) m += " spread footprint exceeds the tile;";
-        if (fl & FLAG_SYNC) m += " grid barrier timed out;";
+        if (fl & FLAG_SYNC) m += " device-side wait timed out;";
         return fail(h, LBIB_E_NUMERIC, m);
     }
     return LBIB_OK;

@@ -99,52 +99,94 @@ hipError_t launch_init(T* f, int32_t nx, int32_t ny, int32_t pitch, int64_t plan
 // 64 x 4 node tiles over a 1-D grid.  Workgroups are dispatched round-robin over the eight
 // XCDs; the remap gives each XCD a contiguous band of tiles, so the x-shifted accesses at a
 // tile's edge land in cache lines the same XCD's L2 already holds.
-template <typename T, int MODE, bool PULL>
+__device__ __forceinline__ int xcd_tile(int b, int nblocks)
+{
+    const int q = nblocks >> 3, r = nblocks & 7, x = b & 7, k = b >> 3;
+    return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+// The force at node (i, j): the body force plus, inside the box d, the spread force of its
+// dense tile (COHERENT: written by a workgroup running beside this one).
+template <bool COHERENT>
+__device__ __forceinline__ void box_force(const TileDesc& d, const int64_t* __restrict__ tile, int i, int j, int nx,
+                                          double& Fx, double& Fy)
+{
+    if (d.active && in_box(d, i, j, nx)) {
+        int di = i - d.i0w;
+        if (di < 0) di += nx;
+        const int64_t* t = tile + 2 * ((size_t)(j - d.j0) * d.w + di);
+        Fx += ldexp((double)(COHERENT ? coherent_load(t) : t[0]), -d.scale);
+        Fy += ldexp((double)(COHERENT ? coherent_load(t + 1) : t[1]), -d.scale);
+    }
+}
+
+// Every node; the particle's spread force from desc / tile when desc != NULL.
+template <typename T, bool PULL>
 __global__ __launch_bounds__(256) void sweep_kernel(const T* __restrict__ fin, T* __restrict__ fout, SweepArgs a,
                                                     const TileDesc* __restrict__ desc,
                                                     const int64_t* __restrict__ tile, int gx, int nblocks)
 {
-    int b = blockIdx.x;
-    {
-        const int q = nblocks >> 3, r = nblocks & 7, x = b & 7, k = b >> 3;
-        b = (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
-    }
+    const int b = xcd_tile(blockIdx.x, nblocks);
     const int i = (b % gx) * 64 + (int)(threadIdx.x & 63);
     const int j = (b / gx) * 4 + (int)(threadIdx.x >> 6);
     if (i >= a.nx || j >= a.ny) return;
     double Fx = a.gx, Fy = a.gy;
-    if (MODE == SWEEP_OUTSIDE) {
-        const TileDesc d = *desc;
-        if (d.active && in_box(d, i, j, a.nx)) return;
-    } else if (desc) {
-        const TileDesc d = *desc;
-        if (d.active && in_box(d, i, j, a.nx)) {
-            int di = i - d.i0w;
-            if (di < 0) di += a.nx;
-            const int64_t* t = tile + 2 * ((size_t)(j - d.j0) * d.w + di);
-            Fx += ldexp((double)t[0], -d.scale);
-            Fy += ldexp((double)t[1], -d.scale);
-        }
-    }
+    if (desc) box_force<false>(*desc, tile, i, j, a.nx, Fx, Fy);
     collide_stream<T, PULL>(fin, fout, a, i, j, Fx, Fy);
 }
 
-// The nodes of the particle's box only.
+// The sweep beside the particle phase (HandoverArgs).  The first nzone workgroups (a multiple
+// of 8, so the XCD remap of the others is unchanged) sweep the tiles of the widened box: they
+// are dispatched first and wait for the particle's force beside the rest of the sweep rather
+// than at its end.  The others sweep the tiles outside it; each loads its populations before
+// it learns the box (no launch writes fin during the sweep), so that wait overlaps the loads.
+// At most 64 VGPRs: eight waves per SIMD.
 template <typename T, bool PULL>
-__global__ __launch_bounds__(256) void sweep_box_kernel(const T* __restrict__ fin, T* __restrict__ fout, SweepArgs a,
-                                                        const TileDesc* __restrict__ desc,
-                                                        const int64_t* __restrict__ tile)
+__global__ __launch_bounds__(256, 8) void sweep_overlap_kernel(const T* __restrict__ fin, T* __restrict__ fout,
+                                                               SweepArgs a, HandoverArgs c, int gx, int nblocks)
 {
-    const TileDesc d = *desc;
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    if (!d.active || k >= d.w * d.h) return;
-    const int di = k % d.w, dj = k / d.w;
-    int i = d.i0w + di;
-    if (i >= a.nx) i -= a.nx;
-    const int j = d.j0 + dj;
-    const int64_t* t = tile + 2 * (size_t)k;
-    collide_stream<T, PULL>(fin, fout, a, i, j, a.gx + ldexp((double)t[0], -d.scale),
-                            a.gy + ldexp((double)t[1], -d.scale));
+    __shared__ TileDesc zs, ds;
+    if ((int)blockIdx.x >= c.nzone) {
+        const int b = xcd_tile((int)blockIdx.x - c.nzone, nblocks);
+        const int tx = b % gx, ty = b / gx;
+        const int i = tx * 64 + (int)(threadIdx.x & 63), j = ty * 4 + (int)(threadIdx.x >> 6);
+        const bool in = i < a.nx && j < a.ny;
+        typename St<T>::C g[9];
+        if (in) update_load<T, PULL>(fin, a, i, j, g);
+        if (threadIdx.x == 0) zs = zone_wait(c.zone_words, c.zone_tag, c.flags);
+        __syncthreads();
+        if (!in || zone_has_tile(zone_tiles(zs, a.nx, a.ny, gx, kZoneMargin), tx, ty, gx)) return;
+        update_store<T, PULL>(fout, a, i, j, g, a.gx, a.gy);
+        return;
+    }
+    if (threadIdx.x == 0) zs = zone_wait(c.zone_words, c.zone_tag, c.flags);
+    __syncthreads();
+    const ZoneTiles zt = zone_tiles(zs, a.nx, a.ny, gx, kZoneMargin);
+    const int nt = zt.ntx * zt.nty;
+    const int e0 = (int)blockIdx.x;
+    if (e0 < nt) {
+        if (threadIdx.x == 0) {
+            wait_counter(c.ready, c.ready_target, c.flags);
+            ds = coherent_load(c.desc);
+        }
+        __syncthreads();
+        const TileDesc d = ds;
+        for (int e = e0; e < nt; e += c.nzone) {
+            int tx = zt.tx0 + e % zt.ntx;
+            if (tx >= gx) tx -= gx;
+            const int i = tx * 64 + (int)(threadIdx.x & 63), j = (zt.ty0 + e / zt.ntx) * 4 + (int)(threadIdx.x >> 6);
+            if (i >= a.nx || j >= a.ny) continue;
+            typename St<T>::C g[9];
+            update_load<T, PULL>(fin, a, i, j, g);
+            double Fx = a.gx, Fy = a.gy;
+            box_force<true>(d, c.tile, i, j, a.nx, Fx, Fy);
+            update_store<T, PULL, true>(fout, a, i, j, g, Fx, Fy);
+        }
+    }
+    // the next particle launch reads these results once every zone workgroup has counted in
+    stores_done();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(c.zdone, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Sweep of a step with several particles (64 x 4 tiles, as sweep_kernel).
@@ -154,11 +196,7 @@ __global__ __launch_bounds__(256) void sweep_multi_kernel(const T* __restrict__ 
                                                           unsigned long long* __restrict__ mnext,
                                                           const PartRef* __restrict__ refs, int gx, int nblocks)
 {
-    int b = blockIdx.x;
-    {
-        const int q = nblocks >> 3, r = nblocks & 7, x = b & 7, k = b >> 3;
-        b = (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
-    }
+    const int b = xcd_tile(blockIdx.x, nblocks);
     const unsigned long long m = mcur[b];
     if (threadIdx.x == 0) mnext[b] = 0ull;
     const int i = (b % gx) * 64 + (int)(threadIdx.x & 63);
@@ -198,39 +236,43 @@ hipError_t launch_sweep_multi(const T* fin, T* fout, const SweepArgs& a, const u
     return hipGetLastError();
 }
 
-template <typename T, bool PULL>
-hipError_t launch_sweep_layout(const T* fin, T* fout, const SweepArgs& a, int mode, const TileDesc* desc,
-                               const int64_t* tile, int32_t box_cap, hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
+template <typename T>
+hipError_t launch_sweep(const T* fin, T* fout, const SweepArgs& a, const TileDesc* desc, const int64_t* tile, bool pull,
+                        hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
 {
-    if (mode == SWEEP_BOX) {
-        hipExtLaunchKernelGGL(sweep_box_kernel<T, PULL>, dim3((box_cap + 255) / 256), dim3(256), 0u, stream, t0, t1,
-                              0u, fin, fout, a, desc, tile);
-        return hipGetLastError();
-    }
     const int gx = (a.nx + 63) / 64, gy = (a.ny + 3) / 4, nb = gx * gy;
-    if (mode == SWEEP_OUTSIDE)
-        hipExtLaunchKernelGGL(sweep_kernel<T, SWEEP_OUTSIDE, PULL>, dim3(nb), dim3(256), 0u, stream, t0, t1, 0u, fin,
-                              fout, a, desc, tile, gx, nb);
+    if (pull)
+        hipExtLaunchKernelGGL(sweep_kernel<T, true>, dim3(nb), dim3(256), 0u, stream, t0, t1, 0u, fin, fout, a, desc,
+                              tile, gx, nb);
     else
-        hipExtLaunchKernelGGL(sweep_kernel<T, SWEEP_ALL, PULL>, dim3(nb), dim3(256), 0u, stream, t0, t1, 0u, fin, fout,
-                              a, desc, tile, gx, nb);
+        hipExtLaunchKernelGGL(sweep_kernel<T, false>, dim3(nb), dim3(256), 0u, stream, t0, t1, 0u, fin, fout, a, desc,
+                              tile, gx, nb);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_sweep(const T* fin, T* fout, const SweepArgs& a, int mode, const TileDesc* desc,
-                        const int64_t* tile, int32_t box_cap, bool pull, hipStream_t stream, hipEvent_t t0,
-                        hipEvent_t t1)
+hipError_t launch_sweep_overlap(const T* fin, T* fout, const SweepArgs& a, const HandoverArgs& c, bool pull,
+                                hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
 {
-    if (pull) return launch_sweep_layout<T, true>(fin, fout, a, mode, desc, tile, box_cap, stream, t0, t1);
-    return launch_sweep_layout<T, false>(fin, fout, a, mode, desc, tile, box_cap, stream, t0, t1);
+    if (c.nzone < 8 || c.nzone > 64 || c.nzone % 8) return hipErrorInvalidValue;
+    const int gx = (a.nx + 63) / 64, gy = (a.ny + 3) / 4, nb = gx * gy;
+    const dim3 grid(nb + c.nzone);
+    if (pull)
+        hipExtLaunchKernelGGL(sweep_overlap_kernel<T, true>, grid, dim3(256), 0u, stream, t0, t1, 0u, fin, fout, a, c,
+                              gx, nb);
+    else
+        hipExtLaunchKernelGGL(sweep_overlap_kernel<T, false>, grid, dim3(256), 0u, stream, t0, t1, 0u, fin, fout, a,
+                              c, gx, nb);
+    return hipGetLastError();
 }
 
 #define LBIB_SWEEP_INSTANTIATE(T)                                                                               \
     template hipError_t launch_init<T>(T*, int32_t, int32_t, int32_t, int64_t, double, double, bool, int32_t,     \
                                        hipStream_t);                                                             \
-    template hipError_t launch_sweep<T>(const T*, T*, const SweepArgs&, int, const TileDesc*, const int64_t*,      \
-                                        int32_t, bool, hipStream_t, hipEvent_t, hipEvent_t);                      \
+    template hipError_t launch_sweep<T>(const T*, T*, const SweepArgs&, const TileDesc*, const int64_t*, bool,     \
+                                        hipStream_t, hipEvent_t, hipEvent_t);                                     \
+    template hipError_t launch_sweep_overlap<T>(const T*, T*, const SweepArgs&, const HandoverArgs&, bool,         \
+                                                hipStream_t, hipEvent_t, hipEvent_t);                             \
     template hipError_t launch_sweep_multi<T>(const T*, T*, const SweepArgs&, const unsigned long long*,           \
                                               unsigned long long*, const PartRef*, bool, hipStream_t, hipEvent_t,  \
                                               hipEvent_t);

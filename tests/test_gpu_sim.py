@@ -374,20 +374,21 @@ def test_kernel_timing_and_step_zero(L):
     ms1, n1 = s.kernel_time(1)
     ms2, n2 = s.kernel_time(2)
     say("timing", ms0, n0, ms1, n1, ms2, n2)
-    # the first step is serial (no predicted box yet), the others overlapped; the particle
-    # launch sweeps its own box, so no launch of kernel 2 (the split phase's second launch)
+    # the first step is serial (no predicted box yet), the others overlapped; one particle
+    # launch and one sweep per step, no launch of kernel 2 (the split phase's second launch)
     assert n0 == 20 and n1 == 20 and n2 == 0 and ms0 > 0 and ms1 > 0 and ms2 == 0
     assert s.bytes_per_update == 144
     s.close()
 
 
-@pytest.mark.parametrize("overlap", [0, 3])
+@pytest.mark.parametrize("overlap", [0, 1, 3])
 def test_particle_fields_in_global_scratch(L, orc, overlap):
     """A circle of radius 200 with 1024 markers: the nodes its supports reach (~5 800, or
     ~3 800 per launch of the split phase) exceed what fits beside its node mask in LDS, so
     the node fields and the node map live in the particle's global scratch (device-scope
-    atomics for the spread).  Fused phase (mode 0) and split phase (mode 3) against the
-    oracle; the two agree bit for bit."""
+    atomics for the spread).  Fused phase serial (mode 0) and overlapped (mode 1: the sweep's
+    box tiles, ~800 of them, go to as many workgroups at the head of its grid) and split phase
+    (mode 3) against the oracle."""
     w = W.channel_small_binding("fp64")
     w["lattice"].update(nx=512, ny=448)
     w["particle"].update(a_major=200.0, b_minor=200.0, xc=256.0, yc=-0.5 + 0.3 + 200.0, n_markers=1024)
@@ -402,3 +403,57 @@ def test_particle_fields_in_global_scratch(L, orc, overlap):
     np.testing.assert_array_equal(tg[:, col("n_bonds")], to[:, col("n_bonds")])
     compare_traces(tg, to, TOL["fp64"], f"  global scratch, overlap {overlap}", w)
     s.close()
+
+
+def _serial_reference(L, w, steps):
+    r = L.Sim(w)
+    r.set_overlap(0)
+    r.trace_enable(steps)
+    r.step(steps)
+    r.sync()
+    out = (r.trace(steps), r.f, r.bonds()[0])
+    r.close()
+    return out
+
+
+def test_overlapped_schedule_switches_and_calls(L):
+    """Overlapped steps in several calls of different lengths, with serial steps between
+    them (the device-side hand-over counts and box slots carry across calls and schedule
+    changes), equal the serial schedule bit for bit."""
+    w = W.channel_small_binding("fp32")
+    steps = 0
+    s = L.Sim(w)
+    s.trace_enable(400)
+    for mode, n in ((1, 1), (1, 7), (1, 64), (0, 3), (1, 5), (0, 1), (1, 120), (1, 1)):
+        s.set_overlap(mode)
+        s.step(n)
+        steps += n
+    s.sync()
+    ref = _serial_reference(L, w, steps)
+    np.testing.assert_array_equal(s.trace(steps), ref[0])
+    np.testing.assert_array_equal(s.f, ref[1])
+    np.testing.assert_array_equal(s.bonds()[0], ref[2])
+    s.close()
+
+
+def test_two_overlapped_simulations_interleaved(L):
+    """Two simulations in the overlapped schedule, their steps enqueued alternately so both
+    run at once (their sweeps leave the same CU to their particle launches): each equals its
+    serial run bit for bit."""
+    wa = W.channel_small_binding("fp64")
+    wb = W.channel_small_binding("fp32")
+    wb["particle"]["xc"] += 37.0
+    sims = [L.Sim(wa), L.Sim(wb)]
+    for s in sims:
+        s.set_overlap(1)
+        s.trace_enable(200)
+    for k in range(20):
+        for s in sims:
+            s.step(10)
+    for s in sims:
+        s.sync()
+    for s, w in zip(sims, (wa, wb)):
+        ref = _serial_reference(L, w, 200)
+        np.testing.assert_array_equal(s.trace(200), ref[0])
+        np.testing.assert_array_equal(s.f, ref[1])
+        s.close()
