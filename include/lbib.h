@@ -231,7 +231,7 @@ lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size);
  * second stream the handle owns and the lattice sweeps on a third (CU-masked: one CU is left
  * to the particle), with no event between the two chains; they hand over through device
  * memory.  The sweep of step n reads the box step n-1 predicted (exactly) for step n and
- * leaves the 64 x 4 tiles of that box, widened by 3 nodes, to workgroups at the head of its
+ * leaves the node tiles of that box, widened by 3 nodes, to workgroups at the head of its
  * grid, which take them once particle phase n has published its spread force; particle phase
  * n+1 starts once those workgroups have stored step n+1's populations around its box.  Every
  * device-side wait is bounded: one that exceeds about a second fails the simulation with

@@ -191,14 +191,19 @@ lbib_status prepare_particle(const lbib_lattice_desc& lat, const lbib_particle_d
     const int side = (int)std::ceil(2.0 * amax + 2.4) + 5;
     if ((double)side * side > 1.0e6) return msg = "particle too large (box of more than 10^6 nodes)", LBIB_E_INVALID;
     p.box_cap = side * side;
-    // 64 x 4 sweep tiles a box of at most side x side nodes, widened by kZoneMargin, reaches
-    const int zs = side + 2 * kZoneMargin;
-    // one sweep workgroup per tile, a multiple of 8, at most 64 (each then takes several): those
-    // that wait for the particle's force never hold so many CUs that its workgroup finds none
-    p.zone_tiles = std::min(64, (((zs + 63) / 64 + 1) * ((zs + 3) / 4 + 1) + 7) / 8 * 8);
+    p.zone_side = side + 2 * kZoneMargin;  // the widened box's side at most
     if (!particle_lds_bytes(p.box_cap) && particle_lds_aux_bytes(p.box_cap) > 158 * 1024)
         return msg = "particle too large for the node mask in LDS", LBIB_E_INVALID;
     return LBIB_OK;
+}
+
+// The overlapped sweep's workgroups for the tiles of the particle's widened box: one per tile
+// it can reach (Tile<PULL>), a multiple of 8, at most 64 (each then takes several): those that
+// wait for the particle's force never hold so many CUs that its workgroup finds none.
+int zone_workgroups(const Particle& p, bool pull)
+{
+    const int tw = pull ? 64 : 256, th = 256 / tw, zs = p.zone_side;
+    return std::min(64, (((zs + tw - 1) / tw + 1) * ((zs + th - 1) / th + 1) + 7) / 8 * 8);
 }
 
 size_t particle_block_bytes(const Particle& p)

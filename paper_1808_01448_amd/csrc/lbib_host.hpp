@@ -61,10 +61,10 @@ struct Particle {
     TileDesc* d_desc = nullptr;
     TileDesc* d_zone = nullptr;  // two slots, by step parity
     // the overlapped schedule's hand-over words (0: force-ready count, 1: zone workgroups'
-    // count, from 2: four slots of the packed box; ParticleArgs, HandoverArgs) and the number of
-    // sweep workgroups that take the tiles of its widened box
+    // count, from 2: four slots of the packed box; ParticleArgs, HandoverArgs) and the side of
+    // its widened box at most
     unsigned long long* d_count = nullptr;
-    int zone_tiles = 0;
+    int zone_side = 0;
     DevParticle* d_st = nullptr;
     lbib_particle_state* d_trace = nullptr;
     int64_t trace_cap = 0, trace_start = 0;
@@ -116,6 +116,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
 // Bytes of the particle's device block (every buffer aligned to 256 bytes).
+int zone_workgroups(const Particle& p, bool pull);
 size_t particle_block_bytes(const Particle& p);
 // Point the particle's buffers into `block` (particle_block_bytes(p) bytes, not owned).
 void carve_particle(Particle& p, char* block);

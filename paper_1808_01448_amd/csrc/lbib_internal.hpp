@@ -196,7 +196,7 @@ hipError_t launch_init(T* f, int32_t nx, int32_t ny, int32_t pitch, int64_t plan
 // step's box as the previous particle launch predicted it (zone_words, two words that carry
 // zone_tag when that launch wrote them; it wrote them after its last read of the buffer this
 // sweep overwrites), waiting until the tags match.  The workgroups of the lattice skip every
-// 64 x 4 tile the box reaches; nzone more workgroups (a multiple of 8, at most 64), before them
+// node tile the box reaches; nzone more workgroups (a multiple of 8, at most 64), before them
 // in the grid, sweep those tiles once the concurrent particle launch has published this step's
 // force (desc and tile; *ready reaches ready_target).  No cycle of waits: a sweep waits for
 // particle launches already running when it starts; its waiting workgroups (at most 64) leave

@@ -343,11 +343,12 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
                 pa.check_prev = h->prev_overlapped ? 1 : 0;
                 const EvPair e1 = timing_events(h, 1);
                 HIPCHK(h, launch_particle<T>(pa, h->stream2, e1.t0, e1.t1));
+                const int nzone = zone_workgroups(p, h->g.pull);
                 const HandoverArgs ha{p.d_count + 2 + 2 * (h->steps & 3), (uint32_t)(prev & 0xffffu), p.d_desc, p.d_tile,
-                                      p.d_count, prev + 1, p.d_count + 1, h->d_flags, p.zone_tiles};
+                                      p.d_count, prev + 1, p.d_count + 1, h->d_flags, nzone};
                 const EvPair e0 = timing_events(h, 0);
                 HIPCHK(h, launch_sweep_overlap<T>(fin, fout, sa, ha, h->g.pull, h->stream3, e0.t0, e0.t1));
-                h->zdone_expected += (unsigned long long)p.zone_tiles;
+                h->zdone_expected += (unsigned long long)nzone;
                 h->prev_overlapped = true;
                 joined = false;
             }

@@ -96,9 +96,9 @@ hipError_t launch_init(T* f, int32_t nx, int32_t ny, int32_t pitch, int64_t plan
     return hipGetLastError();
 }
 
-// 64 x 4 node tiles over a 1-D grid.  Workgroups are dispatched round-robin over the eight
-// XCDs; the remap gives each XCD a contiguous band of tiles, so the x-shifted accesses at a
-// tile's edge land in cache lines the same XCD's L2 already holds.
+// Tiles (Tile<PULL>; 64 x 4 for several particles) over a 1-D grid.  Workgroups are dispatched
+// round-robin over the eight XCDs; the remap gives each XCD a contiguous band of tiles, so the
+// x-shifted accesses at a tile's edge land in cache lines the same XCD's L2 already holds.
 __device__ __forceinline__ int xcd_tile(int b, int nblocks)
 {
     const int q = nblocks >> 3, r = nblocks & 7, x = b & 7, k = b >> 3;
@@ -126,9 +126,10 @@ __global__ __launch_bounds__(256) void sweep_kernel(const T* __restrict__ fin, T
                                                     const TileDesc* __restrict__ desc,
                                                     const int64_t* __restrict__ tile, int gx, int nblocks)
 {
+    using TL = Tile<PULL>;
     const int b = xcd_tile(blockIdx.x, nblocks);
-    const int i = (b % gx) * 64 + (int)(threadIdx.x & 63);
-    const int j = (b / gx) * 4 + (int)(threadIdx.x >> 6);
+    const int i = (b % gx) * TL::W + (int)threadIdx.x % TL::W;
+    const int j = (b / gx) * TL::H + (int)threadIdx.x / TL::W;
     if (i >= a.nx || j >= a.ny) return;
     double Fx = a.gx, Fy = a.gy;
     if (desc) box_force<false>(*desc, tile, i, j, a.nx, Fx, Fy);
@@ -145,23 +146,24 @@ template <typename T, bool PULL>
 __global__ __launch_bounds__(256, 8) void sweep_overlap_kernel(const T* __restrict__ fin, T* __restrict__ fout,
                                                                SweepArgs a, HandoverArgs c, int gx, int nblocks)
 {
+    using TL = Tile<PULL>;
     __shared__ TileDesc zs, ds;
     if ((int)blockIdx.x >= c.nzone) {
         const int b = xcd_tile((int)blockIdx.x - c.nzone, nblocks);
         const int tx = b % gx, ty = b / gx;
-        const int i = tx * 64 + (int)(threadIdx.x & 63), j = ty * 4 + (int)(threadIdx.x >> 6);
+        const int i = tx * TL::W + (int)threadIdx.x % TL::W, j = ty * TL::H + (int)threadIdx.x / TL::W;
         const bool in = i < a.nx && j < a.ny;
         typename St<T>::C g[9];
         if (in) update_load<T, PULL>(fin, a, i, j, g);
         if (threadIdx.x == 0) zs = zone_wait(c.zone_words, c.zone_tag, c.flags);
         __syncthreads();
-        if (!in || zone_has_tile(zone_tiles(zs, a.nx, a.ny, gx, kZoneMargin), tx, ty, gx)) return;
+        if (!in || zone_has_tile(zone_tiles<TL::W, TL::H>(zs, a.nx, a.ny, gx, kZoneMargin), tx, ty, gx)) return;
         update_store<T, PULL>(fout, a, i, j, g, a.gx, a.gy);
         return;
     }
     if (threadIdx.x == 0) zs = zone_wait(c.zone_words, c.zone_tag, c.flags);
     __syncthreads();
-    const ZoneTiles zt = zone_tiles(zs, a.nx, a.ny, gx, kZoneMargin);
+    const ZoneTiles zt = zone_tiles<TL::W, TL::H>(zs, a.nx, a.ny, gx, kZoneMargin);
     const int nt = zt.ntx * zt.nty;
     const int e0 = (int)blockIdx.x;
     if (e0 < nt) {
@@ -174,7 +176,8 @@ __global__ __launch_bounds__(256, 8) void sweep_overlap_kernel(const T* __restri
         for (int e = e0; e < nt; e += c.nzone) {
             int tx = zt.tx0 + e % zt.ntx;
             if (tx >= gx) tx -= gx;
-            const int i = tx * 64 + (int)(threadIdx.x & 63), j = (zt.ty0 + e / zt.ntx) * 4 + (int)(threadIdx.x >> 6);
+            const int i = tx * TL::W + (int)threadIdx.x % TL::W;
+            const int j = (zt.ty0 + e / zt.ntx) * TL::H + (int)threadIdx.x / TL::W;
             if (i >= a.nx || j >= a.ny) continue;
             typename St<T>::C g[9];
             update_load<T, PULL>(fin, a, i, j, g);
@@ -189,7 +192,7 @@ __global__ __launch_bounds__(256, 8) void sweep_overlap_kernel(const T* __restri
     if (threadIdx.x == 0) __hip_atomic_fetch_add(c.zdone, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Sweep of a step with several particles (64 x 4 tiles, as sweep_kernel).
+// Sweep of a step with several particles (64 x 4 tiles: those of the tile mask).
 template <typename T, bool PULL>
 __global__ __launch_bounds__(256) void sweep_multi_kernel(const T* __restrict__ fin, T* __restrict__ fout, SweepArgs a,
                                                           const unsigned long long* __restrict__ mcur,
@@ -240,13 +243,15 @@ template <typename T>
 hipError_t launch_sweep(const T* fin, T* fout, const SweepArgs& a, const TileDesc* desc, const int64_t* tile, bool pull,
                         hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
 {
-    const int gx = (a.nx + 63) / 64, gy = (a.ny + 3) / 4, nb = gx * gy;
-    if (pull)
+    if (pull) {
+        const int gx = (a.nx + 63) / 64, nb = gx * ((a.ny + 3) / 4);
         hipExtLaunchKernelGGL(sweep_kernel<T, true>, dim3(nb), dim3(256), 0u, stream, t0, t1, 0u, fin, fout, a, desc,
                               tile, gx, nb);
-    else
+    } else {
+        const int gx = (a.nx + 255) / 256, nb = gx * a.ny;
         hipExtLaunchKernelGGL(sweep_kernel<T, false>, dim3(nb), dim3(256), 0u, stream, t0, t1, 0u, fin, fout, a, desc,
                               tile, gx, nb);
+    }
     return hipGetLastError();
 }
 
@@ -255,14 +260,15 @@ hipError_t launch_sweep_overlap(const T* fin, T* fout, const SweepArgs& a, const
                                 hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
 {
     if (c.nzone < 8 || c.nzone > 64 || c.nzone % 8) return hipErrorInvalidValue;
-    const int gx = (a.nx + 63) / 64, gy = (a.ny + 3) / 4, nb = gx * gy;
-    const dim3 grid(nb + c.nzone);
-    if (pull)
-        hipExtLaunchKernelGGL(sweep_overlap_kernel<T, true>, grid, dim3(256), 0u, stream, t0, t1, 0u, fin, fout, a, c,
-                              gx, nb);
-    else
-        hipExtLaunchKernelGGL(sweep_overlap_kernel<T, false>, grid, dim3(256), 0u, stream, t0, t1, 0u, fin, fout, a,
-                              c, gx, nb);
+    if (pull) {
+        const int gx = (a.nx + 63) / 64, nb = gx * ((a.ny + 3) / 4);
+        hipExtLaunchKernelGGL(sweep_overlap_kernel<T, true>, dim3(nb + c.nzone), dim3(256), 0u, stream, t0, t1, 0u, fin,
+                              fout, a, c, gx, nb);
+    } else {
+        const int gx = (a.nx + 255) / 256, nb = gx * a.ny;
+        hipExtLaunchKernelGGL(sweep_overlap_kernel<T, false>, dim3(nb + c.nzone), dim3(256), 0u, stream, t0, t1, 0u,
+                              fin, fout, a, c, gx, nb);
+    }
     return hipGetLastError();
 }
 
