@@ -272,11 +272,12 @@ __device__ __forceinline__ TileDesc zone_wait(const unsigned long long* p, uint3
 
 // Node tiles of a lattice sweep, one per 256-thread workgroup: 256 x 1 in the push layout (a
 // wave's x-shifted stores then meet a neighbouring tile's lines at one end of a 256-node row
-// segment, not of a 64-node one: measured 3.5 % faster at 4096 x 1024), 64 x 4 in the pull
-// layout.
+// segment, not of a 64-node one: measured 3.5 % faster than 64 x 4 at 4096 x 1024, 11 % at
+// 8192 x 4096), 128 x 2 in the pull layout (5 % faster than 64 x 4 at 8192 x 4096, 256 x 1
+// slower).
 template <bool PULL>
 struct Tile {
-    static constexpr int W = PULL ? 64 : 256, H = 256 / W;
+    static constexpr int W = PULL ? 128 : 256, H = 256 / W;
 };
 
 // The TW x TH node tiles of the sweep that a box, widened by m nodes on every side, reaches:

@@ -244,7 +244,7 @@ hipError_t launch_sweep(const T* fin, T* fout, const SweepArgs& a, const TileDes
                         hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
 {
     if (pull) {
-        const int gx = (a.nx + 63) / 64, nb = gx * ((a.ny + 3) / 4);
+        const int gx = (a.nx + 127) / 128, nb = gx * ((a.ny + 1) / 2);
         hipExtLaunchKernelGGL(sweep_kernel<T, true>, dim3(nb), dim3(256), 0u, stream, t0, t1, 0u, fin, fout, a, desc,
                               tile, gx, nb);
     } else {
@@ -261,7 +261,7 @@ hipError_t launch_sweep_overlap(const T* fin, T* fout, const SweepArgs& a, const
 {
     if (c.nzone < 8 || c.nzone > 64 || c.nzone % 8) return hipErrorInvalidValue;
     if (pull) {
-        const int gx = (a.nx + 63) / 64, nb = gx * ((a.ny + 3) / 4);
+        const int gx = (a.nx + 127) / 128, nb = gx * ((a.ny + 1) / 2);
         hipExtLaunchKernelGGL(sweep_overlap_kernel<T, true>, dim3(nb + c.nzone), dim3(256), 0u, stream, t0, t1, 0u, fin,
                               fout, a, c, gx, nb);
     } else {
