@@ -178,7 +178,7 @@ __device__ __forceinline__ void collide_stream(const T* __restrict__ fin, T* __r
     update_store<T, PULL>(fout, a, i, j, g, Fx, Fy);
 }
 
-// Hand-over of the particle's force tile to the concurrent sweep (ClaimArgs) without cache
+// Hand-over of the particle's force tile to the concurrent sweep (HandoverArgs) without cache
 // maintenance: loads and stores at agent scope are coherent across the XCDs' L2 caches, so
 // the writer only has to wait for its stores to complete before it sets the ready bit.  (A
 // release or acquire fence at agent scope writes back or invalidates a whole L2, which
