@@ -24,7 +24,8 @@ constexpr double kW[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9
                           1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 
 // Element index of population q of node (i, j) at the start of a step, in the two storage
-// layouts of a population buffer (planes [q][j][i], row pitch `pitch`, plane `plane`):
+// layouts of a population buffer (element q plane + j pitch + i: row-interleaved [j][q][i]
+// with plane = the padded row and pitch = nine of them, or planes [q][j][i]):
 //  - push: the buffer holds the streamed populations, each at its own node;
 //  - pull: the buffer holds the previous step's post-collision populations at the node that
 //    emitted them; population q of (i, j) is the one emitted along e_q by (i - e_x, j - e_y)

@@ -120,8 +120,21 @@ LatticeGeom lattice_geom(const lbib_lattice_desc& d)
     g.elem = d.precision == LBIB_FP64 ? 8 : d.precision == LBIB_FP32 ? 4 : 2;
     g.neq = d.precision == LBIB_FP16_NEQ || d.precision == LBIB_BF16_NEQ;
     const int align = (int)(256 / g.elem);  // rows start on 256-byte boundaries
-    g.pitch = (d.nx + align - 1) / align * align;
-    g.plane = (int64_t)g.pitch * d.ny;
+    const int row = (d.nx + align - 1) / align * align;
+    if (g.neq || 9 * (int64_t)row > INT32_MAX) {
+        // population planes [q][j][i] (the f - f_eq storages keep their three moment planes,
+        // indexed like one population plane, after the nine)
+        g.pitch = row;
+        g.plane = (int64_t)row * d.ny;
+    } else {
+        // row-interleaved [j][q][i]: the nine population segments of a row are adjacent, so
+        // a tile's eighteen access streams fall into a few DRAM pages instead of eighteen
+        // planes a buffer apart
+        g.pitch = 9 * row;
+        g.plane = row;
+        g.interleaved = true;
+    }
+    g.row = row;
     const double H = (double)d.ny;
     g.tau = d.tau;
     g.nu = (d.tau - 0.5) / 3.0;
@@ -130,7 +143,7 @@ LatticeGeom lattice_geom(const lbib_lattice_desc& d)
     g.gx = d.drive == 1 ? 0.0 : 8.0 * g.nu * g.umax / (H * H);
     g.gy = 0.0;
     g.uw = d.drive == 1 ? g.umax : 0.0;
-    g.buf_bytes = (size_t)9 * g.plane * g.elem + (g.neq ? (size_t)3 * g.plane * 4 : 0);
+    g.buf_bytes = (size_t)9 * g.row * d.ny * g.elem + (g.neq ? (size_t)3 * g.plane * 4 : 0);
     g.upd_bytes = (int)(18 * g.elem) + (g.neq ? 24 : 0);
     if (d.precision == LBIB_FP16 || d.precision == LBIB_FP16_NEQ) {
         // the largest deviation f - w to expect is that of the rest population at a few times

@@ -2,7 +2,8 @@
 // the lattice sweep (BGK collision with Guo forcing, eq 1-6, then push-streaming with
 // half-way bounce-back at the two walls and periodic x).
 //
-// Populations are stored shifted, g_q = f_q - w_q, as planes [q][j][i] with a row pitch, in
+// Populations are stored shifted, g_q = f_q - w_q, at element q plane + j pitch + i (rows of
+// nine population segments, or population planes for the f - f_eq storages), in
 // the push layout (streamed values, scattered to the neighbours after the collision) or the
 // pull layout (post-collision values, gathered from the neighbours before it).
 // The shift keeps the FP32 storage accurate at the O(1e-4) velocities of the paper's
