@@ -223,7 +223,8 @@ lbib_status lbib_read_trace(lbib_handle h, int32_t pid, lbib_particle_state* out
 /* Checkpoint: with blob == NULL, *size receives the number of bytes needed; otherwise the
  * complete state (populations, particle, bonds, step counter) is written to blob (which
  * holds *size bytes).  lbib_load restores it into a handle created and initialised with the
- * same descriptors, and clears the failed state. */
+ * same descriptors and buffer layout (push or pull, rows or planes: a blob of another
+ * library build or layout is refused with LBIB_E_INVALID), and clears the failed state. */
 lbib_status lbib_save(lbib_handle h, void* blob, int64_t* size);
 lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size);
 

@@ -407,9 +407,12 @@ lbib_status download_f(lbib_sim* h, std::vector<double>& f)
 
 struct BlobHeader {
     char magic[8];
-    int32_t version, nx, ny, precision, n_particles, nl, layout;
+    int32_t version, nx, ny, precision, n_particles, nl;
+    int32_t layout;  // blob_layout: bit 0 pull, bit 1 row-interleaved buffers
     int64_t steps, pop_bytes;
 };
+
+int32_t blob_layout(const LatticeGeom& g) { return (g.pull ? 1 : 0) | (g.interleaved ? 2 : 0); }
 
 size_t blob_size(lbib_sim* h)
 {
@@ -795,14 +798,14 @@ lbib_status lbib_save(lbib_handle h, void* blob, int64_t* size)
     HIPCHK(h, hipStreamSynchronize(h->stream));
     char* w = (char*)blob;
     BlobHeader hd{};
-    std::memcpy(hd.magic, "LBIBCKP2", 8);
+    std::memcpy(hd.magic, "LBIBCKP3", 8);
     hd.version = LBIB_ABI_VERSION;
     hd.nx = h->desc.nx;
     hd.ny = h->desc.ny;
     hd.precision = h->desc.precision;
     hd.n_particles = (int32_t)h->parts.size();
     hd.nl = h->parts.empty() ? 0 : h->parts[0].nl;
-    hd.layout = h->g.pull ? 1 : 0;
+    hd.layout = blob_layout(h->g);
     hd.steps = h->steps;
     hd.pop_bytes = (int64_t)h->g.buf_bytes;
     std::memcpy(w, &hd, sizeof(hd));
@@ -827,8 +830,8 @@ lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size)
     if (size != (int64_t)blob_size(h)) return fail(h, LBIB_E_INVALID, "lbib_load: blob size does not match this simulation");
     BlobHeader hd;
     std::memcpy(&hd, blob, sizeof(hd));
-    if (std::memcmp(hd.magic, "LBIBCKP2", 8) != 0 || hd.version != LBIB_ABI_VERSION || hd.nx != h->desc.nx ||
-        hd.layout != (h->g.pull ? 1 : 0) ||
+    if (std::memcmp(hd.magic, "LBIBCKP3", 8) != 0 || hd.version != LBIB_ABI_VERSION || hd.nx != h->desc.nx ||
+        hd.layout != blob_layout(h->g) ||
         hd.ny != h->desc.ny || hd.precision != h->desc.precision || hd.n_particles != (int32_t)h->parts.size() ||
         (hd.n_particles && hd.nl != h->parts[0].nl) || hd.pop_bytes != (int64_t)h->g.buf_bytes)
         return fail(h, LBIB_E_INVALID, "lbib_load: checkpoint was made with different descriptors");
