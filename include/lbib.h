@@ -261,12 +261,11 @@ lbib_status lbib_set_overlap(lbib_handle h, int32_t mode);
  * buffers hold the streamed populations; the update collides a node and scatters its
  * results to the neighbours), 1 pull (the buffers hold the post-collision populations; the
  * update gathers a node's inflow from the neighbours, collides and stores at the node),
- * 2 (default) push, but pull for the f - f_eq storages (LBIB_FP16_NEQ, LBIB_BF16_NEQ) when
- * the two buffers together exceed 512 MiB.  Buffers of the other storages interleave the
- * nine populations row by row, where push is the faster update at every size measured; the
- * f - f_eq storages keep population planes, where push's shifted stores cost little only
- * while the buffers fit the GPU's 256 MB last-level cache (MALL), and beyond it the aligned
- * stores of pull move HBM traffic ~25% faster.  The layout is
+ * 2 (default) push.  Buffers interleave the nine populations row by row, where push is the
+ * faster update at the sizes measured; only rows longer than 2^31 / 9 elements fall back to
+ * population planes, where mode 2 picks pull once the two buffers exceed 512 MiB (push's
+ * shifted stores cost little only while the buffers fit the GPU's 256 MB last-level cache).
+ * The layout is
  * invisible at this interface (read-outs, writes and the oracle's populations are the
  * streamed values either way) and results are bit-identical; checkpoints record it and load
  * only into a handle with the same layout.  lbib_get_layout (after lbib_init) gives 1 for

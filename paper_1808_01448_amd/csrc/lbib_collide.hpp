@@ -71,10 +71,11 @@ __device__ __forceinline__ void collide_node(const C g[9], const SweepArgs& a, C
 // the moments stored for this node (rounded to FP32 first, so that every reader forms the same
 // equilibrium from them), and the moments are stored at the node.
 template <typename T, typename C>
-__device__ __forceinline__ void neq_encode(T* fout, const SweepArgs& a, size_t c, const C m[3], C post[9], int pol)
+__device__ __forceinline__ void neq_encode(T* fout, const SweepArgs& a, int i, int j, const C m[3], C post[9], int pol)
 {
     if constexpr (St<T>::neq) {
-        float* mo = neq_moments(fout, a.plane);
+        float* mo = neq_moments(fout, a.pitch, a.plane, a.ny);
+        const size_t c = (size_t)j * neq_mpitch(a.pitch, a.plane) + i;
         const float m0 = (float)m[0], m1 = (float)m[1], m2 = (float)m[2];
         put(mo + c, m0, pol);
         put(mo + a.plane + c, m1, pol);
@@ -99,7 +100,7 @@ __device__ __forceinline__ void push_update(T* __restrict__ fout, const SweepArg
     const int pol = COH ? ST_COH : ST_PLAIN;
     C post[9], m[3];
     collide_node<C>(g, a, (C)Fx, (C)Fy, post, m);
-    neq_encode<T, C>(fout, a, c, m, post, pol);
+    neq_encode<T, C>(fout, a, i, j, m, post, pol);
 
     const int ip = (i + 1 == a.nx) ? 0 : i + 1;
     const int im = (i == 0) ? a.nx - 1 : i - 1;
@@ -144,7 +145,7 @@ __device__ __forceinline__ void pull_update(T* __restrict__ fout, const SweepArg
     const int pol = COH ? ST_COH : ST_NT;
     C post[9], m[3];
     collide_node<C>(g, a, (C)Fx, (C)Fy, post, m);
-    neq_encode<T, C>(fout, a, c, m, post, pol);
+    neq_encode<T, C>(fout, a, i, j, m, post, pol);
 #pragma unroll
     for (int q = 0; q < 9; ++q) st_store(fout, q * P + c, post[q], a.scale, pol);
 }

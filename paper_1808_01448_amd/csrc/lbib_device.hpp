@@ -25,7 +25,8 @@ constexpr double kW[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9
 
 // Element index of population q of node (i, j) at the start of a step, in the two storage
 // layouts of a population buffer (element q plane + j pitch + i: row-interleaved [j][q][i]
-// with plane = the padded row and pitch = nine of them, or planes [q][j][i]):
+// with plane = the padded row and pitch = nine of them, or planes [q][j][i] with pitch = the
+// padded row and plane = pitch ny):
 //  - push: the buffer holds the streamed populations, each at its own node;
 //  - pull: the buffer holds the previous step's post-collision populations at the node that
 //    emitted them; population q of (i, j) is the one emitted along e_q by (i - e_x, j - e_y)
@@ -119,17 +120,28 @@ __device__ __forceinline__ void st_store(bf16_neq_t* p, int64_t i, double v, dou
     st_store((bf16_t*)p, i, (float)v, scale, pol);
 }
 
-// The three FP32 moment planes (rho - 1, u_x, u_y per node, same pitch) that follow the nine
-// population planes of a non-equilibrium buffer.
-template <typename T>
-__device__ __forceinline__ const float* neq_moments(const T* f, int64_t plane)
+// The three FP32 moments (rho - 1, u_x, u_y) of every node of a non-equilibrium buffer follow
+// its nine population segments, laid out like them: moment k of node (i, j) is element
+// k plane + j neq_mpitch + i from neq_moments.  Row-interleaved buffers (pitch = 9 plane, which
+// population planes never satisfy: there plane = pitch ny with ny >= 4) hold rows [j][k][i];
+// population planes are followed by three moment planes.
+__device__ __forceinline__ int64_t neq_mpitch(int pitch, int64_t plane)
 {
-    return (const float*)((const uint16_t*)f + 9 * plane);
+    return (int64_t)pitch == 9 * plane ? 3 * plane : (int64_t)pitch;
+}
+__device__ __forceinline__ int64_t neq_mbase(int pitch, int64_t plane, int ny)
+{
+    return (int64_t)pitch == 9 * plane ? (int64_t)pitch * ny : 9 * plane;
 }
 template <typename T>
-__device__ __forceinline__ float* neq_moments(T* f, int64_t plane)
+__device__ __forceinline__ const float* neq_moments(const T* f, int pitch, int64_t plane, int ny)
 {
-    return (float*)((uint16_t*)f + 9 * plane);
+    return (const float*)((const uint16_t*)f + neq_mbase(pitch, plane, ny));
+}
+template <typename T>
+__device__ __forceinline__ float* neq_moments(T* f, int pitch, int64_t plane, int ny)
+{
+    return (float*)((uint16_t*)f + neq_mbase(pitch, plane, ny));
 }
 
 // e_q . (x, y) for the D2Q9 directions, formed so that the value for the opposite direction
@@ -358,12 +370,13 @@ __device__ __forceinline__ void load_node(const T* f, int i, int j, int nx, int 
 #pragma unroll
     for (int q = 0; q < 9; ++q) g[q] = (R)st_load(f, pop_index(q, i, j, nx, ny, pitch, plane, pull), inv_scale, nt);
     if constexpr (St<T>::neq) {
-        const float* m = neq_moments(f, plane);
+        const float* m = neq_moments(f, pitch, plane, ny);
+        const int64_t mp = neq_mpitch(pitch, plane);
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             int si, sj, dir;
             pop_source(q, i, j, nx, ny, si, sj, dir);
-            const int64_t c = (int64_t)sj * pitch + si;
+            const int64_t c = (int64_t)sj * mp + si;
             const R d = (R)m[c], x = (R)m[plane + c], y = (R)m[2 * plane + c];
             const R eu = e_dot<R>(q, x, y);  // e_dir.u = -e_q.u for a reflected population
             g[q] += feq_from_eu<R>((R)kW[q], (R)1 + d, feq_even_base<R>(d, x, y), dir == q ? eu : -eu);

@@ -121,17 +121,19 @@ LatticeGeom lattice_geom(const lbib_lattice_desc& d)
     g.neq = d.precision == LBIB_FP16_NEQ || d.precision == LBIB_BF16_NEQ;
     const int align = (int)(256 / g.elem);  // rows start on 256-byte boundaries
     const int row = (d.nx + align - 1) / align * align;
-    if (g.neq || 9 * (int64_t)row > INT32_MAX) {
-        // population planes [q][j][i] (the f - f_eq storages keep their three moment planes,
-        // indexed like one population plane, after the nine)
+    if (9 * (int64_t)row > INT32_MAX) {
+        // population planes [q][j][i] (the pitch is a 32-bit value); the f - f_eq storages'
+        // three moment planes follow
         g.pitch = row;
         g.plane = (int64_t)row * d.ny;
+        g.mpitch = row;
     } else {
         // row-interleaved [j][q][i]: the nine population segments of a row are adjacent, so
         // a tile's eighteen access streams fall into a few DRAM pages instead of eighteen
-        // planes a buffer apart
+        // planes a buffer apart; the f - f_eq storages' moments follow as rows [j][k][i]
         g.pitch = 9 * row;
         g.plane = row;
+        g.mpitch = 3 * row;
         g.interleaved = true;
     }
     g.row = row;
@@ -143,7 +145,7 @@ LatticeGeom lattice_geom(const lbib_lattice_desc& d)
     g.gx = d.drive == 1 ? 0.0 : 8.0 * g.nu * g.umax / (H * H);
     g.gy = 0.0;
     g.uw = d.drive == 1 ? g.umax : 0.0;
-    g.buf_bytes = (size_t)9 * g.row * d.ny * g.elem + (g.neq ? (size_t)3 * g.plane * 4 : 0);
+    g.buf_bytes = (size_t)9 * g.row * d.ny * g.elem + (g.neq ? (size_t)3 * g.row * d.ny * 4 : 0);
     g.upd_bytes = (int)(18 * g.elem) + (g.neq ? 24 : 0);
     if (d.precision == LBIB_FP16 || d.precision == LBIB_FP16_NEQ) {
         // the largest deviation f - w to expect is that of the rest population at a few times
@@ -430,7 +432,8 @@ static double feq_shift_host(int q, double drho, double ux, double uy)
 }
 
 // Non-equilibrium storages: the shifted equilibrium the reader of population q at (i, j)
-// adds, from the stored moments m (3 planes) of the node that emitted it.
+// adds, from the stored moments m (moment k of node (i, j) at k plane + j mpitch + i) of the
+// node that emitted it.
 static double neq_term(const LatticeGeom& g, const float* m, int q, int i, int j)
 {
     int si = i, sj = j, dir = q;
@@ -442,7 +445,7 @@ static double neq_term(const LatticeGeom& g, const float* m, int q, int i, int j
         si = si < 0 ? si + g.nx : (si >= g.nx ? si - g.nx : si);
         sj = jj;
     }
-    const int64_t c = (int64_t)sj * g.pitch + si;
+    const int64_t c = (int64_t)sj * g.mpitch + si;
     return feq_shift_host(dir, (double)m[c], (double)m[g.plane + c], (double)m[2 * g.plane + c]);
 }
 
@@ -453,7 +456,7 @@ hipError_t download_populations(const void* fdev, const LatticeGeom& g, std::vec
     std::vector<unsigned char> raw(g.buf_bytes);
     hipError_t e = hipMemcpy(raw.data(), fdev, raw.size(), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return e;
-    const float* mom = (const float*)(raw.data() + (size_t)9 * g.plane * g.elem);
+    const float* mom = (const float*)(raw.data() + (size_t)9 * g.row * ny * g.elem);
     const double inv = 1.0 / g.scale;
     for (int q = 0; q < 9; ++q)
         for (int j = 0; j < ny; ++j)
@@ -479,7 +482,7 @@ hipError_t upload_populations(void* fdev, const LatticeGeom& g, const double* f)
     const int nx = g.nx, ny = g.ny;
     const size_t N = (size_t)nx * ny;
     std::vector<unsigned char> raw(g.buf_bytes, 0);
-    float* mom = (float*)(raw.data() + (size_t)9 * g.plane * g.elem);
+    float* mom = (float*)(raw.data() + (size_t)9 * g.row * ny * g.elem);
     if (g.neq) {
         // each node's moments (rho - 1, u) from the written populations: the equilibrium the
         // values it emits are stored against
@@ -492,7 +495,7 @@ hipError_t upload_populations(void* fdev, const LatticeGeom& g, const double* f)
                     jx += v * kExq[q];
                     jy += v * kEyq[q];
                 }
-                const int64_t c = (int64_t)j * g.pitch + i;
+                const int64_t c = (int64_t)j * g.mpitch + i;
                 mom[c] = (float)(r - 1.0);
                 mom[g.plane + c] = (float)(jx / r);
                 mom[2 * g.plane + c] = (float)(jy / r);

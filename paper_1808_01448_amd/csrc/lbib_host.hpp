@@ -23,6 +23,7 @@ struct LatticeGeom {
     int row = 0;        // elements per row of one population (nx padded to 256 bytes)
     int pitch = 0;      // elements from a node to the one above it (9 row, or row for planes)
     int64_t plane = 0;  // elements from population q to q + 1 of a node (row, or row ny)
+    int64_t mpitch = 0;  // f - f_eq storages: FP32 moment k of (i, j) at k plane + j mpitch + i
     bool interleaved = false;  // rows of nine population segments [j][q][i] (else planes)
     size_t elem = 0;    // bytes per stored population
     bool pull = false;  // buffer layout (push: streamed values; pull: post-collision values)
@@ -32,7 +33,7 @@ struct LatticeGeom {
     int drive = 0;    // 0 body-force Poiseuille, 1 moving top wall (linear shear)
     double uw = 0;    // speed of the top wall (umax for drive 1, else 0)
     bool neq = false;       // values relative to the emitting node's equilibrium, moments beside
-    size_t buf_bytes = 0;   // one population buffer: 9 row ny elements (+ 3 FP32 moment planes)
+    size_t buf_bytes = 0;   // one population buffer: 9 row ny elements (+ 3 row ny FP32 moments)
     int upd_bytes = 0;      // HBM bytes of one lattice update
 };
 

@@ -516,10 +516,10 @@ lbib_status lbib_init(lbib_handle h)
     for (auto& p : h->parts)
         if (!p.has_ligands) return fail(h, LBIB_E_STATE, "lbib_init: lbib_ligands_set missing for a particle");
     const size_t bytes = h->g.buf_bytes;
-    // in row-interleaved buffers the push update is the faster one at every size measured
-    // (up to 2.4 GB per buffer); in population planes its shifted stores are cheap only while
-    // both buffers fit the 256 MB MALL beside the rest of the working set, and far above it
-    // the pull update's aligned stores win
+    // in row-interleaved buffers the push update is the faster one at the sizes measured (up
+    // to 2.4 GB per buffer, every storage); in population planes (rows too long for a 32-bit
+    // pitch) its shifted stores are cheap only while both buffers fit the 256 MB MALL beside
+    // the rest of the working set, and far above it the pull update's aligned stores win
     h->g.pull = h->layout == 1 || (h->layout == 2 && !h->g.interleaved && 2.0 * bytes > 512.0 * 1048576.0);
     hipError_t e;
     if ((e = hipMalloc(&h->fA, bytes)) != hipSuccess || (e = hipMalloc(&h->fB, bytes)) != hipSuccess ||

@@ -3,7 +3,7 @@
 // half-way bounce-back at the two walls and periodic x).
 //
 // Populations are stored shifted, g_q = f_q - w_q, at element q plane + j pitch + i (rows of
-// nine population segments, or population planes for the f - f_eq storages), in
+// nine population segments, or population planes for rows too long for a 32-bit pitch), in
 // the push layout (streamed values, scattered to the neighbours after the collision) or the
 // pull layout (post-collision values, gathered from the neighbours before it).
 // The shift keeps the FP32 storage accurate at the O(1e-4) velocities of the paper's
@@ -76,10 +76,11 @@ __global__ __launch_bounds__(256) void init_kernel(T* f, int nx, int ny, int pit
         st_store(f, q * plane + c, (typename St<T>::C)v, scale, false);
     }
     if constexpr (St<T>::neq) {
-        float* m = neq_moments(f, plane);
-        m[c] = 0.0f;
-        m[plane + c] = (float)init_u(j, ny, umax, drive);
-        m[2 * plane + c] = 0.0f;
+        float* m = neq_moments(f, pitch, plane, ny);
+        const size_t mc = (size_t)j * neq_mpitch(pitch, plane) + i;
+        m[mc] = 0.0f;
+        m[plane + mc] = (float)init_u(j, ny, umax, drive);
+        m[2 * plane + mc] = 0.0f;
     }
 }
 
