@@ -271,14 +271,14 @@ __device__ __forceinline__ TileDesc zone_wait(const unsigned long long* p, uint3
     }
 }
 
-// Node tiles of a lattice sweep, one per 256-thread workgroup: 256 x 1 in the push layout (a
-// wave's x-shifted stores then meet a neighbouring tile's lines at one end of a 256-node row
-// segment, not of a 64-node one: measured 3.5 % faster than 64 x 4 at 4096 x 1024, 11 % at
-// 8192 x 4096), 128 x 2 in the pull layout (5 % faster than 64 x 4 at 8192 x 4096, 256 x 1
-// slower).
+// Node tiles of a lattice sweep, one per 256-thread workgroup: 256 x 1 in both layouts (a
+// wave's x-shifted stores or loads then meet a neighbouring tile's lines at one end of a
+// 256-node row segment, not of a 64-node one).  Measured in row-interleaved buffers, FP32
+// (median sweep times): push 1 % faster than 128 x 2 and 3 % faster than 64 x 4 at
+// 4096 x 1024, about 6 % and 13 % at 8192 x 4096; pull 1-4 % faster than 128 x 2.
 template <bool PULL>
 struct Tile {
-    static constexpr int W = PULL ? 128 : 256, H = 256 / W;
+    static constexpr int W = 256, H = 1;
 };
 
 // The TW x TH node tiles of the sweep that a box, widened by m nodes on every side, reaches:

@@ -217,7 +217,8 @@ lbib_status prepare_particle(const lbib_lattice_desc& lat, const lbib_particle_d
 // wait for the particle's force never hold so many CUs that its workgroup finds none.
 int zone_workgroups(const Particle& p, bool pull)
 {
-    const int tw = pull ? 128 : 256, th = 256 / tw, zs = p.zone_side;
+    (void)pull;  // both layouts sweep 256 x 1 tiles
+    const int tw = 256, th = 1, zs = p.zone_side;
     return std::min(64, (((zs + tw - 1) / tw + 1) * ((zs + th - 1) / th + 1) + 7) / 8 * 8);
 }
 

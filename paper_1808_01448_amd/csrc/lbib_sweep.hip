@@ -246,11 +246,13 @@ hipError_t launch_sweep(const T* fin, T* fout, const SweepArgs& a, const TileDes
                         hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
 {
     if (pull) {
-        const int gx = (a.nx + 127) / 128, nb = gx * ((a.ny + 1) / 2);
+        using TL = Tile<true>;
+        const int gx = (a.nx + TL::W - 1) / TL::W, nb = gx * ((a.ny + TL::H - 1) / TL::H);
         hipExtLaunchKernelGGL(sweep_kernel<T, true>, dim3(nb), dim3(256), 0u, stream, t0, t1, 0u, fin, fout, a, desc,
                               tile, gx, nb);
     } else {
-        const int gx = (a.nx + 255) / 256, nb = gx * a.ny;
+        using TL = Tile<false>;
+        const int gx = (a.nx + TL::W - 1) / TL::W, nb = gx * ((a.ny + TL::H - 1) / TL::H);
         hipExtLaunchKernelGGL(sweep_kernel<T, false>, dim3(nb), dim3(256), 0u, stream, t0, t1, 0u, fin, fout, a, desc,
                               tile, gx, nb);
     }
@@ -263,11 +265,13 @@ hipError_t launch_sweep_overlap(const T* fin, T* fout, const SweepArgs& a, const
 {
     if (c.nzone < 8 || c.nzone > 64 || c.nzone % 8) return hipErrorInvalidValue;
     if (pull) {
-        const int gx = (a.nx + 127) / 128, nb = gx * ((a.ny + 1) / 2);
+        using TL = Tile<true>;
+        const int gx = (a.nx + TL::W - 1) / TL::W, nb = gx * ((a.ny + TL::H - 1) / TL::H);
         hipExtLaunchKernelGGL(sweep_overlap_kernel<T, true>, dim3(nb + c.nzone), dim3(256), 0u, stream, t0, t1, 0u, fin,
                               fout, a, c, gx, nb);
     } else {
-        const int gx = (a.nx + 255) / 256, nb = gx * a.ny;
+        using TL = Tile<false>;
+        const int gx = (a.nx + TL::W - 1) / TL::W, nb = gx * ((a.ny + TL::H - 1) / TL::H);
         hipExtLaunchKernelGGL(sweep_overlap_kernel<T, false>, dim3(nb + c.nzone), dim3(256), 0u, stream, t0, t1, 0u,
                               fin, fout, a, c, gx, nb);
     }
