@@ -78,9 +78,13 @@ def test_16bit_storage_against_oracle(L, orc, prec):
     s.close()
 
 
+@pytest.mark.parametrize("nx", [256, 200])
 @pytest.mark.parametrize("prec", ALL16)
-def test_16bit_layouts_and_schedules_agree(L, prec):
+def test_16bit_layouts_and_schedules_agree(L, prec, nx):
+    """Push, pull and the overlapped schedule give the same fields and records bit for bit;
+    nx = 200 pads every row and leaves a partial tile at the end of it."""
     w = W.channel_small_binding(prec)
+    w["lattice"]["nx"] = nx
     out = []
     for layout, overlap in ((0, 0), (1, 0), (1, 1)):
         s = L.Sim(w, layout=layout)
@@ -104,11 +108,14 @@ def fp16_scale(w):
     return 2.0 ** min(40, max(0, int(np.floor(np.log2(8192.0 / d)))))
 
 
+@pytest.mark.parametrize("nx", [256, 200])
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
-def test_16bit_population_roundtrip(L, prec):
+def test_16bit_population_roundtrip(L, prec, nx):
     """Written populations read back as the storage's rounding (to nearest even) of f - w,
-    FP16 after its power-of-two scale, for deviations from 1e-9 to 1e-3."""
+    FP16 after its power-of-two scale, for deviations from 1e-9 to 1e-3; nx = 200 leaves
+    padding after every population segment of a row."""
     w = W.channel_small_binding(prec)
+    w["lattice"]["nx"] = nx
     s = L.Sim(w)
     f = s.f
     wq = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)[:, None, None]
@@ -143,13 +150,17 @@ def test_16bit_pool_member_equals_standalone(L, prec):
     P.close()
 
 
+@pytest.mark.parametrize("nx", [256, 200])
 @pytest.mark.parametrize("prec", ["fp16_neq", "bf16_neq"])
-def test_neq_population_roundtrip(L, prec):
+def test_neq_population_roundtrip(L, prec, nx):
     """Written populations read back to the storage's rounding of f - f_eq, the equilibrium of
     each emitting node's moments (rho - 1, u) computed from the written values: for random
     deviations from 1e-9 to 1e-3 of the weights the error stays below u/2 of the largest
-    stored value (measured 9.3e-7 / 7.2e-6 absolute against deviations up to 1e-3)."""
+    stored value (measured 9.3e-7 / 7.2e-6 absolute against deviations up to 1e-3).  With
+    nx = 200 every population segment and moment row of a row carries padding, so the host's
+    encoding and the kernels' must agree on the padded strides."""
     w = W.channel_small_binding(prec)
+    w["lattice"]["nx"] = nx
     s = L.Sim(w)
     f = s.f
     wq = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)[:, None, None]
