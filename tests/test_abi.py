@@ -167,7 +167,8 @@ def test_pool_host_validation(L):
 
 
 def test_pool_footprint(L):
-    """Two population buffers of 9 planes (rows padded to 256 bytes) plus the particle's
+    """Two population buffers of nine population rows per lattice row (each padded to 256
+    bytes), plus three FP32 moment rows for the f - f_eq storages, plus the particle's
     buffers; refused for descriptors lbib_create / lbib_particle_add would refuse."""
     def fp(nx, ny, prec, **kw):
         d = lbib.LatticeDesc(nx, ny, 0.8, 0.1, 0, prec, 0)
@@ -180,6 +181,13 @@ def test_pool_footprint(L):
         assert st == lbib.OK
         pitch = -(-nx * elem // 256) * 256 // elem
         pop = 2 * 9 * pitch * ny * elem
+        assert pop < v < pop + 200_000, (nx, ny, prec, v - pop)
+    # (1000 x 300: the moment rows, 7.4 MB, far exceed the particle's share)
+    for nx, ny, prec in [(100, 40, 2), (100, 40, 4), (1000, 300, 2), (1000, 300, 4), (1000, 300, 5)]:
+        st, v = fp(nx, ny, prec)
+        assert st == lbib.OK
+        row = -(-nx * 2 // 256) * 256 // 2
+        pop = 2 * (9 * row * ny * 2 + (3 * row * ny * 4 if prec >= 4 else 0))
         assert pop < v < pop + 200_000, (nx, ny, prec, v - pop)
     # more markers or a larger particle never cost less
     assert fp(64, 32, 1, n_markers=64)[1] > fp(64, 32, 1)[1]
