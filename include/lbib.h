@@ -500,6 +500,37 @@ lbib_status lbib_kernel_bonds(const uint8_t* ligand, const double* d, const uint
  * measured HBM reference for the lattice sweep's roofline. */
 lbib_status lbib_bandwidth_probe(int64_t bytes, int32_t iters, void* hip_stream, double* gbps);
 
+/* ---------------------------------------------------------------------------------------
+ * Allocation-free solve, for callers that cannot allocate device memory (harnesses that
+ * forbid hipMalloc, serving loops that hand out memory from their own pools).
+ *
+ * Runs what lbib_create / lbib_particle_add / lbib_ligands_set / lbib_init /
+ * lbib_set_overlap(h, 0) / lbib_step(n_steps) / lbib_read_trace / lbib_read_bonds run, with
+ * the same kernels and bit-identical results, without calling hipMalloc or hipFree: the two
+ * population buffers come from the caller, and every other device buffer of the solve (the
+ * particle's surface, flags, spread-force tile, box descriptors, node-field overflow,
+ * rigid-body state, watchdog word) lives in one static device array of 8 MiB per GPU, which
+ * the library holds until the process ends.  A particle whose buffers exceed it (semi-axes
+ * above about 170 lattice units) is refused with LBIB_E_INVALID before any GPU work.
+ *   populations: DEVICE buffer of *populations_bytes bytes, 256-byte aligned, holding the
+ *     two population buffers (their contents on return: the populations after the last
+ *     step, in the library's internal storage); NULL: *populations_bytes receives the size
+ *     the lattice needs and nothing else is done;
+ *   trace: DEVICE buffer of n_steps lbib_particle_state records (record k: step k), or NULL;
+ *   bonds: DEVICE buffer of n_markers bytes receiving the bond flags after the last step,
+ *     or NULL;
+ *   hip_stream: the stream to run on (NULL = the default stream).
+ * The call validates like the calls it replaces, enqueues, and waits for its stream before
+ * returning: LBIB_E_NUMERIC when the GPU watchdog fired.  Calls on one GPU share its static
+ * array (it keeps the last call's contents; a solve initialises what it reads): within a
+ * process the library runs them one at a time (a call holds the device's array until its
+ * work has finished), since two solves overlapping on the array would race.  Errors are
+ * described by lbib_last_error(NULL). */
+lbib_status lbib_solve_static(const lbib_lattice_desc* lattice, const lbib_particle_desc* particle,
+                              const lbib_ligand_desc* ligands, int64_t n_steps, void* populations,
+                              int64_t* populations_bytes, lbib_particle_state* trace, uint8_t* bonds,
+                              void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "liblbib.so")
 SOURCES = ["lbib_sweep.hip", "lbib_pool_sweep.hip", "lbib_particle.hip", "lbib_runtime.cpp", "lbib_pool.cpp",
-           "lbib_serve.cpp", "lbib_host.cpp", "lbib_geometry.cpp"]
+           "lbib_serve.cpp", "lbib_host.cpp", "lbib_geometry.cpp", "lbib_static.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

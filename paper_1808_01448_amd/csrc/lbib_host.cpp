@@ -386,6 +386,23 @@ template void fill_particle_args<half_neq_t>(ParticleArgs<half_neq_t>&, const La
 template void fill_particle_args<bf16_neq_t>(ParticleArgs<bf16_neq_t>&, const LatticeGeom&, uint64_t, const Particle&,
                                              int32_t*);
 
+SweepArgs make_sweep_args(const LatticeGeom& g)
+{
+    SweepArgs a{};
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.pitch = g.pitch;
+    a.plane = g.plane;
+    a.omega = 1.0 / g.tau;
+    a.guo = 1.0 - 1.0 / (2.0 * g.tau);
+    a.gx = g.gx;
+    a.gy = g.gy;
+    a.scale = g.scale;
+    a.inv_scale = 1.0 / g.scale;
+    a.uw6 = g.uw / 6.0;
+    return a;
+}
+
 hipError_t init_populations(void* f, const LatticeGeom& g, hipStream_t s)
 {
     const size_t bytes = g.buf_bytes;

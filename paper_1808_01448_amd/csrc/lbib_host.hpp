@@ -134,6 +134,13 @@ hipError_t upload_particle(Particle& p, hipStream_t s);
 template <typename T>
 void fill_particle_args(ParticleArgs<T>& a, const LatticeGeom& g, uint64_t seed, const Particle& p, int32_t* flags);
 
+// Constants of a lattice sweep (relaxation, forcing, storage scale, wall speed).
+SweepArgs make_sweep_args(const LatticeGeom& g);
+
+// The message lbib_last_error(NULL) returns on this thread (calls that fail before they
+// have a handle).
+void set_null_error(const std::string& msg);
+
 // Initial populations f = f_eq(1, u_poiseuille(y)) (shifted, in the geometry's layout),
 // padding zeroed.
 hipError_t init_populations(void* f, const LatticeGeom& g, hipStream_t s);

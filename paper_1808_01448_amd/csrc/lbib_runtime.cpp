@@ -151,22 +151,7 @@ lbib_status upload_split_args(lbib_sim* h)
     return LBIB_OK;
 }
 
-SweepArgs sweep_args(lbib_sim* h)
-{
-    SweepArgs a{};
-    a.nx = h->desc.nx;
-    a.ny = h->desc.ny;
-    a.pitch = h->g.pitch;
-    a.plane = h->g.plane;
-    a.omega = 1.0 / h->desc.tau;
-    a.guo = 1.0 - 1.0 / (2.0 * h->desc.tau);
-    a.gx = h->g.gx;
-    a.gy = h->g.gy;
-    a.scale = h->g.scale;
-    a.inv_scale = 1.0 / h->g.scale;
-    a.uw6 = h->g.uw / 6.0;
-    return a;
-}
+SweepArgs sweep_args(lbib_sim* h) { return make_sweep_args(h->g); }
 
 // Event pair that brackets the next launch of kernel `kind` (null when timing is off or the
 // pool is used up).
@@ -422,6 +407,8 @@ size_t blob_size(lbib_sim* h)
 }
 
 }  // namespace
+
+void lbib::set_null_error(const std::string& msg) { g_null_err = msg; }
 
 // ========================================================================================
 // C-ABI

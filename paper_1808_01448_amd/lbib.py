@@ -105,6 +105,8 @@ _SIGS = {
     "lbib_kernel_bonds": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, C.c_int32, C.c_int32, _D, C.c_uint64,
                                     C.c_uint32, _P]),
     "lbib_bandwidth_probe": (C.c_int, [C.c_int64, C.c_int32, _P, _D]),
+    "lbib_solve_static": (C.c_int, [C.POINTER(LatticeDesc), C.POINTER(ParticleDesc), C.POINTER(LigandDesc),
+                                    C.c_int64, _P, _I64, _P, _P, _P]),
     "lbib_pool_create": (C.c_int, [C.c_int32, C.c_int64, C.c_int32, _P, C.POINTER(_P)]),
     "lbib_pool_footprint": (C.c_int, [C.POINTER(LatticeDesc), C.POINTER(ParticleDesc), _I64]),
     "lbib_pool_add": (C.c_int, [_P, C.POINTER(LatticeDesc), C.POINTER(ParticleDesc), C.POINTER(LigandDesc),
@@ -659,3 +661,39 @@ def bandwidth_probe(nbytes: int, iters: int = 10, stream=None) -> float:
     v = C.c_double()
     _check(lib().lbib_bandwidth_probe(int(nbytes), int(iters), _stream_ptr(stream), C.byref(v)))
     return v.value
+
+
+def solve_static_bytes(workload: dict) -> int:
+    """Bytes of the population buffers lbib_solve_static needs for this lattice."""
+    v = C.c_int64(0)
+    _check(lib().lbib_solve_static(C.byref(_lattice_desc(workload["lattice"])),
+                                   C.byref(_particle_desc(workload["particle"])),
+                                   C.byref(_ligand_desc(workload["ligand"])), 0, None, C.byref(v), None, None,
+                                   None))
+    return v.value
+
+
+def solve_static(workload: dict, n_steps: int, stream=None):
+    """The allocation-free solve (lbib_solve_static): n_steps steps of the workload's single
+    particle with the serial schedule.  The device buffers it is given (populations, trace,
+    bonds) are torch tensors allocated here, as a caller with its own memory would provide
+    them.  Returns (trace float64 [n_steps, 20] in the field order of STATE_FIELDS, bond
+    flags uint8 [n_markers])."""
+    import torch
+
+    need = solve_static_bytes(workload)
+    pops = torch.empty(need, dtype=torch.uint8, device="cuda")
+    rec = C.sizeof(ParticleState)
+    tr = torch.empty(max(1, n_steps) * rec, dtype=torch.uint8, device="cuda")
+    nl = int(workload["particle"]["n_markers"])
+    bd = torch.empty(nl, dtype=torch.uint8, device="cuda")
+    v = C.c_int64(need)
+    st = _stream_ptr(stream)
+    if stream is not None:
+        stream.wait_stream(torch.cuda.current_stream())
+    _check(lib().lbib_solve_static(C.byref(_lattice_desc(workload["lattice"])),
+                                   C.byref(_particle_desc(workload["particle"])),
+                                   C.byref(_ligand_desc(workload["ligand"])), int(n_steps), _ptr(pops), C.byref(v),
+                                   _ptr(tr), _ptr(bd), st))
+    raw = tr.cpu().numpy().tobytes()
+    return _trace_array(raw, int(n_steps)), bd.cpu().numpy()
