@@ -450,6 +450,20 @@ lbib_status lbib_server_progress(lbib_server_handle s, int32_t* n_completed);
 /* Ids of completed requests, oldest first (up to capacity; the rest stay for the next call). */
 lbib_status lbib_server_take_completed(lbib_server_handle s, int64_t* ids, int32_t capacity, int32_t* count);
 
+/* Tracing: every request admitted after this call records the particle record of each of
+ * its first `capacity` steps (0 switches it off for later admissions); lbib_server_read_trace
+ * copies a completed request's records (up to capacity; *count receives how many).  Each
+ * traced admission allocates its record buffer on the device and waits for the server's
+ * stream: it is meant for checking results, not for throughput runs.
+ * lbib_server_read_bonds: a completed request's bond and ligand flags after its last step
+ * (capacity >= n_markers; either output may be NULL).  Both return LBIB_E_STATE for a request
+ * that has not completed. */
+lbib_status lbib_server_set_trace(lbib_server_handle s, int64_t capacity);
+lbib_status lbib_server_read_trace(lbib_server_handle s, int64_t id, lbib_particle_state* out, int64_t capacity,
+                                   int64_t* count);
+lbib_status lbib_server_read_bonds(lbib_server_handle s, int64_t id, uint8_t* bonded, uint8_t* ligand,
+                                   int32_t capacity);
+
 /* A request's current record; lbib_server_release frees a completed one. */
 lbib_status lbib_server_result(lbib_server_handle s, int64_t id, lbib_request_result* out);
 lbib_status lbib_server_release(lbib_server_handle s, int64_t id);

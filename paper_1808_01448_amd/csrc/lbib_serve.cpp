@@ -25,6 +25,11 @@ struct Request {
     int64_t bytes = 0;
     int32_t bypassed = 0;  // admissions of later requests while this one waited at the head
     lbib_request_result res{};
+    // copied out of the pool when the request completes (before it leaves): the bond and
+    // ligand flags after its last step and, when tracing was on at admission, its records
+    std::vector<uint8_t> bonded, ligand;
+    std::vector<lbib_particle_state> trace;
+    int64_t trace_cap = 0;
 };
 
 double now_s(std::chrono::steady_clock::time_point t0)
@@ -47,6 +52,7 @@ struct lbib_server {
     std::vector<int64_t> completed;          // finished or failed, not yet taken
     std::string err;
     int64_t chunks = 0;
+    int64_t trace_cap = 0;  // records kept per request admitted from now on (0: none)
 };
 
 namespace {
@@ -96,6 +102,11 @@ lbib_status admit(lbib_server* h)
             it = h->queue.erase(it);
             continue;
         }
+        if (h->trace_cap > 0) {
+            r->trace_cap = std::min(h->trace_cap, r->steps);
+            if ((s = lbib_pool_trace_enable(h->pool, slot, r->trace_cap)) != LBIB_OK)
+                return pool_fail(h, s, "lbib_server: trace");
+        }
         r->res.state = LBIB_REQ_RUNNING;
         r->res.t_admit = now_s(h->t0);
         r->res.slot = slot;
@@ -124,6 +135,18 @@ lbib_status collect(lbib_server* h)
             return pool_fail(h, s, "lbib_server: status");
         if ((s = lbib_pool_read_particle(h->pool, done[k], &r->res.final_state)) != LBIB_OK)
             return pool_fail(h, s, "lbib_server: read");
+        const int32_t nl = r->part.n_markers;
+        r->bonded.assign((size_t)nl, 0);
+        r->ligand.assign((size_t)nl, 0);
+        if ((s = lbib_pool_read_bonds(h->pool, done[k], r->bonded.data(), r->ligand.data(), nl)) != LBIB_OK)
+            return pool_fail(h, s, "lbib_server: bonds");
+        if (r->trace_cap > 0) {
+            int64_t cnt = 0;
+            r->trace.resize((size_t)r->trace_cap);
+            if ((s = lbib_pool_read_trace(h->pool, done[k], r->trace.data(), r->trace_cap, &cnt)) != LBIB_OK)
+                return pool_fail(h, s, "lbib_server: trace");
+            r->trace.resize((size_t)cnt);
+        }
         r->res.steps_done = steps;
         r->res.state = state == LBIB_POOL_FINISHED ? LBIB_REQ_DONE : LBIB_REQ_FAILED;
         r->res.t_done = t;
@@ -133,6 +156,22 @@ lbib_status collect(lbib_server* h)
         h->completed.push_back(r->id);
     }
     return LBIB_OK;
+}
+
+// A completed request, or nullptr with the error set.
+Request* completed_request(lbib_server* h, int64_t id, const char* what)
+{
+    auto it = h->all.find(id);
+    if (it == h->all.end()) {
+        fail(h, LBIB_E_INVALID, std::string(what) + ": unknown or released request");
+        return nullptr;
+    }
+    const int32_t st = it->second->res.state;
+    if (st != LBIB_REQ_DONE && st != LBIB_REQ_FAILED) {
+        fail(h, LBIB_E_STATE, std::string(what) + ": the request has not completed");
+        return nullptr;
+    }
+    return it->second;
 }
 
 }  // namespace
@@ -238,6 +277,43 @@ lbib_status lbib_server_result(lbib_server_handle h, int64_t id, lbib_request_re
     auto it = h->all.find(id);
     if (it == h->all.end()) return fail(h, LBIB_E_INVALID, "lbib_server_result: unknown or released request");
     *out = it->second->res;
+    return LBIB_OK;
+}
+
+lbib_status lbib_server_set_trace(lbib_server_handle h, int64_t capacity)
+{
+    if (!h) return fail(nullptr, LBIB_E_INVALID, "lbib_server_set_trace: NULL handle");
+    if (capacity < 0 || capacity > ((int64_t)1 << 28))
+        return fail(h, LBIB_E_INVALID, "lbib_server_set_trace: capacity must be in [0, 2^28]");
+    h->trace_cap = capacity;
+    return LBIB_OK;
+}
+
+lbib_status lbib_server_read_trace(lbib_server_handle h, int64_t id, lbib_particle_state* out, int64_t capacity,
+                                   int64_t* count)
+{
+    if (!h) return fail(nullptr, LBIB_E_INVALID, "lbib_server_read_trace: NULL handle");
+    if (!count || capacity < 0 || (capacity > 0 && !out))
+        return fail(h, LBIB_E_INVALID, "lbib_server_read_trace: NULL output or negative capacity");
+    Request* r = completed_request(h, id, "lbib_server_read_trace");
+    if (!r) return h->all.count(id) ? LBIB_E_STATE : LBIB_E_INVALID;
+    const int64_t n = std::min<int64_t>(capacity, (int64_t)r->trace.size());
+    std::copy(r->trace.begin(), r->trace.begin() + n, out);
+    *count = n;
+    return LBIB_OK;
+}
+
+lbib_status lbib_server_read_bonds(lbib_server_handle h, int64_t id, uint8_t* bonded, uint8_t* ligand,
+                                   int32_t capacity)
+{
+    if (!h) return fail(nullptr, LBIB_E_INVALID, "lbib_server_read_bonds: NULL handle");
+    Request* r = completed_request(h, id, "lbib_server_read_bonds");
+    if (!r) return h->all.count(id) ? LBIB_E_STATE : LBIB_E_INVALID;
+    const int32_t nl = (int32_t)r->bonded.size();
+    if (capacity < nl)
+        return fail(h, LBIB_E_INVALID, "lbib_server_read_bonds: capacity below n_markers = " + std::to_string(nl));
+    if (bonded) std::copy(r->bonded.begin(), r->bonded.end(), bonded);
+    if (ligand) std::copy(r->ligand.begin(), r->ligand.end(), ligand);
     return LBIB_OK;
 }
 

@@ -135,6 +135,9 @@ _SIGS = {
     "lbib_server_take_completed": (C.c_int, [_P, _I64, C.c_int32, C.POINTER(C.c_int32)]),
     "lbib_server_result": (C.c_int, [_P, C.c_int64, C.POINTER(RequestResult)]),
     "lbib_server_release": (C.c_int, [_P, C.c_int64]),
+    "lbib_server_set_trace": (C.c_int, [_P, C.c_int64]),
+    "lbib_server_read_trace": (C.c_int, [_P, C.c_int64, C.POINTER(ParticleState), C.c_int64, _I64]),
+    "lbib_server_read_bonds": (C.c_int, [_P, C.c_int64, _U8, _U8, C.c_int32]),
     "lbib_server_stats": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _I64, _I64]),
     "lbib_server_pool": (_P, [_P]),
     "lbib_server_clock": (C.c_double, [_P]),
@@ -604,6 +607,25 @@ class Server:
 
     def release(self, rid: int):
         self._call(lib().lbib_server_release, int(rid))
+
+    def set_trace(self, capacity: int):
+        """Requests admitted from now on record their first `capacity` steps (0: off)."""
+        self._call(lib().lbib_server_set_trace, int(capacity))
+
+    def trace(self, rid: int, capacity: int) -> np.ndarray:
+        """A completed request's records as float64 [count, 20] (field order of STATE_FIELDS)."""
+        buf = (ParticleState * max(1, capacity))()
+        cnt = C.c_int64()
+        self._call(lib().lbib_server_read_trace, int(rid), buf, int(capacity), C.byref(cnt))
+        return _trace_array(buf, cnt.value)
+
+    def bonds(self, rid: int, n_markers: int):
+        """A completed request's (bonded, ligand) flags after its last step."""
+        b = np.zeros(n_markers, np.uint8)
+        lg = np.zeros(n_markers, np.uint8)
+        self._call(lib().lbib_server_read_bonds, int(rid), b.ctypes.data_as(_U8), lg.ctypes.data_as(_U8),
+                   int(n_markers))
+        return b, lg
 
     def stats(self):
         """(queued, running, bytes in use, chunks stepped)."""

@@ -293,3 +293,37 @@ def test_pool_autotune(L):
     w, _ = cases[2]
     assert_same(pooled(P, slots[2], 0), dict(alone(L, w, 1000), trace=np.zeros((0, 20))), "after autotune")
     P.close()
+
+
+def test_pool_fp32_member_of_sweep_size_against_oracle(L, orc):
+    """A member of the parameter sweep's largest grid (2048 x 256, aspect-ratio-3 ellipse of
+    area 0.025 H^2 at a gap of 3e-3 H, ligand density 0.7, bond strength 2, Re 1), FP32,
+    pooled beside two smaller members for 200 steps with the launch shape the autotuner
+    would pick among: its particle series within 1e-5 of the FP64 oracle, bond counts and
+    final flags bit-exact."""
+    from _parity import col, trace_errors
+
+    w = W.sweep_member(2048, 256, "ar3", (7, 10), 2, 1.0, 0, precision="fp32")
+    others = [W.sweep_member(600, 130, "circle", (1, 2), 1, 0.1, 1, precision="fp32"),
+              W.sweep_member(1111, 201, "ar2", (9, 10), 2, 0.01, 2, precision="fp32")]
+    n = 200
+    P = L.Pool(L.FP32)
+    P.set_config(128, 2, 0)
+    s = P.add(w, n)
+    for o_ in others:
+        P.add(o_, n)
+    P.trace_enable(s, n)
+    P.step(n)
+    P.poll()
+    tg = P.trace(s, n)
+    o = orc.Sim.from_workload(w)
+    _, to = o.step(n, trace=True)
+    errs = trace_errors(tg, to, w["particle"])
+    say("sweep-size member vs oracle:", " ".join(f"{k}={v:.2e}" for k, v in errs.items()),
+        "bonds max", int(to[:, col("n_bonds")].max()))
+    for k, v in errs.items():
+        assert v <= 1e-5, (k, v)
+    np.testing.assert_array_equal(tg[:, col("n_bonds")], to[:, col("n_bonds")])
+    np.testing.assert_array_equal(P.bonds(s)[0], o.bonds()[0])
+    assert to[:, col("n_bonds")].max() > 0
+    P.close()

@@ -114,3 +114,83 @@ def test_server_failed_request_and_validation(L):
     for rid, w in zip(ids, ws):
         assert S.result(rid)["final_state"] == alone(L, w)
     S.close()
+
+
+def _served_cases():
+    """Three FP32 solves of different size, shape and flow, each close enough to the receptor
+    wall (gap y_eq) that bonds form from the first steps."""
+    out = []
+    for nx, ny, shape, rl, st, re, seed, steps in ((128, 48, "circle", (1, 2), 1, 0.1, 4, 400),
+                                                   (192, 64, "ar3", (9, 10), 2, 1.0, 9, 300),
+                                                   (96, 40, "ar2", (7, 10), 1, 0.01, 2, 250)):
+        w = W.sweep_member(nx, ny, shape, rl, st, re, seed, precision="fp32", steps=steps,
+                           gap_frac=W.Y_EQ_RATIO * W.Y_CR_HAT)
+        out.append(w)
+    return out
+
+
+def test_served_fp32_requests_against_the_oracle(L, orc):
+    """Served requests against the FP64 oracle: three FP32 solves submitted together to a
+    server whose memory budget holds two at a time, so they share the GPU and the third waits
+    for a slot.  Each request's per-step particle records match the oracle within 1e-5 (bond
+    counts and the final bond flags bit-exact), and its whole trace and bond array equal the
+    same solve run alone bit for bit."""
+    from _parity import col, trace_errors
+
+    ws = _served_cases()
+    fp = sorted(L.Pool.footprint(w) for w in ws)
+    S = L.Server(L.FP32, budget_bytes=fp[-1] + fp[-2], max_members=8, chunk_steps=37, max_bypass=0)
+    S.set_trace(max(int(w["steps"]) for w in ws))
+    ids = [S.submit(w, int(w["steps"])) for w in ws]
+    done, waited = set(), False
+    while len(done) < len(ws):
+        S.progress()
+        q, r, _, _ = S.stats()
+        waited |= q > 0 and r > 0
+        done.update(S.take_completed())
+    assert waited, "the budget should have made a request wait while others ran"
+    for rid, w in zip(ids, ws):
+        n, nl = int(w["steps"]), int(w["particle"]["n_markers"])
+        res = S.result(rid)
+        assert res["state"] == L.REQ_DONE and res["steps_done"] == n
+        tg = S.trace(rid, n)
+        bg, lg = S.bonds(rid, nl)
+        assert tg.shape == (n, 20)
+        o = orc.Sim.from_workload(w)
+        _, to = o.step(n, trace=True)
+        errs = trace_errors(tg, to, w["particle"])
+        say(w["name"], "bonds max", int(to[:, col("n_bonds")].max()), " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+        for k, v in errs.items():
+            assert v <= 1e-5, (w["name"], k, v)
+        np.testing.assert_array_equal(tg[:, col("n_bonds")], to[:, col("n_bonds")])
+        np.testing.assert_array_equal(tg[:, col("n_probing")], to[:, col("n_probing")])
+        bo, lo = o.bonds()
+        np.testing.assert_array_equal(bg, bo)
+        np.testing.assert_array_equal(lg, lo)
+        assert to[:, col("n_bonds")].max() > 0
+        s = L.Sim(w)
+        s.trace_enable(n)
+        s.step(n)
+        s.sync()
+        np.testing.assert_array_equal(tg, s.trace(n))
+        np.testing.assert_array_equal(bg, s.bonds()[0])
+        s.close()
+    with pytest.raises(L.LbibError) as ei:
+        S.trace(10**9, 1)
+    assert ei.value.status == L.E_INVALID
+    S.close()
+
+
+def test_server_trace_of_a_request_still_running(L):
+    ws = _served_cases()[:1]
+    S = L.Server(L.FP32, budget_bytes=1 << 30, max_members=4, chunk_steps=5, max_bypass=0)
+    S.set_trace(10)
+    rid = S.submit(ws[0], 400)
+    S.progress()
+    with pytest.raises(L.LbibError) as ei:
+        S.trace(rid, 10)
+    assert ei.value.status == L.E_STATE
+    with pytest.raises(L.LbibError) as ei:
+        S.bonds(rid, int(ws[0]["particle"]["n_markers"]))
+    assert ei.value.status == L.E_STATE
+    S.close()
