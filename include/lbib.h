@@ -79,7 +79,8 @@ typedef enum {
  * LBIB_FP16_NEQ and LBIB_BF16_NEQ store instead f - f_eq(rho, u) of the node that emitted
  * each population (its non-equilibrium part, typically 10^-2 of f - w_q), in the same two
  * formats (FP16 with the same scale rule), with that node's rho - 1, u_x and u_y kept beside
- * in FP32; the collision runs in FP64.  Bytes per lattice update: 60. */
+ * in FP32; the sweep computes in FP32 (the emitting nodes' equilibria, the collision, the new
+ * equilibrium), the particle phase in FP64.  Bytes per lattice update: 60. */
 enum { LBIB_FP64 = 0, LBIB_FP32 = 1, LBIB_FP16 = 2, LBIB_BF16 = 3, LBIB_FP16_NEQ = 4, LBIB_BF16_NEQ = 5 };
 
 /* Lattice (section "Modeling the adhesion dynamics ..."; Table 1).  drive: 0 body-force

@@ -59,8 +59,9 @@ struct bf16_neq_t {
     uint16_t b;
 };
 
-// Storage traits: the bits in memory, the type the collision computes in (FP64 for the FP64,
-// FP32 and non-equilibrium storages, FP32 for the 16-bit f - w ones) and whether the stored
+// Storage traits: the bits in memory, the type the sweep computes in (FP64 for the FP64 and
+// FP32 storages, FP32 for every 16-bit one: the loads' equilibria of the emitting nodes, the
+// collision and the stored equilibrium of the node's new moments) and whether the stored
 // values are relative to the emitting node's equilibrium.
 template <typename T>
 struct St;
@@ -91,13 +92,13 @@ struct St<bf16_t> {
 template <>
 struct St<half_neq_t> {
     using raw = uint16_t;
-    using C = double;
+    using C = float;
     static constexpr bool neq = true;
 };
 template <>
 struct St<bf16_neq_t> {
     using raw = uint16_t;
-    using C = double;
+    using C = float;
     static constexpr bool neq = true;
 };
 
