@@ -160,7 +160,7 @@ lbib_status lbib_create(const lbib_lattice_desc* desc, void* hip_stream, lbib_ha
 /* Add a particle (up to 64 per simulation); *particle_id receives its index, which also keys
  * its bond draws.  Particles interact only through the fluid (the paper's particles do not
  * collide; placements must not overlap).  With several particles each step runs the split
- * particle phase (see lbib_set_overlap, mode 3). */
+ * particle phase (see lbib_set_overlap). */
 lbib_status lbib_particle_add(lbib_handle h, const lbib_particle_desc* desc, int32_t* particle_id);
 
 /* Decorate particle particle_id with ligands; required before lbib_init when a particle
@@ -242,20 +242,25 @@ lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size);
  * and a sweep of all nodes run one after the other on the handle's stream.  Mode 2 (the
  * default) overlaps when one sweep moves at least 64 MiB.  Both schedules give bit-identical
  * results. */
-/* Mode 3 (used whenever a simulation has several particles): the particle phase runs as two
- * launches over all particles -- first every particle stages its box and spreads its marker
- * forces, then every particle evaluates its probe loads (with the spread force of every
- * particle that reaches a probe node, summed in particle order), bonds and rigid-body update
- * -- and the sweep adds at each node the force of every particle whose box reaches it, in
- * particle order.  For a single particle it gives the same results as modes 0-2.  Kernel
- * timing then reports the first launch as kernel 1 and the second as kernel 2.  With several
- * particles, modes 0 and 2 run both halves as one launch whose workgroups (one per particle,
- * each taking a CU) wait for each other between the spread and the loads; it starts after
- * the stream's previous work, and a wait that exceeds a few seconds (other streams keeping
- * every CU busy) fails the simulation with LBIB_E_NUMERIC rather than hang: use mode 3 beside
- * such work.  Mode 3 runs the two launches and the sweep in order on the handle's stream;
- * mode 1 runs the second launch on a second stream beside the sweep.  All give the same
- * results bit for bit. */
+/* Several particles in one lattice: the particle phase is split in two launches over all
+ * particles -- first every particle stages its box and spreads its marker forces, then every
+ * particle evaluates its probe loads (with the spread force of every particle that reaches a
+ * probe node, summed in particle order), bonds and rigid-body update -- and the sweep adds at
+ * each node the force of every particle whose box reaches it, in particle order.  Modes 1 and
+ * 2 (the default) chain them over two streams: the spread launch and the sweep run on the
+ * handle's stream, the loads launch on a second stream beside the sweep, and the streams hand
+ * over through counters in device memory (a loads launch waits for its step's spreads, the
+ * next spread launch for those loads); no launch waits for a later one and no workgroup for
+ * another of its own launch, so other work on the device only delays it.  Modes 0 and 3 run
+ * the two launches and the sweep in order on the handle's stream.  Mode 4 runs both halves
+ * as one launch whose workgroups (one per particle, each taking a CU) meet at a grid barrier
+ * between the spread and the loads: it is correct only while all of them are resident at
+ * once, which holds on an otherwise idle device; beside other streams' work the barrier's
+ * wait can time out (after about a second) and fail the simulation with LBIB_E_NUMERIC, so it
+ * is never chosen by default.  For a single particle, mode 3 runs the split phase and mode 4
+ * equals modes 0-2.  All modes give the same results bit for bit.  Kernel timing reports the
+ * spread launch (or the one launch) as kernel 1 and the loads launch as kernel 2 (in the
+ * chained schedule its time includes its wait for the spreads). */
 lbib_status lbib_set_overlap(lbib_handle h, int32_t mode);
 
 /* Storage layout of the population buffers, chosen before lbib_init: mode 0 push (the

@@ -253,11 +253,19 @@ hipError_t launch_particle(const ParticleArgs<T>& a, hipStream_t stream, hipEven
                            hipEvent_t t1 = nullptr);
 // The two launches of the split particle phase (mode 1: spread and mark; mode 2: loads,
 // bonds, update), one workgroup per particle of args[0..n); lds: the dynamic LDS of the
-// launch (the most particle_launch_lds of the particles).
+// launch (the most particle_launch_lds of the particles).  ch: the device-side hand-over when
+// the two launches run on different streams -- each workgroup starts once *wait has reached
+// wait_target (NULL: no wait) and, its phase done, adds 1 to *done (NULL: none) with a
+// device-scope release; the wait is bounded and raises FLAG_SYNC.
+struct SplitChain {
+    const unsigned long long* wait = nullptr;
+    unsigned long long wait_target = 0;
+    unsigned long long* done = nullptr;
+};
 template <typename T>
 hipError_t launch_particle_split(const ParticleArgs<T>* args, int32_t n, const T* f, unsigned long long* pmask,
                                  int32_t mode, int32_t max_nl, size_t lds, hipStream_t stream,
-                                 hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+                                 hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr, const SplitChain& ch = SplitChain{});
 // The same phase as one launch: every workgroup spreads, then all meet at a grid barrier
 // (bar: a counter that only grows; this launch waits for it to reach target = its previous
 // value + n), then each evaluates its loads, bonds and update.  The n <= 64 workgroups

@@ -616,6 +616,9 @@ __device__ __forceinline__ void mark_tiles(const ParticleArgs<T>& a, int x0, int
     }
 }
 
+// A double of the particle state, stored coherently across the XCDs' L2 caches.
+__device__ __forceinline__ void state_store(double* p, double v) { coherent_store((int64_t*)p, __double_as_longlong(v)); }
+
 // What the first part of the particle phase hands to the rest.
 template <int MPT>
 struct PhaseCtx {
@@ -893,7 +896,8 @@ __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const Phase
         if (l < nl) {
             const double rx = c.G.X[k] - xc, ry = c.G.Y[k] - yc;
             const uint8_t b = bond_update(LIG[k], BND[k], D[k], Tf, bp, a.seed, step, (uint32_t)l, a.pid);
-            a.bond[l] = b;
+            // coherent: the next step's spread may run on another XCD without a release here
+            __hip_atomic_store(a.bond + l, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             acc[0] += TX[k];
             acc[1] += TY[k];
             acc[2] += rx * TY[k] - ry * TX[k];
@@ -951,19 +955,20 @@ __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const Phase
         const double nth = (2.0 / 3.0) * (2.0 * th - 0.5 * c.th1 + nom);
         if (!(isfinite(Fx) && isfinite(Fy) && isfinite(M) && isfinite(nux) && isfinite(nuy) && isfinite(nom)))
             fl |= FLAG_NONFINITE;
-        st->xc1 = xc;
-        st->yc1 = yc;
-        st->th1 = th;
-        st->ux1 = ux;
-        st->uy1 = uy;
-        st->om1 = om;
-        st->xc = nxc;
-        st->yc = nyc;
-        st->th = nth;
-        st->ux = nux;
-        st->uy = nuy;
-        st->om = nom;
-        st->step = step + 1;
+        // the state the next step starts from, stored coherently (as the bond flags)
+        state_store(&st->xc1, xc);
+        state_store(&st->yc1, yc);
+        state_store(&st->th1, th);
+        state_store(&st->ux1, ux);
+        state_store(&st->uy1, uy);
+        state_store(&st->om1, om);
+        state_store(&st->xc, nxc);
+        state_store(&st->yc, nyc);
+        state_store(&st->th, nth);
+        state_store(&st->ux, nux);
+        state_store(&st->uy, nuy);
+        state_store(&st->om, nom);
+        coherent_store(&st->step, step + 1);
         lbib_particle_state rec;
         rec.step = step;
         rec.xc = nxc;
@@ -1182,19 +1187,50 @@ __global__ __launch_bounds__(PB) void particle_kernel(ParticleArgs<T> a, uint32_
     particle_phase<T, MPT, 0>(a, (char*)lds_dyn, lds_bytes);
 }
 
+// Hand-over between the two launches of the split phase when they run on different streams.
+// chain_wait: one thread polls the monotonic counter until it reaches target (bounded: past
+// about a second it raises FLAG_SYNC and goes on), then its device-scope acquire drops stale
+// copies from the caches the workgroup reads through, before the barrier lets every wave read.
+// chain_publish: the barrier completes every wave's stores; one thread's device-scope release
+// makes them visible to every XCD and counts this workgroup in.
+__device__ __forceinline__ void chain_wait(const unsigned long long* ctr, unsigned long long target, int32_t* flags)
+{
+    if (threadIdx.x == 0) {
+        wait_counter(ctr, target, flags);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+// COHERENT: everything the waiting launch reads was stored coherently (the loads launch's
+// particle state and bond flags), so waiting for the stores to complete replaces the release,
+// which would write back the XCD's whole L2 -- costly beside a concurrent sweep's stores.
+template <bool COHERENT>
+__device__ __forceinline__ void chain_publish(unsigned long long* ctr)
+{
+    if (COHERENT) stores_done();
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_fetch_add(ctr, 1ull, COHERENT ? __ATOMIC_RELAXED : __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Split particle phase of a simulation with several particles: workgroup b runs particle b
 // in MODE 1 (spread) or MODE 2 (loads, bonds, update) on the populations f of this step and
-// the step's tile mask.
+// the step's tile mask.  wait (optional): start once *wait reaches wait_target; done
+// (optional): count this workgroup in at *done when its phase is complete.
 template <typename T, int MPT, int MODE>
 __global__ __launch_bounds__(PB) void split_particle_kernel(const ParticleArgs<T>* __restrict__ args,
                                                             const T* __restrict__ f,
-                                                            unsigned long long* __restrict__ pmask, uint32_t lds_bytes)
+                                                            unsigned long long* __restrict__ pmask, uint32_t lds_bytes,
+                                                            const unsigned long long* wait,
+                                                            unsigned long long wait_target, unsigned long long* done)
 {
     extern __shared__ double lds_dyn[];
     ParticleArgs<T> a = args[blockIdx.x];
     a.f = f;
     a.pmask = pmask;
+    if (wait) chain_wait(wait, wait_target, a.flags);
     particle_phase<T, MPT, MODE>(a, (char*)lds_dyn, lds_bytes);
+    if (done) chain_publish<MODE == 2>(done);
 }
 
 template <typename K>
@@ -1208,26 +1244,26 @@ hipError_t allow_max_lds(K kernel, bool& done)
 
 template <typename T, int MPT, int MODE>
 hipError_t launch_split_mode(const ParticleArgs<T>* args, int32_t n, const T* f, unsigned long long* pmask, size_t lds,
-                             hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
+                             const SplitChain& ch, hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
 {
     static bool attr = false;
     hipError_t e = allow_max_lds(split_particle_kernel<T, MPT, MODE>, attr);
     if (e != hipSuccess) return e;
     hipExtLaunchKernelGGL(split_particle_kernel<T, MPT, MODE>, dim3(n), dim3(PB), (uint32_t)lds, stream, t0, t1, 0u,
-                          args, f, pmask, (uint32_t)lds);
+                          args, f, pmask, (uint32_t)lds, ch.wait, ch.wait_target, ch.done);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_particle_split(const ParticleArgs<T>* args, int32_t n, const T* f, unsigned long long* pmask,
                                  int32_t mode, int32_t max_nl, size_t lds, hipStream_t stream, hipEvent_t t0,
-                                 hipEvent_t t1)
+                                 hipEvent_t t1, const SplitChain& ch)
 {
     if (n <= 0) return hipSuccess;
     if (n > kMaxParticles || lds > kLdsMax || lds < kLdsHead || (mode != 1 && mode != 2)) return hipErrorInvalidValue;
 #define LBIB_SPLIT(M)                                                                                \
-    return mode == 1 ? launch_split_mode<T, M, 1>(args, n, f, pmask, lds, stream, t0, t1)           \
-                     : launch_split_mode<T, M, 2>(args, n, f, pmask, lds, stream, t0, t1)
+    return mode == 1 ? launch_split_mode<T, M, 1>(args, n, f, pmask, lds, ch, stream, t0, t1)       \
+                     : launch_split_mode<T, M, 2>(args, n, f, pmask, lds, ch, stream, t0, t1)
     if (max_nl <= PB) LBIB_SPLIT(1);
     if (max_nl <= 2 * PB) LBIB_SPLIT(2);
 #undef LBIB_SPLIT
@@ -1479,7 +1515,8 @@ hipError_t launch_copy(const float4* src, float4* dst, int64_t n, hipStream_t st
                                                 int32_t, size_t, hipStream_t, hipEvent_t, hipEvent_t);          \
     template hipError_t launch_particle<T>(const ParticleArgs<T>&, hipStream_t, hipEvent_t, hipEvent_t);        \
     template hipError_t launch_particle_split<T>(const ParticleArgs<T>*, int32_t, const T*, unsigned long long*, \
-                                                 int32_t, int32_t, size_t, hipStream_t, hipEvent_t, hipEvent_t); \
+                                                 int32_t, int32_t, size_t, hipStream_t, hipEvent_t, hipEvent_t,  \
+                                                 const SplitChain&);                                               \
     template hipError_t launch_particle_fused<T>(const ParticleArgs<T>*, int32_t, const T*, unsigned long long*, \
                                                  int32_t, size_t, unsigned long long*, unsigned long long,        \
                                                  hipStream_t);

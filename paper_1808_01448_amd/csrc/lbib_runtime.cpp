@@ -44,7 +44,7 @@ struct lbib_sim {
     unsigned long long zdone_expected = 0;  // zone workgroups of the overlapped sweeps enqueued
     bool prev_overlapped = false;           // the last step enqueued ran overlapped
     hipEvent_t evA = nullptr, evB = nullptr, evC = nullptr;
-    int overlap = 2;  // 0 serial, 1 overlapped, 2 chosen by lattice size, 3 split particle phase
+    int overlap = 2;  // 0 serial, 1 overlapped, 2 chosen by lattice size, 3 split particle phase, 4 one-launch split phase
     int layout = 2;   // 0 push, 1 pull, 2 chosen by lattice size (at lbib_init)
     bool zone_valid = false;  // the zone slot of the next step holds its box
     int state = 0;  // 0 created, 1 running, 2 failed
@@ -59,11 +59,11 @@ struct lbib_sim {
     // split particle phase (several particles, or overlap mode 3): the two tile masks (by
     // step parity), every particle's box and tile, the particle arguments on the device
     unsigned long long* d_masks = nullptr;
-    // one-launch split phase: grid-barrier counter (grows by the particle count per launch),
-    // launches made, and whether the device has a CU for every particle's workgroup
+    // hand-over counters of the split phase (they only grow): [0] the one-launch phase's grid
+    // barrier (mode 4), [1] spread workgroups done, [2] loads workgroups done (the chained
+    // schedule); the launches of each enqueued so far
     unsigned long long* d_bar = nullptr;
-    uint64_t bar_launches = 0;
-    bool one_launch = false;
+    uint64_t bar_launches = 0, spread_launches = 0, loads_launches = 0;
     int32_t mtx = 0;
     int64_t ntiles = 0;
     PartRef* d_refs = nullptr;
@@ -233,44 +233,52 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
             unsigned long long* mnext = h->d_masks + (par ^ 1) * h->ntiles;
             const int32_t np = (int32_t)h->parts.size();
             const ParticleArgs<T>* args = (const ParticleArgs<T>*)h->d_args;
-            // mode 1: the second particle launch (which reads the populations of the step and
-            // writes only particle state) runs on the second stream beside the sweep, and the
-            // next step's first launch waits for both.  The two cross-stream waits cost more
-            // than the overlap saves at the sizes measured (2048 x 512, 32 particles: 67.6
-            // against 55.2 us per step), so no other mode uses it.
-            const bool ovl = h->overlap == 1;
-            if (!joined) HIPCHK(h, hipStreamWaitEvent(h->stream, h->evB, 0));
-            // modes 0 and 2 with several particles: both halves in one launch, met at a grid
-            // barrier (same results; no second launch, no second staging of the supports).
-            // Its workgroups (one CU each) start together: the stream's previous work is done.
-            bool done = false;
-            if (h->one_launch && np > 1 && (h->overlap == 0 || h->overlap == 2)) {
+            // chained schedule (modes 1 and 2): the loads launch of step n runs on the second
+            // stream beside the sweep of step n; the two streams hand over on the device.  The
+            // loads launch starts once every spread workgroup of step n has counted in; the
+            // spread launch of step n+1 (after the sweep of step n on the caller's stream)
+            // once every loads workgroup of step n has (it rewrites the force lists those read,
+            // and the particle state they write), so the sweep of step n+1, which overwrites
+            // the populations the loads of step n read, follows it.  No launch waits for a
+            // later one, and no workgroup waits for another of its own launch.
+            // Mode 4: both halves as one launch met at a grid barrier (no second launch or
+            // staging; it needs all its workgroups resident together, see lbib_set_overlap).
+            // Modes 0 and 3: the two launches and the sweep in order on the caller's stream.
+            const bool chain = h->overlap == 1 || h->overlap == 2;
+            if (chain && joined) {  // the second stream starts after the caller's work
+                HIPCHK(h, hipEventRecord(h->evA, h->stream));
+                HIPCHK(h, hipStreamWaitEvent(h->stream2, h->evA, 0));
+                joined = false;
+            }
+            if (h->overlap == 4) {
                 const EvPair e1 = timing_events(h, 1);
                 if (e1.t0) HIPCHK(h, hipEventRecord(e1.t0, h->stream));
                 const unsigned long long target = (unsigned long long)(h->bar_launches + 1) * (unsigned long long)np;
                 HIPCHK(h, launch_particle_fused<T>(args, np, fin, mcur, h->max_nl, h->lds_bytes, h->d_bar, target,
                                                    h->stream));
                 h->bar_launches += 1;
-                done = true;
                 if (e1.t1) HIPCHK(h, hipEventRecord(e1.t1, h->stream));
-            }
-            hipStream_t s2 = h->stream;
-            if (!done) {
-                const EvPair e1 = timing_events(h, 1);
-                HIPCHK(h, launch_particle_split<T>(args, np, fin, mcur, 1, h->max_nl, h->lds_bytes, h->stream,
-                                                   e1.t0, e1.t1));
-                if (ovl) {
-                    HIPCHK(h, hipEventRecord(h->evA, h->stream));
-                    HIPCHK(h, hipStreamWaitEvent(h->stream2, h->evA, 0));
-                    s2 = h->stream2;
+            } else {
+                SplitChain c1, c2;
+                if (chain) {
+                    c1.wait = h->d_bar + 2;
+                    c1.wait_target = (unsigned long long)np * h->loads_launches;
+                    c1.done = h->d_bar + 1;
+                    c2.wait = h->d_bar + 1;
+                    c2.wait_target = (unsigned long long)np * (h->spread_launches + 1);
+                    c2.done = h->d_bar + 2;
                 }
+                const EvPair e1 = timing_events(h, 1);
+                HIPCHK(h, launch_particle_split<T>(args, np, fin, mcur, 1, h->max_nl, h->lds_bytes, h->stream, e1.t0,
+                                                   e1.t1, c1));
                 const EvPair e2 = timing_events(h, 2);
-                HIPCHK(h, launch_particle_split<T>(args, np, fin, mcur, 2, h->max_nl, h->lds_bytes, s2, e2.t0, e2.t1));
-                if (ovl) HIPCHK(h, hipEventRecord(h->evB, h->stream2));
+                HIPCHK(h, launch_particle_split<T>(args, np, fin, mcur, 2, h->max_nl, h->lds_bytes,
+                                                   chain ? h->stream2 : h->stream, e2.t0, e2.t1, c2));
+                h->spread_launches += 1;
+                h->loads_launches += 1;
             }
             const EvPair e0 = timing_events(h, 0);
             HIPCHK(h, launch_sweep_multi<T>(fin, fout, sa, mcur, mnext, h->d_refs, h->g.pull, h->stream, e0.t0, e0.t1));
-            joined = !ovl;
             h->zone_valid = false;
         } else if (h->parts.empty()) {
             const EvPair e0 = timing_events(h, 0);
@@ -342,12 +350,14 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
         h->steps += 1;
     }
     if (!joined) {
-        // everything enqueued is ordered before later work on the caller's stream
-        if (h->prev_overlapped) {  // the particle and sweep chains of one particle
+        // everything enqueued is ordered before later work on the caller's stream: the sweep
+        // chain of one overlapped particle, and the second stream (its particle chain, or the
+        // loads launches of the chained split phase)
+        if (h->prev_overlapped && !split) {
             HIPCHK(h, hipEventRecord(h->evA, h->stream3));
-            HIPCHK(h, hipEventRecord(h->evB, h->stream2));
             HIPCHK(h, hipStreamWaitEvent(h->stream, h->evA, 0));
         }
+        HIPCHK(h, hipEventRecord(h->evB, h->stream2));
         HIPCHK(h, hipStreamWaitEvent(h->stream, h->evB, 0));
         HIPCHK(h, hipEventRecord(h->evA, h->stream));
     }
@@ -545,14 +555,10 @@ lbib_status lbib_init(lbib_handle h)
             h->lds_bytes = std::max(h->lds_bytes, particle_launch_lds(p.box_cap));
         }
         const size_t args_bytes = np * std::max(sizeof(ParticleArgs<double>), sizeof(ParticleArgs<float>));
-        int cus = 0, dev = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
-            h->one_launch = cus >= (int)np;
-        h->bar_launches = 0;
-        if ((e = dalloc(&h->d_bar, 1)) != hipSuccess ||
-            (e = hipMemsetAsync(h->d_bar, 0, sizeof(unsigned long long), h->stream)) != hipSuccess)
-            return bail(e, "lbib_init: barrier counter");
+        h->bar_launches = h->spread_launches = h->loads_launches = 0;
+        if ((e = dalloc(&h->d_bar, 3)) != hipSuccess ||
+            (e = hipMemsetAsync(h->d_bar, 0, 3 * sizeof(unsigned long long), h->stream)) != hipSuccess)
+            return bail(e, "lbib_init: hand-over counters");
         if ((e = dalloc(&h->d_masks, (size_t)(2 * h->ntiles))) != hipSuccess ||
             (e = dalloc(&h->d_refs, np)) != hipSuccess || (e = hipMalloc(&h->d_args, args_bytes)) != hipSuccess)
             return bail(e, "lbib_init: device allocation");
@@ -883,7 +889,7 @@ lbib_status lbib_kernel_time(lbib_handle h, int32_t kernel, double* total_ms, in
 lbib_status lbib_set_overlap(lbib_handle h, int32_t mode)
 {
     if (!h) return fail(nullptr, LBIB_E_INVALID, "lbib_set_overlap: NULL handle");
-    if (mode < 0 || mode > 3) return fail(h, LBIB_E_INVALID, "lbib_set_overlap: mode must be 0, 1, 2 or 3");
+    if (mode < 0 || mode > 4) return fail(h, LBIB_E_INVALID, "lbib_set_overlap: mode must be 0, 1, 2, 3 or 4");
     h->overlap = mode;
     return LBIB_OK;
 }

@@ -385,8 +385,10 @@ class Sim:
         return bool(v.value)
 
     def set_overlap(self, mode):
-        """0 / False: serial; 1 / True: overlapped; 2: chosen by lattice size (default); 3: the
-        split particle phase (always used with several particles)."""
+        """0 / False: serial; 1 / True: overlapped (one particle) or chained split phase (several);
+        2: chosen by lattice size for one particle, chained for several (default); 3: the split
+        particle phase in order on one stream; 4: several particles' split phase as one launch
+        met at a grid barrier (needs an otherwise idle device)."""
         self._call(lib().lbib_set_overlap, int(mode))
 
     # -- timing --------------------------------------------------------------------------

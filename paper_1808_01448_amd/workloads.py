@@ -88,6 +88,16 @@ def channel_large_fp32() -> dict:
     )
 
 
+def channel_beyond_cache_fp32() -> dict:
+    """The 4096 x 1024 problem on an 8192 x 4096 channel (2.4 GB of FP32 populations, far
+    beyond the 256 MB last-level cache): the ellipse scaled with H (semi-axes 96 and 32, 512
+    markers), the same Re, gap, ligands and bonds."""
+    w = scaled(channel_large_fp32(), 8192, 4096, name="channel_8192x4096_ellipse_ar3_fp32")
+    w["particle"]["n_markers"] = 512
+    w["particle"]["xc"] = 2048.0
+    return w
+
+
 def scaled(w: dict, nx: int, ny: int, *, name: str | None = None) -> dict:
     """The same particle problem on a different channel: the particle keeps its size relative
     to H and its gap relative to H (used for sizes between the two configurations above)."""

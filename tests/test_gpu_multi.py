@@ -154,8 +154,9 @@ def test_multi_layouts_and_checkpoint(L):
 
 
 def test_multi_overlapped_schedule_identical(L):
-    """Mode 1 (the probe launch beside the sweep on a second stream) gives the results of the
-    serial schedule bit for bit."""
+    """Mode 1 (the chained schedule: the loads launch beside the sweep on a second stream,
+    handing over through device counters) gives the results of the serial schedule bit for
+    bit."""
     w = W.multi_particle_channel(256, 96, 6, seed=4, precision="fp32", area_frac=0.02)
     outs = []
     for mode in (0, 1):
@@ -185,18 +186,63 @@ def test_sixty_four_particles_against_oracle(L, orc):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp16"])
-def test_one_launch_equals_two_launches(L, prec):
-    """Several particles: the one cooperative launch (spread, grid barrier, loads; the default)
-    and the two launches of mode 3 give the same particles, bonds and populations bit for
-    bit, including neighbours whose probe supports reach each other's spread."""
+def test_schedules_of_several_particles_agree(L, prec):
+    """Several particles: the chained schedule (default), the two launches in order on one
+    stream (mode 3) and the one launch met at a grid barrier (mode 4, on this otherwise idle
+    device) give the same particles, bonds and populations bit for bit, including neighbours
+    whose probe supports reach each other's spread."""
     w = W.multi_particle_channel(256, 96, 8, seed=6, precision=prec, area_frac=0.03)
     outs = []
-    for mode in (2, 3):
+    for mode in (2, 3, 4):
         s, tr = gpu_run(L, w, 200, overlap=mode)
         outs.append(([s.particle(k) for k in range(8)], tr, s.f, [s.bonds(k)[0] for k in range(8)]))
         s.close()
-    assert outs[0][0] == outs[1][0]
-    for k in range(8):
-        np.testing.assert_array_equal(outs[0][1][k], outs[1][1][k])
-        np.testing.assert_array_equal(outs[0][3][k], outs[1][3][k])
-    np.testing.assert_array_equal(outs[0][2], outs[1][2])
+    for o in outs[1:]:
+        assert outs[0][0] == o[0]
+        for k in range(8):
+            np.testing.assert_array_equal(outs[0][1][k], o[1][k])
+            np.testing.assert_array_equal(outs[0][3][k], o[3][k])
+        np.testing.assert_array_equal(outs[0][2], o[2])
+
+
+def test_chained_simulations_interleaved_beside_other_work(L):
+    """Two simulations with several particles, each on its own stream in the default chained
+    schedule, enqueued alternately in calls of different lengths while a third stream keeps
+    the device busy with matrix products: each equals its serial run (mode 3) bit for bit.
+    Nothing in the chained schedule needs its workgroups resident together, so other work only
+    delays it."""
+    wa = W.multi_particle_channel(512, 128, 6, seed=8, precision="fp32", area_frac=0.02)
+    wb = W.multi_particle_channel(384, 96, 5, seed=9, precision="fp16", area_frac=0.02)
+    calls = [(17, 5), (3, 40), (60, 1), (20, 25)]
+    n_a, n_b = sum(c[0] for c in calls), sum(c[1] for c in calls)
+    refs = []
+    for w, n in ((wa, n_a), (wb, n_b)):
+        s, tr = gpu_run(L, w, n, overlap=3)
+        refs.append((tr, s.f, [s.bonds(k)[0] for k in range(len(w["particles"]))]))
+        s.close()
+    sa_, sb_, sx = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
+    a, b = L.Sim(wa, stream=sa_), L.Sim(wb, stream=sb_)
+    for sim, w, n in ((a, wa, n_a), (b, wb, n_b)):
+        for k in range(len(w["particles"])):
+            sim.trace_enable(n, k)
+    x = torch.randn(6144, 6144, device="cuda")
+    torch.cuda.synchronize()
+    with torch.cuda.stream(sx):
+        y = x
+        for _ in range(4):
+            y = torch.mm(y, x) * 1e-4
+    for ka, kb in calls:
+        a.step(ka)
+        b.step(kb)
+    a.sync()
+    b.sync()
+    torch.cuda.synchronize()
+    for sim, w, n, ref in ((a, wa, n_a, refs[0]), (b, wb, n_b, refs[1])):
+        np_ = len(w["particles"])
+        for k in range(np_):
+            np.testing.assert_array_equal(sim.trace(n, k), ref[0][k])
+            np.testing.assert_array_equal(sim.bonds(k)[0], ref[2][k])
+        np.testing.assert_array_equal(sim.f, ref[1])
+    a.close()
+    b.close()
+    del y
