@@ -28,9 +28,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 METRIC = "aggregate MLUPS & % HBM roofline; batched/served vs plain; p50/p99 solve latency"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweep_4096x1024_fp32.json")
-# the lattice sweep's device code: the counters in TRAFFIC_FILE are valid for these sources only
+TRAFFIC_FILE_BEYOND = os.path.join(ROOT, "profiles", "traffic_sweep_8192x4096_storages.json")
+# the lattice sweep's device code: the counters in the traffic files are valid for these sources only
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1808_01448_amd", "csrc", f)
-               for f in ("lbib_sweep.hip", "lbib_collide.hpp", "lbib_device.hpp")]
+               for f in ("lbib_sweep.hip", "lbib_collide.hpp", "lbib_device.hpp", "lbib_internal.hpp")]
 LEGS = ("beyond", "c1", "batched", "multi", "serve", "cpu")
 
 
@@ -55,6 +56,21 @@ def measured_traffic(cells: int):
     if t.get("kernel_source_sha256_16") != kernel_source_hash() or t.get("cells") != cells:
         return None
     return t.get("hbm_bytes_per_launch")
+
+
+def measured_traffic_beyond(storage: str, cells: int):
+    """HBM bytes per sweep launch of the 8192 x 4096 leg for one storage, from the committed
+    counter summary, or None when it was taken on a different kernel source."""
+    try:
+        t = json.load(open(TRAFFIC_FILE_BEYOND))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    for e in t.get("entries", []):
+        if e.get("storage") == storage and e.get("cells") == cells:
+            return e.get("hbm_bytes_per_launch")
+    return None
 
 
 def timed_window(sim, steps: int, stream) -> dict:
@@ -149,8 +165,10 @@ def beyond_cache_leg(steps: int, stream) -> dict:
             "mlups": round(cells * steps / win["seconds"] / 1e6, 1),
             "ms_per_step": round(win["seconds"] * 1e3 / steps, 4),
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(achieved / HBM_PEAK_GBS, 4), "avg_launch_us": round(sweep_ms * 1e3, 2),
-                         "launches_timed": n0,
+                         "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "traffic": measured_traffic_beyond(prec, cells),
+                         "algorithmic_bytes_per_launch": bpu * cells,
+                         "avg_launch_us": round(sweep_ms * 1e3, 2), "launches_timed": n0,
                          "copy_same_bytes_gbs": round(copy_gbs, 1),
                          "frac_of_measured_copy": round(achieved / copy_gbs, 4) if copy_gbs > 0 else None},
             "particle_launch_avg_us": round(part_ms * 1e3, 2),
@@ -321,16 +339,16 @@ def serving_leg(n: int, scale: float, stream) -> dict:
     # once, through the server and through the plain server; the served figure sets the rate
     sample = [dict(w, steps=max(1, w["steps"] // 4)) for w in ws[: max(1, n // 2)]]
     log(f"bench: serving at saturation, {len(sample)} requests arriving together")
-    sat = measure.serve_trace(sample, np.zeros(len(sample)), stream=stream)
+    sat = measure.serve_trace(sample, np.zeros(len(sample)), stream=stream, progress=log)
     log(f"bench: served at saturation {sat['mlups']:.0f} MLUPS; plain server")
-    sat_plain = measure.plain_fifo(sample, np.zeros(len(sample)), stream=stream)
+    sat_plain = measure.plain_fifo(sample, np.zeros(len(sample)), stream=stream, progress=log)
     capacity = sat["mlups"] * 1e6 / mean_lu
     rate = 0.7 * capacity
     arrivals = W.poisson_arrivals(n, rate, seed=0)
     log(f"bench: serving {n} requests at {rate:.2f}/s (capacity {capacity:.2f}/s)")
-    srv = measure.serve_trace(ws, arrivals, stream=stream)
+    srv = measure.serve_trace(ws, arrivals, stream=stream, progress=log)
     log(f"bench: served in {srv['makespan_s']:.2f} s; plain server on the same trace")
-    plain = measure.plain_fifo(ws, arrivals, stream=stream)
+    plain = measure.plain_fifo(ws, arrivals, stream=stream, progress=log)
     same = all(r["final_state"] == p for r, p in zip(srv["results"], plain["finals"]))
     ls, lp = measure.percentiles(srv["latency_s"]), measure.percentiles(plain["latency_s"])
     return {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -54,6 +55,12 @@ struct lbib_sim {
     void* fB = nullptr;
     std::vector<Particle> parts;
     int32_t* d_flags = nullptr;
+    // the flags word as of the end of the last lbib_step call, copied (stream-ordered) into
+    // pinned host memory at that call's end, and the event that marks that end: lbib_sync and
+    // the reads take the flags from there instead of a synchronous copy after their wait
+    int32_t* h_flags = nullptr;
+    bool h_flags_valid = false;
+    hipEvent_t ev_end = nullptr;
     int64_t steps = 0;
     Timing timing;
     // split particle phase (several particles, or overlap mode 3): the two tile masks (by
@@ -105,6 +112,11 @@ void free_all(lbib_sim* h)
     if (h->fB) (void)hipFree(h->fB);
     h->fA = h->fB = nullptr;
     dfree(h->d_flags);
+    if (h->h_flags) (void)hipHostFree(h->h_flags);
+    h->h_flags = nullptr;
+    h->h_flags_valid = false;
+    if (h->ev_end) (void)hipEventDestroy(h->ev_end);
+    h->ev_end = nullptr;
     dfree(h->d_masks);
     dfree(h->d_bar);
     dfree(h->d_refs);
@@ -217,6 +229,7 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
 {
     const SweepArgs sa = sweep_args(h);
     bool joined = true;
+    h->h_flags_valid = false;  // until this call's copy is enqueued
     const bool split = h->parts.size() > 1 || (h->overlap == 3 && !h->parts.empty());
     if (split && h->args_dirty) {
         lbib_status st = upload_split_args<T>(h);
@@ -361,13 +374,23 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
         HIPCHK(h, hipStreamWaitEvent(h->stream, h->evB, 0));
         HIPCHK(h, hipEventRecord(h->evA, h->stream));
     }
+    if (n > 0) {
+        HIPCHK(h, hipMemcpyAsync(h->h_flags, h->d_flags, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipEventRecord(h->ev_end, h->stream));
+        h->h_flags_valid = true;
+    }
     return LBIB_OK;
 }
 
+// Callers have synchronised the handle's stream, so the copy of the last lbib_step call has
+// landed.
 lbib_status check_flags(lbib_sim* h)
 {
     int32_t fl = 0;
-    HIPCHK(h, hipMemcpy(&fl, h->d_flags, sizeof(fl), hipMemcpyDeviceToHost));
+    if (h->h_flags_valid)
+        fl = *(volatile int32_t*)h->h_flags;
+    else
+        HIPCHK(h, hipMemcpy(&fl, h->d_flags, sizeof(fl), hipMemcpyDeviceToHost));
     if (fl) {
         h->state = 2;
         std::string m = "numerical failure:";
@@ -381,8 +404,18 @@ lbib_status check_flags(lbib_sim* h)
     return LBIB_OK;
 }
 
+// Waits for the handle's stream.  The end of the last lbib_step call is polled for up to
+// 2 ms first (a blocking wait's wake-up costs tens of microseconds, a large share of a short
+// call); longer waits block.
 lbib_status sync_check(lbib_sim* h)
 {
+    if (h->h_flags_valid) {
+        const auto t0 = std::chrono::steady_clock::now();
+        hipError_t q;
+        while ((q = hipEventQuery(h->ev_end)) == hipErrorNotReady)
+            if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(2000)) break;
+        if (q != hipSuccess && q != hipErrorNotReady) return hip_fail(h, q, "hipEventQuery");
+    }
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return check_flags(h);
 }
@@ -538,6 +571,11 @@ lbib_status lbib_init(lbib_handle h)
     };
     if ((e = hipMemsetAsync(h->fB, 0, bytes, h->stream)) != hipSuccess) return bail(e, "hipMemset");
     if ((e = hipMemsetAsync(h->d_flags, 0, sizeof(int32_t), h->stream)) != hipSuccess) return bail(e, "hipMemset");
+    if ((e = hipHostMalloc((void**)&h->h_flags, sizeof(int32_t), hipHostMallocDefault)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&h->ev_end, hipEventDisableTiming)) != hipSuccess)
+        return bail(e, "lbib_init: pinned flags");
+    *h->h_flags = 0;
+    h->h_flags_valid = false;
     if ((e = init_populations(h->fA, h->g, h->stream)) != hipSuccess) return bail(e, "init kernel");
     if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return bail(e, "lbib_init: sync");
     for (auto& p : h->parts)
@@ -842,6 +880,7 @@ lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size)
     }
     const int32_t zero = 0;
     HIPCHK(h, hipMemcpy(h->d_flags, &zero, sizeof(zero), hipMemcpyHostToDevice));
+    h->h_flags_valid = false;
     h->steps = hd.steps;
     h->state = 1;
     h->zone_valid = false;

@@ -103,10 +103,11 @@ def _lu(w: dict) -> int:
 
 
 def serve_trace(ws: list, arrivals, *, chunk_steps: int = 200, max_bypass: int = 8, budget_bytes: int = 16 << 30,
-                max_members: int = 4096, stream=None, autotune: bool = False) -> dict:
+                max_members: int = 4096, stream=None, autotune: bool = False, progress=None) -> dict:
     """Run the requests through the server in real time: request k is submitted when the
     server's clock passes arrivals[k] (seconds after the start) and stamped with that arrival
-    time.  Returns per-request latencies (arrival -> result) and the aggregate throughput."""
+    time.  Returns per-request latencies (arrival -> result) and the aggregate throughput.
+    progress (optional): called with a line of text after every 32nd completed request."""
     S = lbib.Server(lbib.FP32, budget_bytes=budget_bytes, max_members=max_members, chunk_steps=chunk_steps,
                     max_bypass=max_bypass, stream=stream)
     try:
@@ -129,6 +130,8 @@ def serve_trace(ws: list, arrivals, *, chunk_steps: int = 200, max_bypass: int =
             for rid in S.take_completed():
                 res[ids[rid]] = S.result(rid)
                 S.release(rid)
+                if progress and len(res) % 32 == 0:
+                    progress(f"served {len(res)}/{n} requests, {S.clock() - t0:.1f} s")
         t_end = S.clock()
         lat = np.array([res[k]["t_done"] - res[k]["t_arrival"] for k in range(n)])
         wait = np.array([res[k]["t_admit"] - res[k]["t_arrival"] for k in range(n)])
@@ -142,9 +145,10 @@ def serve_trace(ws: list, arrivals, *, chunk_steps: int = 200, max_bypass: int =
         S.close()
 
 
-def plain_fifo(ws: list, arrivals, *, stream=None) -> dict:
+def plain_fifo(ws: list, arrivals, *, stream=None, progress=None) -> dict:
     """The plain server: one simulation at a time in arrival order, each created when the
-    previous one has finished (or at its arrival), stepped to completion and read."""
+    previous one has finished (or at its arrival), stepped to completion and read.
+    progress (optional): called with a line of text after every 32nd completed request."""
     t0 = time.perf_counter()
     lat = np.zeros(len(ws))
     finals = []
@@ -160,6 +164,8 @@ def plain_fifo(ws: list, arrivals, *, stream=None) -> dict:
         finally:
             s.close()
         lat[k] = time.perf_counter() - t0 - arrivals[k]
+        if progress and (k + 1) % 32 == 0:
+            progress(f"plain server: {k + 1}/{len(ws)} requests, {time.perf_counter() - t0:.1f} s")
     makespan = time.perf_counter() - t0
     lu = sum(_lu(w) for w in ws)
     return {"latency_s": lat, "makespan_s": makespan, "mlups": lu / makespan / 1e6, "finals": finals}
