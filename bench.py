@@ -223,6 +223,11 @@ def batched_leg(steps: int, stream) -> dict:
     log(f"bench: plain sequential {seq['mlups']:.0f} MLUPS; plain concurrent")
     conc = measure.plain_concurrent(ws, steps, 5)
     log(f"bench: plain concurrent {conc['mlups']:.0f} MLUPS")
+    # the captured-graph form of the pool step at the autotuner's tile shape: runs of 50 steps
+    # replayed as one HIP graph (the autotuner keeps it only when it is faster)
+    tx, tpb, _ = pool["config"]
+    graph = measure.pool_throughput(ws, steps, 20, stream=stream, config=(tx, tpb, 50))
+    log(f"bench: pool with graph replay {graph['mlups']:.0f} MLUPS")
     sweep_gbs = 72.0 * cells / (pool["sweep_avg_us"] * 1e-6) / 1e9
     return {
         "workload": "parameter sweep: 216 simulations (shape x ligand density x bond strength x Re x seed), "
@@ -235,6 +240,8 @@ def batched_leg(steps: int, stream) -> dict:
         "speedup_vs_plain_concurrent": round(pool["mlups"] / conc["mlups"], 3),
         "pool_ms_per_step": round(pool["ms_per_step"], 4),
         "pool_config": dict(zip(("tile_x", "tiles_per_block", "graph_steps"), pool["config"])),
+        "pool_graph_replay": {"mlups": round(graph["mlups"], 1), "ms_per_step": round(graph["ms_per_step"], 4),
+                              "config": dict(zip(("tile_x", "tiles_per_block", "graph_steps"), graph["config"]))},
         "pool_sweep_avg_us": round(pool["sweep_avg_us"], 2),
         "pool_particle_avg_us": round(pool["particle_avg_us"], 2),
         "pool_sweep_roofline": {"bound": "hbm", "achieved": round(sweep_gbs, 1), "peak": HBM_PEAK_GBS,
