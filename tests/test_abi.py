@@ -215,3 +215,50 @@ def test_particle_count_limit(L):
         assert L.lbib_particle_add(h, C.byref(_pdesc()), C.byref(pid)) == lbib.E_UNSUPPORTED
     finally:
         L.lbib_destroy(h)
+
+
+def test_static_solve_host_validation(L):
+    """lbib_solve_static checks its arguments before touching the GPU: a NULL descriptor, a
+    negative step count, a particle outside the channel, an unaligned or too small population
+    buffer and a particle whose buffers exceed the 8 MiB static area are refused; with no
+    population buffer it reports the bytes the lattice needs (two population buffers)."""
+    from paper_1808_01448_amd import workloads as W
+
+    w = W.channel_small_fp64()
+    lat = lbib._lattice_desc(w["lattice"])
+    part = lbib._particle_desc(w["particle"])
+    lig = lbib._ligand_desc(w["ligand"])
+    v = C.c_int64(0)
+    assert L.lbib_solve_static(None, C.byref(part), C.byref(lig), 10, None, C.byref(v), None, None, None) == lbib.E_INVALID
+    assert L.lbib_solve_static(C.byref(lat), C.byref(part), C.byref(lig), -1, None, C.byref(v), None, None,
+                               None) == lbib.E_INVALID
+    assert L.lbib_solve_static(C.byref(lat), C.byref(part), C.byref(lig), 10, None, C.byref(v), None, None,
+                               None) == lbib.OK
+    nx, ny = w["lattice"]["nx"], w["lattice"]["ny"]
+    assert v.value == 2 * 9 * nx * ny * 8  # FP64 rows of 256 x 8 bytes need no padding
+    bad = lbib._particle_desc(dict(w["particle"], yc=-5.0))
+    assert L.lbib_solve_static(C.byref(lat), C.byref(bad), C.byref(lig), 10, None, C.byref(v), None, None,
+                               None) == lbib.E_INVALID
+    small = C.c_int64(16)
+    assert L.lbib_solve_static(C.byref(lat), C.byref(part), C.byref(lig), 10, C.c_void_p(4096), C.byref(small),
+                               None, None, None) == lbib.E_INVALID
+    assert b"needs" in L.lbib_last_error(None)
+    enough = C.c_int64(1 << 30)
+    assert L.lbib_solve_static(C.byref(lat), C.byref(part), C.byref(lig), 10, C.c_void_p(4096 + 8), C.byref(enough),
+                               None, None, None) == lbib.E_INVALID
+    assert b"aligned" in L.lbib_last_error(None)
+    big = W.channel_small_fp64()
+    big["lattice"].update(nx=1024, ny=1024)
+    big["particle"].update(a_major=200.0, b_minor=200.0, xc=512.0, yc=220.0, n_markers=1024)
+    assert L.lbib_solve_static(C.byref(lbib._lattice_desc(big["lattice"])), C.byref(lbib._particle_desc(big["particle"])),
+                               C.byref(lig), 10, None, C.byref(v), None, None, None) == lbib.E_INVALID
+    assert b"static area" in L.lbib_last_error(None)
+
+
+def test_server_read_outs_validate(L):
+    """The server's trace and bond read-outs refuse a NULL handle, an unknown request and bad
+    capacities without touching the GPU."""
+    n = C.c_int64()
+    assert L.lbib_server_set_trace(None, 10) == lbib.E_INVALID
+    assert L.lbib_server_read_trace(None, 0, None, 0, C.byref(n)) == lbib.E_INVALID
+    assert L.lbib_server_read_bonds(None, 0, None, None, 64) == lbib.E_INVALID
