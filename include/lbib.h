@@ -238,7 +238,7 @@ lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size);
  * n+1 starts once those workgroups have stored step n+1's populations around its box.  Every
  * device-side wait is bounded: one that exceeds about a second fails the simulation with
  * LBIB_E_NUMERIC.  Serial (mode 0), always on the first step after lbib_init / lbib_load /
- * lbib_write_particle, and where CU masking is unavailable or ny >= 65536: the particle phase
+ * lbib_write_particle, and where CU masking is unavailable or ny >= 2^23: the particle phase
  * and a sweep of all nodes run one after the other on the handle's stream.  Mode 2 (the
  * default) overlaps when one sweep moves at least 64 MiB.  Both schedules give bit-identical
  * results. */

@@ -67,6 +67,64 @@ __device__ __forceinline__ void collide_node(const C g[9], const SweepArgs& a, C
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// Addressing of the sweeps.  Every sweep tile is at least one wave wide and exactly one row
+// per wave, so the row j of a node is the same for all lanes of its wave: each (row,
+// population) segment's base address is formed in scalar registers, and each lane adds the
+// 32-bit byte offset of its column, which the loads and stores take as their vector operand.
+// (A 64-bit address per lane and access costs two to three vector instructions; in the
+// 16-bit storages that was a third of the work of a node.)  The bases are running sums, one
+// 64-bit scalar addition of a plane or a row per segment, rather than a 64-bit product per
+// segment: scalar instructions issue at the rate of vector ones, one per cycle per CU.  The
+// update functions below take j wave-uniform and i in [0, nx).
+// ---------------------------------------------------------------------------------------
+// An opaque copy of a lane's 32-bit offset (no instruction): the compiler can then neither
+// widen it to 64 bits nor push the base addition into the arms of a select that formed it.
+__device__ __forceinline__ uint32_t opaque(uint32_t v)
+{
+    asm("" : "+v"(v));
+    return v;
+}
+struct Cols {
+    uint32_t o[3];  // byte offsets of the columns i - 1, i, i + 1 (periodic)
+};
+template <typename S>
+__device__ __forceinline__ Cols cols(int i, int nx)
+{
+    const uint32_t im = i == 0 ? nx - 1 : i - 1, ip = i + 1 == nx ? 0 : i + 1, sz = sizeof(S);
+    return Cols{{opaque(im * sz), opaque((uint32_t)i * sz), opaque(ip * sz)}};
+}
+// A wave-uniform pointer passed through readfirstlane (a no-op on such a value): the compiler
+// keeps it whole in scalar registers, cannot fold a lane's offset into it, and cannot turn a
+// chain of such bases back into products.  It is rebuilt as a global-memory pointer, so the
+// accesses stay global ones.
+template <typename S>
+__device__ __forceinline__ S* sbase(S* p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return (S*)(__attribute__((address_space(1))) S*)(((uint64_t)hi << 32) | lo);
+}
+template <typename S>
+__device__ __forceinline__ const S* sbase(const S* p)
+{
+    return sbase(const_cast<S*>(p));
+}
+// The segment n elements on from base b.
+template <typename S>
+__device__ __forceinline__ S* snext(S* b, int64_t n)
+{
+    return sbase(b + n);
+}
+// The element at byte offset off from base b.
+template <typename S>
+__device__ __forceinline__ S* at(S* b, uint32_t off)
+{
+    return (S*)((__attribute__((address_space(1))) char*)(__attribute__((address_space(1))) S*)sbase(b) + off);
+}
+__device__ __forceinline__ int wave_row(int j) { return __builtin_amdgcn_readfirstlane(j); }
+
 // Non-equilibrium storages: the post-collision values leave relative to the equilibrium of
 // the moments stored for this node (rounded to FP32 first, so that every reader forms the same
 // equilibrium from them), and the moments are stored at the node.
@@ -74,12 +132,14 @@ template <typename T, typename C>
 __device__ __forceinline__ void neq_encode(T* fout, const SweepArgs& a, int i, int j, const C m[3], C post[9], int pol)
 {
     if constexpr (St<T>::neq) {
-        float* mo = neq_moments(fout, a.pitch, a.plane, a.ny);
-        const size_t c = (size_t)j * neq_mpitch(a.pitch, a.plane) + i;
+        float* m0p = sbase(neq_moments(fout, a.pitch, a.plane, a.ny) + (int64_t)j * neq_mpitch(a.pitch, a.plane));
+        float* m1p = snext(m0p, a.plane);
+        float* m2p = snext(m1p, a.plane);
+        const uint32_t o = (uint32_t)i * 4u;
         const float m0 = (float)m[0], m1 = (float)m[1], m2 = (float)m[2];
-        put(mo + c, m0, pol);
-        put(mo + a.plane + c, m1, pol);
-        put(mo + 2 * a.plane + c, m2, pol);
+        put(at(m0p, o), m0, pol);
+        put(at(m1p, o), m1, pol);
+        put(at(m2p, o), m2, pol);
         C feq[9];
         feq_shift_all<C>((C)m0, (C)m1, (C)m2, feq);
 #pragma unroll
@@ -87,7 +147,7 @@ __device__ __forceinline__ void neq_encode(T* fout, const SweepArgs& a, int i, i
     }
 }
 
-// Push layout: collide node (i, j), whose populations g load_node presented, and scatter
+// Push layout: collide node (i, j), whose populations update_load presented, and scatter
 // its results to the neighbours, with half-way bounce-back at the two walls and periodic x.
 // COH: coherent stores (a concurrently running launch reads the results).
 template <typename T, bool COH = false>
@@ -95,43 +155,36 @@ __device__ __forceinline__ void push_update(T* __restrict__ fout, const SweepArg
                                             const typename St<T>::C (&g)[9], double Fx, double Fy)
 {
     using C = typename St<T>::C;
-    const int64_t P = a.plane;
-    const size_t c = (size_t)j * a.pitch + i;
+    j = wave_row(j);
+    const int64_t P = a.plane, R = a.pitch;
     const int pol = COH ? ST_COH : ST_PLAIN;
     C post[9], m[3];
     collide_node<C>(g, a, (C)Fx, (C)Fy, post, m);
     neq_encode<T, C>(fout, a, i, j, m, post, pol);
 
-    const int ip = (i + 1 == a.nx) ? 0 : i + 1;
-    const int im = (i == 0) ? a.nx - 1 : i - 1;
-    const size_t up = (size_t)(j + 1) * a.pitch, dn = (size_t)(j - 1) * a.pitch, row = (size_t)j * a.pitch;
+    const Cols c = cols<T>(i, a.nx);
     const bool top = (j + 1 == a.ny), bot = (j == 0);
     const double sc = a.scale;
-    // shifted values reflect unchanged: w_q = w_opp(q)
-    st_store(fout, 0 * P + c, post[0], sc, pol);
-    st_store(fout, 1 * P + row + ip, post[1], sc, pol);
-    st_store(fout, 3 * P + row + im, post[3], sc, pol);
-    if (!top) {
-        st_store(fout, 2 * P + up + i, post[2], sc, pol);
-        st_store(fout, 5 * P + up + ip, post[5], sc, pol);
-        st_store(fout, 6 * P + up + im, post[6], sc, pol);
-    } else {
-        st_store(fout, 4 * P + c, post[2], sc, pol);
-        st_store(fout, 7 * P + c, post[5], sc, pol);
-        st_store(fout, 8 * P + c, post[6], sc, pol);
-    }
-    if (!bot) {
-        st_store(fout, 4 * P + dn + i, post[4], sc, pol);
-        st_store(fout, 7 * P + dn + im, post[7], sc, pol);
-        st_store(fout, 8 * P + dn + ip, post[8], sc, pol);
-    } else {
-        st_store(fout, 2 * P + c, post[4], sc, pol);
-        st_store(fout, 5 * P + c, post[7], sc, pol);
-        st_store(fout, 6 * P + c, post[8], sc, pol);
-    }
+    auto out = [&](T* b, uint32_t o, C v) { st_store(at(b, o), 0, v, sc, pol); };
+    // every value is stored once: along e_q into plane q of the neighbour in the row above
+    // (q = 2, 5, 6), below (4, 7, 8) or alongside; where that link crosses a wall it reflects
+    // into plane opp(q) of the node itself (shifted values reflect unchanged: w_q = w_opp(q))
+    T* b[9];
+    b[0] = sbase(fout + (int64_t)j * R);
+#pragma unroll
+    for (int q = 1; q < 9; ++q) b[q] = snext(b[q - 1], P);
+    out(b[0], c.o[1], post[0]);
+    out(b[1], c.o[2], post[1]);
+    out(b[3], c.o[0], post[3]);
+    out(top ? b[4] : snext(b[2], R), c.o[1], post[2]);
+    out(top ? b[7] : snext(b[5], R), opaque(top ? c.o[1] : c.o[2]), post[5]);
+    out(top ? b[8] : snext(b[6], R), opaque(top ? c.o[1] : c.o[0]), post[6]);
+    out(bot ? b[2] : snext(b[4], -R), c.o[1], post[4]);
+    out(bot ? b[5] : snext(b[7], -R), opaque(bot ? c.o[1] : c.o[0]), post[7]);
+    out(bot ? b[6] : snext(b[8], -R), opaque(bot ? c.o[1] : c.o[2]), post[8]);
 }
 
-// Pull layout: collide node (i, j), whose inflow g load_node gathered from the previous
+// Pull layout: collide node (i, j), whose inflow update_load gathered from the previous
 // step's post-collision values (bounce-back across the walls), and store the post-collision
 // values at (i, j) itself.  Every store is aligned and each value is written once, so both
 // go past the caches; the gathers hit lines neighbouring waves also read.
@@ -140,23 +193,77 @@ __device__ __forceinline__ void pull_update(T* __restrict__ fout, const SweepArg
                                             const typename St<T>::C (&g)[9], double Fx, double Fy)
 {
     using C = typename St<T>::C;
-    const int64_t P = a.plane;
-    const size_t c = (size_t)j * a.pitch + i;
+    j = wave_row(j);
     const int pol = COH ? ST_COH : ST_NT;
     C post[9], m[3];
     collide_node<C>(g, a, (C)Fx, (C)Fy, post, m);
     neq_encode<T, C>(fout, a, i, j, m, post, pol);
+    T* b = sbase(fout + (int64_t)j * a.pitch);
+    const uint32_t o = (uint32_t)i * (uint32_t)sizeof(T);
 #pragma unroll
-    for (int q = 0; q < 9; ++q) st_store(fout, q * P + c, post[q], a.scale, pol);
+    for (int q = 0; q < 9; ++q) {
+        st_store(at(b, o), 0, post[q], a.scale, pol);
+        if (q < 8) b = snext(b, a.plane);
+    }
 }
 
 // The populations of node (i, j) at the start of a step in the compute type, read past the
-// caches (they are read once per step).
+// caches (they are read once per step): the values load_node presents, addressed by rows.
 template <typename T, bool PULL>
 __device__ __forceinline__ void update_load(const T* __restrict__ fin, const SweepArgs& a, int i, int j,
                                             typename St<T>::C (&g)[9])
 {
-    load_node<T, typename St<T>::C>(fin, i, j, a.nx, a.ny, a.pitch, a.plane, PULL, a.inv_scale, a.uw6, true, g);
+    using C = typename St<T>::C;
+    j = wave_row(j);
+    const int64_t P = a.plane, R = a.pitch;
+    const Cols c = cols<T>(i, a.nx);
+    const bool top = (j + 1 == a.ny), bot = (j == 0);
+    // plane q of the node's own row
+    const T* b[9];
+    b[0] = sbase(fin + (int64_t)j * R);
+#pragma unroll
+    for (int q = 1; q < 9; ++q) b[q] = snext(b[q - 1], P);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        // push: the value at the node itself; pull: the one (i - e_x, j - e_y) emitted along
+        // e_q, or the node's own along opp(q) where that link crosses a wall (pop_index)
+        const T* p = b[q];
+        uint32_t o = c.o[1];
+        if (PULL && kEy[q] != 0) {
+            const bool wall = kEy[q] > 0 ? bot : top;
+            p = wall ? b[kOpp[q]] : snext(b[q], -kEy[q] * R);
+            o = kEx[q] == 0 ? c.o[1] : opaque(wall ? c.o[1] : c.o[1 - kEx[q]]);
+        } else if (PULL) {
+            o = c.o[1 - kEx[q]];
+        }
+        g[q] = (C)st_load(at(p, o), 0, a.inv_scale, true);
+    }
+    if constexpr (St<T>::neq) {
+        // plus the shifted equilibrium of the node that emitted each value (pop_source): the
+        // moments k = 0, 1, 2 of rows j - 1, j, j + 1
+        const int64_t mp = neq_mpitch(a.pitch, a.plane);
+        const float* mr[3][3];
+        mr[1][0] = sbase(neq_moments(fin, a.pitch, a.plane, a.ny) + (int64_t)j * mp);
+        mr[0][0] = snext(mr[1][0], -mp);
+        mr[2][0] = snext(mr[1][0], mp);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            mr[r][1] = snext(mr[r][0], P);
+            mr[r][2] = snext(mr[r][1], P);
+        }
+        const Cols cm = cols<float>(i, a.nx);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const bool wall = kEy[q] > 0 ? bot : kEy[q] < 0 ? top : false;
+            const int r = 1 - kEy[q];  // the emitter's row j - e_y, as an index of mr
+            const float* const* rb = wall ? mr[1] : mr[r];
+            const uint32_t o = kEx[q] == 0 ? cm.o[1] : opaque(wall ? cm.o[1] : cm.o[1 - kEx[q]]);
+            const C d = (C)*at(rb[0], o), x = (C)*at(rb[1], o), y = (C)*at(rb[2], o);
+            const C eu = e_dot<C>(q, x, y);  // e_dir.u = -e_q.u for a reflected population
+            g[q] += feq_from_eu<C>((C)kW[q], (C)1 + d, feq_even_base<C>(d, x, y), wall ? -eu : eu);
+        }
+    }
+    wall_reflect<C>(g, j, a.ny, a.uw6);
 }
 
 template <typename T, bool PULL, bool COH = false>
@@ -229,48 +336,6 @@ __device__ __forceinline__ void publish_counter(unsigned long long* p, unsigned 
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// A predicted box in two 64-bit words, each carrying a 16-bit tag, so that one coherent
-// load of each gives a consistent box (both tags current) without a separate flag: word 0
-// i0w (32 bits), j0 (16); word 1 w (16), h (16), active (1); tag in the top 16 bits of
-// both.  Needs j0, w, h < 2^16.
-__device__ __forceinline__ void zone_pack(const TileDesc& z, uint32_t tag, unsigned long long* p)
-{
-    const unsigned long long t = (unsigned long long)(tag & 0xffffu) << 48;
-    const bool ok = z.active && z.j0 < 65536 && z.w < 65536 && z.h < 65536;
-    coherent_store((int64_t*)p, (int64_t)(t | ((unsigned long long)(uint32_t)z.j0 << 32) | (uint32_t)z.i0w));
-    coherent_store((int64_t*)p + 1, (int64_t)(t | ((unsigned long long)ok << 32) | ((unsigned long long)(uint32_t)z.h << 16) |
-                                             (uint32_t)z.w));
-}
-// Waits (one lane) until both words of the box carry tag, then unpacks it (inactive when the
-// wait times out, which raises FLAG_SYNC).  The first attempt uses plain loads: the tags
-// validate whatever they return (a stale copy only carries an older tag), and once the box is
-// written they mostly hit in the L2 that the first workgroup of the XCD filled.
-__device__ __forceinline__ TileDesc zone_wait(const unsigned long long* p, uint32_t tag, int32_t* flags)
-{
-    TileDesc z{};
-    const unsigned long long t = tag & 0xffffu;
-    unsigned long long w0 = p[0], w1 = p[1];
-    for (unsigned polls = 0;; ++polls) {
-        if ((w0 >> 48) == t && (w1 >> 48) == t) {
-            z.i0w = (int32_t)(uint32_t)w0;
-            z.j0 = (int32_t)((w0 >> 32) & 0xffffu);
-            z.w = (int32_t)(w1 & 0xffffu);
-            z.h = (int32_t)((w1 >> 16) & 0xffffu);
-            z.active = (int32_t)((w1 >> 32) & 1u);
-            return z;
-        }
-        if ((polls & 255u) == 0 && (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_SYNC))
-            return z;
-        if (polls > (1u << 20)) {
-            atomicOr(flags, FLAG_SYNC);
-            return z;
-        }
-        if (polls) __builtin_amdgcn_s_sleep(1);
-        w0 = (unsigned long long)coherent_load((const int64_t*)p);
-        w1 = (unsigned long long)coherent_load((const int64_t*)p + 1);
-    }
-}
-
 // Node tiles of a lattice sweep, one per 256-thread workgroup: 256 x 1 in both layouts (a
 // wave's x-shifted stores or loads then meet a neighbouring tile's lines at one end of a
 // 256-node row segment, not of a 64-node one).  Measured in row-interleaved buffers, FP32
@@ -280,6 +345,8 @@ template <bool PULL>
 struct Tile {
     static constexpr int W = 256, H = 1;
 };
+static_assert(Tile<true>::W == Tile<false>::W && Tile<true>::H == Tile<false>::H,
+              "the particle phase predicts the box's tiles for either layout");
 
 // The TW x TH node tiles of the sweep that a box, widened by m nodes on every side, reaches:
 // columns tx0, tx0 + 1, ... (ntx of them, periodic over the gx columns; the last column may be
@@ -316,6 +383,74 @@ __device__ __forceinline__ bool zone_has_tile(const ZoneTiles& t, int tx, int ty
     int k = tx - t.tx0;
     if (k < 0) k += gx;
     return k < t.ntx;
+}
+
+// The sweep tiles of a predicted box (zone_tiles) in two 64-bit words, each carrying a 16-bit
+// tag, so that one coherent load of each gives a consistent value (both tags current) without
+// a separate flag: word 0 tx0 (24 bits), ty0 (24); word 1 ntx (24), nty (23); tag in the top
+// 16 bits of both.  Needs gx < 2^24 and ny < 2^23 (no tiles otherwise).
+__device__ __forceinline__ void zone_pack(const ZoneTiles& z, uint32_t tag, unsigned long long* p)
+{
+    const unsigned long long t = (unsigned long long)(tag & 0xffffu) << 48;
+    const bool ok = z.ntx > 0 && z.nty > 0 && z.tx0 < (1 << 24) && z.ntx < (1 << 24) && z.ty0 < (1 << 24) &&
+                    z.nty < (1 << 23);
+    const unsigned long long w0 = ok ? ((unsigned long long)z.ty0 << 24) | (unsigned long long)z.tx0 : 0ull;
+    const unsigned long long w1 = ok ? ((unsigned long long)z.nty << 24) | (unsigned long long)z.ntx : 0ull;
+    coherent_store((int64_t*)p, (int64_t)(t | w0));
+    coherent_store((int64_t*)p + 1, (int64_t)(t | w1));
+}
+__device__ __forceinline__ ZoneTiles zone_unpack(unsigned long long w0, unsigned long long w1)
+{
+    return ZoneTiles{(int)(w0 & 0xffffffu), (int)(w1 & 0xffffffu), (int)((w0 >> 24) & 0xffffffu),
+                     (int)((w1 >> 24) & 0x7fffffu)};
+}
+// Waits (one lane) until both words carry tag, then unpacks them (no tiles when the wait
+// times out, which raises FLAG_SYNC).  The first attempt uses plain loads: the tags validate
+// whatever they return (a stale copy only carries an older tag), and once the words are
+// written they mostly hit in the L2 that the first workgroup of the XCD filled.
+__device__ __forceinline__ ZoneTiles zone_wait(const unsigned long long* p, uint32_t tag, int32_t* flags)
+{
+    const unsigned long long t = tag & 0xffffu;
+    unsigned long long w0 = p[0], w1 = p[1];
+    for (unsigned polls = 0;; ++polls) {
+        if ((w0 >> 48) == t && (w1 >> 48) == t) return zone_unpack(w0, w1);
+        if ((polls & 255u) == 0 && (__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_SYNC))
+            return ZoneTiles{0, 0, 0, 0};
+        if (polls > (1u << 20)) {
+            atomicOr(flags, FLAG_SYNC);
+            return ZoneTiles{0, 0, 0, 0};
+        }
+        if (polls) __builtin_amdgcn_s_sleep(1);
+        w0 = (unsigned long long)coherent_load((const int64_t*)p);
+        w1 = (unsigned long long)coherent_load((const int64_t*)p + 1);
+    }
+}
+// The same for a whole wave without a barrier: every lane reads the two words (one cache
+// line) and the wave goes by the first lane's values, so the result is wave-uniform.
+__device__ __forceinline__ unsigned long long first_lane(unsigned long long v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ ZoneTiles zone_wait_wave(const unsigned long long* p, uint32_t tag, int32_t* flags)
+{
+    const unsigned long long t = tag & 0xffffu;
+    unsigned long long w0 = first_lane(p[0]), w1 = first_lane(p[1]);
+    for (unsigned polls = 0;; ++polls) {
+        if ((w0 >> 48) == t && (w1 >> 48) == t) return zone_unpack(w0, w1);
+        if ((polls & 255u) == 0 &&
+            (__builtin_amdgcn_readfirstlane(__hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) &
+             FLAG_SYNC))
+            return ZoneTiles{0, 0, 0, 0};
+        if (polls > (1u << 20)) {
+            if (__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)) == 0) atomicOr(flags, FLAG_SYNC);
+            return ZoneTiles{0, 0, 0, 0};
+        }
+        if (polls) __builtin_amdgcn_s_sleep(1);
+        w0 = first_lane((unsigned long long)coherent_load((const int64_t*)p));
+        w1 = first_lane((unsigned long long)coherent_load((const int64_t*)p + 1));
+    }
 }
 
 __device__ __forceinline__ bool in_box(const TileDesc& d, int i, int j, int nx)

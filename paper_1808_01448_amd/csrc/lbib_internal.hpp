@@ -103,6 +103,43 @@ struct St<bf16_neq_t> {
 };
 
 // Lattice constants of one sweep.
+// Division by a divisor that is fixed for a launch, as a multiply and a shift (Granlund and
+// Montgomery, "Division by invariant integers using multiplication", PLDI 1994, Theorem 4.2
+// with N = 31): with l = ceil(log2 d), s = 31 + l and m = ceil(2^s / d), which is below 2^32,
+// floor(n / d) = floor(n m / 2^s) for every 0 <= n < 2^31.  The sweeps split their tile
+// index into column and row with it: three scalar instructions instead of a division.
+struct FastDiv {
+    uint32_t d, m, s;
+};
+__host__ __device__ constexpr FastDiv make_fastdiv(uint32_t d)
+{
+    uint32_t l = 0;
+    while ((1ull << l) < d) ++l;
+    const uint64_t two_s = 1ull << (31 + l);
+    return FastDiv{d, (uint32_t)((two_s + d - 1) / d), 31 + l};
+}
+__host__ __device__ constexpr uint32_t fdiv(uint32_t n, FastDiv f)
+{
+    return (uint32_t)(((uint64_t)n * f.m) >> f.s);
+}
+constexpr bool fastdiv_checks()
+{
+    const uint32_t ds[] = {1, 2, 3, 5, 7, 31, 32, 33, 255, 256, 257, 1000, 4097, 65535, 65537, 8388607, 8388608};
+    const uint32_t ns[] = {0, 1, 2, 3, 255, 256, 4095, 65536, 12345678, 0x7ffffffeu, 0x7fffffffu};
+    for (uint32_t d : ds) {
+        const FastDiv f = make_fastdiv(d);
+        for (uint32_t n : ns)
+            for (uint32_t k = 0; k < 3; ++k) {
+                const uint32_t x = n >= k ? n - k : n;
+                if (fdiv(x, f) != x / d) return false;
+            }
+        const uint32_t top = 0x7fffffffu / d * d;  // the largest multiple of d, and its neighbours
+        if (fdiv(top, f) != top / d || (top && fdiv(top - 1, f) != (top - 1) / d)) return false;
+    }
+    return true;
+}
+static_assert(fastdiv_checks(), "multiply-shift division");
+
 struct SweepArgs {
     int32_t nx, ny, pitch;
     int64_t plane;  // elements per population plane (pitch * ny)
@@ -167,9 +204,9 @@ struct ParticleArgs {
     int32_t mtx;
     int32_t nparts;  // entries of refs
     // hand-over of the overlapped schedule (NULL: none): once its tile and desc have completed
-    // the particle stores ready_value into the monotonic counter *ready; its prediction of the
-    // next box goes to the two words at zone_words, packed with zone_tag (zone_pack), after
-    // its last read of f
+    // the particle stores ready_value into the monotonic counter *ready; the sweep tiles of
+    // its prediction of the next box go to the two words at zone_words, packed with zone_tag
+    // (zone_pack), after its last read of f
     unsigned long long* ready;
     unsigned long long ready_value;
     unsigned long long* zone_words;
@@ -193,10 +230,10 @@ template <typename T>
 hipError_t launch_init(T* f, int32_t nx, int32_t ny, int32_t pitch, int64_t plane, double umax, double scale,
                        bool pull, int32_t drive, hipStream_t stream);
 // The sweep beside the particle phase of one particle (the overlapped schedule), on its own
-// stream with no event between it and the particle's launches.  Every workgroup reads this
-// step's box as the previous particle launch predicted it (zone_words, two words that carry
-// zone_tag when that launch wrote them; it wrote them after its last read of the buffer this
-// sweep overwrites), waiting until the tags match.  The workgroups of the lattice skip every
+// stream with no event between it and the particle's launches.  Every wave reads the sweep
+// tiles of this step's box as the previous particle launch predicted it (zone_words, two
+// words that carry zone_tag when that launch wrote them; it wrote them after its last read
+// of the buffer this sweep overwrites), waiting until the tags match.  The workgroups of the lattice skip every
 // node tile the box reaches; nzone more workgroups (a multiple of 8, at most 64), before them
 // in the grid, sweep those tiles once the concurrent particle launch has published this step's
 // force (desc and tile; *ready reaches ready_target).  No cycle of waits: a sweep waits for
@@ -289,7 +326,7 @@ struct PoolSweep {
     T* fA;  // buffer of the even steps
     T* fB;  // buffer of the odd steps
     const int64_t* tile;
-    int32_t gx;      // tiles along x
+    FastDiv gx;      // tiles along x
     int32_t ntiles;  // tiles of this member
 };
 // Sweep configurations a pool can use: tile width BX in {64, 128, 256} nodes (256/BX rows),

@@ -1025,7 +1025,11 @@ __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const Phase
             a.zone[a.parity_out] = z;
             // the next sweep reads the box from these words, and overwrites f once it has
             // them: f was last read by the probes, whose results the update above used
-            if (a.zone_words) zone_pack(z, a.zone_tag, a.zone_words);
+            if (a.zone_words) {
+                using TL = Tile<false>;
+                const int gx = (a.nx + TL::W - 1) / TL::W;
+                zone_pack(zone_tiles<TL::W, TL::H>(z, a.nx, a.ny, gx, kZoneMargin), a.zone_tag, a.zone_words);
+            }
         }
     }
 }

@@ -243,8 +243,9 @@ lbib_status rebuild(lbib_pool* h)
         s.fB = (T*)m.fB;
         s.tile = m.p.d_tile;
         const int by = 256 / h->cfg.bx;
-        s.gx = (m.g.nx + h->cfg.bx - 1) / h->cfg.bx;
-        s.ntiles = s.gx * ((m.g.ny + by - 1) / by);
+        const int gx = (m.g.nx + h->cfg.bx - 1) / h->cfg.bx;
+        s.gx = make_fastdiv((uint32_t)gx);
+        s.ntiles = gx * ((m.g.ny + by - 1) / by);
         if ((int64_t)table.size() + s.ntiles / h->cfg.tpb + 1 > 0x7fffffff)
             return fail(h, LBIB_E_INVALID, "pool: more than 2^31 sweep blocks");
         for (int32_t t = 0; t < s.ntiles; t += h->cfg.tpb) table.push_back(make_int2((int)k, t));

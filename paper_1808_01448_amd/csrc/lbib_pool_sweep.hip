@@ -28,6 +28,7 @@ __global__ __launch_bounds__(256) void pool_sweep_kernel(const PoolSweep<T>* __r
                                                          const int2* __restrict__ table, int nblocks)
 {
     constexpr int BY = 256 / BX;
+    static_assert(BX >= 64, "the sweep's addressing takes each wave's nodes from one row");
     int b = blockIdx.x;
     {
         const int q = nblocks >> 3, r = nblocks & 7, x = b & 7, k = b >> 3;
@@ -43,8 +44,9 @@ __global__ __launch_bounds__(256) void pool_sweep_kernel(const PoolSweep<T>* __r
     const int tx = (int)(threadIdx.x % BX), ty = (int)(threadIdx.x / BX);
     const int tend = min(e.y + TPB, ps.ntiles);
     for (int t = e.y; t < tend; ++t) {
-        const int i = (t % ps.gx) * BX + tx;
-        const int j = (t / ps.gx) * BY + ty;
+        const int row = (int)fdiv((uint32_t)t, ps.gx);
+        const int i = (t - row * (int)ps.gx.d) * BX + tx;
+        const int j = row * BY + ty;
         if (i >= a.nx || j >= a.ny) continue;
         double Fx = a.gx, Fy = a.gy;
         if (d.active && in_box(d, i, j, a.nx)) {

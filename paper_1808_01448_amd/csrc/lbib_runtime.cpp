@@ -316,7 +316,7 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
             // the sweep and the particle's wait for each other on the device, and the particle
             // must always find a CU.
             bool overlap = h->overlap == 1 || (h->overlap == 2 && sweep_bytes(h) >= 64.0 * 1048576.0);
-            if (h->desc.ny >= 65536) overlap = false;  // the packed box (zone_pack)
+            if (h->desc.ny >= (1 << 23)) overlap = false;  // the packed tiles (zone_pack)
             if (overlap && h->zone_valid) HIPCHK(h, ensure_sweep_stream(h));
             if (!h->masked) overlap = false;
             if (!overlap || !h->zone_valid) {

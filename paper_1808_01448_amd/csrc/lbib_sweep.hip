@@ -126,12 +126,14 @@ __device__ __forceinline__ void box_force(const TileDesc& d, const int64_t* __re
 template <typename T, bool PULL>
 __global__ __launch_bounds__(256) void sweep_kernel(const T* __restrict__ fin, T* __restrict__ fout, SweepArgs a,
                                                     const TileDesc* __restrict__ desc,
-                                                    const int64_t* __restrict__ tile, int gx, int nblocks)
+                                                    const int64_t* __restrict__ tile, FastDiv gx, int nblocks)
 {
     using TL = Tile<PULL>;
+    static_assert(TL::W >= 64, "the sweep's addressing takes each wave's nodes from one row");
     const int b = xcd_tile(blockIdx.x, nblocks);
-    const int i = (b % gx) * TL::W + (int)threadIdx.x % TL::W;
-    const int j = (b / gx) * TL::H + (int)threadIdx.x / TL::W;
+    const int ty = (int)fdiv((uint32_t)b, gx), tx = b - ty * (int)gx.d;
+    const int i = tx * TL::W + (int)threadIdx.x % TL::W;
+    const int j = ty * TL::H + (int)threadIdx.x / TL::W;
     if (i >= a.nx || j >= a.ny) return;
     double Fx = a.gx, Fy = a.gy;
     if (desc) box_force<false>(*desc, tile, i, j, a.nx, Fx, Fy);
@@ -143,29 +145,34 @@ __global__ __launch_bounds__(256) void sweep_kernel(const T* __restrict__ fin, T
 // are dispatched first and wait for the particle's force beside the rest of the sweep rather
 // than at its end.  The others sweep the tiles outside it; each loads its populations before
 // it learns the box (no launch writes fin during the sweep), so that wait overlaps the loads.
-// At most 64 VGPRs: eight waves per SIMD.
+// At most 64 VGPRs (eight waves per SIMD); for the f - f_eq storages, whose loads of 27
+// moments are then issued in small groups with a wait after each, at most 80 (six or seven).
 template <typename T, bool PULL>
-__global__ __launch_bounds__(256, 8) void sweep_overlap_kernel(const T* __restrict__ fin, T* __restrict__ fout,
-                                                               SweepArgs a, HandoverArgs c, int gx, int nblocks)
+__global__ __launch_bounds__(256, St<T>::neq ? 6 : 8) void sweep_overlap_kernel(const T* __restrict__ fin,
+                                                                                 T* __restrict__ fout, SweepArgs a,
+                                                                                 HandoverArgs c, FastDiv gxd,
+                                                                                 int nblocks)
 {
     using TL = Tile<PULL>;
-    __shared__ TileDesc zs, ds;
+    __shared__ ZoneTiles zs;
+    __shared__ TileDesc ds;
+    const int gx = (int)gxd.d;
     if ((int)blockIdx.x >= c.nzone) {
         const int b = xcd_tile((int)blockIdx.x - c.nzone, nblocks);
-        const int tx = b % gx, ty = b / gx;
+        const int ty = (int)fdiv((uint32_t)b, gxd), tx = b - ty * gx;
         const int i = tx * TL::W + (int)threadIdx.x % TL::W, j = ty * TL::H + (int)threadIdx.x / TL::W;
         const bool in = i < a.nx && j < a.ny;
         typename St<T>::C g[9];
         if (in) update_load<T, PULL>(fin, a, i, j, g);
-        if (threadIdx.x == 0) zs = zone_wait(c.zone_words, c.zone_tag, c.flags);
-        __syncthreads();
-        if (!in || zone_has_tile(zone_tiles<TL::W, TL::H>(zs, a.nx, a.ny, gx, kZoneMargin), tx, ty, gx)) return;
+        // each wave learns the box's tiles by itself (no barrier)
+        const ZoneTiles zt = zone_wait_wave(c.zone_words, c.zone_tag, c.flags);
+        if (!in || zone_has_tile(zt, tx, ty, gx)) return;
         update_store<T, PULL>(fout, a, i, j, g, a.gx, a.gy);
         return;
     }
     if (threadIdx.x == 0) zs = zone_wait(c.zone_words, c.zone_tag, c.flags);
     __syncthreads();
-    const ZoneTiles zt = zone_tiles<TL::W, TL::H>(zs, a.nx, a.ny, gx, kZoneMargin);
+    const ZoneTiles zt = zs;
     const int nt = zt.ntx * zt.nty;
     const int e0 = (int)blockIdx.x;
     if (e0 < nt) {
@@ -194,18 +201,19 @@ __global__ __launch_bounds__(256, 8) void sweep_overlap_kernel(const T* __restri
     if (threadIdx.x == 0) __hip_atomic_fetch_add(c.zdone, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Sweep of a step with several particles (64 x 4 tiles: those of the tile mask).
+// Sweep of a step with several particles (64 x 4 tiles, a row per wave: those of the tile mask).
 template <typename T, bool PULL>
 __global__ __launch_bounds__(256) void sweep_multi_kernel(const T* __restrict__ fin, T* __restrict__ fout, SweepArgs a,
                                                           const unsigned long long* __restrict__ mcur,
                                                           unsigned long long* __restrict__ mnext,
-                                                          const PartRef* __restrict__ refs, int gx, int nblocks)
+                                                          const PartRef* __restrict__ refs, FastDiv gx, int nblocks)
 {
     const int b = xcd_tile(blockIdx.x, nblocks);
     const unsigned long long m = mcur[b];
     if (threadIdx.x == 0) mnext[b] = 0ull;
-    const int i = (b % gx) * 64 + (int)(threadIdx.x & 63);
-    const int j = (b / gx) * 4 + (int)(threadIdx.x >> 6);
+    const int ty = (int)fdiv((uint32_t)b, gx), tx = b - ty * (int)gx.d;
+    const int i = tx * 64 + (int)(threadIdx.x & 63);
+    const int j = ty * 4 + (int)(threadIdx.x >> 6);
     if (i >= a.nx || j >= a.ny) return;
     double Fx = a.gx, Fy = a.gy;
     for (unsigned long long r = m; r; r &= r - 1) {
@@ -234,10 +242,10 @@ hipError_t launch_sweep_multi(const T* fin, T* fout, const SweepArgs& a, const u
     const int gx = (a.nx + 63) / 64, gy = (a.ny + 3) / 4, nb = gx * gy;
     if (pull)
         hipExtLaunchKernelGGL(sweep_multi_kernel<T, true>, dim3(nb), dim3(256), 0u, stream, t0, t1, 0u, fin, fout, a,
-                              mcur, mnext, refs, gx, nb);
+                              mcur, mnext, refs, make_fastdiv(gx), nb);
     else
         hipExtLaunchKernelGGL(sweep_multi_kernel<T, false>, dim3(nb), dim3(256), 0u, stream, t0, t1, 0u, fin, fout,
-                              a, mcur, mnext, refs, gx, nb);
+                              a, mcur, mnext, refs, make_fastdiv(gx), nb);
     return hipGetLastError();
 }
 
@@ -249,12 +257,12 @@ hipError_t launch_sweep(const T* fin, T* fout, const SweepArgs& a, const TileDes
         using TL = Tile<true>;
         const int gx = (a.nx + TL::W - 1) / TL::W, nb = gx * ((a.ny + TL::H - 1) / TL::H);
         hipExtLaunchKernelGGL(sweep_kernel<T, true>, dim3(nb), dim3(256), 0u, stream, t0, t1, 0u, fin, fout, a, desc,
-                              tile, gx, nb);
+                              tile, make_fastdiv(gx), nb);
     } else {
         using TL = Tile<false>;
         const int gx = (a.nx + TL::W - 1) / TL::W, nb = gx * ((a.ny + TL::H - 1) / TL::H);
         hipExtLaunchKernelGGL(sweep_kernel<T, false>, dim3(nb), dim3(256), 0u, stream, t0, t1, 0u, fin, fout, a, desc,
-                              tile, gx, nb);
+                              tile, make_fastdiv(gx), nb);
     }
     return hipGetLastError();
 }
@@ -268,12 +276,12 @@ hipError_t launch_sweep_overlap(const T* fin, T* fout, const SweepArgs& a, const
         using TL = Tile<true>;
         const int gx = (a.nx + TL::W - 1) / TL::W, nb = gx * ((a.ny + TL::H - 1) / TL::H);
         hipExtLaunchKernelGGL(sweep_overlap_kernel<T, true>, dim3(nb + c.nzone), dim3(256), 0u, stream, t0, t1, 0u, fin,
-                              fout, a, c, gx, nb);
+                              fout, a, c, make_fastdiv(gx), nb);
     } else {
         using TL = Tile<false>;
         const int gx = (a.nx + TL::W - 1) / TL::W, nb = gx * ((a.ny + TL::H - 1) / TL::H);
         hipExtLaunchKernelGGL(sweep_overlap_kernel<T, false>, dim3(nb + c.nzone), dim3(256), 0u, stream, t0, t1, 0u,
-                              fin, fout, a, c, gx, nb);
+                              fin, fout, a, c, make_fastdiv(gx), nb);
     }
     return hipGetLastError();
 }
