@@ -40,14 +40,29 @@ __device__ __forceinline__ void collide_node(const C g[9], const SweepArgs& a, C
 {
     C drho, jx, jy;
     shifted_moments<C, C>(g, drho, jx, jy);
-    const C omega = (C)a.omega, guo = (C)a.guo, keep = (C)1 - omega;
-    const C r = drho / ((C)1 + drho);
+    constexpr bool f32 = sizeof(C) == 4;
+    C omega, keep, b3, b9, r;
+    if constexpr (f32) {
+        // constants rounded once on the host; the reciprocal instruction (1 ulp) for the
+        // divide, whose error sits far below the 16-bit storage's rounding
+        omega = a.omega_f;
+        keep = a.keep_f;
+        b3 = a.b3_f;
+        b9 = a.b9_f;
+        r = drho * __builtin_amdgcn_rcpf((C)1 + drho);
+    } else {
+        omega = (C)a.omega;
+        keep = (C)1 - omega;
+        b3 = (C)3 * (C)a.guo;
+        b9 = (C)9 * (C)a.guo;
+        r = drho / ((C)1 + drho);
+    }
     const C jxF = fma((C)0.5, Fx, jx), jyF = fma((C)0.5, Fy, jy);
     const C ux = fma(-jxF, r, jxF), uy = fma(-jyF, r, jyF);
     const C uu = fma(ux, ux, uy * uy);
     const C uF = fma(ux, Fx, uy * Fy);
     const C orho = fma(omega, drho, omega);  // omega rho
-    const C a3 = (C)3 * orho, a45 = (C)4.5 * orho, b3 = (C)3 * guo, b9 = (C)9 * guo;
+    const C a3 = (C)3 * orho, a45 = (C)4.5 * orho;
     const C iso = fma(-b3, uF, fma((C)-1.5 * orho, uu, omega * drho));
     post[0] = fma(keep, g[0], (C)kW[0] * iso);
     auto pair = [&](int q, int o, C eu, C eF) {
@@ -125,6 +140,43 @@ __device__ __forceinline__ S* at(S* b, uint32_t off)
 }
 __device__ __forceinline__ int wave_row(int j) { return __builtin_amdgcn_readfirstlane(j); }
 
+// Columns i - 1, i, i + 1 (periodic) of one row segment of a float plane, for a wave whose
+// active lanes hold the consecutive columns of one row (lane L at column i0 + L; lanes past the
+// row's end inactive): each lane loads its own column and takes its neighbours' values from
+// the adjacent lanes by one-lane wave shifts; the two values beyond the wave's ends come from
+// scalar loads and go to its first and last active lane.  One aligned load per row segment
+// instead of three, two of them straddling cache lines.
+struct WaveCols {
+    uint32_t own;      // byte offset of the lane's column
+    int left, right;   // the columns beyond the wave's two ends (wave-uniform)
+    bool first, last;  // the lane is the wave's first / last active one
+};
+__device__ __forceinline__ WaveCols wave_cols(int i, int nx)
+{
+    const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    const int i0 = __builtin_amdgcn_readfirstlane(i - lane);
+    const int nact = min(64, nx - i0);
+    WaveCols w;
+    w.own = opaque((uint32_t)i * 4u);
+    w.left = i0 == 0 ? nx - 1 : i0 - 1;
+    w.right = i0 + nact == nx ? 0 : i0 + nact;
+    w.first = lane == 0;
+    w.last = lane == nact - 1;
+    return w;
+}
+__device__ __forceinline__ void row_trio(const float* b, const WaveCols& w, float (&v)[3])
+{
+    const float c = *at(b, w.own);
+    const float hl = sbase(b)[w.left], hr = sbase(b)[w.right];
+    const int ci = __builtin_bit_cast(int, c);
+    // DPP wave_shr:1 (lane L reads lane L - 1) and wave_shl:1 (lane L reads lane L + 1)
+    const float sl = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(ci, ci, 0x138, 0xf, 0xf, false));
+    const float sr = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(ci, ci, 0x130, 0xf, 0xf, false));
+    v[0] = w.first ? hl : sl;
+    v[1] = c;
+    v[2] = w.last ? hr : sr;
+}
+
 // Non-equilibrium storages: the post-collision values leave relative to the equilibrium of
 // the moments stored for this node (rounded to FP32 first, so that every reader forms the same
 // equilibrium from them), and the moments are stored at the node.
@@ -140,10 +192,11 @@ __device__ __forceinline__ void neq_encode(T* fout, const SweepArgs& a, int i, i
         put(at(m0p, o), m0, pol);
         put(at(m1p, o), m1, pol);
         put(at(m2p, o), m2, pol);
-        C feq[9];
-        feq_shift_all<C>((C)m0, (C)m1, (C)m2, feq);
+        const C x = (C)m1, y = (C)m2;
+        const FeqNode<C> n = feq_node<C>((C)m0, x, y);
+        post[0] = fma(-(C)kW[0], feq_r0<C>(n), post[0]);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) post[q] -= feq[q];
+        for (int q = 1; q < 9; ++q) post[q] = fma(-(C)kW[q], feq_r<C>(n, e_dot<C>(q, x, y)), post[q]);
     }
 }
 
@@ -239,28 +292,52 @@ __device__ __forceinline__ void update_load(const T* __restrict__ fin, const Swe
         g[q] = (C)st_load(at(p, o), 0, a.inv_scale, true);
     }
     if constexpr (St<T>::neq) {
-        // plus the shifted equilibrium of the node that emitted each value (pop_source): the
-        // moments k = 0, 1, 2 of rows j - 1, j, j + 1
+        // plus the shifted equilibrium of the node that emitted each value (pop_source), from
+        // the moments k = 0, 1, 2 of columns i - 1, i, i + 1 of rows j - 1, j, j + 1
         const int64_t mp = neq_mpitch(a.pitch, a.plane);
-        const float* mr[3][3];
-        mr[1][0] = sbase(neq_moments(fin, a.pitch, a.plane, a.ny) + (int64_t)j * mp);
-        mr[0][0] = snext(mr[1][0], -mp);
-        mr[2][0] = snext(mr[1][0], mp);
+        const float* m1 = sbase(neq_moments(fin, a.pitch, a.plane, a.ny) + (int64_t)j * mp);
+        if (!top && !bot) {
+            const WaveCols wc = wave_cols(i, a.nx);
+            float mv[3][3][3];  // [row j - 1 + r][moment k][column i - 1 + c]
 #pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            mr[r][1] = snext(mr[r][0], P);
-            mr[r][2] = snext(mr[r][1], P);
-        }
-        const Cols cm = cols<float>(i, a.nx);
+            for (int r = 0; r < 3; ++r) {
+                const float* b = r == 1 ? m1 : snext(m1, (r - 1) * mp);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            const bool wall = kEy[q] > 0 ? bot : kEy[q] < 0 ? top : false;
-            const int r = 1 - kEy[q];  // the emitter's row j - e_y, as an index of mr
-            const float* const* rb = wall ? mr[1] : mr[r];
-            const uint32_t o = kEx[q] == 0 ? cm.o[1] : opaque(wall ? cm.o[1] : cm.o[1 - kEx[q]]);
-            const C d = (C)*at(rb[0], o), x = (C)*at(rb[1], o), y = (C)*at(rb[2], o);
-            const C eu = e_dot<C>(q, x, y);  // e_dir.u = -e_q.u for a reflected population
-            g[q] += feq_from_eu<C>((C)kW[q], (C)1 + d, feq_even_base<C>(d, x, y), wall ? -eu : eu);
+                for (int k = 0; k < 3; ++k) {
+                    row_trio(b, wc, mv[r][k]);
+                    if (k < 2) b = snext(b, P);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const int r = 1 - kEy[q], c = 1 - kEx[q];  // the emitter (i - e_x, j - e_y)
+                const C x = (C)mv[r][1][c], y = (C)mv[r][2][c];
+                const FeqNode<C> n = feq_node<C>((C)mv[r][0][c], x, y);
+                g[q] = fma((C)kW[q], q == 0 ? feq_r0<C>(n) : feq_r<C>(n, e_dot<C>(q, x, y)), g[q]);
+            }
+        } else {
+            // a wall row: a link that crosses the wall reflects, emitted by the node itself
+            const float* mr[3][3];
+            mr[1][0] = m1;
+            mr[0][0] = bot ? m1 : snext(m1, -mp);
+            mr[2][0] = top ? m1 : snext(m1, mp);
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                mr[r][1] = snext(mr[r][0], P);
+                mr[r][2] = snext(mr[r][1], P);
+            }
+            const Cols cm = cols<float>(i, a.nx);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const bool wall = kEy[q] > 0 ? bot : kEy[q] < 0 ? top : false;
+                const int r = 1 - kEy[q];  // the emitter's row j - e_y, as an index of mr
+                const float* const* rb = wall ? mr[1] : mr[r];
+                const uint32_t o = kEx[q] == 0 ? cm.o[1] : opaque(wall ? cm.o[1] : cm.o[1 - kEx[q]]);
+                const C x = (C)*at(rb[1], o), y = (C)*at(rb[2], o);
+                const FeqNode<C> n = feq_node<C>((C)*at(rb[0], o), x, y);
+                const C eu = e_dot<C>(q, x, y);  // e_dir.u = -e_q.u for a reflected population
+                g[q] = fma((C)kW[q], q == 0 ? feq_r0<C>(n) : feq_r<C>(n, wall ? -eu : eu), g[q]);
+            }
         }
     }
     wall_reflect<C>(g, j, a.ny, a.uw6);

@@ -59,7 +59,8 @@ __device__ __forceinline__ float st_load(const half_t* p, int64_t i, double inv_
 {
     const uint16_t* r = (const uint16_t*)p;
     const uint16_t b = nt ? __builtin_nontemporal_load(r + i) : r[i];
-    return (float)__builtin_bit_cast(_Float16, b) * (float)inv_scale;
+    // x s as one mixed-precision fma (adding -0 leaves every product, -0 included, unchanged)
+    return __builtin_fmaf((float)__builtin_bit_cast(_Float16, b), (float)inv_scale, -0.0f);
 }
 __device__ __forceinline__ float st_load(const bf16_t* p, int64_t i, double, bool nt)
 {
@@ -105,10 +106,8 @@ __device__ __forceinline__ void st_store(half_t* p, int64_t i, float v, double s
 }
 __device__ __forceinline__ void st_store(bf16_t* p, int64_t i, float v, double, int pol)
 {
-    uint32_t x = __builtin_bit_cast(uint32_t, v);
-    // round to nearest even on the 16 dropped bits; NaN stays a quiet NaN
-    x = (x & 0x7fffffffu) > 0x7f800000u ? 0x7fc00000u : x + 0x7fffu + ((x >> 16) & 1u);
-    put((uint16_t*)p + i, (uint16_t)(x >> 16), pol);
+    // the conversion instruction: round to nearest even, NaN stays a NaN
+    put((uint16_t*)p + i, __builtin_bit_cast(uint16_t, (__bf16)v), pol);
 }
 
 __device__ __forceinline__ void st_store(half_neq_t* p, int64_t i, double v, double scale, int pol)
@@ -162,41 +161,41 @@ __device__ __forceinline__ C e_dot(int q, C x, C y)
     }
 }
 
-// Shifted equilibrium (eq 2) f_eq,q(rho, u) - w_q = w_q (drho + rho A),
-// A = 3 e.u + 9/2 (e.u)^2 - 3/2 u^2, split by parity in e_q: w_q (E + O) with
-// E = (drho - 3/2 rho u^2) + 9/2 rho (e.u)^2 and O = 3 rho e.u.  Opposite directions differ
-// only in the sign of e.u, which flips O and leaves E bit for bit, so feq_shift_all (pairs
-// sharing E) and feq_shift (one direction) give identical values.
+// Shifted equilibrium (eq 2) f_eq,q - w_q = w_q (drho + rho A), A = 3 e.u + 9/2 (e.u)^2 -
+// 3/2 u^2, as w_q r_q with r_q = drho + rho (e.u (3 + 9/2 e.u) + P) and P = -3/2 u^2 per node:
+// three fused operations per direction once rho and P are known (r_0 = drho + rho P).  The
+// writers (neq_encode) and the readers (load_node, update_load) of the f - f_eq storages form
+// r_q from the same stored FP32 moments with this one sequence, so both sides agree bit for
+// bit; e.u for the opposite direction is the exact negative (e_dot).
 template <typename C>
-__device__ __forceinline__ C feq_even_base(C drho, C ux, C uy)
+struct FeqNode {
+    C drho, rho, P;
+};
+template <typename C>
+__device__ __forceinline__ FeqNode<C> feq_node(C drho, C ux, C uy)
 {
-    return fma((C)-1.5 * ((C)1 + drho), fma(ux, ux, uy * uy), drho);
+    return FeqNode<C>{drho, (C)1 + drho, (C)-1.5 * fma(ux, ux, uy * uy)};
 }
 template <typename C>
-__device__ __forceinline__ C feq_from_eu(C w, C rho, C base, C eu)
+__device__ __forceinline__ C feq_r(const FeqNode<C>& n, C eu)
 {
-    return w * (fma((C)4.5 * rho * eu, eu, base) + (C)3 * rho * eu);
+    return fma(n.rho, fma(eu, fma((C)4.5, eu, (C)3), n.P), n.drho);
+}
+template <typename C>
+__device__ __forceinline__ C feq_r0(const FeqNode<C>& n)
+{
+    return fma(n.rho, n.P, n.drho);
+}
+// f_eq,q - w_q of direction q (eu: e_q.u).
+template <typename C>
+__device__ __forceinline__ C feq_shift_eu(int q, const FeqNode<C>& n, C eu)
+{
+    return (C)kW[q] * (q == 0 ? feq_r0<C>(n) : feq_r<C>(n, eu));
 }
 template <typename C>
 __device__ __forceinline__ C feq_shift(int q, C drho, C ux, C uy)
 {
-    return feq_from_eu<C>((C)kW[q], (C)1 + drho, feq_even_base<C>(drho, ux, uy), e_dot<C>(q, ux, uy));
-}
-template <typename C>
-__device__ __forceinline__ void feq_shift_all(C drho, C ux, C uy, C out[9])
-{
-    const C rho = (C)1 + drho, base = feq_even_base<C>(drho, ux, uy);
-    const C r45 = (C)4.5 * rho, r3 = (C)3 * rho;
-    out[0] = feq_from_eu<C>((C)kW[0], rho, base, (C)0);
-    auto pair = [&](int q, int o, C eu) {
-        const C even = fma(r45 * eu, eu, base), odd = r3 * eu;
-        out[q] = (C)kW[q] * (even + odd);
-        out[o] = (C)kW[q] * (even - odd);
-    };
-    pair(1, 3, ux);
-    pair(2, 4, uy);
-    pair(5, 7, ux + uy);
-    pair(6, 8, uy - ux);
+    return feq_shift_eu<C>(q, feq_node<C>(drho, ux, uy), e_dot<C>(q, ux, uy));
 }
 
 // The node that emitted population q of node (i, j) and the direction it emitted it in:
@@ -377,9 +376,10 @@ __device__ __forceinline__ void load_node(const T* f, int i, int j, int nx, int 
             int si, sj, dir;
             pop_source(q, i, j, nx, ny, si, sj, dir);
             const int64_t c = (int64_t)sj * mp + si;
-            const R d = (R)m[c], x = (R)m[plane + c], y = (R)m[2 * plane + c];
+            const R x = (R)m[plane + c], y = (R)m[2 * plane + c];
+            const FeqNode<R> n = feq_node<R>((R)m[c], x, y);
             const R eu = e_dot<R>(q, x, y);  // e_dir.u = -e_q.u for a reflected population
-            g[q] += feq_from_eu<R>((R)kW[q], (R)1 + d, feq_even_base<R>(d, x, y), dir == q ? eu : -eu);
+            g[q] = fma((R)kW[q], q == 0 ? feq_r0<R>(n) : feq_r<R>(n, dir == q ? eu : -eu), g[q]);
         }
     }
     wall_reflect<R>(g, j, ny, uw6);

@@ -400,6 +400,11 @@ SweepArgs make_sweep_args(const LatticeGeom& g)
     a.scale = g.scale;
     a.inv_scale = 1.0 / g.scale;
     a.uw6 = g.uw / 6.0;
+    a.omega_f = (float)a.omega;
+    a.keep_f = (float)(1.0 - a.omega);
+    a.b3_f = (float)(3.0 * a.guo);
+    a.b9_f = (float)(9.0 * a.guo);
+    a.inv_scale_f = (float)a.inv_scale;
     return a;
 }
 
@@ -427,9 +432,9 @@ static double wall_term(const LatticeGeom& g, int q)
     return q == 7 ? -g.uw / 6.0 : q == 8 ? g.uw / 6.0 : 0.0;
 }
 
-// Shifted equilibrium f_eq,q - w_q of moments (drho, u), in the device's operation order:
-// w_q (E + O) with the even part E = (drho - 3/2 rho u^2) + 9/2 rho (e.u)^2 and the odd part
-// O = 3 rho e.u, e.u formed so that opposite directions give exact negatives.
+// Shifted equilibrium f_eq,q - w_q = w_q r_q of moments (drho, u), in the device's order of
+// operations (feq_r): r_q = drho + rho (e.u (3 + 9/2 e.u) + P) with P = -3/2 u^2, e.u formed
+// so that opposite directions give exact negatives.
 static double feq_shift_host(int q, double drho, double ux, double uy)
 {
     double eu = 0.0;
@@ -444,9 +449,9 @@ static double feq_shift_host(int q, double drho, double ux, double uy)
         case 8: eu = ux - uy; break;
         default: break;
     }
-    const double rho = 1.0 + drho;
-    const double base = std::fma(-1.5 * rho, std::fma(ux, ux, uy * uy), drho);
-    return kWq[q] * (std::fma(4.5 * rho * eu, eu, base) + 3.0 * rho * eu);
+    const double rho = 1.0 + drho, P = -1.5 * std::fma(ux, ux, uy * uy);
+    const double r = q == 0 ? std::fma(rho, P, drho) : std::fma(rho, std::fma(eu, std::fma(4.5, eu, 3.0), P), drho);
+    return kWq[q] * r;
 }
 
 // Non-equilibrium storages: the shifted equilibrium the reader of population q at (i, j)

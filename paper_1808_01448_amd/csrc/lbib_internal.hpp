@@ -148,6 +148,9 @@ struct SweepArgs {
     double gx, gy;  // uniform body force
     double scale, inv_scale;  // stored value = (f - w) scale (a power of two; 1 but for FP16)
     double uw6;     // speed of the moving top wall / 6 (0: resting walls); see wall_reflect
+    // the FP32 update of the 16-bit storages: omega, 1 - omega, 3 guo, 9 guo, inv_scale (each
+    // the double value rounded once)
+    float omega_f, keep_f, b3_f, b9_f, inv_scale_f;
 };
 
 // Where the sweep and the probes of a multi-particle step find particle p's spread force:

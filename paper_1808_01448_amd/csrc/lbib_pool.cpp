@@ -228,17 +228,7 @@ lbib_status rebuild(lbib_pool* h)
         lds_bytes = std::max(lds_bytes, particle_launch_lds(m.p.box_cap));
         PoolSweep<T>& s = sims[k];
         s = PoolSweep<T>{};
-        s.a.nx = m.g.nx;
-        s.a.ny = m.g.ny;
-        s.a.pitch = m.g.pitch;
-        s.a.plane = m.g.plane;
-        s.a.omega = 1.0 / m.g.tau;
-        s.a.guo = 1.0 - 1.0 / (2.0 * m.g.tau);
-        s.a.gx = m.g.gx;
-        s.a.gy = m.g.gy;
-        s.a.scale = m.g.scale;
-        s.a.inv_scale = 1.0 / m.g.scale;
-        s.a.uw6 = m.g.uw / 6.0;
+        s.a = make_sweep_args(m.g);
         s.fA = (T*)m.fA;
         s.fB = (T*)m.fB;
         s.tile = m.p.d_tile;

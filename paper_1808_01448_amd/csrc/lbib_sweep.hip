@@ -148,7 +148,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(const T* __restrict__ fin, T
 // At most 64 VGPRs (eight waves per SIMD); for the f - f_eq storages, whose loads of 27
 // moments are then issued in small groups with a wait after each, at most 80 (six or seven).
 template <typename T, bool PULL>
-__global__ __launch_bounds__(256, St<T>::neq ? 6 : 8) void sweep_overlap_kernel(const T* __restrict__ fin,
+__global__ __launch_bounds__(256, St<T>::neq ? 7 : 8) void sweep_overlap_kernel(const T* __restrict__ fin,
                                                                                  T* __restrict__ fout, SweepArgs a,
                                                                                  HandoverArgs c, FastDiv gxd,
                                                                                  int nblocks)
@@ -182,6 +182,9 @@ __global__ __launch_bounds__(256, St<T>::neq ? 6 : 8) void sweep_overlap_kernel(
         }
         __syncthreads();
         const TileDesc d = ds;
+        // one iteration at a time: an unrolled copy of the update would raise the register
+        // allocation of the whole kernel, whose other workgroups run the plain update
+#pragma unroll 1
         for (int e = e0; e < nt; e += c.nzone) {
             int tx = zt.tx0 + e % zt.ntx;
             if (tx >= gx) tx -= gx;
