@@ -216,25 +216,12 @@ hipError_t ensure_sweep_stream(lbib_sim* h)
 // Bytes one lattice sweep moves (every population read and written once).
 double sweep_bytes(const lbib_sim* h) { return (double)h->desc.nx * h->desc.ny * h->g.upd_bytes; }
 
-// Mode 2's choice of schedule.  The overlapped schedule hides the particle phase (15-20 us
-// for the particles here) behind the sweep, and its sweep costs a few per cent more than the
-// plain one (a CU left out, the box check of every wave; the f - f_eq sweep also runs a wave
-// fewer per SIMD beside its hand-over code).  Measured on MI355X it wins from about 64 MiB per
-// sweep, and breaks even near 2 GiB for the storages of populations alone and near 512 MiB
-// for f - f_eq (8192 x 4096: FP16 overlapped 225 us, serial 205 + 20; FP16 f - f_eq
-// overlapped 441 us, serial 384 + 20), where the serial schedule takes over.
-bool overlap_pays(const lbib_sim* h)
-{
-    const double b = sweep_bytes(h), MiB = 1048576.0;
-    return b >= 64.0 * MiB && b <= (h->g.neq ? 512.0 : 2048.0) * MiB;
-}
-
 // One time step is the particle phase then the lattice sweep.  Serial schedule: both on the
 // caller's stream.  Overlapped schedule (when the previous step has predicted this step's
 // box): the particle phase runs on the second stream while the caller's stream sweeps the
 // lattice on a third, with no event between the two chains but the particle's wait for the
 // previous sweep: the sweep waits on the device for the previous particle launch, and the
-// tiles of the predicted box, which need the spread force, go to workgroups at the head of
+// tiles of the predicted box, which need the spread force, go to workgroups at the end of
 // its grid, which wait for the force to be published (HandoverArgs).  Both schedules compute
 // every node with the same arithmetic.
 template <typename T>
@@ -324,10 +311,11 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
             pa.zone_words = p.d_count + 2 + 2 * ((h->steps + 1) & 3);
             pa.zone_tag = (uint32_t)((prev + 1) & 0xffffu);
             h->plaunches = prev + 1;
-            // the overlapped schedule (overlap_pays) needs the CU-masked sweep stream: workgroups
-            // of the sweep and the particle's wait for each other on the device, and the
-            // particle must always find a CU.
-            bool overlap = h->overlap == 1 || (h->overlap == 2 && overlap_pays(h));
+            // the overlapped schedule wins once a sweep moves more than ~64 MiB (the particle
+            // phase then hides behind it).  It needs the CU-masked sweep stream: workgroups of
+            // the sweep and the particle's wait for each other on the device, and the particle
+            // must always find a CU.
+            bool overlap = h->overlap == 1 || (h->overlap == 2 && sweep_bytes(h) >= 64.0 * 1048576.0);
             if (h->desc.ny >= (1 << 23)) overlap = false;  // the packed tiles (zone_pack)
             if (overlap && h->zone_valid) HIPCHK(h, ensure_sweep_stream(h));
             if (!h->masked) overlap = false;
