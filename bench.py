@@ -58,19 +58,21 @@ def measured_traffic(cells: int):
     return t.get("hbm_bytes_per_launch")
 
 
-def measured_traffic_beyond(storage: str, cells: int):
-    """HBM bytes per sweep launch of the 8192 x 4096 leg for one storage, from the committed
-    counter summary, or None when it was taken on a different kernel source."""
+def measured_traffic_beyond(storage: str, cells: int) -> dict:
+    """HBM bytes per sweep launch of the 8192 x 4096 leg for one storage and the sweep kernel
+    they were counted on, from the committed counter summary (None for both when it was taken
+    on a different kernel source)."""
+    none = {"traffic": None, "kernel": None}
     try:
         t = json.load(open(TRAFFIC_FILE_BEYOND))
     except (OSError, ValueError):
-        return None
+        return none
     if t.get("kernel_source_sha256_16") != kernel_source_hash():
-        return None
+        return none
     for e in t.get("entries", []):
         if e.get("storage") == storage and e.get("cells") == cells:
-            return e.get("hbm_bytes_per_launch")
-    return None
+            return {"traffic": e.get("hbm_bytes_per_launch"), "kernel": e.get("kernel")}
+    return none
 
 
 def timed_window(sim, steps: int, stream) -> dict:
@@ -166,7 +168,7 @@ def beyond_cache_leg(steps: int, stream) -> dict:
             "ms_per_step": round(win["seconds"] * 1e3 / steps, 4),
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(achieved / HBM_PEAK_GBS, 4),
-                         "traffic": measured_traffic_beyond(prec, cells),
+                         **measured_traffic_beyond(prec, cells),
                          "algorithmic_bytes_per_launch": bpu * cells,
                          "avg_launch_us": round(sweep_ms * 1e3, 2), "launches_timed": n0,
                          "copy_same_bytes_gbs": round(copy_gbs, 1),

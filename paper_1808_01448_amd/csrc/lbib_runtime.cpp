@@ -221,7 +221,7 @@ double sweep_bytes(const lbib_sim* h) { return (double)h->desc.nx * h->desc.ny *
 // box): the particle phase runs on the second stream while the caller's stream sweeps the
 // lattice on a third, with no event between the two chains but the particle's wait for the
 // previous sweep: the sweep waits on the device for the previous particle launch, and the
-// tiles of the predicted box, which need the spread force, go to workgroups at the end of
+// tiles of the predicted box, which need the spread force, go to workgroups at the head of
 // its grid, which wait for the force to be published (HandoverArgs).  Both schedules compute
 // every node with the same arithmetic.
 template <typename T>
