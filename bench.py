@@ -443,16 +443,21 @@ def main():
     log(f"bench: {ms_step * 1e3:.2f} us/step ({mlups:.0f} MLUPS); {args.long_steps}-step window")
     long_win = timed_window(sim, args.long_steps, stream)
     long_ms = long_win["seconds"] * 1e3 / args.long_steps
+    # what one lbib_step call costs beyond its steps (launch and synchronisation latency on
+    # the host, the joins of the two streams at the call's start and end on the GPU): a short
+    # window of its own against the long window's rate, the median of five
+    ks = 20
+    shorts = [timed_window(sim, ks, stream) for _ in range(5)]
+    fixed = sorted((x["seconds"] - ks * long_ms * 1e-3) * 1e6 for x in shorts)[2]
+    fixed_gpu = sorted((x["gpu_seconds"] - ks * long_win["gpu_seconds"] / args.long_steps) * 1e6 for x in shorts)[2]
     window = {
         "ms_per_step_gpu_events": round(win["gpu_seconds"] * 1e3 / args.steps, 5),
         "long_window": {"steps": args.long_steps, "ms_per_step": round(long_ms, 5),
                         "ms_per_step_gpu_events": round(long_win["gpu_seconds"] * 1e3 / args.long_steps, 5),
                         "mlups": round(cells * args.long_steps / long_win["seconds"] / 1e6, 1)},
-        # what one lbib_step call costs beyond its steps: launch and synchronisation latency on
-        # the host, and the joins of the two streams at the call's start and end on the GPU
-        "fixed_cost_us_per_call": round((dt - args.steps * long_ms * 1e-3) * 1e6, 1),
-        "fixed_cost_us_per_call_gpu_events": round(
-            (win["gpu_seconds"] - args.steps * long_win["gpu_seconds"] / args.long_steps) * 1e6, 1),
+        "short_window_steps": ks,
+        "fixed_cost_us_per_call": round(fixed, 1),
+        "fixed_cost_us_per_call_gpu_events": round(fixed_gpu, 1),
     }
 
     roofline = None
