@@ -182,9 +182,9 @@ def beyond_cache_leg(steps: int, stream) -> dict:
 
 def c1_leg(steps: int, stream, with_cpu: bool) -> dict:
     """The 256 x 64 FP64 channel (circle, 64 markers, Re 0.1): 2.36 MB of populations stay in
-    the caches, so a step is bound by the latency of its two launches and their hand-over,
-    not by HBM.  Reported as time per step; the oracle runs the same steps on one thread and
-    on all cores."""
+    the caches, so a step is bound by the latency of the particle phase (the sweep runs beside
+    it in the overlapped schedule) and the hand-over, not by HBM.  Reported as time per step;
+    the oracle runs the same steps on one thread and on all cores."""
     from paper_1808_01448_amd import lbib
     from paper_1808_01448_amd import workloads as W
 
@@ -203,7 +203,8 @@ def c1_leg(steps: int, stream, with_cpu: bool) -> dict:
            "us_per_step_gpu_events": round(win["gpu_seconds"] * 1e6 / steps, 3),
            "mlups": round(cells * steps / win["seconds"] / 1e6, 1),
            "sweep_avg_us": round(sweep_ms * 1e3, 2), "particle_launch_avg_us": round(part_ms * 1e3, 2),
-           "bound": "latency (two dependent launches per step; 2.36 MB of state stays in the caches)"}
+           "bound": "latency: the particle phase's chain of dependent steps, with the sweep overlapped behind it "
+                    "(2.36 MB of state stays in the caches)"}
     if with_cpu:
         out["oracle_one_thread"] = cpu_oracle(w, 2000, threads=1)
         out["oracle_all_cores"] = cpu_oracle(w, 2000)

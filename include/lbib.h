@@ -240,8 +240,8 @@ lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size);
  * LBIB_E_NUMERIC.  Serial (mode 0), always on the first step after lbib_init / lbib_load /
  * lbib_write_particle, and where CU masking is unavailable or ny >= 2^23: the particle phase
  * and a sweep of all nodes run one after the other on the handle's stream.  Mode 2 (the
- * default) overlaps when one sweep moves at least 64 MiB.  Both schedules give bit-identical
- * results. */
+ * default) overlaps wherever it can (the faster schedule at every lattice size measured).
+ * Both schedules give bit-identical results. */
 /* Several particles in one lattice: the particle phase is split in two launches over all
  * particles -- first every particle stages its box and spreads its marker forces, then every
  * particle evaluates its probe loads (with the spread force of every particle that reaches a
