@@ -35,14 +35,14 @@ constexpr double kW[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9
 // Streaming is a permutation, so both layouts present the same values.
 __device__ __forceinline__ int64_t pop_index(int q, int i, int j, int nx, int ny, int pitch, int64_t plane, bool pull)
 {
-    if (pull) {
-        const int sj = j - kEy[q];
-        if (sj < 0 || sj >= ny) return kOpp[q] * plane + (int64_t)j * pitch + i;
-        int si = i - kEx[q];
-        si = si < 0 ? si + nx : (si >= nx ? si - nx : si);
-        return q * plane + (int64_t)sj * pitch + si;
-    }
-    return q * plane + (int64_t)j * pitch + i;
+    // selects rather than branches, so a caller's loads of several nodes can all be in flight
+    const int sj = j - kEy[q];
+    const bool wall = sj < 0 || sj >= ny;
+    int si = i - kEx[q];
+    si = si < 0 ? si + nx : (si >= nx ? si - nx : si);
+    const bool moved = pull && !wall;
+    const int qq = pull && wall ? kOpp[q] : q;
+    return qq * plane + (int64_t)(moved ? sj : j) * pitch + (moved ? si : i);
 }
 
 // Loads and stores of one stored population (f - w, in the compute type of the storage),
@@ -204,17 +204,12 @@ __device__ __forceinline__ C feq_shift(int q, C drho, C ux, C uy)
 __device__ __forceinline__ void pop_source(int q, int i, int j, int nx, int ny, int& si, int& sj, int& dir)
 {
     const int jj = j - kEy[q];
-    if (jj < 0 || jj >= ny) {
-        si = i;
-        sj = j;
-        dir = kOpp[q];
-        return;
-    }
+    const bool wall = jj < 0 || jj >= ny;
     int ii = i - kEx[q];
     ii = ii < 0 ? ii + nx : (ii >= nx ? ii - nx : ii);
-    si = ii;
-    sj = jj;
-    dir = q;
+    si = wall ? i : ii;
+    sj = wall ? j : jj;
+    dir = wall ? kOpp[q] : q;
 }
 
 // Density and momentum of shifted populations g_q = f_q - w_q: rho = 1 + sum g (the weights
@@ -362,6 +357,12 @@ __device__ __forceinline__ void wall_reflect(C (&g)[9], int j, int ny, double uw
 // from a buffer in either layout as type R: the stored value, plus, for the non-equilibrium
 // storages, the shifted equilibrium of the node that emitted it (from the stored moments),
 // plus the moving wall's term.
+// Three consecutive FP32 values of a row, read by one load (global loads of several dwords
+// need only dword alignment).
+struct alignas(4) RowTriple {
+    float v[3];
+};
+
 template <typename T, typename R>
 __device__ __forceinline__ void load_node(const T* f, int i, int j, int nx, int ny, int pitch, int64_t plane, bool pull,
                                           double inv_scale, double uw6, bool nt, R (&g)[9])
@@ -371,15 +372,40 @@ __device__ __forceinline__ void load_node(const T* f, int i, int j, int nx, int 
     if constexpr (St<T>::neq) {
         const float* m = neq_moments(f, pitch, plane, ny);
         const int64_t mp = neq_mpitch(pitch, plane);
+        // The moments of the 3 x 3 neighbourhood, mm[r][k][c] = moment k of node
+        // (i - 1 + c, j - 1 + r) (periodic in x): each row's three columns come from one load
+        // of columns c0 .. c0 + 2, c0 kept inside the row (nx >= 4), and at the two edge
+        // columns the column across the periodic edge from a load of its own.  Rows past a
+        // wall are read clamped and never used (such links take the node's own moments).
+        const int c0 = min(max(i - 1, 0), nx - 3);
+        const bool wl = i == 0, wr = i == nx - 1;
+        const int cw = wl ? nx - 1 : 0;
+        float mm[3][3][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const int64_t row = (int64_t)min(max(j - 1 + r, 0), ny - 1) * mp;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const RowTriple t = *(const RowTriple*)(m + k * plane + row + c0);
+                float e = 0.0f;
+                if (wl || wr) e = m[k * plane + row + cw];
+                mm[r][k][0] = wl ? e : (wr ? t.v[1] : t.v[0]);
+                mm[r][k][1] = wl ? t.v[0] : (wr ? t.v[2] : t.v[1]);
+                mm[r][k][2] = wl ? t.v[1] : (wr ? e : t.v[2]);
+            }
+        }
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-            int si, sj, dir;
-            pop_source(q, i, j, nx, ny, si, sj, dir);
-            const int64_t c = (int64_t)sj * mp + si;
-            const R x = (R)m[plane + c], y = (R)m[2 * plane + c];
-            const FeqNode<R> n = feq_node<R>((R)m[c], x, y);
+            // the node that emitted population q (pop_source): (i - e_x, j - e_y) along q, or
+            // the node itself along opp(q) where that link crosses a wall
+            const int sj = j - kEy[q];
+            const bool wall = sj < 0 || sj >= ny;
+            const int r = 1 - kEy[q], c = 1 - kEx[q];  // constants once the loop is unrolled
+            const R d = (R)(wall ? mm[1][0][1] : mm[r][0][c]);
+            const R x = (R)(wall ? mm[1][1][1] : mm[r][1][c]), y = (R)(wall ? mm[1][2][1] : mm[r][2][c]);
+            const FeqNode<R> n = feq_node<R>(d, x, y);
             const R eu = e_dot<R>(q, x, y);  // e_dir.u = -e_q.u for a reflected population
-            g[q] = fma((R)kW[q], q == 0 ? feq_r0<R>(n) : feq_r<R>(n, dir == q ? eu : -eu), g[q]);
+            g[q] = fma((R)kW[q], q == 0 ? feq_r0<R>(n) : feq_r<R>(n, wall ? -eu : eu), g[q]);
         }
     }
     wall_reflect<R>(g, j, ny, uw6);

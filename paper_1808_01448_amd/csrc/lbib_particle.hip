@@ -178,7 +178,7 @@ struct OvEntry {
 constexpr int kMaxParticles = 64;
 constexpr int kFields = 6;                      // per marked node: 4 doubles + 2 64-bit integers
 constexpr size_t kSlotBytes = kFields * 8 + 4;  // the fields and the node map entry
-constexpr int kFillU = 4;                       // marked nodes per lane in flight while filling
+constexpr int kFillU = 4;                       // marked nodes per lane in flight while summing forces
 constexpr size_t kLdsMax = 158 * 1024;          // dynamic LDS a workgroup may take beside the static part
 constexpr size_t kLdsHead = sizeof(OvEntry) * kMaxParticles;
 
@@ -403,32 +403,45 @@ __device__ __forceinline__ int overlap_list(const ParticleArgs<T>& a, const Part
     return n;
 }
 
-// Node fields at the marked nodes: slots s0 + tid + u PB for u < kFillU per round, so the
-// loads of kFillU nodes per lane are in flight at once and neighbouring lanes read
+// Marked nodes per lane whose loads are in flight at once while filling: four, or two where a
+// node takes 36 loads (the f - f_eq storages: nine values and the three moments of each of
+// their nine sources) in a phase whose other state would then spill.
+template <typename T>
+constexpr int fill_nodes_per_lane(int mode)
+{
+    return St<T>::neq && mode != 1 ? 2 : 4;
+}
+
+// Node fields at the marked nodes: slots s0 + tid + u PB for u < U per round, so the
+// loads of U nodes per lane are in flight at once and neighbouring lanes read
 // neighbouring nodes of a row.  TOTAL (the probe launch of several particles): also the
 // total spread force at each node, summed over the overlapping particles in particle order.
-template <typename T, bool TOTAL>
+template <typename T, bool TOTAL, int U>
 __device__ __forceinline__ void fill_nodes(const ParticleArgs<T>& a, const NodeView& B, const int* nodes, int nm,
                                            int x0, int y0, int w, const OvEntry* ov, int nov)
 {
-    for (int s0 = 0; s0 < nm; s0 += PB * kFillU) {
-        int kk[kFillU], ii[kFillU], jj[kFillU];
-        double v[kFillU][9];
+    for (int s0 = 0; s0 < nm; s0 += PB * U) {
+        int kk[U], ii[U], jj[U];
+        double v[U][9];
+        // A wave loads the nodes of its slots of the round where it has any (so a small box
+        // issues no loads for empty waves); a slot past the end in such a wave reads the first
+        // marked node and stores nothing, so the wave's loads carry no divergent branch.
 #pragma unroll
-        for (int u = 0; u < kFillU; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int sl = s0 + u * PB + (int)threadIdx.x;
-            kk[u] = sl < nm ? nodes[sl] : -1;
-            ii[u] = jj[u] = 0;
-            if (kk[u] >= 0) {
-                jj[u] = y0 + kk[u] / w;
-                ii[u] = wrap(x0 + kk[u] % w, a.nx);
-                load_node<T, double>(a.f, ii[u], jj[u], a.nx, a.ny, a.pitch, a.plane, a.pull != 0, a.inv_scale, a.uw6,
-                                     false, v[u]);
-            }
+            const int k = nodes[sl < nm ? sl : 0];
+            kk[u] = sl < nm ? k : -1;
+            jj[u] = y0 + k / w;
+            ii[u] = wrap(x0 + k % w, a.nx);
         }
-        double fx[kFillU], fy[kFillU];
 #pragma unroll
-        for (int u = 0; u < kFillU; ++u) fx[u] = fy[u] = 0.0;
+        for (int u = 0; u < U; ++u)
+            if (s0 + u * PB + (int)(threadIdx.x & ~63u) < nm)
+                load_node<T, double>(a.f, ii[u], jj[u], a.nx, a.ny, a.pitch, a.plane, a.pull != 0, a.inv_scale,
+                                     a.uw6, false, v[u]);
+        double fx[U], fy[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) fx[u] = fy[u] = 0.0;
         if (TOTAL) {
             // two overlapping particles per round, so their index and force loads overlap;
             // the sums still run in particle order
@@ -437,12 +450,12 @@ __device__ __forceinline__ void fill_nodes(const ParticleArgs<T>& a, const NodeV
                 OvEntry E[2];
                 E[0] = ov[e0];
                 E[1] = ov[e0 + ne - 1];
-                int n[2][kFillU];
-                uint2 r[2][kFillU];
+                int n[2][U];
+                uint2 r[2][U];
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
 #pragma unroll
-                    for (int u = 0; u < kFillU; ++u) {
+                    for (int u = 0; u < U; ++u) {
                         int di = ii[u] - E[q].i0w;
                         if (di < 0) di += a.nx;
                         const int dj = jj[u] - E[q].j0;
@@ -450,12 +463,12 @@ __device__ __forceinline__ void fill_nodes(const ParticleArgs<T>& a, const NodeV
                                                                                                    : -1;
                         r[q][u] = n[q][u] >= 0 ? E[q].ring[n[q][u] >> 5] : make_uint2(0u, 0u);
                     }
-                int64_t tx[2][kFillU], ty[2][kFillU];
-                bool in[2][kFillU];
+                int64_t tx[2][U], ty[2][U];
+                bool in[2][U];
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
 #pragma unroll
-                    for (int u = 0; u < kFillU; ++u) {
+                    for (int u = 0; u < U; ++u) {
                         const int nn = n[q][u];
                         in[q][u] = nn >= 0 && ((r[q][u].x >> (nn & 31)) & 1u);
                         tx[q][u] = ty[q][u] = 0;
@@ -468,7 +481,7 @@ __device__ __forceinline__ void fill_nodes(const ParticleArgs<T>& a, const NodeV
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
 #pragma unroll
-                    for (int u = 0; u < kFillU; ++u) {
+                    for (int u = 0; u < U; ++u) {
                         if (!in[q][u]) continue;
                         fx[u] += ldexp((double)tx[q][u], -E[q].scale);
                         fy[u] += ldexp((double)ty[q][u], -E[q].scale);
@@ -476,7 +489,7 @@ __device__ __forceinline__ void fill_nodes(const ParticleArgs<T>& a, const NodeV
             }
         }
 #pragma unroll
-        for (int u = 0; u < kFillU; ++u) {
+        for (int u = 0; u < U; ++u) {
             if (kk[u] < 0) continue;
             const int sl = s0 + u * PB + (int)threadIdx.x;
             double dr, jx, jy;
@@ -653,7 +666,7 @@ __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const Phase
     int flags = c.flags;
     DevParticle* st = a.st;
 
-    fill_nodes<T, MODE == 2>(a, B, c.nodes, c.nmarked, x0, y0, w, ov, nov);
+    fill_nodes<T, MODE == 2, fill_nodes_per_lane<T>(MODE)>(a, B, c.nodes, c.nmarked, x0, y0, w, ov, nov);
     __syncthreads();
 
     // ---- markers: MLS interpolation and direct forcing ----------------------------------
