@@ -183,3 +183,34 @@ def test_sweep_commutes_with_periodic_shift(L, prec, layout):
         s.close()
     say("shift", prec, "layout", layout, "largest change over the run", float(np.abs(out[0] - f0).max()))
     np.testing.assert_array_equal(out[1], np.roll(out[0], k, axis=2))
+
+
+@pytest.mark.parametrize("layout", [0, 1])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16", "bf16", "fp16_neq", "bf16_neq"])
+def test_particle_across_the_seam_is_a_shifted_copy(L, prec, layout):
+    """A particle moved by 80 columns (560 -> 640 on a 640-column lattice, where it straddles
+    the periodic seam) gives the shifted run bit for bit: every x coordinate stays in the binade
+    [512, 1024) in both runs, so no rounding changes (the FP64 oracle does the same, tested on
+    the CPU).  It holds the particle phase's wrapped supports, node loads (for the f - f_eq
+    storages the moments of the columns across the seam), spreads and probes, and the sweep's
+    box at the seam, to the arithmetic of the interior, in the default schedule."""
+    k, steps = 80, 40
+    out = []
+    for xc in (560.0, 560.0 + k):
+        w = W.channel_small_binding(prec)
+        w["lattice"]["nx"] = 640
+        w["particle"]["xc"] = xc
+        s = L.Sim(w, layout=layout)
+        s.trace_enable(steps)
+        s.step(steps)
+        s.sync()
+        out.append(dict(trace=s.trace(steps), f=s.f, bonds=s.bonds()[0]))
+        s.close()
+    a, b = out
+    ix = L.STATE_FIELDS.index("xc")
+    rest = [c for c in range(len(L.STATE_FIELDS)) if c != ix]
+    say("seam shift", prec, "layout", layout, "bonds", int(a["bonds"].sum()), "final xc", a["trace"][-1, ix])
+    np.testing.assert_array_equal(b["trace"][:, ix], a["trace"][:, ix] + k)
+    np.testing.assert_array_equal(b["trace"][:, rest], a["trace"][:, rest])
+    np.testing.assert_array_equal(b["f"], np.roll(a["f"], k, axis=2))
+    np.testing.assert_array_equal(b["bonds"], a["bonds"])

@@ -81,6 +81,38 @@ def test_translation_symmetry(orc):
         assert err <= 1e-9, (cols, err)
 
 
+def seam_shift_workload(xc: float) -> dict:
+    """The 256 x 64 binding case on a 640-column lattice with the circle at xc."""
+    w = W.channel_small_binding("fp64")
+    w["lattice"]["nx"] = 640
+    w["particle"]["xc"] = xc
+    return w
+
+
+def test_shift_across_the_seam_is_exact(orc):
+    """Moving the particle by a whole number of columns moves the solution with it, bit for bit,
+    as long as every x coordinate stays in one binade in both runs (here [512, 1024): markers,
+    probes, and the second-order update's intermediates), so that no rounding changes.  The
+    circle at xc = 640 straddles the periodic seam of the 640-column lattice; at 560 it does
+    not: the seam's wrapped supports, spreads and probes must act exactly like interior ones.
+    Bonds form (their draws are keyed by step, element and particle, not position)."""
+    k, steps = 80, 40
+    runs = []
+    for xc in (560.0, 560.0 + k):
+        o = orc.Sim.from_workload(seam_shift_workload(xc))
+        flags, tr = o.step_all(steps)
+        assert flags == 0
+        runs.append((tr[:, 0, :], o.f, o.bonds_k(0)[0]))
+        o.close()
+    (ta, fa, ba), (tb, fb, bb) = runs
+    np.testing.assert_array_equal(tb[:, 1], ta[:, 1] + k)
+    rest = [c for c in range(ta.shape[1]) if c != 1]
+    np.testing.assert_array_equal(tb[:, rest], ta[:, rest])
+    np.testing.assert_array_equal(fb, np.roll(fa, k, axis=2))
+    np.testing.assert_array_equal(bb, ba)
+    assert ba.sum() > 0
+
+
 def test_relabelling_permutes_trajectories(orc):
     """Listing the same two particles in the other order gives the same motions, swapped."""
     w = two_particles(nx=160, x0=30.0, dx=80.0, shape=1, theta1=0.4)
