@@ -136,6 +136,8 @@ void fill_particle_args(ParticleArgs<T>& a, const LatticeGeom& g, uint64_t seed,
 
 // Constants of a lattice sweep (relaxation, forcing, storage scale, wall speed).
 SweepArgs make_sweep_args(const LatticeGeom& g);
+// Whether the lattice sweep of step `step` takes its tiles in reverse order (see lbib_host.cpp).
+bool reverse_sweep(const LatticeGeom& g, int64_t step);
 
 // The message lbib_last_error(NULL) returns on this thread (calls that fail before they
 // have a handle).

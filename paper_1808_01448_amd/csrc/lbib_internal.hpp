@@ -262,7 +262,7 @@ struct HandoverArgs {
 };
 template <typename T>
 hipError_t launch_sweep_overlap(const T* fin, T* fout, const SweepArgs& a, const HandoverArgs& c, bool pull,
-                                hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+                                hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr, bool rev = false);
 // Sweep of a step with several particles: node forces from every particle whose box reaches
 // the node (listed by the tile mask mcur, summed in particle order); each block also clears
 // its tile's word of mnext, the mask of the next step.
@@ -272,10 +272,11 @@ hipError_t launch_sweep_multi(const T* fin, T* fout, const SweepArgs& a, const u
                               hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 // Sweep of every node, with the spread force of desc / tile when desc != NULL.  t0 / t1
 // (optional) receive the kernel's own start and end times.  pull selects the layout of the
-// population buffers (pop_index in lbib_device.hpp).
+// population buffers (pop_index in lbib_device.hpp); rev, the reverse tile order
+// (reverse_sweep).
 template <typename T>
 hipError_t launch_sweep(const T* fin, T* fout, const SweepArgs& a, const TileDesc* desc, const int64_t* tile, bool pull,
-                        hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+                        hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr, bool rev = false);
 // LDS of the particle phase.  particle_lds_aux_bytes: the node mask, its prefix counts, the
 // fill queues and the overlap list, which must not exceed 158 KB.  particle_lds_bytes: that
 // plus the node fields of every node of a box of box_cap nodes, or 0 when this exceeds

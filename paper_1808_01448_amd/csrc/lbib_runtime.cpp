@@ -213,7 +213,6 @@ hipError_t ensure_sweep_stream(lbib_sim* h)
     return hipStreamCreateWithFlags(&h->stream3, hipStreamNonBlocking);
 }
 
-// Bytes one lattice sweep moves (every population read and written once).
 // One time step is the particle phase then the lattice sweep.  Serial schedule: both on the
 // caller's stream.  Overlapped schedule (when the previous step has predicted this step's
 // box): the particle phase runs on the second stream while the caller's stream sweeps the
@@ -293,7 +292,8 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
             h->zone_valid = false;
         } else if (h->parts.empty()) {
             const EvPair e0 = timing_events(h, 0);
-            HIPCHK(h, launch_sweep<T>(fin, fout, sa, nullptr, nullptr, h->g.pull, h->stream, e0.t0, e0.t1));
+            HIPCHK(h, launch_sweep<T>(fin, fout, sa, nullptr, nullptr, h->g.pull, h->stream, e0.t0, e0.t1,
+                                      reverse_sweep(h->g, h->steps)));
         } else {
             Particle& p = h->parts[0];
             ParticleArgs<T> pa = particle_args<T>(h, p);
@@ -330,7 +330,8 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
                 const EvPair e1 = timing_events(h, 1);
                 HIPCHK(h, launch_particle<T>(pa, h->stream, e1.t0, e1.t1));
                 const EvPair e0 = timing_events(h, 0);
-                HIPCHK(h, launch_sweep<T>(fin, fout, sa, p.d_desc, p.d_tile, h->g.pull, h->stream, e0.t0, e0.t1));
+                HIPCHK(h, launch_sweep<T>(fin, fout, sa, p.d_desc, p.d_tile, h->g.pull, h->stream, e0.t0, e0.t1,
+                                          reverse_sweep(h->g, h->steps)));
                 h->zone_valid = true;
                 h->prev_overlapped = false;
             } else {
@@ -352,7 +353,8 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
                 const HandoverArgs ha{p.d_count + 2 + 2 * (h->steps & 3), (uint32_t)(prev & 0xffffu), p.d_desc, p.d_tile,
                                       p.d_count, prev + 1, p.d_count + 1, h->d_flags, nzone};
                 const EvPair e0 = timing_events(h, 0);
-                HIPCHK(h, launch_sweep_overlap<T>(fin, fout, sa, ha, h->g.pull, h->stream3, e0.t0, e0.t1));
+                HIPCHK(h, launch_sweep_overlap<T>(fin, fout, sa, ha, h->g.pull, h->stream3, e0.t0, e0.t1,
+                                                  reverse_sweep(h->g, h->steps)));
                 h->zdone_expected += (unsigned long long)nzone;
                 h->prev_overlapped = true;
                 joined = false;

@@ -95,7 +95,8 @@ lbib_status enqueue_solve(const LatticeGeom& g, uint64_t seed, Particle& p, int6
         pa.zone_words = p.d_count + 2 + 2 * ((step + 1) & 3);
         pa.zone_tag = (uint32_t)((step + 1) & 0xffff);
         SCHK(launch_particle<T>(pa, s));
-        SCHK(launch_sweep<T>((const T*)fA, (T*)fB, sa, p.d_desc, p.d_tile, g.pull, s));
+        SCHK(launch_sweep<T>((const T*)fA, (T*)fB, sa, p.d_desc, p.d_tile, g.pull, s, nullptr, nullptr,
+                             reverse_sweep(g, step)));
         std::swap(fA, fB);
     }
     return LBIB_OK;

@@ -122,15 +122,19 @@ __device__ __forceinline__ void box_force(const TileDesc& d, const int64_t* __re
     }
 }
 
-// Every node; the particle's spread force from desc / tile when desc != NULL.
+// Every node; the particle's spread force from desc / tile when desc != NULL.  rev: the tiles
+// in reverse order (odd steps of a lattice well beyond the last-level cache, so that the first
+// tiles read are the last the previous sweep wrote).
 template <typename T, bool PULL>
 __global__ __launch_bounds__(256) void sweep_kernel(const T* __restrict__ fin, T* __restrict__ fout, SweepArgs a,
                                                     const TileDesc* __restrict__ desc,
-                                                    const int64_t* __restrict__ tile, FastDiv gx, int nblocks)
+                                                    const int64_t* __restrict__ tile, FastDiv gx, int nblocks,
+                                                    int rev)
 {
     using TL = Tile<PULL>;
     static_assert(TL::W >= 64, "the sweep's addressing takes each wave's nodes from one row");
-    const int b = xcd_tile(blockIdx.x, nblocks);
+    int b = xcd_tile(blockIdx.x, nblocks);
+    if (rev) b = nblocks - 1 - b;
     const int ty = (int)fdiv((uint32_t)b, gx), tx = b - ty * (int)gx.d;
     const int i = tx * TL::W + (int)threadIdx.x % TL::W;
     const int j = ty * TL::H + (int)threadIdx.x / TL::W;
@@ -145,20 +149,22 @@ __global__ __launch_bounds__(256) void sweep_kernel(const T* __restrict__ fin, T
 // are dispatched first and wait for the particle's force beside the rest of the sweep rather
 // than at its end.  The others sweep the tiles outside it; each loads its populations before
 // it learns the box (no launch writes fin during the sweep), so that wait overlaps the loads.
+// rev: the other workgroups' tiles in reverse order, as in sweep_kernel.
 // At most 64 VGPRs (eight waves per SIMD); for the f - f_eq storages, whose loads of 27
 // moments are then issued in small groups with a wait after each, at most 80 (six or seven).
 template <typename T, bool PULL>
 __global__ __launch_bounds__(256, St<T>::neq ? 7 : 8) void sweep_overlap_kernel(const T* __restrict__ fin,
                                                                                  T* __restrict__ fout, SweepArgs a,
                                                                                  HandoverArgs c, FastDiv gxd,
-                                                                                 int nblocks)
+                                                                                 int nblocks, int rev)
 {
     using TL = Tile<PULL>;
     __shared__ ZoneTiles zs;
     __shared__ TileDesc ds;
     const int gx = (int)gxd.d;
     if ((int)blockIdx.x >= c.nzone) {
-        const int b = xcd_tile((int)blockIdx.x - c.nzone, nblocks);
+        int b = xcd_tile((int)blockIdx.x - c.nzone, nblocks);
+        if (rev) b = nblocks - 1 - b;
         const int ty = (int)fdiv((uint32_t)b, gxd), tx = b - ty * gx;
         const int i = tx * TL::W + (int)threadIdx.x % TL::W, j = ty * TL::H + (int)threadIdx.x / TL::W;
         const bool in = i < a.nx && j < a.ny;
@@ -254,37 +260,37 @@ hipError_t launch_sweep_multi(const T* fin, T* fout, const SweepArgs& a, const u
 
 template <typename T>
 hipError_t launch_sweep(const T* fin, T* fout, const SweepArgs& a, const TileDesc* desc, const int64_t* tile, bool pull,
-                        hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
+                        hipStream_t stream, hipEvent_t t0, hipEvent_t t1, bool rev)
 {
     if (pull) {
         using TL = Tile<true>;
         const int gx = (a.nx + TL::W - 1) / TL::W, nb = gx * ((a.ny + TL::H - 1) / TL::H);
         hipExtLaunchKernelGGL(sweep_kernel<T, true>, dim3(nb), dim3(256), 0u, stream, t0, t1, 0u, fin, fout, a, desc,
-                              tile, make_fastdiv(gx), nb);
+                              tile, make_fastdiv(gx), nb, (int)rev);
     } else {
         using TL = Tile<false>;
         const int gx = (a.nx + TL::W - 1) / TL::W, nb = gx * ((a.ny + TL::H - 1) / TL::H);
         hipExtLaunchKernelGGL(sweep_kernel<T, false>, dim3(nb), dim3(256), 0u, stream, t0, t1, 0u, fin, fout, a, desc,
-                              tile, make_fastdiv(gx), nb);
+                              tile, make_fastdiv(gx), nb, (int)rev);
     }
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_sweep_overlap(const T* fin, T* fout, const SweepArgs& a, const HandoverArgs& c, bool pull,
-                                hipStream_t stream, hipEvent_t t0, hipEvent_t t1)
+                                hipStream_t stream, hipEvent_t t0, hipEvent_t t1, bool rev)
 {
     if (c.nzone < 8 || c.nzone > 64 || c.nzone % 8) return hipErrorInvalidValue;
     if (pull) {
         using TL = Tile<true>;
         const int gx = (a.nx + TL::W - 1) / TL::W, nb = gx * ((a.ny + TL::H - 1) / TL::H);
         hipExtLaunchKernelGGL(sweep_overlap_kernel<T, true>, dim3(nb + c.nzone), dim3(256), 0u, stream, t0, t1, 0u, fin,
-                              fout, a, c, make_fastdiv(gx), nb);
+                              fout, a, c, make_fastdiv(gx), nb, (int)rev);
     } else {
         using TL = Tile<false>;
         const int gx = (a.nx + TL::W - 1) / TL::W, nb = gx * ((a.ny + TL::H - 1) / TL::H);
         hipExtLaunchKernelGGL(sweep_overlap_kernel<T, false>, dim3(nb + c.nzone), dim3(256), 0u, stream, t0, t1, 0u,
-                              fin, fout, a, c, make_fastdiv(gx), nb);
+                              fin, fout, a, c, make_fastdiv(gx), nb, (int)rev);
     }
     return hipGetLastError();
 }
@@ -293,9 +299,9 @@ hipError_t launch_sweep_overlap(const T* fin, T* fout, const SweepArgs& a, const
     template hipError_t launch_init<T>(T*, int32_t, int32_t, int32_t, int64_t, double, double, bool, int32_t,     \
                                        hipStream_t);                                                             \
     template hipError_t launch_sweep<T>(const T*, T*, const SweepArgs&, const TileDesc*, const int64_t*, bool,     \
-                                        hipStream_t, hipEvent_t, hipEvent_t);                                     \
+                                        hipStream_t, hipEvent_t, hipEvent_t, bool);                               \
     template hipError_t launch_sweep_overlap<T>(const T*, T*, const SweepArgs&, const HandoverArgs&, bool,         \
-                                                hipStream_t, hipEvent_t, hipEvent_t);                             \
+                                                hipStream_t, hipEvent_t, hipEvent_t, bool);                       \
     template hipError_t launch_sweep_multi<T>(const T*, T*, const SweepArgs&, const unsigned long long*,           \
                                               unsigned long long*, const PartRef*, bool, hipStream_t, hipEvent_t,  \
                                               hipEvent_t);
