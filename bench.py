@@ -174,6 +174,9 @@ def beyond_cache_leg(steps: int, stream) -> dict:
                          "copy_same_bytes_gbs": round(copy_gbs, 1),
                          "frac_of_measured_copy": round(achieved / copy_gbs, 4) if copy_gbs > 0 else None},
             "particle_launch_avg_us": round(part_ms * 1e3, 2),
+            # the library's rule (both buffers at least twice the last-level cache, f - w storages)
+            "tile_order": ("the same every step" if prec.endswith("_neq")
+                           else "reversed on odd steps: a sweep first reads the tiles the previous one wrote last"),
         }
         log(f"bench: beyond cache {prec}: sweep {sweep_ms * 1e3:.1f} us = {achieved:.0f} GB/s "
             f"({achieved / HBM_PEAK_GBS:.3f} of 8 TB/s, {achieved / copy_gbs:.3f} of the copy {copy_gbs:.0f} GB/s)")
