@@ -239,7 +239,10 @@ lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size);
  * device-side wait is bounded: one that exceeds about a second fails the simulation with
  * LBIB_E_NUMERIC.  Serial (mode 0), always on the first step after lbib_init / lbib_load /
  * lbib_write_particle, and where CU masking is unavailable or ny >= 2^23: the particle phase
- * and a sweep of all nodes run one after the other on the handle's stream.  Mode 2 (the
+ * and a sweep of all nodes run one after the other on the handle's stream.  The overlapped
+ * schedule's sweep stream is CU-masked, which takes a hardware queue of its own: at most 8
+ * simulations per device hold one at a time, and the others run the serial schedule until
+ * one of those is destroyed.  Mode 2 (the
  * default) overlaps wherever it can (the faster schedule at every lattice size measured).
  * Both schedules give bit-identical results. */
 /* Several particles in one lattice: the particle phase is split in two launches over all

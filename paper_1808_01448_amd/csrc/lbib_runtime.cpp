@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -41,6 +42,7 @@ struct lbib_sim {
     hipStream_t stream2 = nullptr;  // particle chain of the overlapped schedule
     hipStream_t stream3 = nullptr;  // its sweep: every CU but one (created at first use)
     bool masked = false;            // stream3 is CU-masked (the overlapped schedule needs it)
+    int masked_dev = -1;            // the device whose masked-stream count it holds
     unsigned long long plaunches = 0;  // single-particle launches since lbib_init (hand-over counts)
     unsigned long long zdone_expected = 0;  // zone workgroups of the overlapped sweeps enqueued
     bool prev_overlapped = false;           // the last step enqueued ran overlapped
@@ -82,6 +84,29 @@ struct lbib_sim {
 };
 
 namespace {
+
+// CU-masked streams held by live simulations, per device.  Each takes a hardware queue of its
+// own, and the runtime does not refuse one too many but faults (a probe created 224 in one
+// process, then the next creation crashed inside the runtime), so at most kMaxMaskedStreams
+// simulations per device hold one; the others run the serial schedule (the same results).
+constexpr int kMaxMaskedStreams = 8;
+constexpr int kMaxDevices = 64;
+std::mutex g_masked_mu;
+int g_masked[kMaxDevices] = {};
+
+bool take_masked_stream(int dev)
+{
+    std::lock_guard<std::mutex> lock(g_masked_mu);
+    if (dev < 0 || dev >= kMaxDevices || g_masked[dev] >= kMaxMaskedStreams) return false;
+    ++g_masked[dev];
+    return true;
+}
+
+void give_masked_stream(int dev)
+{
+    std::lock_guard<std::mutex> lock(g_masked_mu);
+    if (dev >= 0 && dev < kMaxDevices && g_masked[dev] > 0) --g_masked[dev];
+}
 
 thread_local std::string g_null_err;
 
@@ -133,6 +158,8 @@ void free_all(lbib_sim* h)
     if (h->stream2) (void)hipStreamDestroy(h->stream2);
     if (h->stream3) (void)hipStreamDestroy(h->stream3);
     h->stream2 = h->stream3 = nullptr;
+    if (h->masked) give_masked_stream(h->masked_dev);
+    h->masked = false;
 }
 
 template <typename T>
@@ -199,17 +226,20 @@ hipError_t ensure_sweep_stream(lbib_sim* h)
     hipDeviceProp_t prop;
     e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
-    if (e == hipSuccess && prop.multiProcessorCount > 64) {
+    if (e == hipSuccess && prop.multiProcessorCount > 64 && take_masked_stream(dev)) {
         const int n = prop.multiProcessorCount;
         std::vector<uint32_t> mask((size_t)(n + 31) / 32, 0u);
         for (int cu = 1; cu < n; ++cu) mask[cu / 32] |= 1u << (cu % 32);
         if (hipExtStreamCreateWithCUMask(&h->stream3, (uint32_t)mask.size(), mask.data()) == hipSuccess) {
             h->masked = true;
+            h->masked_dev = dev;
             return hipSuccess;
         }
+        give_masked_stream(dev);
         (void)hipGetLastError();
     }
-    // no CU masking: the overlapped schedule stays off (the stream marks the attempt)
+    // no CU masking (or every masked stream of the device taken): the overlapped schedule
+    // stays off (the stream marks the attempt)
     return hipStreamCreateWithFlags(&h->stream3, hipStreamNonBlocking);
 }
 

@@ -476,6 +476,35 @@ def test_overlapped_schedule_switches_and_calls(L):
     s.close()
 
 
+def test_many_overlapped_simulations_in_one_process(L):
+    """240 simulations asking for the overlapped schedule in one process: each overlapped one
+    holds a CU-masked stream (a hardware queue of its own), and the runtime faults rather than
+    refuses once a process holds a few hundred, so the library gives masked streams to at most
+    8 simulations per device and runs the others serially.  Their steps enqueued alternately,
+    every simulation equals the serial run bit for bit; after they are destroyed, new
+    simulations take the freed masked streams."""
+    w = W.channel_small_binding("fp32")
+    w["lattice"].update(nx=64, ny=32)
+    w["particle"].update(xc=32.0, a_major=4.0, b_minor=4.0, n_markers=32)
+    steps = 6
+    ref = _serial_reference(L, w, steps)
+    for count in (240, 12):
+        sims = [L.Sim(w) for _ in range(count)]
+        for s in sims:
+            s.set_overlap(1)
+            s.trace_enable(steps)
+        for k in range(steps):
+            for s in sims:
+                s.step(1)
+        for s in sims:
+            s.sync()
+        say("many simulations", count)
+        for s in sims:
+            np.testing.assert_array_equal(s.trace(steps), ref[0])
+            np.testing.assert_array_equal(s.f, ref[1])
+            s.close()
+
+
 def test_two_overlapped_simulations_interleaved(L):
     """Two simulations in the overlapped schedule, their steps enqueued alternately so both
     run at once (their sweeps leave the same CU to their particle launches): each equals its
