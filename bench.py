@@ -283,8 +283,8 @@ def multi_leg(steps: int, err_steps: int, stream) -> dict:
 
     out = {"workload": "2048 x 512 channel, 32 particles (aspect ratio U[1,3], area 0.025 H^2, random angle, "
                        "boundary gaps >= 4 lu), Re 0.1, tau 0.8, ligand density and bond strength per particle",
-           "schedule": "chained split phase (the default): spread launch, then the sweep on the simulation's stream "
-                       "and the loads launch on a second stream beside it",
+           "schedule": "one-launch split phase (the default): workgroups claim their particles, spread, meet and "
+                       "evaluate the loads; then the sweep",
            "unit": "MLUPS", "steps_timed": steps, "error_steps": err_steps,
            "oracle_seconds": round(t_orc, 2), "storages": {}}
     for prec in ("fp32", "fp16", "bf16", "fp16_neq", "bf16_neq"):
@@ -322,9 +322,9 @@ def multi_leg(steps: int, err_steps: int, stream) -> dict:
         log(f"bench: {prec}: {out['storages'][prec]['mlups']} MLUPS, velocity error {err['velocity']:.2e}")
     # the schedules of the split particle phase on the FP32 case (results are bit-identical)
     out["schedules_fp32"] = {}
-    for mode, name in ((2, "chained (default): loads launch beside the sweep, device hand-over"),
-                       (3, "serial: spread, loads, sweep in order on one stream"),
-                       (4, "one launch with a grid barrier (needs every workgroup resident; opt-in)")):
+    for mode, name in ((2, "one launch (default): particles claimed by their workgroups, no co-residency needed"),
+                       (1, "chained: loads launch beside the sweep, device hand-over"),
+                       (3, "serial: spread, loads, sweep in order on one stream")):
         s = lbib.Sim(W.with_precision(w, "fp32"), stream=stream)
         s.set_overlap(mode)
         s.step(20)

@@ -245,25 +245,28 @@ lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size);
  * one of those is destroyed.  Mode 2 (the
  * default) overlaps wherever it can (the faster schedule at every lattice size measured).
  * Both schedules give bit-identical results. */
-/* Several particles in one lattice: the particle phase is split in two launches over all
+/* Several particles in one lattice: the particle phase is split in two halves over all
  * particles -- first every particle stages its box and spreads its marker forces, then every
  * particle evaluates its probe loads (with the spread force of every particle that reaches a
  * probe node, summed in particle order), bonds and rigid-body update -- and the sweep adds at
- * each node the force of every particle whose box reaches it, in particle order.  Modes 1 and
- * 2 (the default) chain them over two streams: the spread launch and the sweep run on the
- * handle's stream, the loads launch on a second stream beside the sweep, and the streams hand
- * over through counters in device memory (a loads launch waits for its step's spreads, the
- * next spread launch for those loads); no launch waits for a later one and no workgroup for
- * another of its own launch, so other work on the device only delays it.  Modes 0 and 3 run
- * the two launches and the sweep in order on the handle's stream.  Mode 4 runs both halves
- * as one launch whose workgroups (one per particle, each taking a CU) meet at a grid barrier
- * between the spread and the loads: it is correct only while all of them are resident at
- * once, which holds on an otherwise idle device; beside other streams' work the barrier's
- * wait can time out (after about a second) and fail the simulation with LBIB_E_NUMERIC, so it
- * is never chosen by default.  For a single particle, mode 3 runs the split phase and mode 4
- * equals modes 0-2.  All modes give the same results bit for bit.  Kernel timing reports the
- * spread launch (or the one launch) as kernel 1 and the loads launch as kernel 2 (in the
- * chained schedule its time includes its wait for the spreads). */
+ * each node the force of every particle whose box reaches it, in particle order.  Modes 2 (the
+ * default) and 4 run both halves as one launch: workgroup b claims particle b, stages the
+ * union of its marker and probe supports once, spreads, and waits for every particle's spread
+ * before its loads; it waits only while every particle is claimed (a claimer is running), and
+ * a workgroup that finds a particle unclaimed (its workgroup not resident, e.g. beside other
+ * streams' work) claims and spreads the unclaimed particles itself and then runs the loads
+ * half of each particle it holds, so the launch needs no co-residency.  Mode 5 runs that
+ * launch on a single workgroup, which takes this path every step (slow; for testing).  Mode 1
+ * chains two launches over two streams: the spread launch and the sweep run on the handle's
+ * stream, the loads launch on a second stream beside the sweep, and the streams hand over
+ * through counters in device memory (a loads launch waits for its step's spreads, the next
+ * spread launch for those loads); no launch waits for a later one and no workgroup for another
+ * of its own launch.  Modes 0 and 3 run the two launches and the sweep in order on the handle's
+ * stream.  Every wait on the device is bounded: past about a second it fails the simulation
+ * with LBIB_E_NUMERIC.  For a single particle, mode 3 runs the split phase and modes 4 and 5
+ * equal mode 0.  All modes give the same results bit for bit.  Kernel timing reports the spread
+ * launch (or the one launch) as kernel 1 and the loads launch as kernel 2 (in the chained
+ * schedule its time includes its wait for the spreads). */
 lbib_status lbib_set_overlap(lbib_handle h, int32_t mode);
 
 /* Storage layout of the population buffers, chosen before lbib_init: mode 0 push (the

@@ -307,15 +307,16 @@ template <typename T>
 hipError_t launch_particle_split(const ParticleArgs<T>* args, int32_t n, const T* f, unsigned long long* pmask,
                                  int32_t mode, int32_t max_nl, size_t lds, hipStream_t stream,
                                  hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr, const SplitChain& ch = SplitChain{});
-// The same phase as one launch: every workgroup spreads, then all meet at a grid barrier
-// (bar: a counter that only grows; this launch waits for it to reach target = its previous
-// value + n), then each evaluates its loads, bonds and update.  The n <= 64 workgroups
-// (one CU each) must be resident together: the caller launches it only on a stream whose
-// previous work has finished and the barrier's wait is bounded.
+// The same phase as one launch of `workgroups` (1..n) workgroups for the n particles: each
+// claims a particle and spreads it, they meet before the loads, bonds and update, and a
+// workgroup that finds a particle unclaimed there (its workgroup not resident) does that
+// particle's work itself, so the launch assumes no co-residency.  bar: four counters that
+// only grow, [0] spreads and [3] claims, each at target - n before the launch and at target
+// after it.  Fewer workgroups than particles make every launch take that path.
 template <typename T>
-hipError_t launch_particle_fused(const ParticleArgs<T>* args, int32_t n, const T* f, unsigned long long* pmask,
-                                 int32_t max_nl, size_t lds, unsigned long long* bar, unsigned long long target,
-                                 hipStream_t stream);
+hipError_t launch_particle_fused(const ParticleArgs<T>* args, int32_t n, int32_t workgroups, const T* f,
+                                 unsigned long long* pmask, int32_t max_nl, size_t lds, unsigned long long* bar,
+                                 unsigned long long target, hipStream_t stream);
 
 // A pool of independent simulations stepped together (one launch per kernel per step).
 // The particle launch runs member active[b] in workgroup b and copies the member's box

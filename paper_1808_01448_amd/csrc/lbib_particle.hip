@@ -588,23 +588,34 @@ __device__ __forceinline__ void total_forces(const ParticleArgs<T>& a, const Nod
     }
 }
 
-// Barrier of every workgroup of the one-launch split phase.  The workgroup barrier completes
-// every wave's stores into the L2 of its XCD; one thread then releases them at device scope
-// (writing back the L2), counts in, and polls (sleeping between polls) until the count
-// reaches the launch's target; its device-scope acquire invalidates the CU's caches, which
-// every wave of the workgroup shares, before the second workgroup barrier lets them read.
-// The workgroups are co-resident by size: at most 64 of them, one per CU (their LDS), and
-// the previous launch on the stream has finished.  The wait gives up after kSpinLimit polls
-// and raises FLAG_SYNC, so every workgroup always finishes.
+// Meeting point of the one-launch split phase, which assumes nothing about which of its
+// workgroups are resident together.  Workgroups claim particles (claim_particle), which the
+// counter at ctr + kClaimWord counts; here the workgroup barrier completes every wave's stores,
+// one thread releases them at device scope and counts this spread in at *ctr, then polls until
+// every spread of the launch has counted in (target).  It waits only while every particle is
+// claimed: a claimer is running, so its spread will count in.  While a particle is unclaimed
+// (its workgroup may be waiting for a CU this one holds) it returns false at once, and the
+// caller spreads the unclaimed particles itself.  Its device-scope acquire invalidates the
+// CU's caches, which every wave of the workgroup shares, before the second workgroup barrier
+// lets them read.  The wait gives up after kSpinLimit polls and raises FLAG_SYNC, so every
+// workgroup always finishes.
 constexpr unsigned kSpinLimit = 1u << 22;
+constexpr int kClaimWord = 3;   // claims counted in this launch (after the chained schedule's two words)
+constexpr int kClaimWords = 4;  // then one claim word per particle
 
-__device__ __forceinline__ void grid_barrier(unsigned long long* ctr, unsigned long long target, int& flags)
+__device__ __forceinline__ bool claimed_barrier(unsigned long long* ctr, unsigned long long target, int& flags)
 {
+    __shared__ int go;
     __syncthreads();
     if (threadIdx.x == 0) {
         __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = 1;
         unsigned polls = 0;
         while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(ctr + kClaimWord, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                ok = 0;
+                break;
+            }
             if (++polls > kSpinLimit) {
                 flags |= FLAG_SYNC;
                 break;
@@ -612,8 +623,24 @@ __device__ __forceinline__ void grid_barrier(unsigned long long* ctr, unsigned l
             __builtin_amdgcn_s_sleep(1);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        go = ok;
     }
     __syncthreads();
+    return go != 0;
+}
+
+// Claims particle k for this launch: its claim word (ctr + kClaimWords + k) holds the number
+// of the last launch that claimed it, so an exchange with this launch's number claims it at
+// most once per launch without a reset; the one that claims it also counts it at
+// ctr + kClaimWord.  Different particles' claims touch different words, so workgroups claiming
+// their own particles at once do not contend.
+__device__ __forceinline__ bool claim_particle(unsigned long long* ctr, int k, unsigned long long launch)
+{
+    const unsigned long long was =
+        __hip_atomic_exchange(ctr + kClaimWords + k, launch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (was == launch) return false;
+    __hip_atomic_fetch_add(ctr + kClaimWord, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
 }
 
 // Set this particle's bit in the step's mask of every 64 x 4 tile its box reaches.
@@ -652,7 +679,7 @@ struct PhaseCtx {
 // in LDS, else in the global scratch (plain loads and stores ordered by the workgroup
 // barriers, device-scope atomics for the force).
 template <typename T, int MPT, bool LDS, int MODE>
-__device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const PhaseCtx<MPT>& c, const NodeView& B,
+__device__ __forceinline__ bool phase_body(const ParticleArgs<T>& a, const PhaseCtx<MPT>& c, const NodeView& B,
                                            OvEntry* ov, int nov, double (*shd)[NW], int (*shi)[NW])
 {
     const int tid = threadIdx.x;
@@ -815,12 +842,19 @@ __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const Phase
         const int op[1] = {1};
         block_int<1>(v, op, shi);
         if (tid == 0 && v[0]) atomicOr(a.flags, v[0]);
-        return;
+        return true;
     }
     if (MODE == 4) {
         // every particle's list, index, box and tile bits of this step are written: meet,
         // then read the other boxes and sum the total spread force at the marked nodes
-        grid_barrier(a.bar, a.bar_target, flags);
+        if (!claimed_barrier(a.bar, a.bar_target, flags)) {
+            // a particle is unclaimed: publish this spread's flags, leave the loads to the caller
+            int v[1] = {flags};
+            const int op[1] = {1};
+            block_int<1>(v, op, shi);
+            if (tid == 0 && v[0]) atomicOr(a.flags, v[0]);
+            return false;
+        }
         PartRef rq{};
         TileDesc dq{};
         if (tid < a.nparts) {
@@ -1045,12 +1079,13 @@ __device__ __forceinline__ void phase_body(const ParticleArgs<T>& a, const Phase
             }
         }
     }
+    return true;
 }
 
 // Lays out the node fields and the node map of the marked nodes from base (LDS: dynamic LDS,
 // else the global scratch), writes the map and runs the rest of the phase.
 template <typename T, int MPT, bool LDS, int MODE>
-__device__ __forceinline__ void phase_rest(const ParticleArgs<T>& a, PhaseCtx<MPT>& c, double* base, OvEntry* ov,
+__device__ __forceinline__ bool phase_rest(const ParticleArgs<T>& a, PhaseCtx<MPT>& c, double* base, OvEntry* ov,
                                            int nov, double (*shd)[NW], int (*shi)[NW])
 {
     const int m = c.nmarked;
@@ -1065,7 +1100,7 @@ __device__ __forceinline__ void phase_rest(const ParticleArgs<T>& a, PhaseCtx<MP
     c.nodes = nodes;
     write_node_map(c.mask, c.pre, (c.nbox + 31) / 32, nodes);
     __syncthreads();
-    phase_body<T, MPT, LDS, MODE>(a, c, B, ov, nov, shd, shi);
+    return phase_body<T, MPT, LDS, MODE>(a, c, B, ov, nov, shd, shi);
 }
 
 // One particle's phase, run by one workgroup.  MPT markers per thread (nl <= MPT * PB);
@@ -1076,11 +1111,12 @@ __device__ __forceinline__ void phase_rest(const ParticleArgs<T>& a, PhaseCtx<MP
 // particle's tile and marks the step's tile mask; MODE 2 stages the probe supports with the
 // total spread force there and evaluates the probe loads, the bonds, the wall force and the
 // rigid-body update.
+// Returns false only in MODE 4, when the phase stopped after its spread (claimed_barrier).
+// shd, shi: the workgroup's reduction scratch in LDS.
 template <typename T, int MPT, int MODE>
-__device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, char* lds, uint32_t lds_bytes)
+__device__ __forceinline__ bool particle_phase(const ParticleArgs<T>& a, char* lds, uint32_t lds_bytes,
+                                               double (*shd)[NW], int (*shi)[NW])
 {
-    __shared__ double shd[8][NW];
-    __shared__ int shi[8][NW];
     const int tid = threadIdx.x;
     OvEntry* ov = (OvEntry*)lds;
     const int wcap = (a.box_cap + 31) / 32;
@@ -1191,10 +1227,16 @@ __device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, char* l
         c.nmarked = 0;
         if (tid == 0) c.flags |= FLAG_TILE;
     }
-    if (fits || !a.box_global)
-        phase_rest<T, MPT, true, MODE>(a, c, fields, ov, nov, shd, shi);
-    else
-        phase_rest<T, MPT, false, MODE>(a, c, a.box_global, ov, nov, shd, shi);
+    if (fits || !a.box_global) return phase_rest<T, MPT, true, MODE>(a, c, fields, ov, nov, shd, shi);
+    return phase_rest<T, MPT, false, MODE>(a, c, a.box_global, ov, nov, shd, shi);
+}
+
+template <typename T, int MPT, int MODE>
+__device__ __forceinline__ void particle_phase(const ParticleArgs<T>& a, char* lds, uint32_t lds_bytes)
+{
+    __shared__ double shd[8][NW];
+    __shared__ int shi[8][NW];
+    (void)particle_phase<T, MPT, MODE>(a, lds, lds_bytes, shd, shi);
 }
 
 template <typename T, int MPT>
@@ -1287,44 +1329,97 @@ hipError_t launch_particle_split(const ParticleArgs<T>* args, int32_t n, const T
     return hipErrorInvalidValue;
 }
 
-// The split phase as one launch (MODE 4): workgroup b runs particle b; the workgroups meet
-// at a grid barrier between the spread and the loads.
+// One particle's phase (MODE 1 or 2) on the one-launch phase's fallback path, out of line so
+// that its registers do not weigh on the common path.
+template <typename T, int MPT, int MODE>
+__device__ __noinline__ void fallback_phase(const ParticleArgs<T>* args, int k, const T* f, unsigned long long* pmask,
+                                            uint32_t lds_bytes, double (*shd)[NW], int (*shi)[NW])
+{
+    extern __shared__ double lds_dyn[];
+    ParticleArgs<T> b = args[__builtin_amdgcn_readfirstlane(k)];
+    b.f = f;
+    b.pmask = pmask;
+    (void)particle_phase<T, MPT, MODE>(b, (char*)lds_dyn, lds_bytes, shd, shi);
+}
+
+// The split phase as one launch (MODE 4), assuming nothing about which of its workgroups are
+// resident together.  Workgroup b claims particle b (claim_particle), stages the union of its
+// marker and probe supports once, spreads, and meets the others at claimed_barrier before the
+// loads.  One that starts after its particle was claimed by another has nothing to do.  One
+// that finds a particle unclaimed at the barrier (its workgroup not started, perhaps waiting
+// for a CU this one holds) claims and spreads every particle still unclaimed (MODE 1), waits
+// until every spread has counted in, and runs the loads half (MODE 2) of each particle it
+// holds, its own first: every wait is then on running workgroups.  A launch with fewer
+// workgroups than particles takes that path.  ctr: [0] spreads counted in and [kClaimWord]
+// claims counted, both at target - np before the launch and at target after it; from
+// [kClaimWords], a claim word per particle (claim_particle); launch: this launch's number.
 template <typename T, int MPT>
 __global__ __launch_bounds__(PB) void fused_particle_kernel(const ParticleArgs<T>* __restrict__ args,
                                                             const T* __restrict__ f,
                                                             unsigned long long* __restrict__ pmask, uint32_t lds_bytes,
-                                                            unsigned long long* bar, unsigned long long target)
+                                                            unsigned long long* ctr, unsigned long long target, int np,
+                                                            unsigned long long launch)
 {
     extern __shared__ double lds_dyn[];
-    ParticleArgs<T> a = args[blockIdx.x];
-    a.f = f;
-    a.pmask = pmask;
-    a.bar = bar;
-    a.bar_target = target;
-    particle_phase<T, MPT, 4>(a, (char*)lds_dyn, lds_bytes);
+    __shared__ double shd[8][NW];
+    __shared__ int shi[8][NW];
+    __shared__ int took;
+    __shared__ int held[kMaxParticles];
+    const int p = (int)blockIdx.x;
+    if (threadIdx.x == 0) took = claim_particle(ctr, p, launch) ? 1 : 0;
+    __syncthreads();
+    if (!took) return;
+    {
+        ParticleArgs<T> a = args[p];
+        a.f = f;
+        a.pmask = pmask;
+        a.bar = ctr;
+        a.bar_target = target;
+        if (particle_phase<T, MPT, 4>(a, (char*)lds_dyn, lds_bytes, shd, shi)) return;
+    }
+    int nheld = 0;
+    for (int q = 0; q < np; ++q) {
+        __syncthreads();
+        if (threadIdx.x == 0)
+            took = __hip_atomic_load(ctr + kClaimWords + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != launch &&
+                   claim_particle(ctr, q, launch);
+        __syncthreads();
+        if (!took) continue;
+        fallback_phase<T, MPT, 1>(args, q, f, pmask, lds_bytes, shd, shi);
+        chain_publish<false>(ctr);
+        if (threadIdx.x == 0) held[nheld] = q;
+        ++nheld;
+    }
+    chain_wait(ctr, target, args[p].flags);
+    for (int k = -1; k < nheld; ++k) {
+        __syncthreads();
+        fallback_phase<T, MPT, 2>(args, k < 0 ? p : held[k], f, pmask, lds_bytes, shd, shi);
+    }
 }
 
 template <typename T, int MPT>
-hipError_t launch_fused_mpt(const ParticleArgs<T>* args, int32_t n, const T* f, unsigned long long* pmask, size_t lds,
-                            unsigned long long* bar, unsigned long long target, hipStream_t stream)
+hipError_t launch_fused_mpt(const ParticleArgs<T>* args, int32_t n, int32_t wg, const T* f, unsigned long long* pmask,
+                            size_t lds, unsigned long long* bar, unsigned long long target, hipStream_t stream)
 {
     static bool attr = false;
     hipError_t e = allow_max_lds(fused_particle_kernel<T, MPT>, attr);
     if (e != hipSuccess) return e;
-    hipExtLaunchKernelGGL(fused_particle_kernel<T, MPT>, dim3(n), dim3(PB), (uint32_t)lds, stream, nullptr, nullptr, 0u,
-                          args, f, pmask, (uint32_t)lds, bar, target);
+    hipExtLaunchKernelGGL(fused_particle_kernel<T, MPT>, dim3(wg), dim3(PB), (uint32_t)lds, stream, nullptr, nullptr,
+                          0u, args, f, pmask, (uint32_t)lds, bar, target, (int)n, target / (unsigned long long)n);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_particle_fused(const ParticleArgs<T>* args, int32_t n, const T* f, unsigned long long* pmask,
-                                 int32_t max_nl, size_t lds, unsigned long long* bar, unsigned long long target,
-                                 hipStream_t stream)
+hipError_t launch_particle_fused(const ParticleArgs<T>* args, int32_t n, int32_t workgroups, const T* f,
+                                 unsigned long long* pmask, int32_t max_nl, size_t lds, unsigned long long* bar,
+                                 unsigned long long target, hipStream_t stream)
 {
     if (n <= 0) return hipSuccess;
-    if (n > kMaxParticles || lds > kLdsMax || lds < kLdsHead || !bar) return hipErrorInvalidValue;
-    if (max_nl <= PB) return launch_fused_mpt<T, 1>(args, n, f, pmask, lds, bar, target, stream);
-    if (max_nl <= 2 * PB) return launch_fused_mpt<T, 2>(args, n, f, pmask, lds, bar, target, stream);
+    if (n > kMaxParticles || workgroups < 1 || workgroups > n || lds > kLdsMax || lds < kLdsHead || !bar ||
+        target < (unsigned long long)n)
+        return hipErrorInvalidValue;
+    if (max_nl <= PB) return launch_fused_mpt<T, 1>(args, n, workgroups, f, pmask, lds, bar, target, stream);
+    if (max_nl <= 2 * PB) return launch_fused_mpt<T, 2>(args, n, workgroups, f, pmask, lds, bar, target, stream);
     return hipErrorInvalidValue;
 }
 
@@ -1534,9 +1629,9 @@ hipError_t launch_copy(const float4* src, float4* dst, int64_t n, hipStream_t st
     template hipError_t launch_particle_split<T>(const ParticleArgs<T>*, int32_t, const T*, unsigned long long*, \
                                                  int32_t, int32_t, size_t, hipStream_t, hipEvent_t, hipEvent_t,  \
                                                  const SplitChain&);                                               \
-    template hipError_t launch_particle_fused<T>(const ParticleArgs<T>*, int32_t, const T*, unsigned long long*, \
-                                                 int32_t, size_t, unsigned long long*, unsigned long long,        \
-                                                 hipStream_t);
+    template hipError_t launch_particle_fused<T>(const ParticleArgs<T>*, int32_t, int32_t, const T*,             \
+                                                 unsigned long long*, int32_t, size_t, unsigned long long*,       \
+                                                 unsigned long long, hipStream_t);
 LBIB_PARTICLE_INSTANTIATE(double)
 LBIB_PARTICLE_INSTANTIATE(float)
 LBIB_PARTICLE_INSTANTIATE(half_t)

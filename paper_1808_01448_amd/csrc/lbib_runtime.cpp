@@ -273,7 +273,7 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
             unsigned long long* mnext = h->d_masks + (par ^ 1) * h->ntiles;
             const int32_t np = (int32_t)h->parts.size();
             const ParticleArgs<T>* args = (const ParticleArgs<T>*)h->d_args;
-            // chained schedule (modes 1 and 2): the loads launch of step n runs on the second
+            // chained schedule (mode 1): the loads launch of step n runs on the second
             // stream beside the sweep of step n; the two streams hand over on the device.  The
             // loads launch starts once every spread workgroup of step n has counted in; the
             // spread launch of step n+1 (after the sweep of step n on the caller's stream)
@@ -281,21 +281,25 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
             // and the particle state they write), so the sweep of step n+1, which overwrites
             // the populations the loads of step n read, follows it.  No launch waits for a
             // later one, and no workgroup waits for another of its own launch.
-            // Mode 4: both halves as one launch met at a grid barrier (no second launch or
-            // staging; it needs all its workgroups resident together, see lbib_set_overlap).
-            // Modes 0 and 3: the two launches and the sweep in order on the caller's stream.
-            const bool chain = h->overlap == 1 || h->overlap == 2;
+            // Modes 2 (the default) and 4: both halves as one launch whose workgroups claim the
+            // particles and meet between the halves (no second launch, and each workgroup
+            // stages its supports once); a workgroup that finds a particle unclaimed there does
+            // its work itself, so no co-residency is assumed.  Mode 5: the same launch on one
+            // workgroup, which then takes that path every step.  Modes 0 and 3: the two
+            // launches and the sweep in order on the caller's stream.
+            const bool chain = h->overlap == 1;
+            const bool one_launch = h->overlap == 2 || h->overlap == 4 || h->overlap == 5;
             if (chain && joined) {  // the second stream starts after the caller's work
                 HIPCHK(h, hipEventRecord(h->evA, h->stream));
                 HIPCHK(h, hipStreamWaitEvent(h->stream2, h->evA, 0));
                 joined = false;
             }
-            if (h->overlap == 4) {
+            if (one_launch) {
                 const EvPair e1 = timing_events(h, 1);
                 if (e1.t0) HIPCHK(h, hipEventRecord(e1.t0, h->stream));
                 const unsigned long long target = (unsigned long long)(h->bar_launches + 1) * (unsigned long long)np;
-                HIPCHK(h, launch_particle_fused<T>(args, np, fin, mcur, h->max_nl, h->lds_bytes, h->d_bar, target,
-                                                   h->stream));
+                HIPCHK(h, launch_particle_fused<T>(args, np, h->overlap == 5 ? 1 : np, fin, mcur, h->max_nl,
+                                                   h->lds_bytes, h->d_bar, target, h->stream));
                 h->bar_launches += 1;
                 if (e1.t1) HIPCHK(h, hipEventRecord(e1.t1, h->stream));
             } else {
@@ -624,9 +628,13 @@ lbib_status lbib_init(lbib_handle h)
             h->lds_bytes = std::max(h->lds_bytes, particle_launch_lds(p.box_cap));
         }
         const size_t args_bytes = np * std::max(sizeof(ParticleArgs<double>), sizeof(ParticleArgs<float>));
+        // monotonic counters: [0] spreads of the one-launch phase, [1] [2] the chained
+        // schedule's hand-over, [3] the one-launch phase's claims, then one claim word per
+        // particle (up to 64)
+        constexpr size_t kCounters = 4 + 64;
         h->bar_launches = h->spread_launches = h->loads_launches = 0;
-        if ((e = dalloc(&h->d_bar, 3)) != hipSuccess ||
-            (e = hipMemsetAsync(h->d_bar, 0, 3 * sizeof(unsigned long long), h->stream)) != hipSuccess)
+        if ((e = dalloc(&h->d_bar, kCounters)) != hipSuccess ||
+            (e = hipMemsetAsync(h->d_bar, 0, kCounters * sizeof(unsigned long long), h->stream)) != hipSuccess)
             return bail(e, "lbib_init: hand-over counters");
         if ((e = dalloc(&h->d_masks, (size_t)(2 * h->ntiles))) != hipSuccess ||
             (e = dalloc(&h->d_refs, np)) != hipSuccess || (e = hipMalloc(&h->d_args, args_bytes)) != hipSuccess)
@@ -959,7 +967,7 @@ lbib_status lbib_kernel_time(lbib_handle h, int32_t kernel, double* total_ms, in
 lbib_status lbib_set_overlap(lbib_handle h, int32_t mode)
 {
     if (!h) return fail(nullptr, LBIB_E_INVALID, "lbib_set_overlap: NULL handle");
-    if (mode < 0 || mode > 4) return fail(h, LBIB_E_INVALID, "lbib_set_overlap: mode must be 0, 1, 2, 3 or 4");
+    if (mode < 0 || mode > 5) return fail(h, LBIB_E_INVALID, "lbib_set_overlap: mode must be 0 to 5");
     h->overlap = mode;
     return LBIB_OK;
 }

@@ -386,9 +386,10 @@ class Sim:
 
     def set_overlap(self, mode):
         """0 / False: serial; 1 / True: overlapped (one particle) or chained split phase (several);
-        2: chosen by lattice size for one particle, chained for several (default); 3: the split
-        particle phase in order on one stream; 4: several particles' split phase as one launch
-        met at a grid barrier (needs an otherwise idle device)."""
+        2 (default): overlapped for one particle, the one-launch split phase for several; 3: the
+        split particle phase in order on one stream; 4: several particles' split phase as one
+        launch (workgroups claim their particles, no co-residency needed); 5: that launch on a
+        single workgroup (its fallback path every step; for testing)."""
         self._call(lib().lbib_set_overlap, int(mode))
 
     # -- timing --------------------------------------------------------------------------

@@ -187,13 +187,16 @@ def test_sixty_four_particles_against_oracle(L, orc):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp16"])
 def test_schedules_of_several_particles_agree(L, prec):
-    """Several particles: the chained schedule (default), the two launches in order on one
-    stream (mode 3) and the one launch met at a grid barrier (mode 4, on this otherwise idle
-    device) give the same particles, bonds and populations bit for bit, including neighbours
-    whose probe supports reach each other's spread."""
+    """Several particles: the chained schedule (mode 1), the two launches in order on one
+    stream (mode 3), the one launch whose workgroups claim the particles and meet before the
+    loads (mode 4) and the same launch on a single workgroup (mode 5: it claims the first
+    particle, finds the others unclaimed, spreads them itself and runs every particle's loads,
+    the path a launch takes when its workgroups are not resident together) give the same
+    particles, bonds and populations bit for bit, including neighbours whose probe supports
+    reach each other's spread."""
     w = W.multi_particle_channel(256, 96, 8, seed=6, precision=prec, area_frac=0.03)
     outs = []
-    for mode in (2, 3, 4):
+    for mode in (1, 3, 4, 5, 2):
         s, tr = gpu_run(L, w, 200, overlap=mode)
         outs.append(([s.particle(k) for k in range(8)], tr, s.f, [s.bonds(k)[0] for k in range(8)]))
         s.close()
@@ -205,12 +208,13 @@ def test_schedules_of_several_particles_agree(L, prec):
         np.testing.assert_array_equal(outs[0][2], o[2])
 
 
-def test_chained_simulations_interleaved_beside_other_work(L):
-    """Two simulations with several particles, each on its own stream in the default chained
-    schedule, enqueued alternately in calls of different lengths while a third stream keeps
-    the device busy with matrix products: each equals its serial run (mode 3) bit for bit.
-    Nothing in the chained schedule needs its workgroups resident together, so other work only
-    delays it."""
+@pytest.mark.parametrize("mode", [1, 4])
+def test_chained_simulations_interleaved_beside_other_work(L, mode):
+    """Two simulations with several particles, each on its own stream in the chained schedule
+    (mode 1) or the one-launch phase (mode 4), enqueued alternately in calls of different
+    lengths while a third stream keeps the device busy with matrix products: each equals its
+    serial run (mode 3) bit for bit.  Neither schedule needs its workgroups resident together,
+    so other work only delays it."""
     wa = W.multi_particle_channel(512, 128, 6, seed=8, precision="fp32", area_frac=0.02)
     wb = W.multi_particle_channel(384, 96, 5, seed=9, precision="fp16", area_frac=0.02)
     calls = [(17, 5), (3, 40), (60, 1), (20, 25)]
@@ -223,6 +227,7 @@ def test_chained_simulations_interleaved_beside_other_work(L):
     sa_, sb_, sx = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
     a, b = L.Sim(wa, stream=sa_), L.Sim(wb, stream=sb_)
     for sim, w, n in ((a, wa, n_a), (b, wb, n_b)):
+        sim.set_overlap(mode)
         for k in range(len(w["particles"])):
             sim.trace_enable(n, k)
     x = torch.randn(6144, 6144, device="cuda")
