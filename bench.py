@@ -46,23 +46,24 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(cells: int):
-    """HBM bytes per sweep launch from the committed rocprofv3 counter summary, or None when
-    the counters were taken on a different kernel source."""
+def measured_traffic(cells: int) -> dict:
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary and the sweep
+    kernel they were counted on (None for both when taken on a different kernel source)."""
+    none = {"traffic": None, "traffic_kernel": None}
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
-        return None
+        return none
     if t.get("kernel_source_sha256_16") != kernel_source_hash() or t.get("cells") != cells:
-        return None
-    return t.get("hbm_bytes_per_launch")
+        return none
+    return {"traffic": t.get("hbm_bytes_per_launch"), "traffic_kernel": t.get("kernel")}
 
 
 def measured_traffic_beyond(storage: str, cells: int) -> dict:
     """HBM bytes per sweep launch of the 8192 x 4096 leg for one storage and the sweep kernel
     they were counted on, from the committed counter summary (None for both when it was taken
     on a different kernel source)."""
-    none = {"traffic": None, "kernel": None}
+    none = {"traffic": None, "traffic_kernel": None}
     try:
         t = json.load(open(TRAFFIC_FILE_BEYOND))
     except (OSError, ValueError):
@@ -71,7 +72,7 @@ def measured_traffic_beyond(storage: str, cells: int) -> dict:
         return none
     for e in t.get("entries", []):
         if e.get("storage") == storage and e.get("cells") == cells:
-            return {"traffic": e.get("hbm_bytes_per_launch"), "kernel": e.get("kernel")}
+            return {"traffic": e.get("hbm_bytes_per_launch"), "traffic_kernel": e.get("kernel")}
     return none
 
 
@@ -135,7 +136,15 @@ def cpu_oracle(workload: dict, steps: int, threads: int | None = None) -> dict:
     }
 
 
-def beyond_cache_leg(steps: int, stream) -> dict:
+STORAGE_TYPE = {"fp32": "float", "fp64": "double", "fp16": "half_t", "bf16": "bf16_t", "fp16_neq": "half_neq_t",
+                "bf16_neq": "bf16_neq_t"}
+
+
+def sweep_kernel_name(prec: str, serial: bool) -> str:
+    return ("sweep_kernel" if serial else "sweep_overlap_kernel") + f"<{STORAGE_TYPE[prec]}, push>"
+
+
+def beyond_cache_leg(steps: int, stream, serial: bool = False) -> dict:
     """The sweep far beyond the 256 MB last-level cache: 8192 x 4096 channel with the scaled
     ellipse, every storage precision, each with its own roofline block (HIP-event-timed sweep
     average against 8 TB/s and against a copy of one population buffer measured in the same
@@ -151,6 +160,8 @@ def beyond_cache_leg(steps: int, stream) -> dict:
         w = W.with_precision(base, prec)
         sim = lbib.Sim(w, stream=stream)
         try:
+            if serial:
+                sim.set_overlap(0)
             bpu = sim.bytes_per_update
             sim.step(20)
             sim.sync()
@@ -167,7 +178,7 @@ def beyond_cache_leg(steps: int, stream) -> dict:
             "mlups": round(cells * steps / win["seconds"] / 1e6, 1),
             "ms_per_step": round(win["seconds"] * 1e3 / steps, 4),
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "kernel": sweep_kernel_name(prec, serial),
                          **measured_traffic_beyond(prec, cells),
                          "algorithmic_bytes_per_launch": bpu * cells,
                          "avg_launch_us": round(sweep_ms * 1e3, 2), "launches_timed": n0,
@@ -395,6 +406,10 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=100, help="oracle steps of the CPU baseline on all cores")
     ap.add_argument("--cpu-steps-one-thread", type=int, default=10, help="oracle steps on one thread")
     ap.add_argument("--no-timing-events", action="store_true", help="time only the whole steps")
+    ap.add_argument("--serial-schedule", action="store_true",
+                    help="run the 4096 x 1024 and 8192 x 4096 legs in the serial schedule (for counter collection, "
+                         "which serialises kernel dispatches: the overlapped schedule's device-side hand-over between "
+                         "its two streams does not survive that, its bounded waits time out)")
     ap.add_argument("--beyond-steps", type=int, default=200, help="timed steps per storage of the 8192 x 4096 leg")
     ap.add_argument("--c1-steps", type=int, default=2000, help="timed steps of the 256 x 64 FP64 leg")
     ap.add_argument("--batched-steps", type=int, default=200, help="steps of the 216-simulation sweep")
@@ -433,6 +448,8 @@ def main():
     cells = nx * ny
     log(f"bench: building {w['name']}")
     sim = lbib.Sim(w, stream=stream)
+    if args.serial_schedule:
+        sim.set_overlap(0)
     bpu = sim.bytes_per_update
     pull = sim.pull
     log(f"bench: warmup {args.warmup} steps")
@@ -475,8 +492,8 @@ def main():
         achieved = bpu * cells / (sweep_ms * 1e-3) / 1e9
         roofline = {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(cells),
-            "kernel": "sweep_overlap_kernel<float, push>", "algorithmic_bytes_per_launch": bpu * cells,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), **measured_traffic(cells),
+            "kernel": sweep_kernel_name("fp32", args.serial_schedule), "algorithmic_bytes_per_launch": bpu * cells,
             "avg_launch_us": round(sweep_ms * 1e3, 2), "launches_timed": n0,
             "timing": f"HIP events (hipExtLaunchKernelGGL) on the sweep's stream over {kr} steps after the "
                       f"timed windows",
@@ -484,14 +501,16 @@ def main():
             "working_set_note": "302 MB of populations against a 256 MB last-level cache: part of each sweep is "
                                 "served from that cache; beyond_cache gives the sweep at 2.4 GB",
             "particle_launch_avg_us": round(part_ms * 1e3, 2),
-            "schedule": "particle phases and sweeps on two streams with no event between them, handing "
-                        "over through device memory; the sweep's box tiles are taken by workgroups at the "
-                        "head of its grid once the particle has published its spread force",
+            "schedule": ("serial: the particle phase, then a sweep of every node, on one stream"
+                         if args.serial_schedule else
+                         "particle phases and sweeps on two streams with no event between them, handing "
+                         "over through device memory; the sweep's box tiles are taken by workgroups at the "
+                         "head of its grid once the particle has published its spread force"),
         }
     p = sim.particle()
     sim.close()
 
-    beyond = beyond_cache_leg(args.beyond_steps, stream) if "beyond" in legs else None
+    beyond = beyond_cache_leg(args.beyond_steps, stream, args.serial_schedule) if "beyond" in legs else None
     c1 = c1_leg(args.c1_steps, stream, "cpu" in legs) if "c1" in legs else None
     batched = batched_leg(args.batched_steps, stream) if "batched" in legs else None
     multi = multi_leg(args.multi_steps, args.multi_err_steps, stream) if "multi" in legs else None
