@@ -237,7 +237,8 @@ lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size);
  * grid, which take them once particle phase n has published its spread force; particle phase
  * n+1 starts once those workgroups have stored step n+1's populations around its box.  Every
  * device-side wait is bounded: one that exceeds about a second fails the simulation with
- * LBIB_E_NUMERIC.  Serial (mode 0), always on the first step after lbib_init / lbib_load /
+ * LBIB_E_NUMERIC.  Its two streams must run concurrently: a tool that serialises kernel
+ * dispatches (hardware-counter collection) makes those waits time out, so run mode 0 under it.  Serial (mode 0), always on the first step after lbib_init / lbib_load /
  * lbib_write_particle, and where CU masking is unavailable or ny >= 2^23: the particle phase
  * and a sweep of all nodes run one after the other on the handle's stream.  The overlapped
  * schedule's sweep stream is CU-masked, which takes a hardware queue of its own: at most 8
