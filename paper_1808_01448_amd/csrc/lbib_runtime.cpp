@@ -221,11 +221,14 @@ EvPair timing_events(lbib_sim* h, int kind)
 
 // The overlapped schedule's sweep stream: a CU mask that leaves one CU out of the sweep, a
 // CU its workgroups can never hold while they wait on the device for the particle's.  (A
-// one-workgroup launch goes to an XCD its queue chooses, so the particle may still queue
-// behind the sweep's dispatch; it parks on its CU a step ahead, so this costs no time, and
-// leaving one CU of every XCD out measured 3 % slower.)  Created at the first overlapped step
-// (each masked stream holds a hardware queue); without CU masking the overlapped schedule
-// stays off.
+// one-workgroup launch goes to the XCD and shader engine its queue chooses, not to that CU:
+// measured, the particle's workgroup used eight CUs of one shader engine and never the free
+// one, for any one of the mask bits tried.  It starts once enough of a CU is free, which a
+// dispatching sweep refills as fast as its workgroups retire: when the particle launch misses
+// a sweep's drain it runs after the next one's, and the step takes 59 instead of 46 us at
+// 4096 x 1024 until the call ends.  Leaving one CU of every XCD out measured 3 % slower.)
+// Created at the first overlapped step (each masked stream holds a hardware queue); without
+// CU masking the overlapped schedule stays off.
 hipError_t ensure_sweep_stream(lbib_sim* h)
 {
     if (h->stream3) return hipSuccess;
