@@ -510,11 +510,14 @@ def main():
             "working_set_note": "302 MB of populations against a 256 MB last-level cache: part of each sweep is "
                                 "served from that cache; beyond_cache gives the sweep at 2.4 GB",
             "particle_launch_avg_us": round(part_ms * 1e3, 2),
+            "particle_timing": ("one launch per step" if args.serial_schedule else
+                                "one resident launch over a call's steps: its duration divided by the steps"),
             "schedule": ("serial: the particle phase, then a sweep of every node, on one stream"
                          if args.serial_schedule else
                          "particle phases and sweeps on two streams with no event between them, handing "
-                         "over through device memory; the sweep's box tiles are taken by workgroups at the "
-                         "head of its grid once the particle has published its spread force"),
+                         "over through device memory; one particle launch stays resident over a call's "
+                         "steps, and the sweep's box tiles are taken by workgroups at the head of its grid "
+                         "once the particle has published its spread force"),
         }
     p = sim.particle()
     sim.close()

@@ -244,8 +244,12 @@ lbib_status lbib_load(lbib_handle h, const void* blob, int64_t size);
  * schedule's sweep stream is CU-masked, which takes a hardware queue of its own: at most 8
  * simulations per device hold one at a time, and the others run the serial schedule until
  * one of those is destroyed.  Mode 2 (the
- * default) overlaps wherever it can (the faster schedule at every lattice size measured).
- * Both schedules give bit-identical results. */
+ * default) overlaps wherever it can (the faster schedule at every lattice size measured) and
+ * runs the particle phases of a call's overlapped steps as one launch (up to 1024 steps each)
+ * whose workgroup stays on its CU from step to step; mode 1 launches the particle phase once
+ * per step, and such a launch can be dispatched only once a running sweep drains, which may
+ * leave it a sweep behind for the rest of the call.  Both schedules give bit-identical
+ * results. */
 /* Several particles in one lattice: the particle phase is split in two halves over all
  * particles -- first every particle stages its box and spreads its marker forces, then every
  * particle evaluates its probe loads (with the spread force of every particle that reaches a
@@ -289,7 +293,8 @@ lbib_status lbib_get_layout(lbib_handle h, int32_t* pull);
 /* Kernel timing: HIP events bracket every launch of the kernels selected by the bit mask
  * `enable` (0 switches timing off): bit 0 the lattice sweep (kernel 0), bit 1 the particle
  * phase (kernel 1; in the overlapped schedule the launch includes its wait for the previous
- * sweep), bit 2 the second particle launch of the split phase (kernel 2).  lbib_kernel_time
+ * sweep, and mode 2's launch over several steps counts as one launch per step), bit 2 the
+ * second particle launch of the split phase (kernel 2).  lbib_kernel_time
  * synchronises and returns the summed milliseconds and launch counts since the last enable.
  * The events add work between the launches they time: time whole steps without them. */
 lbib_status lbib_kernel_timing(lbib_handle h, int32_t enable);

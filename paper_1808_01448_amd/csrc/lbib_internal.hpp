@@ -292,6 +292,24 @@ size_t particle_scratch_bytes(int32_t box_cap);
 template <typename T>
 hipError_t launch_particle(const ParticleArgs<T>& a, hipStream_t stream, hipEvent_t t0 = nullptr,
                            hipEvent_t t1 = nullptr);
+// The overlapped schedule's particle phase of nsteps consecutive steps as one launch whose
+// workgroup stays on its CU from step to step.  Step step0 + k takes the arguments of a
+// launch of that step alone (`a` holds those of step step0): it reads f_even (k even) or f_odd,
+// its box slots are (step0 + k) mod 2, its ready value and zone tag advance by k, its zone
+// words are the pair at zone_base + 2 ((step0 + k + 1) mod 4), the count it waits for advances
+// by k nzone, and every step after the first checks its box against the previous one.
+template <typename T>
+struct ParticleRun {
+    const T* f_even;
+    const T* f_odd;
+    unsigned long long* zone_base;
+    int64_t step0;
+    int32_t nsteps;
+    int32_t nzone;
+};
+template <typename T>
+hipError_t launch_particle_run(const ParticleArgs<T>& a, const ParticleRun<T>& run, hipStream_t stream,
+                               hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 // The two launches of the split particle phase (mode 1: spread and mark; mode 2: loads,
 // bonds, update), one workgroup per particle of args[0..n); lds: the dynamic LDS of the
 // launch (the most particle_launch_lds of the particles).  ch: the device-side hand-over when

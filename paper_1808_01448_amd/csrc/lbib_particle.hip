@@ -1246,6 +1246,72 @@ __global__ __launch_bounds__(PB) void particle_kernel(ParticleArgs<T> a, uint32_
     particle_phase<T, MPT, 0>(a, (char*)lds_dyn, lds_bytes);
 }
 
+// ParticleRun: one workgroup runs the particle phase of every step of the run in turn.  A
+// launch per step needs about half a CU's registers before it can start; while the concurrent
+// sweep is dispatching, each CU's freed slots go to further sweep workgroups, so such a launch
+// that misses the previous sweep's drain starts only after the next one's, and its force comes
+// after that sweep's bulk (59 instead of 46 us per step at 4096 x 1024, until the call ends).
+// A workgroup that keeps its CU is never queued behind the sweep.  The step body is a call,
+// not inlined: a loop around the inlined phase keeps values live across its back edge and
+// spills; the call takes only the step index and reads the run's arguments from a copy in LDS.
+template <typename T>
+struct RunStage {
+    ParticleArgs<T> a;
+    ParticleRun<T> run;
+    uint32_t lds_bytes;
+};
+constexpr size_t kRunStageBytes = 768;
+static_assert(sizeof(RunStage<double>) <= kRunStageBytes && sizeof(RunStage<half_neq_t>) <= kRunStageBytes,
+              "the run's arguments fit their LDS copy");
+__shared__ __align__(16) unsigned char run_stage[kRunStageBytes];
+
+template <typename T, int MPT>
+__device__ __noinline__ void run_step(int32_t k_in)
+{
+    extern __shared__ double lds_dyn[];
+    const int32_t k = __builtin_amdgcn_readfirstlane(k_in);
+    // the copy's words are uniform: each goes to a scalar register as it is read
+    RunStage<T> sg;
+    {
+        static_assert(sizeof(RunStage<T>) % 4 == 0, "whole words");
+        constexpr int nw = (int)(sizeof(RunStage<T>) / 4);
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(run_stage);
+        uint32_t w[nw];
+#pragma unroll
+        for (int i = 0; i < nw; ++i) w[i] = __builtin_amdgcn_readfirstlane(src[i]);
+        __builtin_memcpy(&sg, w, sizeof(sg));
+    }
+    ParticleArgs<T> a = sg.a;
+    const ParticleRun<T> run = sg.run;
+    const uint32_t lds_bytes = sg.lds_bytes;
+    const int64_t step = run.step0 + k;
+    a.f = (k & 1) ? run.f_odd : run.f_even;
+    a.parity_in = (int32_t)(step & 1);
+    a.parity_out = a.parity_in ^ 1;
+    a.ready_value += (unsigned long long)k;
+    a.zone_words = run.zone_base + 2 * ((step + 1) & 3);
+    a.zone_tag = (uint32_t)(a.ready_value & 0xffffu);
+    a.zdone_target += (unsigned long long)k * (unsigned long long)run.nzone;
+    if (k > 0) a.check_prev = 1;
+    particle_phase<T, MPT, 0>(a, (char*)lds_dyn, lds_bytes);
+}
+
+template <typename T, int MPT>
+__global__ __launch_bounds__(PB) void particle_run_kernel(ParticleArgs<T> a, ParticleRun<T> run, uint32_t lds_bytes)
+{
+    if (threadIdx.x == 0) {
+        RunStage<T>& sg = *reinterpret_cast<RunStage<T>*>(run_stage);
+        sg.a = a;
+        sg.run = run;
+        sg.lds_bytes = lds_bytes;
+    }
+    __syncthreads();
+    for (int32_t k = 0; k < run.nsteps; ++k) {
+        run_step<T, MPT>(k);
+        __syncthreads();  // every wave is done with this step's LDS before the next step's writes
+    }
+}
+
 // Hand-over between the two launches of the split phase when they run on different streams.
 // chain_wait: one thread polls the monotonic counter until it reaches target (bounded: past
 // about a second it raises FLAG_SYNC and goes on), then its device-scope acquire drops stale
@@ -1499,6 +1565,31 @@ hipError_t launch_particle(const ParticleArgs<T>& a, hipStream_t stream, hipEven
     return hipErrorInvalidValue;
 }
 
+template <typename T, int MPT>
+hipError_t launch_particle_run_mpt(const ParticleArgs<T>& a, const ParticleRun<T>& run, hipStream_t stream,
+                                   hipEvent_t t0, hipEvent_t t1)
+{
+    static bool attr = false;
+    hipError_t e = allow_max_lds(particle_run_kernel<T, MPT>, attr);
+    if (e != hipSuccess) return e;
+    const size_t lds = particle_launch_lds(a.box_cap);
+    if (particle_lds_aux_bytes(a.box_cap) > lds) return hipErrorInvalidValue;
+    hipExtLaunchKernelGGL(particle_run_kernel<T, MPT>, dim3(1), dim3(PB), (uint32_t)lds, stream, t0, t1, 0u, a, run,
+                          (uint32_t)lds);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_particle_run(const ParticleArgs<T>& a, const ParticleRun<T>& run, hipStream_t stream, hipEvent_t t0,
+                               hipEvent_t t1)
+{
+    if (run.nsteps <= 0 || !run.f_even || !run.f_odd || !run.zone_base || !a.ready || !a.zdone || !a.check_zone)
+        return hipErrorInvalidValue;
+    if (a.nl <= PB) return launch_particle_run_mpt<T, 1>(a, run, stream, t0, t1);
+    if (a.nl <= 2 * PB) return launch_particle_run_mpt<T, 2>(a, run, stream, t0, t1);
+    return hipErrorInvalidValue;
+}
+
 // ---------------------------------------------------------------------------------------
 // Kernel-level entry points (same device functions as the time step)
 // ---------------------------------------------------------------------------------------
@@ -1626,6 +1717,8 @@ hipError_t launch_copy(const float4* src, float4* dst, int64_t n, hipStream_t st
     template hipError_t launch_pool_particle<T>(const ParticleArgs<T>*, const int32_t*, TileDesc*, int32_t,      \
                                                 int32_t, size_t, hipStream_t, hipEvent_t, hipEvent_t);          \
     template hipError_t launch_particle<T>(const ParticleArgs<T>&, hipStream_t, hipEvent_t, hipEvent_t);        \
+    template hipError_t launch_particle_run<T>(const ParticleArgs<T>&, const ParticleRun<T>&, hipStream_t,      \
+                                               hipEvent_t, hipEvent_t);                                          \
     template hipError_t launch_particle_split<T>(const ParticleArgs<T>*, int32_t, const T*, unsigned long long*, \
                                                  int32_t, int32_t, size_t, hipStream_t, hipEvent_t, hipEvent_t,  \
                                                  const SplitChain&);                                               \

@@ -207,7 +207,9 @@ struct EvPair {
     hipEvent_t t0 = nullptr, t1 = nullptr;
 };
 
-EvPair timing_events(lbib_sim* h, int kind)
+// `steps`: the steps the launch covers, counted as that many launches (the overlapped
+// schedule's particle run).
+EvPair timing_events(lbib_sim* h, int kind, int64_t steps = 1)
 {
     Timing& t = h->timing;
     EvPair p;
@@ -215,18 +217,23 @@ EvPair timing_events(lbib_sim* h, int kind)
     p.t0 = t.ev[kind][t.used[kind]];
     p.t1 = t.ev[kind][t.used[kind] + 1];
     t.used[kind] += 2;
-    t.launches[kind] += 1;
+    t.launches[kind] += steps;
     return p;
 }
+
+// Longest run of steps one resident particle launch of the overlapped schedule covers; a
+// longer call enqueues one such launch after another.
+constexpr int64_t kRunSteps = 1024;
 
 // The overlapped schedule's sweep stream: a CU mask that leaves one CU out of the sweep, a
 // CU its workgroups can never hold while they wait on the device for the particle's.  (A
 // one-workgroup launch goes to the XCD and shader engine its queue chooses, not to that CU:
 // measured, the particle's workgroup used eight CUs of one shader engine and never the free
 // one, for any one of the mask bits tried.  It starts once enough of a CU is free, which a
-// dispatching sweep refills as fast as its workgroups retire: when the particle launch misses
-// a sweep's drain it runs after the next one's, and the step takes 59 instead of 46 us at
-// 4096 x 1024 until the call ends.  Leaving one CU of every XCD out measured 3 % slower.)
+// dispatching sweep refills as fast as its workgroups retire: a particle launch per step that
+// misses a sweep's drain runs after the next one's, and the step takes 59 instead of 46 us at
+// 4096 x 1024 until the call ends, which is why mode 2 keeps one particle launch resident over
+// a call's steps.  Leaving one CU of every XCD out measured 3 % slower.)
 // Created at the first overlapped step (each masked stream holds a hardware queue); without
 // CU masking the overlapped schedule stays off.
 hipError_t ensure_sweep_stream(lbib_sim* h)
@@ -272,6 +279,7 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
     // event and cross-stream wait at the call's start: ~20 us of a short call); anything this
     // call enqueues on it clears this
     bool idle = stream_idle(h->stream);
+    int64_t run_left = 0;  // steps still covered by the resident particle launch already enqueued
     h->h_flags_valid = false;  // until this call's copy is enqueued
     const bool split = h->parts.size() > 1 || (h->overlap == 3 && !h->parts.empty());
     if (split && h->args_dirty) {
@@ -380,6 +388,7 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
                     HIPCHK(h, hipStreamWaitEvent(h->stream, h->evB, 0));
                     joined = true;
                 }
+                if (run_left != 0) return fail(h, LBIB_E_STATE, "lbib_step: a serial step inside a resident particle run");
                 pa.check_zone = 0;
                 idle = false;
                 const EvPair e1 = timing_events(h, 1);
@@ -402,9 +411,22 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
                 pa.zdone = p.d_count + 1;
                 pa.zdone_target = h->zdone_expected;
                 pa.check_prev = h->prev_overlapped ? 1 : 0;
-                const EvPair e1 = timing_events(h, 1);
-                HIPCHK(h, launch_particle<T>(pa, h->stream2, e1.t0, e1.t1));
                 const int nzone = zone_workgroups(p, h->g.pull);
+                if (h->overlap == 1) {  // a launch per step
+                    const EvPair e1 = timing_events(h, 1);
+                    HIPCHK(h, launch_particle<T>(pa, h->stream2, e1.t0, e1.t1));
+                } else {
+                    // mode 2: one launch for this step and the call's later ones (every later
+                    // step of the call is overlapped too), its workgroup resident between them
+                    if (run_left == 0) {
+                        const int64_t len = std::min<int64_t>(n - s, kRunSteps);
+                        const ParticleRun<T> run{fin, (const T*)h->fB, p.d_count + 2, h->steps, (int32_t)len, nzone};
+                        const EvPair e1 = timing_events(h, 1, len);
+                        HIPCHK(h, launch_particle_run<T>(pa, run, h->stream2, e1.t0, e1.t1));
+                        run_left = len;
+                    }
+                    --run_left;
+                }
                 const HandoverArgs ha{p.d_count + 2 + 2 * (h->steps & 3), (uint32_t)(prev & 0xffffu), p.d_desc, p.d_tile,
                                       p.d_count, prev + 1, p.d_count + 1, h->d_flags, nzone};
                 const EvPair e0 = timing_events(h, 0);

@@ -385,8 +385,9 @@ class Sim:
         return bool(v.value)
 
     def set_overlap(self, mode):
-        """0 / False: serial; 1 / True: overlapped (one particle) or chained split phase (several);
-        2 (default): overlapped for one particle, the one-launch split phase for several; 3: the
+        """0 / False: serial; 1 / True: overlapped with a particle launch per step (one particle)
+        or chained split phase (several); 2 (default): overlapped with one resident particle
+        launch over a call's steps (one particle), the one-launch split phase (several); 3: the
         split particle phase in order on one stream; 4: several particles' split phase as one
         launch (workgroups claim their particles, no co-residency needed); 5: that launch on a
         single workgroup (its fallback path every step; for testing)."""

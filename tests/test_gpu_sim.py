@@ -314,15 +314,17 @@ def test_large_fp64_lattice_alternating_sweep_order(L, orc):
 # Determinism, checkpoints, failure handling
 # ----------------------------------------------------------------------------------------
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_overlapped_schedule_is_bit_identical(L, prec):
-    """The overlapped schedule (particle phase concurrent with the sweep outside its box)
+def test_overlapped_schedule_is_bit_identical(L, prec, mode):
+    """The overlapped schedule (particle phase concurrent with the sweep outside its box), with
+    a particle launch per step (mode 1) or one resident launch over the call's steps (mode 2),
     equals the serial one bit for bit, also across a state overwrite that invalidates the
     predicted box."""
     w = W.channel_small_binding(prec)
     a = L.Sim(w)
     b = L.Sim(w)
-    a.set_overlap(True)
+    a.set_overlap(mode)
     b.set_overlap(False)
     a.trace_enable(400)
     b.trace_enable(400)
@@ -402,33 +404,36 @@ def test_failure_nonfinite(L):
     s.close()
 
 
-def test_kernel_timing_and_step_zero(L):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_kernel_timing_and_step_zero(L, mode):
     w = W.channel_small_fp64()
     s = L.Sim(w)
     s.step(0)
     assert s.particle()["step"] == -1
-    s.set_overlap(True)
+    s.set_overlap(mode)
     s.kernel_timing(True)
     s.step(20)
     ms0, n0 = s.kernel_time(0)
     ms1, n1 = s.kernel_time(1)
     ms2, n2 = s.kernel_time(2)
-    say("timing", ms0, n0, ms1, n1, ms2, n2)
-    # the first step is serial (no predicted box yet), the others overlapped; one particle
-    # launch and one sweep per step, no launch of kernel 2 (the split phase's second launch)
+    say("timing", mode, ms0, n0, ms1, n1, ms2, n2)
+    # the first step is serial (no predicted box yet), the others overlapped: one particle
+    # launch per step (mode 1) or one for the 19 overlapped steps, counted per step (mode 2);
+    # one sweep per step, no launch of kernel 2 (the split phase's second launch)
     assert n0 == 20 and n1 == 20 and n2 == 0 and ms0 > 0 and ms1 > 0 and ms2 == 0
     assert s.bytes_per_update == 144
     s.close()
 
 
-@pytest.mark.parametrize("overlap", [0, 1, 3])
+@pytest.mark.parametrize("overlap", [0, 1, 2, 3])
 def test_particle_fields_in_global_scratch(L, orc, overlap):
     """A circle of radius 200 with 1024 markers: the nodes its supports reach (~5 800, or
     ~3 800 per launch of the split phase) exceed what fits beside its node mask in LDS, so
     the node fields and the node map live in the particle's global scratch (device-scope
     atomics for the spread).  Fused phase serial (mode 0) and overlapped (mode 1: the sweep's
-    box tiles, ~800 of them, go to as many workgroups at the head of its grid) and split phase
-    (mode 3) against the oracle."""
+    box tiles, ~800 of them, go to as many workgroups at the head of its grid; mode 2: the same
+    with the resident particle launch, whose dynamic LDS request is then the largest) and split
+    phase (mode 3) against the oracle."""
     w = W.channel_small_binding("fp64")
     w["lattice"].update(nx=512, ny=448)
     w["particle"].update(a_major=200.0, b_minor=200.0, xc=256.0, yc=-0.5 + 0.3 + 200.0, n_markers=1024)
@@ -456,7 +461,8 @@ def _serial_reference(L, w, steps):
     return out
 
 
-def test_overlapped_schedule_switches_and_calls(L):
+@pytest.mark.parametrize("overlapped", [1, 2])
+def test_overlapped_schedule_switches_and_calls(L, overlapped):
     """Overlapped steps in several calls of different lengths, with serial steps between
     them (the device-side hand-over counts and box slots carry across calls and schedule
     changes), equal the serial schedule bit for bit."""
@@ -465,7 +471,7 @@ def test_overlapped_schedule_switches_and_calls(L):
     s = L.Sim(w)
     s.trace_enable(400)
     for mode, n in ((1, 1), (1, 7), (1, 64), (0, 3), (1, 5), (0, 1), (1, 120), (1, 1)):
-        s.set_overlap(mode)
+        s.set_overlap(overlapped if mode else 0)
         s.step(n)
         steps += n
     s.sync()
@@ -476,7 +482,29 @@ def test_overlapped_schedule_switches_and_calls(L):
     s.close()
 
 
-def test_many_overlapped_simulations_in_one_process(L):
+def test_resident_particle_runs_across_long_calls(L):
+    """Mode 2 runs a call's overlapped particle phases as resident launches of at most 1024
+    steps: calls of 1100 and 1030 steps (two launches each, the second taking over the
+    hand-over counts, box slots and buffers from the first), with a mode-1 call and a serial
+    step between them, equal the serial schedule bit for bit."""
+    w = W.channel_small_binding("fp32")
+    seq = ((2, 1100), (1, 3), (0, 1), (2, 1030))
+    steps = sum(n for _, n in seq)
+    s = L.Sim(w)
+    s.trace_enable(steps)
+    for mode, n in seq:
+        s.set_overlap(mode)
+        s.step(n)
+    s.sync()
+    ref = _serial_reference(L, w, steps)
+    np.testing.assert_array_equal(s.trace(steps), ref[0])
+    np.testing.assert_array_equal(s.f, ref[1])
+    np.testing.assert_array_equal(s.bonds()[0], ref[2])
+    s.close()
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_many_overlapped_simulations_in_one_process(L, mode):
     """240 simulations asking for the overlapped schedule in one process: each overlapped one
     holds a CU-masked stream (a hardware queue of its own), and the runtime faults rather than
     refuses once a process holds a few hundred, so the library gives masked streams to at most
@@ -491,7 +519,7 @@ def test_many_overlapped_simulations_in_one_process(L):
     for count in (240, 12):
         sims = [L.Sim(w) for _ in range(count)]
         for s in sims:
-            s.set_overlap(1)
+            s.set_overlap(mode)
             s.trace_enable(steps)
         for k in range(steps):
             for s in sims:
@@ -505,16 +533,17 @@ def test_many_overlapped_simulations_in_one_process(L):
             s.close()
 
 
-def test_two_overlapped_simulations_interleaved(L):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_two_overlapped_simulations_interleaved(L, mode):
     """Two simulations in the overlapped schedule, their steps enqueued alternately so both
-    run at once (their sweeps leave the same CU to their particle launches): each equals its
-    serial run bit for bit."""
+    run at once (in mode 2 both resident particle launches at once): each equals its serial
+    run bit for bit."""
     wa = W.channel_small_binding("fp64")
     wb = W.channel_small_binding("fp32")
     wb["particle"]["xc"] += 37.0
     sims = [L.Sim(wa), L.Sim(wb)]
     for s in sims:
-        s.set_overlap(1)
+        s.set_overlap(mode)
         s.trace_enable(200)
     for k in range(20):
         for s in sims:
