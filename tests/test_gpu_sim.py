@@ -534,6 +534,38 @@ def test_many_overlapped_simulations_in_one_process(L, mode):
 
 
 @pytest.mark.parametrize("mode", [1, 2])
+def test_overlapped_calls_behind_pending_work_on_the_callers_stream(L, mode):
+    """lbib_step starts its second and third streams after whatever the caller's stream still
+    holds (an event and two waits), and skips that join when the stream is idle.  Calls made
+    while a matrix product is pending on the simulation's own stream, and one after the stream
+    has drained, equal the serial schedule bit for bit."""
+    w = W.channel_small_binding("fp32")
+    calls = (9, 1, 40, 3, 25)
+    steps = sum(calls)
+    st = torch.cuda.Stream()
+    s = L.Sim(w, stream=st)
+    s.set_overlap(mode)
+    s.trace_enable(steps)
+    x = torch.randn(4096, 4096, device="cuda")
+    torch.cuda.synchronize()
+    for k, n in enumerate(calls):
+        if k == 3:
+            torch.cuda.synchronize()  # this call finds the stream idle
+        else:
+            with torch.cuda.stream(st):
+                y = torch.mm(x, x)
+        s.step(n)
+    s.sync()
+    torch.cuda.synchronize()
+    ref = _serial_reference(L, w, steps)
+    np.testing.assert_array_equal(s.trace(steps), ref[0])
+    np.testing.assert_array_equal(s.f, ref[1])
+    np.testing.assert_array_equal(s.bonds()[0], ref[2])
+    s.close()
+    del y
+
+
+@pytest.mark.parametrize("mode", [1, 2])
 def test_two_overlapped_simulations_interleaved(L, mode):
     """Two simulations in the overlapped schedule, their steps enqueued alternately so both
     run at once (in mode 2 both resident particle launches at once): each equals its serial
