@@ -450,7 +450,6 @@ lbib_status enqueue_steps(lbib_sim* h, int64_t n)
         }
         HIPCHK(h, hipEventRecord(h->evB, h->stream2));
         HIPCHK(h, hipStreamWaitEvent(h->stream, h->evB, 0));
-        HIPCHK(h, hipEventRecord(h->evA, h->stream));
     }
     if (n > 0) {
         HIPCHK(h, hipMemcpyAsync(h->h_flags, h->d_flags, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
